@@ -1,0 +1,566 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms,
+library routines (scipy, numpy, torch CPU), invariants, a brute-force
+per-pixel blend, central finite differences, published known answers and
+hand-evaluated fixtures under tests/golden/.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def one_gaussian_scene(mean, quat, log_scale, logit, colour=None, sh=None, deg=0):
+    K = (deg + 1) ** 2
+    if sh is None:
+        sh = np.zeros((3 * K, 1), np.float32)
+        c = np.asarray(colour if colour is not None else (0.2, 0.5, 0.8), np.float64)
+        sh[0:3, 0] = (c - 0.5) / synth.Y00
+    return synth.Scene(np.asarray(mean, np.float32).reshape(3, 1), np.asarray(quat, np.float32).reshape(4, 1),
+                       np.asarray(log_scale, np.float32).reshape(3, 1), np.asarray([logit], np.float32),
+                       np.asarray(sh, np.float32).reshape(3 * K, -1), deg)
+
+
+def axis_camera(W=64, H=48, campos=(0.0, 0.0, 0.0)):
+    """Camera looking down +z with R = I (x right, y down)."""
+    return synth.make_camera(np.eye(3), campos, W, H)
+
+
+# ------------------------------------------------------------------------------------------
+# Projection (App. A.1: Sigma = R S S^T R^T, Sigma_2D = J W Sigma W^T J^T)
+# ------------------------------------------------------------------------------------------
+def test_isotropic_closed_form_footprint():
+    """An isotropic Gaussian of scale s on the optical axis at depth z projects to the principal
+    point with Sigma_2D = ((f s / z)^2 + 0.3) I, hence r = ceil(3 sqrt(.)), for any rotation."""
+    cam = axis_camera(64, 48)
+    rng = np.random.default_rng(1)
+    for z, s in [(2.0, 0.01), (3.0, 0.05), (7.5, 0.2), (1.0, 0.003)]:
+        q = rng.normal(size=4)
+        sc = one_gaussian_scene((0, 0, z), q, np.log([s, s, s]), 0.3)
+        p = oracle.project(sc, cam)
+        z32, s32 = float(np.float32(z)), float(np.exp(np.float64(np.float32(np.log(s)))))
+        var = (cam.fx * s32 / z32) ** 2 + float(np.float32(0.3))
+        assert p.uv[0] == pytest.approx([cam.cx, cam.cy], abs=1e-12)
+        assert p.conic[0] == pytest.approx([1.0 / var, 0.0, 1.0 / var], rel=1e-10, abs=1e-14)
+        assert p.radius[0] == math.ceil(3.0 * math.sqrt(var))
+        assert p.depth[0] == pytest.approx(z32, abs=0)
+
+
+def numeric_jacobian(f, x, h=1e-6):
+    J = np.zeros((2, 3))
+    for k in range(3):
+        e = np.zeros(3); e[k] = h
+        J[:, k] = (f(x + e) - f(x - e)) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_projection_matches_numeric_jacobian_and_scipy_rotation(seed):
+    """Sigma_2D from a numerically differentiated pinhole map and scipy's rotation matrix."""
+    rng = np.random.default_rng(seed)
+    R_cam = Rotation.from_rotvec(rng.normal(scale=0.2, size=3)).as_matrix()
+    campos = rng.normal(scale=0.3, size=3)
+    cam = synth.make_camera(R_cam, campos, 96, 80)
+    # a point in front of the camera, within the clamp
+    xc = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), 1.0]) * rng.uniform(2, 6)
+    Rw = cam.R.astype(np.float64)
+    mean = Rw.T @ (xc - cam.t.astype(np.float64))
+    q = rng.normal(size=4).astype(np.float32)
+    ls = rng.normal(-2.5, 0.5, size=3).astype(np.float32)
+    sc = one_gaussian_scene(mean, q, ls, 0.0)
+    p = oracle.project(sc, cam)
+    # expected, from library rotation (scalar-last) and numeric derivative of the pinhole map
+    qd = q.astype(np.float64)
+    Rq = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+    S = np.diag(np.exp(ls.astype(np.float64)))
+    Sigma = Rq @ S @ S.T @ Rq.T
+    m64 = sc.mean[:, 0].astype(np.float64)
+    tcam = Rw @ m64 + cam.t.astype(np.float64)
+
+    def pin(x):
+        return np.array([cam.fx * x[0] / x[2] + cam.cx, cam.fy * x[1] / x[2] + cam.cy])
+
+    J = numeric_jacobian(pin, tcam)
+    S2 = J @ Rw @ Sigma @ Rw.T @ J.T + float(np.float32(0.3)) * np.eye(2)
+    conic = np.linalg.inv(S2)
+    assert p.uv[0] == pytest.approx(pin(tcam), rel=1e-12)
+    np.testing.assert_allclose([conic[0, 0], conic[0, 1], conic[1, 1]], p.conic[0], rtol=1e-6, atol=1e-9)
+    lam = np.linalg.eigvalsh(S2).max()
+    assert p.radius[0] == math.ceil(3 * math.sqrt(lam))
+
+
+def test_rotation_invariants_via_isotropy():
+    """Isotropic s makes Sigma = s^2 I for every q (R R^T = I), so the footprint ignores q."""
+    cam = axis_camera(64, 64)
+    rng = np.random.default_rng(3)
+    base = oracle.project(one_gaussian_scene((0.1, -0.2, 3), (1, 0, 0, 0), np.log([0.04] * 3), 0.0), cam)
+    for _ in range(10):
+        p = oracle.project(one_gaussian_scene((0.1, -0.2, 3), rng.normal(size=4), np.log([0.04] * 3), 0.0), cam)
+        np.testing.assert_allclose(p.conic, base.conic, rtol=1e-12)
+
+
+def test_cull_near_plane_and_behind():
+    cam = axis_camera(64, 64)
+    for z, vis in [(0.1, False), (0.2, False), (0.2001, True), (-3.0, False)]:
+        p = oracle.project(one_gaussian_scene((0, 0, z), (1, 0, 0, 0), np.log([0.001] * 3), 0.0), cam)
+        assert bool(p.visible[0]) == vis
+
+
+# ------------------------------------------------------------------------------------------
+# SH colour (App. A.1 "view-dependent color property"; basis choice documented)
+# ------------------------------------------------------------------------------------------
+def sphere_grid(nt=200, nphi=400):
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    ph = (np.arange(nphi) + 0.5) * 2 * np.pi / nphi
+    T, Pp = np.meshgrid(th, ph, indexing="ij")
+    w = np.sin(T) * (np.pi / nt) * (2 * np.pi / nphi)
+    d = np.stack([np.sin(T) * np.cos(Pp), np.sin(T) * np.sin(Pp), np.cos(T)], -1).reshape(-1, 3)
+    return d, w.reshape(-1), T.reshape(-1), Pp.reshape(-1)
+
+
+def test_sh_orthonormal_by_quadrature():
+    d, w, _, _ = sphere_grid()
+    Y = oracle.sh_eval(3, d)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=2e-4)
+
+
+def test_sh_matches_scipy_real_combinations():
+    from scipy.special import sph_harm_y
+    d, _, th, ph = sphere_grid(20, 30)
+    Y = oracle.sh_eval(3, d)
+    for l in range(4):
+        for m in range(-l, l + 1):
+            if m == 0:
+                ref = sph_harm_y(l, 0, th, ph).real
+            elif m > 0:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, m, th, ph).real
+            else:
+                ref = math.sqrt(2) * (-1) ** m * sph_harm_y(l, -m, th, ph).imag
+            np.testing.assert_allclose(Y[:, l * l + m + l], ref, atol=1e-12, err_msg=f"l={l} m={m}")
+
+
+def test_degree0_colour_and_clamp():
+    cam = axis_camera()
+    for c, want in [((0.2, 0.5, 0.9), (0.2, 0.5, 0.9)), ((-0.3, 0.0, 1.4), (0.0, 0.0, 1.4))]:
+        p = oracle.project(one_gaussian_scene((0, 0, 3), (1, 0, 0, 0), np.log([0.05] * 3), 0.0, colour=c), cam)
+        np.testing.assert_allclose(p.rgb[0], want, atol=1e-7)
+
+
+# ------------------------------------------------------------------------------------------
+# Blend (App. A.1: C = sum c_i a_i prod_{j<i} (1 - a_j); thresholds documented)
+# ------------------------------------------------------------------------------------------
+def test_single_gaussian_closed_form():
+    cam = axis_camera(64, 48)
+    bg = (0.1, 0.2, 0.3)
+    for logit in (-1.0, 2.0, 8.0):
+        sc = one_gaussian_scene((0.05, -0.03, 2.0), (0.9, 0.1, 0.3, -0.2), np.log([0.03, 0.02, 0.01]), logit,
+                                colour=(0.9, 0.4, 0.1))
+        vr = oracle.render_view(sc, cam, bg=bg)
+        p = vr.proj
+        TX, TY = oracle.tiles_of(cam, (16, 16))
+        ys, xs = np.mgrid[0:48, 0:64]
+        dx = p.uv[0, 0] - xs; dy = p.uv[0, 1] - ys
+        A, B, Cc = p.conic[0]
+        P = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+        a = np.minimum(float(np.float32(0.99)), p.opacity[0] * np.exp(P))
+        x0, y0, x1, y1 = p.rect[0]
+        inside = (xs // 16 >= x0) & (xs // 16 < x1) & (ys // 16 >= y0) & (ys // 16 < y1)
+        use = inside & (a >= float(np.float32(1 / 255))) & (P <= 0)
+        for ch in range(3):
+            want = np.where(use, p.rgb[0, ch] * a + (1 - a) * bg[ch], bg[ch])
+            np.testing.assert_allclose(vr.rgb[ch], want, atol=1e-15)
+
+
+def test_two_gaussians_closed_form_depth_order():
+    cam = axis_camera(32, 32)
+    mean = np.array([[0.0, 0.01], [0.0, 0.0], [2.0, 1.5]], np.float32)  # second is nearer
+    sc = synth.Scene(mean, np.array([[1, 1], [0, 0], [0, 0], [0, 0]], np.float32),
+                     np.log(np.full((3, 2), 0.05, np.float32)), np.array([0.5, -0.5], np.float32),
+                     ((np.array([[0.9, 0.1], [0.2, 0.7], [0.3, 0.3]]) - 0.5) / synth.Y00).astype(np.float32), 0)
+    bg = (0.05, 0.1, 0.15)
+    vr = oracle.render_view(sc, cam, bg=bg)
+    p = vr.proj
+    ys, xs = np.mgrid[0:32, 0:32]
+
+    def alpha(g):
+        dx = p.uv[g, 0] - xs; dy = p.uv[g, 1] - ys
+        A, B, Cc = p.conic[g]
+        P = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+        a = np.minimum(float(np.float32(0.99)), p.opacity[g] * np.exp(P))
+        return np.where(a >= float(np.float32(1 / 255)), a, 0.0)
+
+    a1, a2 = alpha(1), alpha(0)  # nearer first
+    for ch in range(3):
+        want = p.rgb[1, ch] * a1 + p.rgb[0, ch] * a2 * (1 - a1) + (1 - a1) * (1 - a2) * bg[ch]
+        np.testing.assert_allclose(vr.rgb[ch], want, atol=1e-13)
+
+
+def brute_force_pixel(p, gids, px, py, bg):
+    """Per-pixel definition: the Gaussians whose rectangle holds this pixel's tile, sorted by
+    (float32 depth, index), walked front to back with the documented thresholds."""
+    order = sorted(gids, key=lambda g: (np.float32(p.depth[g]), g))
+    T, Cc, last = 1.0, np.zeros(3), 0
+    amax, amin, tstop = float(np.float32(0.99)), float(np.float32(1 / 255)), float(np.float32(1e-4))
+    for i, g in enumerate(order):
+        dx, dy = p.uv[g, 0] - px, p.uv[g, 1] - py
+        A, B, C_ = p.conic[g]
+        P = -0.5 * (A * dx * dx + C_ * dy * dy) - B * dx * dy
+        if P > 0:
+            continue
+        a = min(amax, p.opacity[g] * math.exp(P))
+        if a < amin:
+            continue
+        Tn = T * (1 - a)
+        if Tn < tstop:
+            break
+        Cc += p.rgb[g] * a * T
+        T = Tn
+        last = i + 1
+    return Cc + T * np.asarray(bg), T, last
+
+
+@pytest.mark.parametrize("seed,deg", [(0, 0), (1, 1), (2, 3)])
+def test_tiled_blend_equals_brute_force(seed, deg):
+    sc, cams, _ = synth.tiny_scene(seed, 40, 40, 36, sh_degree=deg, log_scale_mu=-2.2)
+    cam = cams[0]
+    bg = (0.3, 0.1, 0.2)
+    vr = oracle.render_view(sc, cam, bg=bg)
+    p = vr.proj
+    TX, TY = oracle.tiles_of(cam, (16, 16))
+    for py in range(0, 36, 3):
+        for px in range(0, 40, 3):
+            tx, ty = px // 16, py // 16
+            gids = [g for g in range(sc.n) if p.visible[g] and p.rect[g, 0] <= tx < p.rect[g, 2]
+                    and p.rect[g, 1] <= ty < p.rect[g, 3]]
+            C_, T, last = brute_force_pixel(p, gids, float(px), float(py), bg)
+            np.testing.assert_allclose(vr.rgb[:, py, px], C_, atol=1e-14)
+            assert vr.t_final[py, px] == pytest.approx(T, abs=1e-15)
+            assert vr.n_contrib[py, px] == last
+
+
+def white_scene(sc):
+    out = sc.copy()
+    out.sh[:] = 0
+    out.sh[0:3] = (1.0 - 0.5) / synth.Y00
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_blend_invariants(seed):
+    """sum_i a_i T_i + T_final = 1 (render white with black background); T_final >= 1e-4;
+    a pixel whose walk stopped early has T_final < 1e-2 (since alpha <= 0.99)."""
+    sc, cams, _ = synth.single_view_scene(seed)
+    sc = white_scene(sc)
+    vr = oracle.render_view(sc, cams[0], bg=(0, 0, 0))
+    np.testing.assert_allclose(vr.rgb[0] + vr.t_final, 1.0, atol=1e-12)
+    assert vr.t_final.min() >= float(np.float32(1e-4))
+    # dense pile-up: many opaque Gaussians at one pixel stop early
+    n = 60
+    dense = synth.Scene(np.tile(np.array([[0.0], [0.0], [0.0]], np.float32), (1, n)) +
+                        np.linspace(0, 0.5, n, dtype=np.float32)[None] * np.array([[0], [0], [1]], np.float32),
+                        np.tile(np.array([[1], [0], [0], [0]], np.float32), (1, n)),
+                        np.full((3, n), np.log(0.3), np.float32), np.full(n, 3.0, np.float32),
+                        np.full((3, n), 0.5 / synth.Y00, np.float32), 0)
+    vr2 = oracle.render_view(dense, cams[0], bg=(0, 0, 0))
+    lens = vr2.ranges[:, 1] - vr2.ranges[:, 0]
+    centre_tile = (64 // 16) * 8 + 64 // 16
+    assert vr2.n_contrib[64, 64] < lens[centre_tile]
+    assert vr2.t_final[64, 64] < 1e-2
+    assert vr2.t_final[64, 64] >= float(np.float32(1e-4))
+
+
+def test_transmittance_monotone_along_lists():
+    sc, cams, _ = synth.tiny_scene(4, 50, 32, 32, log_scale_mu=-2.0)
+    vr = oracle.render_view(white_scene(sc), cams[0])
+    # T after k entries is non-increasing in k: check via prefix renders with truncated lists
+    Ts = []
+    for cut in range(0, 60, 5):
+        r = vr.ranges.copy()
+        r[:, 1] = np.minimum(r[:, 1], r[:, 0] + cut)
+        vrk = oracle.render_view(white_scene(sc), cams[0], key_data=(vr.keys, vr.vals, r))
+        Ts.append(vrk.t_final)
+    for a, b in zip(Ts, Ts[1:]):
+        assert np.all(b <= a + 1e-15)
+
+
+# ------------------------------------------------------------------------------------------
+# Keys, sort, ranges
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_keys_sort_ranges_against_numpy(seed):
+    sc, cams, _ = synth.single_view_scene(seed)
+    cam = cams[0]
+    p = oracle.project(sc, cam)
+    k, v, r = oracle.keys(p, cam)
+    TX, TY = oracle.tiles_of(cam, (16, 16))
+    # library sort of the same (key, value) multiset
+    raw = []
+    for g in range(sc.n):
+        if not p.visible[g]:
+            continue
+        x0, y0, x1, y1 = p.rect[g]
+        for ty in range(y0, y1):
+            for tx in range(x0, x1):
+                raw.append(((ty * TX + tx) << 32) | int(p.depth_bits[g]))
+    raw_v = []
+    for g in range(sc.n):
+        if p.visible[g]:
+            x0, y0, x1, y1 = p.rect[g]
+            raw_v += [g] * ((x1 - x0) * (y1 - y0))
+    raw = np.array(raw, np.uint64); raw_v = np.array(raw_v, np.uint32)
+    order = np.argsort(raw, kind="stable")
+    np.testing.assert_array_equal(k, raw[order])
+    np.testing.assert_array_equal(v, raw_v[order])
+    tiles = (k >> np.uint64(32)).astype(np.int64)
+    lo = np.searchsorted(tiles, np.arange(TX * TY), side="left")
+    hi = np.searchsorted(tiles, np.arange(TX * TY), side="right")
+    empty = lo == hi
+    lo[empty] = 0; hi[empty] = 0
+    np.testing.assert_array_equal(r[:, 0], lo)
+    np.testing.assert_array_equal(r[:, 1], hi)
+    # depth bits are the float32 camera-space depth
+    assert np.all(p.depth_bits[p.visible] == p.depth[p.visible].astype(np.float32).view(np.uint32))
+
+
+# ------------------------------------------------------------------------------------------
+# Gradients: central finite differences of L = sum dl * render
+# ------------------------------------------------------------------------------------------
+def _loss_and_sig(sc, cam, dl, bg):
+    vr = oracle.render_view(sc, cam, bg=bg)
+    return float(np.sum(vr.rgb * dl)), (vr.keys.tobytes(), vr.signature.tobytes())
+
+
+@pytest.mark.parametrize("seed,deg", [(0, 1), (1, 3), (2, 0)])
+def test_gradients_match_finite_differences(seed, deg):
+    sc, cams, dls = synth.tiny_scene(seed, 6, 32, 32, sh_degree=deg, log_scale_mu=-2.0, spread=0.4)
+    cam, dl = cams[0], dls[0].astype(np.float64)
+    bg = (0.2, 0.1, 0.05)
+    g, _, _, _ = oracle.render_backward(sc, [cam], [dl], bg=bg)
+    # scene with float64 planes so the perturbation is exact
+    sc64 = synth.Scene(sc.mean.astype(np.float64), sc.quat.astype(np.float64), sc.log_scale.astype(np.float64),
+                       sc.logit.astype(np.float64), sc.sh.astype(np.float64), deg)
+    checked = skipped = 0
+    for name in ("mean", "quat", "log_scale", "logit", "sh"):
+        arr = getattr(sc64, name)
+        ana = getattr(g, name)
+        for idx in np.ndindex(arr.shape):
+            x = arr[idx]
+            h = 1e-6 * max(1.0, abs(x))
+            arr[idx] = x + h
+            lp, sp = _loss_and_sig(sc64, cam, dl, bg)
+            arr[idx] = x - h
+            lm, sm = _loss_and_sig(sc64, cam, dl, bg)
+            arr[idx] = x
+            if sp != sm:
+                skipped += 1
+                continue
+            fd = (lp - lm) / (2 * h)
+            scale = max(abs(fd), 1e-3)
+            assert abs(ana[idx] - fd) <= 2e-5 * scale + 1e-7, f"{name}{idx}: analytic {ana[idx]} fd {fd}"
+            checked += 1
+    assert checked > 0.9 * (checked + skipped)
+
+
+# ------------------------------------------------------------------------------------------
+# Shift (Sec. 3.3): p' = p + mu_n, q' = norm(q) x norm(sigma_n)
+# ------------------------------------------------------------------------------------------
+def test_shift_zero_offsets_is_identity():
+    sc, _, _ = synth.single_view_scene(0, n=50)
+    dyn = np.arange(0, 50, 3, dtype=np.int32)
+    dpos = np.zeros((3, dyn.size)); drot = np.tile([[1.0], [0], [0], [0]], (1, dyn.size))
+    m, q = oracle.shift_fwd(sc, dyn, dpos, drot)
+    np.testing.assert_array_equal(m, sc.mean.astype(np.float64))
+    qn = sc.quat.astype(np.float64) / np.linalg.norm(sc.quat.astype(np.float64), axis=0)
+    np.testing.assert_allclose(q[:, dyn], qn[:, dyn], atol=1e-15)
+
+
+def test_shift_rotation_composes_like_scipy():
+    rng = np.random.default_rng(7)
+    sc, _, _ = synth.single_view_scene(1, n=20)
+    sc.quat = (sc.quat * rng.uniform(0.5, 2.0, size=(1, 20))).astype(np.float32)  # unnormalised input
+    dyn = np.arange(20, dtype=np.int32)
+    dpos = rng.normal(0, 0.01, size=(3, 20)); drot = rng.normal(size=(4, 20))
+    m, q = oracle.shift_fwd(sc, dyn, dpos, drot)
+    for j in range(20):
+        a = sc.quat[:, j].astype(np.float64); b = drot[:, j]
+        Ra = Rotation.from_quat([a[1], a[2], a[3], a[0]])
+        Rb = Rotation.from_quat([b[1], b[2], b[3], b[0]])
+        Rq = Rotation.from_quat([q[1, j], q[2, j], q[3, j], q[0, j]])
+        np.testing.assert_allclose(Rq.as_matrix(), (Ra * Rb).as_matrix(), atol=1e-12)
+        assert np.linalg.norm(q[:, j]) == pytest.approx(1.0, abs=1e-14)
+    np.testing.assert_allclose(m, sc.mean.astype(np.float64) + dpos, atol=0)
+
+
+def test_shift_adjoint_finite_differences():
+    rng = np.random.default_rng(11)
+    sc, _, _ = synth.single_view_scene(2, n=12)
+    dyn = np.array([1, 4, 7, 11], np.int32)
+    dpos = rng.normal(0, 0.01, size=(3, 4)); drot = rng.normal(size=(4, 4))
+    wm = rng.normal(size=(3, 12)); wq = rng.normal(size=(4, 12))
+    ddp, ddr = oracle.shift_adj(sc, dyn, drot, wm, wq)
+
+    def L(dp, dr):
+        m, q = oracle.shift_fwd(sc, dyn, dp, dr)
+        return float(np.sum(m * wm) + np.sum(q * wq))
+
+    for arr, ana in ((dpos, ddp), (drot, ddr)):
+        for idx in np.ndindex(arr.shape):
+            x = arr[idx]; h = 1e-6
+            arr[idx] = x + h; lp = L(dpos, drot)
+            arr[idx] = x - h; lm = L(dpos, drot)
+            arr[idx] = x
+            assert ana[idx] == pytest.approx((lp - lm) / (2 * h), rel=1e-6, abs=1e-8)
+
+
+# ------------------------------------------------------------------------------------------
+# Adam (textbook, bias-corrected)
+# ------------------------------------------------------------------------------------------
+def test_adam_matches_torch_over_ten_steps():
+    rng = np.random.default_rng(3)
+    p0 = rng.normal(size=257)
+    grads = [rng.normal(size=257) * 10 ** rng.uniform(-3, 1) for _ in range(10)]
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-15
+    t = torch.tensor(p0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([t], lr=lr, betas=(b1, b2), eps=eps)
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for k, g in enumerate(grads, start=1):
+        opt.zero_grad(); t.grad = torch.tensor(g, dtype=torch.float64); opt.step()
+        p, m, v = oracle.adam(p, g, m, v, lr, b1, b2, eps, k)
+        np.testing.assert_allclose(p, t.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([3.0, -0.5, 1e-4, 0.0])
+    p, _, _ = oracle.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 0.01, 0.9, 0.999, 1e-15, 1)
+    np.testing.assert_allclose(p, -0.01 * g / (np.abs(g) + 1e-15), rtol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# L1 fidelity term and error map (Eqs. 2/3, Sec. 3.4)
+# ------------------------------------------------------------------------------------------
+def test_l1_against_torch():
+    rng = np.random.default_rng(0)
+    r = rng.uniform(size=(3, 3, 9, 11)).astype(np.float32)
+    t = rng.uniform(size=(3, 3, 9, 11)).astype(np.float32)
+    t[0, 0, 0, 0] = r[0, 0, 0, 0]
+    loss, dl, err = oracle.l1_loss_grad(r, t)
+    rt = torch.tensor(r, dtype=torch.float64, requires_grad=True)
+    lt = torch.nn.functional.l1_loss(rt, torch.tensor(t, dtype=torch.float64))
+    lt.backward()
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    np.testing.assert_allclose(dl, rt.grad.numpy(), rtol=1e-12)
+    np.testing.assert_allclose(err, np.abs(r.astype(np.float64) - t).mean(1), rtol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Densification (Sec. 3.4, Alg. 1, Eq. 4)
+# ------------------------------------------------------------------------------------------
+def test_alg1_golden_fixture():
+    rows = np.loadtxt(os.path.join(GOLDEN, "alg1_pixels.txt"), comments="#")
+    cam = synth.make_camera(np.diag([1.0, -1.0, -1.0]), (0, 0, 4), 128, 128)
+    xy, ok = oracle.alg1(rows[:, 0:3].T, cam)
+    for i, row in enumerate(rows):
+        assert ok[i] == bool(row[5])
+        if ok[i]:
+            assert tuple(xy[i]) == (int(row[3]), int(row[4]))
+
+
+def test_alg1_equals_rounded_pinhole_mean():
+    sc, cams, _ = synth.multiview_scene(0, n=3000, n_views=3, width=320, height=240, with_grads=False)
+    for cam in cams:
+        p = oracle.project(sc, cam)
+        xy, ok = oracle.alg1(sc.mean, cam)
+        u, v = p.uv[:, 0], p.uv[:, 1]
+        inside = (np.floor(u + 0.5) >= 0) & (np.floor(u + 0.5) < cam.width) & (np.floor(v + 0.5) >= 0) & \
+                 (np.floor(v + 0.5) < cam.height) & (p.depth > 0)
+        far = (np.abs(u - np.floor(u) - 0.5) > 1e-6) & (np.abs(v - np.floor(v) - 0.5) > 1e-6)
+        np.testing.assert_array_equal(ok[far], inside[far])
+        sel = far & ok
+        np.testing.assert_array_equal(xy[sel, 0], np.floor(u[sel] + 0.5).astype(np.int32))
+        np.testing.assert_array_equal(xy[sel, 1], np.floor(v[sel] + 0.5).astype(np.int32))
+
+
+def test_densify_selection_matches_set_definition():
+    rng = np.random.default_rng(5)
+    sc, cams, _ = synth.multiview_scene(1, n=800, n_views=4, width=64, height=48, with_grads=False)
+    errs = [rng.uniform(0, 1, size=(48, 64)).astype(np.float32) for _ in cams]
+    gsum = rng.exponential(1.0, size=800).astype(np.float32)
+    cnt = rng.integers(0, 5, size=800).astype(np.int32)
+    gamma, tp, te = 0.6, 1.5, 0.4
+    sel, score, in_err = oracle.densify_select(sc.mean, cams, errs, gsum, cnt, gamma, tp, te)
+    # set-level restatement of Eq. (4) from the Alg. 1 pixels
+    S_err = set()
+    best = np.zeros(800, np.float32)
+    for c, cam in enumerate(cams):
+        xy, ok = oracle.alg1(sc.mean, cam)
+        for g in np.nonzero(ok)[0]:
+            e = errs[c][xy[g, 1], xy[g, 0]]
+            best[g] = max(best[g], e)
+            if e > np.float32(gamma):
+                S_err.add(int(g))
+    gbar = np.where(cnt > 0, gsum / np.maximum(cnt, 1).astype(np.float32), np.float32(0)).astype(np.float32)
+    S_pos = {int(g) for g in range(800) if gbar[g] > np.float32(tp)}
+    S_low = {int(g) for g in range(800) if gbar[g] > np.float32(te)}
+    S = S_pos | (S_err & S_low)
+    assert set(sel.tolist()) == S
+    want = sorted(S, key=lambda g: (-best[g], g))
+    assert sel.tolist() == want
+
+
+def test_splitmix64_known_answers():
+    for line in open(os.path.join(GOLDEN, "splitmix64_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        seed, i, val = line.split()
+        assert oracle.splitmix64(int(seed), int(i)) == int(val, 16)
+
+
+def _planes(sc, cap):
+    def pad(a):
+        out = np.zeros(a.shape[:-1] + (cap,), np.float32)
+        out[..., :a.shape[-1]] = a
+        return out
+    return dict(mean=pad(sc.mean), quat=pad(sc.quat), log_scale=pad(sc.log_scale), logit=pad(sc.logit), sh=pad(sc.sh))
+
+
+def test_spawn_invariants():
+    sc, _, _ = synth.single_view_scene(0, n=100)
+    cap = 300
+    sel = np.array([5, 17, 3], np.int32)
+    pl = _planes(sc, cap)
+    before = {k: v.copy() for k, v in pl.items()}
+    n_app, cm = oracle.spawn(pl, 100, cap, sel, 250, seed=9)
+    assert n_app == 200  # capped by capacity
+    for k in pl:
+        np.testing.assert_array_equal(pl[k][..., :100], before[k][..., :100])
+    for j in range(n_app):
+        parent, child = sel[j % 3], 100 + j
+        np.testing.assert_array_equal(pl["quat"][:, child], pl["quat"][:, parent])
+        np.testing.assert_array_equal(pl["sh"][:, child], pl["sh"][:, parent])
+        assert pl["logit"][child] == pl["logit"][parent]
+        np.testing.assert_allclose(pl["log_scale"][:, child], pl["log_scale"][:, parent] - np.log(1.6), atol=1e-6)
+        s = np.exp(pl["log_scale"][:, parent].astype(np.float64))
+        assert np.linalg.norm(cm[:, j] - pl["mean"][:, parent]) <= 6 * np.linalg.norm(s) + 1e-9
+    pl2 = _planes(sc, cap)
+    n2, cm2 = oracle.spawn(pl2, 100, cap, sel, 250, seed=9)
+    np.testing.assert_array_equal(cm, cm2)
+    assert oracle.spawn(_planes(sc, cap), 100, cap, np.zeros(0, np.int32), 250, seed=9)[0] == 0
+    assert oracle.spawn(_planes(sc, cap), 100, cap, sel, 50, seed=9)[0] == 50
+
+
+def test_child_normals_distribution():
+    from scipy import stats
+    z = np.array([oracle.child_normals(123, j) for j in range(4000)])
+    for k in range(3):
+        assert stats.kstest(z[:, k], "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 0.06
