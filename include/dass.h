@@ -1,0 +1,245 @@
+/*
+ * dass.h -- C ABI of the MI355X (gfx950) hot path of per-timestep Gaussian-splatting
+ * streaming (DASS, arXiv 2411.14847).
+ *
+ * The problem statement (Sec. 3.1): at timestep t, start from the Gaussians of t-1 and fit
+ * them to C synchronised views, by rendering and back-propagating through the tile-based
+ * differentiable rasterizer (App. A.1), shifting the dynamic Gaussians (Sec. 3.3), updating
+ * with Adam, and appending Gaussians where the error is large (Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller unless stated otherwise;
+ *     structs passed by pointer (dass_gaussians, dass_camera, ...) live in HOST memory.
+ *   - Layout is structure-of-arrays: a parameter with P components is P planes of
+ *     `capacity` floats ("[P][capacity]"), so Gaussian g's component p is at p*capacity+g.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream) and the calls
+ *     return before it finishes.  They never synchronise the host and never allocate
+ *     (except dass_create / dass_reserve / dass_sync and the debug exports).
+ *   - Errors are returned as dass_status, never thrown or aborted.  Arguments are checked
+ *     before anything is enqueued (DASS_E_INVALID).  A request larger than the reserved
+ *     limits returns DASS_E_CAPACITY at once when the host can tell; device-side overflow of
+ *     the tile-key buffer is recorded on the device and returned by the next dass_sync().
+ *     HIP launch failures return DASS_E_HIP; dass_last_error() then holds a message.
+ *   - Gradient outputs ACCUMULATE (+=); the caller zeroes them.
+ *   - One context per stream / host thread; calls on one context must not overlap.
+ */
+#ifndef DASS_H
+#define DASS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dass_ctx_s* dass_ctx;
+typedef void* dass_stream; /* hipStream_t */
+
+typedef enum {
+  DASS_OK = 0,
+  DASS_E_INVALID = 1,     /* bad argument (null pointer, size out of range, ...)   */
+  DASS_E_OOM = 2,         /* device allocation failed (create / reserve only)      */
+  DASS_E_CAPACITY = 3,    /* request exceeds the reserved limits                   */
+  DASS_E_HIP = 4,         /* a HIP call failed                                     */
+  DASS_E_UNSUPPORTED = 5  /* valid request this build does not handle              */
+} dass_status;
+
+#define DASS_MAX_VIEWS 32  /* views per render call */
+#define DASS_MAX_SH_DEGREE 3
+
+/* Gaussians G_t = {G^base, G^var} (Sec. 3.1): rows [0, n_base) are the base set, rows
+ * [n_base, n) the densified set.  Parametrisation (App. A.1): position mu, rotation
+ * quaternion q = (w,x,y,z) (any non-zero norm; normalised inside), scale s = exp(log_scale),
+ * opacity o = sigmoid(opacity_logit), colour from real spherical harmonics of degree
+ * sh_degree: plane k*3+c holds basis k (k = l*l + l + m) of channel c, and
+ * rgb_c = max(0, sum_k sh[k*3+c] Y_k(normalise(mu - campos)) + 0.5). */
+typedef struct {
+  int32_t n;          /* live Gaussians, 0 <= n <= capacity                  */
+  int32_t capacity;   /* plane stride (floats)                               */
+  int32_t n_base;     /* 0 <= n_base <= n                                    */
+  int32_t sh_degree;  /* 0..3                                                */
+  float* mean;        /* [3][capacity]                                       */
+  float* quat;        /* [4][capacity]                                       */
+  float* log_scale;   /* [3][capacity]                                       */
+  float* opacity_logit; /* [capacity]                                        */
+  float* sh;          /* [3*(sh_degree+1)^2][capacity]                       */
+} dass_gaussians;
+
+/* Pinhole camera: x_cam = R x_world + t (R row-major), camera frame x right, y down,
+ * z forward; pixel (u,v) = (fx x/z + cx, fy y/z + cy), pixel centres at integer
+ * coordinates; campos = camera centre in world space (for the view direction of the colour). */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float campos[3];
+  int32_t width, height;
+} dass_camera;
+
+/* One rendered view: rgb [3][height][width], t_final (final transmittance) [height][width],
+ * n_contrib [height][width] = number of entries of the pixel's tile list up to and
+ * including the last one blended. */
+typedef struct {
+  float* rgb;
+  float* t_final;
+  int32_t* n_contrib;
+} dass_image;
+
+/* Gradients with the layout of dass_gaussians (capacity stride).  Any pointer may be NULL
+ * to skip that parameter.  Accumulated (+=). */
+typedef struct {
+  float* mean;
+  float* quat;
+  float* log_scale;
+  float* opacity_logit;
+  float* sh;
+} dass_grads;
+
+/* Render options.  tile_w x tile_h must be 16x16 in this build. */
+typedef struct {
+  int32_t tile_w, tile_h;
+  uint32_t flags; /* reserved, 0 */
+} dass_opts;
+
+/* Sizes the context reserves device memory for. */
+typedef struct {
+  int32_t max_gaussians; /* capacity of the scenes rendered                     */
+  int32_t max_views;     /* views per render call (<= DASS_MAX_VIEWS)            */
+  int64_t max_keys;      /* tile keys per render call, summed over its views     */
+  int64_t max_tiles;     /* tiles per render call, summed over its views         */
+} dass_limits;
+
+/* ---- context ---------------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` and reserves `limits`.  Returns DASS_E_HIP if no
+ * device is available, DASS_E_OOM if the reservation fails. */
+dass_status dass_create(dass_ctx* out, int32_t device, const dass_limits* limits);
+
+/* Grows (never shrinks) the reservation.  Synchronises the context's device. */
+dass_status dass_reserve(dass_ctx ctx, const dass_limits* limits);
+
+/* Frees everything the context owns.  NULL is allowed. */
+void dass_destroy(dass_ctx ctx);
+
+/* Message for the last failing call on this context (valid until the next call). */
+const char* dass_last_error(dass_ctx ctx);
+
+/* Waits for `stream` and returns DASS_E_CAPACITY if a render since the previous sync ran out
+ * of tile-key space (its outputs are then invalid), DASS_E_HIP on an asynchronous HIP
+ * error, DASS_OK otherwise.  Clears the recorded device error. */
+dass_status dass_sync(dass_ctx ctx, dass_stream stream);
+
+/* ---- hot path --------------------------------------------------------------------------- */
+
+/* Forward of the tile-based rasterizer (App. A.1) for n_views cameras in one pass:
+ * projection of each Gaussian (Sigma = R S S^T R^T; Sigma_2D = J W Sigma W^T J^T + 0.3 I;
+ * cull at camera depth <= 0.2; radius ceil(3 sqrt(lambda_max(Sigma_2D)))), tile keys
+ * (tile << 32 | float32 depth bits) for every tile of the Gaussian's rectangle, a stable
+ * sort by key, per-tile ranges, and the front-to-back blend of each pixel
+ * C = sum_i c_i a_i prod_{j<i}(1-a_j) + T_final * bg with a_i = min(0.99, o_i G_i(pixel)),
+ * entries with a_i < 1/255 skipped, and the walk stopped before an entry that would take
+ * the transmittance below 1e-4.  out[v] receives view v.  The context keeps the sorted
+ * tile lists for the matching render_bwd.
+ * Errors: DASS_E_INVALID (null pointers, n > capacity, sh_degree > 3, n_views outside
+ * [1, min(max_views, DASS_MAX_VIEWS)], width/height <= 0, tiles other than 16x16);
+ * DASS_E_CAPACITY (n > max_gaussians, total tiles > max_tiles; key overflow via dass_sync). */
+dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
+                       int32_t n_views, const float bg[3], dass_image* out,
+                       const dass_opts* opts, dass_stream stream);
+
+/* Reverse-mode adjoint of the matching render_fwd (same ctx, g, cams, bg; no render on the
+ * context in between).  dl_drgb: host array of n_views device pointers, each [3][H][W].
+ * Accumulates dL/d(parameter) into `grads`, and for every Gaussian visible in a view adds the
+ * L2 norm of dL/d(pixel-space mean) of that view to gradnorm_sum[g] and 1 to grad_count[g]
+ * (the historical view-space positional gradient of Sec. 3.4; either may be NULL).  The
+ * transmittance of each entry is recovered from T_final walking the list backwards; no
+ * per-pixel lists are stored.  Derivatives through an active clamp (alpha = 0.99, colour
+ * = 0, Jacobian clamp) are zero.  Float atomics make the sums order-nondeterministic. */
+dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
+                       int32_t n_views, const float bg[3], const dass_image* fwd_out,
+                       const float* const* dl_drgb, dass_grads* grads, float* gradnorm_sum,
+                       int32_t* grad_count, const dass_opts* opts, dass_stream stream);
+
+#define DASS_FWD 0
+#define DASS_ADJOINT 1
+
+/* Dynamics-aware shift (Sec. 3.3): for the dynamic Gaussians dyn_idx[j] (distinct indices
+ * in [0, in->n)), mu' = mu + dpos[:,j] and q' = normalise(q) (x) normalise(drot[:,j])
+ * (Hamilton product, (w,x,y,z)); every other Gaussian keeps mu and q.
+ * DASS_FWD: writes out->mean and out->quat for rows [0, in->n) (out may not alias in; its
+ *   other planes are not touched -- point them at in's).  d_out, d_dpos, d_drot unused.
+ * DASS_ADJOINT: d_dpos[:,j] += d_out->mean[:,dyn_idx[j]], d_drot[:,j] += the adjoint of the
+ *   product and both normalisations applied to d_out->quat[:,dyn_idx[j]].  out unused.
+ * dpos [3][n_dyn], drot [4][n_dyn], d_dpos [3][n_dyn], d_drot [4][n_dyn]. */
+dass_status shift_apply(dass_ctx ctx, int32_t mode, const int32_t* dyn_idx, int32_t n_dyn,
+                        const float* dpos, const float* drot, const dass_gaussians* in,
+                        dass_gaussians* out, const dass_grads* d_out, float* d_dpos,
+                        float* d_drot, dass_stream stream);
+
+/* One parameter group of adam_step: n contiguous floats (param, grad, m, v). */
+typedef struct {
+  float* param;
+  const float* grad;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+} dass_adam_group;
+
+/* Adam with bias correction (step is 1-based), all groups in one pass:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps).
+ * `groups` is a host array.  Errors: DASS_E_INVALID for n_groups < 1, step < 1, null
+ * pointers in a group with n > 0, or negative n. */
+dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1,
+                      float beta2, float eps, int32_t step, dass_stream stream);
+
+/* Error-guided densification (Sec. 3.4, Alg. 1, Eq. 4).  For every base Gaussian n in
+ * [0, g->n_base): its Alg. 1 pixel in each view (full projection, Round(z) = floor(z+0.5),
+ * x from x_norm and W, y from y_norm and H; points behind a camera or off the image are not
+ * projected); S_err = Gaussians whose pixel has err > gamma_err in some view; with
+ * gbar = gradnorm_sum/grad_count (0 if the count is 0), the set
+ * S = {gbar > tau_pos} u (S_err n {gbar > tau_err}) is ranked by its largest error at its
+ * pixels (descending), ties by index.  Child j in [0, K) copies parent S[j mod |S|], with
+ * K = 0 if S is empty, else min(k_max, capacity - n); the child's mean moves by
+ * R diag(s) z with z three standard normals from SplitMix64(seed) draws 4j..4j+3 through
+ * Box-Muller, and its log-scale drops by ln 1.6.  Children are written to rows [n, n+K).
+ * K is written to the device scalar *n_appended; the caller reads it and advances g->n.
+ * err_maps: host array of n_views device pointers [H][W]; gradnorm_sum, grad_count [n_base]. */
+dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* err_maps,
+                           const dass_camera* cams, int32_t n_views, const float* gradnorm_sum,
+                           const int32_t* grad_count, float gamma_err, float tau_pos,
+                           float tau_err, int32_t k_max, uint64_t seed, int32_t* n_appended,
+                           dass_stream stream);
+
+/* L1 term of the fidelity loss (Eqs. 2/3 with lambda = 0) and the error map of Sec. 3.4:
+ * with V = n_views and each view's render/target [3][H][W],
+ * L = (1/V) sum_v mean_{c,p} |render - target|; dl_drgb = sign(render - target)/(3 H W V)
+ * (written, not accumulated); err[v] [H][W] = mean over channels of |render - target|;
+ * *loss (device float) += L.  Host arrays of n_views device pointers; err may be NULL. */
+dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views,
+                              const float* const* render, const float* const* target,
+                              float* const* dl_drgb, float* const* err, float* loss,
+                              dass_stream stream);
+
+/* ---- debug exports (synchronise; for parity tests) ------------------------------------- */
+
+/* Sorted tile keys of view `view` of the last render_fwd: copies up to `max` keys
+ * ((tile << 32) | float32 depth bits, tile = ty*tiles_x + tx) and values (Gaussian index) into
+ * the device buffers, writes the view's ranges [tiles][2] (int64, offsets within the view's
+ * key list; (0,0) for an empty tile) into the device buffer `ranges`, and the key count into
+ * *count (host).  DASS_E_CAPACITY if the view has more than `max` keys. */
+dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t* vals,
+                            int64_t max, int64_t* ranges, int64_t* count);
+
+/* Per-Gaussian projection of g into one camera as render_fwd computes it, [n][16] doubles
+ * (device): u, v, A, B, C (conic), opacity, r, g, b, depth, radius, x0, y0, x1, y1 (tile
+ * rectangle), visible (integers converted to double). */
+dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cam,
+                                  double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DASS_H */

@@ -1,0 +1,255 @@
+"""Python binding of libdass over torch device tensors.
+
+PyTorch provides device memory and streams only: every step of the hot path runs in the
+library's HIP kernels, reached through the C ABI of include/dass.h.  There is no CPU
+fallback -- a missing or unloadable library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _ffi as F
+
+
+class DassError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{F.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def n_sh(deg: int) -> int:
+    return (deg + 1) * (deg + 1)
+
+
+@dataclass
+class GaussianBuffers:
+    """Structure-of-arrays parameter planes with `capacity` columns (rows [0,n) live)."""
+    mean: torch.Tensor       # (3, cap)
+    quat: torch.Tensor       # (4, cap)
+    log_scale: torch.Tensor  # (3, cap)
+    logit: torch.Tensor      # (cap,)
+    sh: torch.Tensor         # (3K, cap)
+    n: int
+    n_base: int
+    sh_degree: int
+
+    @property
+    def capacity(self) -> int:
+        return int(self.mean.shape[1])
+
+    @staticmethod
+    def allocate(capacity: int, sh_degree: int, device="cuda") -> "GaussianBuffers":
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device=device)
+        return GaussianBuffers(z(3, capacity), z(4, capacity), z(3, capacity), z(capacity),
+                               z(3 * n_sh(sh_degree), capacity), 0, 0, sh_degree)
+
+    @staticmethod
+    def from_arrays(mean, quat, log_scale, logit, sh, sh_degree: int, capacity: Optional[int] = None,
+                    n_base: Optional[int] = None, device="cuda") -> "GaussianBuffers":
+        n = int(np.asarray(mean).shape[1])
+        cap = capacity if capacity is not None else n
+        g = GaussianBuffers.allocate(cap, sh_degree, device)
+        for dst, src in ((g.mean, mean), (g.quat, quat), (g.log_scale, log_scale), (g.sh, sh)):
+            dst[:, :n] = torch.as_tensor(np.asarray(src, np.float32), device=device)
+        g.logit[:n] = torch.as_tensor(np.asarray(logit, np.float32), device=device)
+        g.n = n
+        g.n_base = n if n_base is None else n_base
+        return g
+
+    def planes(self):
+        return (self.mean, self.quat, self.log_scale, self.logit, self.sh)
+
+    def struct(self) -> F.Gaussians:
+        return F.Gaussians(self.n, self.capacity, self.n_base, self.sh_degree, _ptr(self.mean), _ptr(self.quat),
+                           _ptr(self.log_scale), _ptr(self.logit), _ptr(self.sh))
+
+    def zeros_like(self) -> "GaussianBuffers":
+        g = GaussianBuffers.allocate(self.capacity, self.sh_degree, self.mean.device)
+        g.n, g.n_base = self.n, self.n_base
+        return g
+
+    def clone(self) -> "GaussianBuffers":
+        return GaussianBuffers(self.mean.clone(), self.quat.clone(), self.log_scale.clone(), self.logit.clone(),
+                               self.sh.clone(), self.n, self.n_base, self.sh_degree)
+
+
+def grads_struct(g: Optional[GaussianBuffers]) -> F.Grads:
+    if g is None:
+        return F.Grads()
+    return F.Grads(_ptr(g.mean), _ptr(g.quat), _ptr(g.log_scale), _ptr(g.logit), _ptr(g.sh))
+
+
+def camera_struct(cam) -> F.Camera:
+    c = F.Camera()
+    c.R[:] = [float(x) for x in np.asarray(cam.R, np.float32).reshape(-1)]
+    c.t[:] = [float(x) for x in np.asarray(cam.t, np.float32).reshape(-1)]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.campos[:] = [float(x) for x in np.asarray(cam.campos, np.float32).reshape(-1)]
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def cameras_array(cams):
+    arr = (F.Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera_struct(c)
+    return arr
+
+
+@dataclass
+class RenderOut:
+    rgb: torch.Tensor        # (3, H, W)
+    t_final: torch.Tensor    # (H, W)
+    n_contrib: torch.Tensor  # (H, W) int32
+
+    @staticmethod
+    def allocate(cam, device="cuda") -> "RenderOut":
+        H, W = int(cam.height), int(cam.width)
+        return RenderOut(torch.empty(3, H, W, device=device), torch.empty(H, W, device=device),
+                         torch.empty(H, W, dtype=torch.int32, device=device))
+
+    def struct(self) -> F.Image:
+        return F.Image(_ptr(self.rgb), _ptr(self.t_final), _ptr(self.n_contrib))
+
+
+def keys_needed_estimate(n_gaussians: int, n_views: int, tiles_per_gaussian: float = 16.0) -> int:
+    return int(n_gaussians * n_views * tiles_per_gaussian)
+
+
+class Context:
+    """One libdass context (device workspace + state of the last render_fwd)."""
+
+    def __init__(self, max_gaussians: int, max_views: int, max_keys: int, max_tiles: int, device: int = 0):
+        self._lib = F.lib()
+        self.device = device
+        self._h = C.c_void_p()
+        lim = F.Limits(max_gaussians, max_views, max_keys, max_tiles)
+        st = self._lib.dass_create(C.byref(self._h), device, C.byref(lim))
+        if st != F.DASS_OK:
+            raise DassError(st, "dass_create failed")
+        self.limits = lim
+
+    def close(self):
+        if self._h:
+            self._lib.dass_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != F.DASS_OK:
+            msg = self._lib.dass_last_error(self._h)
+            raise DassError(st, msg.decode() if msg else "")
+
+    # ---- context ---------------------------------------------------------------------------
+    def reserve(self, max_gaussians=0, max_views=1, max_keys=0, max_tiles=0):
+        self._check(self._lib.dass_reserve(self._h, C.byref(F.Limits(max_gaussians, max_views, max_keys,
+                                                                        max_tiles))))
+
+    def sync(self, stream=None):
+        self._check(self._lib.dass_sync(self._h, _stream(stream)))
+
+    # ---- hot path --------------------------------------------------------------------------
+    def render_fwd(self, g: GaussianBuffers, cams: Sequence, bg=(0.0, 0.0, 0.0), out=None, stream=None):
+        out = out if out is not None else [RenderOut.allocate(c, g.mean.device) for c in cams]
+        imgs = (F.Image * len(cams))(*[o.struct() for o in out])
+        bgf = (C.c_float * 3)(*[float(x) for x in bg])
+        gs = g.struct()
+        opts = F.Opts(16, 16, 0)
+        self._check(self._lib.render_fwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs,
+                                         C.byref(opts), _stream(stream)))
+        return out
+
+    def render_bwd(self, g: GaussianBuffers, cams: Sequence, bg, fwd_out, dl_drgb, grads: GaussianBuffers,
+                   gradnorm: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None, stream=None):
+        imgs = (F.Image * len(cams))(*[o.struct() for o in fwd_out])
+        dls = (C.c_void_p * len(cams))(*[_ptr(d) for d in dl_drgb])
+        bgf = (C.c_float * 3)(*[float(x) for x in bg])
+        gs = g.struct()
+        gr = grads_struct(grads)
+        opts = F.Opts(16, 16, 0)
+        self._check(self._lib.render_bwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs, dls,
+                                         C.byref(gr), _ptr(gradnorm), _ptr(count), C.byref(opts), _stream(stream)))
+
+    def shift_fwd(self, g: GaussianBuffers, out: GaussianBuffers, dyn_idx: torch.Tensor, dpos: torch.Tensor,
+                  drot: torch.Tensor, stream=None):
+        gs, os_ = g.struct(), out.struct()
+        self._check(self._lib.shift_apply(self._h, F.DASS_FWD, _ptr(dyn_idx), int(dyn_idx.numel()), _ptr(dpos),
+                                          _ptr(drot), C.byref(gs), C.byref(os_), None, None, None, _stream(stream)))
+
+    def shift_adjoint(self, g: GaussianBuffers, dyn_idx: torch.Tensor, drot: torch.Tensor, d_out: GaussianBuffers,
+                      d_dpos: torch.Tensor, d_drot: torch.Tensor, stream=None):
+        gs = g.struct()
+        gr = grads_struct(d_out)
+        self._check(self._lib.shift_apply(self._h, F.DASS_ADJOINT, _ptr(dyn_idx), int(dyn_idx.numel()), None,
+                                          _ptr(drot), C.byref(gs), None, C.byref(gr), _ptr(d_dpos), _ptr(d_drot),
+                                          _stream(stream)))
+
+    def adam_step(self, groups, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
+        """groups: sequence of (param, grad, m, v, lr) with equal-length contiguous float32 tensors."""
+        arr = (F.AdamGroup * len(groups))()
+        for i, (p, g, m, v, lr) in enumerate(groups):
+            arr[i] = F.AdamGroup(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
+        self._check(self._lib.adam_step(self._h, arr, len(groups), beta1, beta2, eps, int(step), _stream(stream)))
+
+    def l1_loss_grad(self, cams, renders, targets, dl_out, err_out=None, loss: Optional[torch.Tensor] = None,
+                     stream=None):
+        V = len(cams)
+        R = (C.c_void_p * V)(*[_ptr(r) for r in renders])
+        T = (C.c_void_p * V)(*[_ptr(t) for t in targets])
+        D = (C.c_void_p * V)(*[_ptr(d) for d in dl_out])
+        E = (C.c_void_p * V)(*[_ptr(e) for e in err_out]) if err_out is not None else None
+        self._check(self._lib.dass_l1_loss_grad(self._h, cameras_array(cams), V, R, T, D, E, _ptr(loss),
+                                                _stream(stream)))
+
+    def densify_append(self, g: GaussianBuffers, err_maps, cams, gradnorm, count, gamma_err, tau_pos, tau_err,
+                       k_max, seed, n_appended: torch.Tensor, stream=None):
+        """Appends children in rows [g.n, g.n + K); K lands in n_appended (device int32); the caller
+        reads it and advances g.n."""
+        gs = g.struct()
+        E = (C.c_void_p * len(cams))(*[_ptr(e) for e in err_maps])
+        self._check(self._lib.densify_append(self._h, C.byref(gs), E, cameras_array(cams), len(cams), _ptr(gradnorm),
+                                             _ptr(count), float(gamma_err), float(tau_pos), float(tau_err),
+                                             int(k_max), int(seed), _ptr(n_appended), _stream(stream)))
+
+    # ---- debug -----------------------------------------------------------------------------
+    def debug_keys(self, view: int, max_keys: int, n_tiles: int, device="cuda"):
+        keys = torch.empty(max(max_keys, 1), dtype=torch.int64, device=device)
+        vals = torch.empty(max(max_keys, 1), dtype=torch.int32, device=device)
+        ranges = torch.empty(n_tiles, 2, dtype=torch.int64, device=device)
+        cnt = C.c_int64()
+        self._check(self._lib.dass_debug_keys(self._h, view, _ptr(keys), _ptr(vals), max_keys, _ptr(ranges),
+                                              C.byref(cnt)))
+        c = cnt.value
+        return (keys[:c].cpu().numpy().view(np.uint64), vals[:c].cpu().numpy().view(np.uint32),
+                ranges.cpu().numpy())
+
+    def debug_projection(self, g: GaussianBuffers, cam):
+        out = torch.empty(max(g.n, 1), 16, dtype=torch.float64, device=g.mean.device)
+        gs = g.struct()
+        self._check(self._lib.dass_debug_projection(self._h, C.byref(gs), C.byref(camera_struct(cam)), _ptr(out)))
+        return out[:g.n].cpu().numpy()

@@ -1,0 +1,573 @@
+// Host layer of libdass: context and workspace, argument checks, and the launch sequences of
+// the exported entry points.  No entry point on the hot path allocates or synchronises.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dass_internal.h"
+
+namespace dass {
+int adam_per_block();
+int l1_per_block();
+}  // namespace dass
+
+using namespace dass;
+
+struct dass_ctx_s {
+  int device = 0;
+  dass_limits lim{};
+  Workspace ws;
+  std::vector<void*> allocs;
+  std::string last_error;
+  // state kept by render_fwd for the matching render_bwd
+  bool have_fwd = false;
+  int fwd_n = 0, fwd_nv = 0, fwd_stride = 0;
+  int64_t fwd_tiles = 0;
+  int fwd_key_buf = 0;
+  CamsK fwd_cams{};
+};
+
+namespace {
+
+dass_status fail(dass_ctx ctx, dass_status st, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(ctx, DASS_E_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+dass_status check_launch(dass_ctx ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, DASS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return DASS_OK;
+}
+
+int bit_width(uint64_t x) {
+  int b = 0;
+  while (x) {
+    b++;
+    x >>= 1;
+  }
+  return b;
+}
+
+template <typename T>
+dass_status dev_alloc(dass_ctx ctx, T** p, size_t count) {
+  void* q = nullptr;
+  size_t bytes = count * sizeof(T);
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, DASS_E_OOM, "hipMalloc of %zu bytes failed", bytes);
+  }
+  ctx->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return DASS_OK;
+}
+
+void free_all(dass_ctx ctx) {
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  ctx->allocs.clear();
+  ctx->ws = Workspace{};
+}
+
+dass_status check_limits(dass_ctx ctx, const dass_limits* l) {
+  if (!l) return fail(ctx, DASS_E_INVALID, "limits is NULL");
+  if (l->max_gaussians < 0 || l->max_views < 1 || l->max_views > DASS_MAX_VIEWS || l->max_keys < 0 ||
+      l->max_tiles < 0)
+    return fail(ctx, DASS_E_INVALID, "limits out of range");
+  if (l->max_keys > 0xFFFFFFFFll || l->max_tiles > 0x7FFFFFFFll)
+    return fail(ctx, DASS_E_INVALID, "max_keys must be < 2^32 and max_tiles < 2^31");
+  if ((int64_t)l->max_views * l->max_gaussians > 0xFFFFFFFFll)
+    return fail(ctx, DASS_E_INVALID, "max_views * max_gaussians must be < 2^32");
+  return DASS_OK;
+}
+
+dass_status allocate(dass_ctx ctx, const dass_limits& l) {
+  free_all(ctx);
+  Workspace& w = ctx->ws;
+  w.cap_vn = (int64_t)l.max_views * l.max_gaussians;
+  w.cap_keys = l.max_keys;
+  w.cap_tiles = l.max_tiles;
+  const int64_t vn = w.cap_vn > 0 ? w.cap_vn : 1;
+  dass_status s;
+#define ALLOC(ptr, cnt) \
+  if ((s = dev_alloc(ctx, &(ptr), (size_t)(cnt))) != DASS_OK) return s;
+  ALLOC(w.rec_u, vn);
+  ALLOC(w.tt_u, vn);
+  ALLOC(w.rect_u, vn);
+  ALLOC(w.dkey[0], vn);
+  ALLOC(w.dkey[1], vn);
+  ALLOC(w.dval[0], vn);
+  ALLOC(w.dval[1], vn);
+  ALLOC(w.rec_s, vn);
+  ALLOC(w.rect_s, vn);
+  ALLOC(w.tt_s, vn);
+  ALLOC(w.off_s, vn + 1);
+  ALLOC(w.inv, vn);
+  ALLOC(w.g2d, vn * 9);
+  ALLOC(w.keys[0], w.cap_keys > 0 ? w.cap_keys : 1);
+  ALLOC(w.keys[1], w.cap_keys > 0 ? w.cap_keys : 1);
+  ALLOC(w.vals[0], w.cap_keys > 0 ? w.cap_keys : 1);
+  ALLOC(w.vals[1], w.cap_keys > 0 ? w.cap_keys : 1);
+  ALLOC(w.ranges, w.cap_tiles > 0 ? w.cap_tiles : 1);
+  ALLOC(w.hist, 256 * 1024);
+  ALLOC(w.scan_tmp, scan_tmp_elems(vn));
+  ALLOC(w.counters, 16);
+  ALLOC(w.err, 1);
+#undef ALLOC
+  w.gid_s = w.dval[0];
+  HIP_TRY(ctx, hipMemset(w.counters, 0, 16 * sizeof(uint32_t)));
+  HIP_TRY(ctx, hipMemset(w.err, 0, sizeof(uint32_t)));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  ctx->lim = l;
+  ctx->have_fwd = false;
+  return DASS_OK;
+}
+
+dass_status check_scene(dass_ctx ctx, const dass_gaussians* g) {
+  if (!g) return fail(ctx, DASS_E_INVALID, "gaussians is NULL");
+  if (g->n < 0 || g->capacity < 0 || g->n > g->capacity || g->n_base < 0 || g->n_base > g->n)
+    return fail(ctx, DASS_E_INVALID, "need 0 <= n_base <= n <= capacity (n=%d, n_base=%d, capacity=%d)", g->n,
+                g->n_base, g->capacity);
+  if (g->sh_degree < 0 || g->sh_degree > DASS_MAX_SH_DEGREE)
+    return fail(ctx, DASS_E_INVALID, "sh_degree %d outside [0,3]", g->sh_degree);
+  if (g->n > 0 && (!g->mean || !g->quat || !g->log_scale || !g->opacity_logit || !g->sh))
+    return fail(ctx, DASS_E_INVALID, "a parameter plane is NULL");
+  return DASS_OK;
+}
+
+dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, CamsK& out, int64_t& total_tiles) {
+  if (!cams) return fail(ctx, DASS_E_INVALID, "cams is NULL");
+  if (nv < 1 || nv > DASS_MAX_VIEWS || nv > ctx->lim.max_views)
+    return fail(ctx, nv > ctx->lim.max_views && nv <= DASS_MAX_VIEWS ? DASS_E_CAPACITY : DASS_E_INVALID,
+                "n_views %d outside [1, %d]", nv, std::min(DASS_MAX_VIEWS, ctx->lim.max_views));
+  total_tiles = 0;
+  std::memset(&out, 0, sizeof(out));
+  for (int v = 0; v < nv; v++) {
+    const dass_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 65535 * kTile || c.height > 65535 * kTile)
+      return fail(ctx, DASS_E_INVALID, "view %d: bad size %dx%d", v, c.width, c.height);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(ctx, DASS_E_INVALID, "view %d: focal lengths must be > 0", v);
+    CamK& k = out.c[v];
+    std::memcpy(k.R, c.R, sizeof(k.R));
+    std::memcpy(k.t, c.t, sizeof(k.t));
+    k.fx = c.fx;
+    k.fy = c.fy;
+    k.cx = c.cx;
+    k.cy = c.cy;
+    std::memcpy(k.campos, c.campos, sizeof(k.campos));
+    k.W = c.width;
+    k.H = c.height;
+    k.TX = (c.width + kTile - 1) / kTile;
+    k.TY = (c.height + kTile - 1) / kTile;
+    k.tile_base = (int)total_tiles;
+    total_tiles += (int64_t)k.TX * k.TY;
+  }
+  if (total_tiles > ctx->ws.cap_tiles)
+    return fail(ctx, DASS_E_CAPACITY, "%lld tiles exceed max_tiles %lld", (long long)total_tiles,
+                (long long)ctx->ws.cap_tiles);
+  return DASS_OK;
+}
+
+dass_status check_opts(dass_ctx ctx, const dass_opts* o) {
+  if (o && (o->tile_w != kTile || o->tile_h != kTile))
+    return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (16x16 only)", o->tile_w, o->tile_h);
+  return DASS_OK;
+}
+
+SceneK scene_of(const dass_gaussians* g) {
+  SceneK s;
+  s.mean = g->mean;
+  s.quat = g->quat;
+  s.log_scale = g->log_scale;
+  s.logit = g->opacity_logit;
+  s.sh = g->sh;
+  s.n = g->n;
+  s.stride = g->capacity;
+  s.deg = g->sh_degree;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+dass_status dass_create(dass_ctx* out, int32_t device, const dass_limits* limits) {
+  if (!out) return DASS_E_INVALID;
+  *out = nullptr;
+  dass_ctx ctx = new (std::nothrow) dass_ctx_s();
+  if (!ctx) return DASS_E_OOM;
+  dass_status s = check_limits(ctx, limits);
+  if (s != DASS_OK) {
+    delete ctx;
+    return s;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    delete ctx;
+    return DASS_E_HIP;
+  }
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return DASS_E_HIP;
+  }
+  s = allocate(ctx, *limits);
+  if (s != DASS_OK) {
+    free_all(ctx);
+    delete ctx;
+    return s;
+  }
+  *out = ctx;
+  return DASS_OK;
+}
+
+dass_status dass_reserve(dass_ctx ctx, const dass_limits* limits) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s = check_limits(ctx, limits);
+  if (s != DASS_OK) return s;
+  dass_limits l = ctx->lim;
+  l.max_gaussians = std::max(l.max_gaussians, limits->max_gaussians);
+  l.max_views = std::max(l.max_views, limits->max_views);
+  l.max_keys = std::max(l.max_keys, limits->max_keys);
+  l.max_tiles = std::max(l.max_tiles, limits->max_tiles);
+  if (l.max_gaussians == ctx->lim.max_gaussians && l.max_views == ctx->lim.max_views &&
+      l.max_keys == ctx->lim.max_keys && l.max_tiles == ctx->lim.max_tiles)
+    return DASS_OK;
+  s = check_limits(ctx, &l);
+  if (s != DASS_OK) return s;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  return allocate(ctx, l);
+}
+
+void dass_destroy(dass_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_all(ctx);
+  delete ctx;
+}
+
+const char* dass_last_error(dass_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+dass_status dass_sync(dass_ctx ctx, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  uint32_t err = 0;
+  HIP_TRY(ctx, hipMemcpy(&err, ctx->ws.err, sizeof(err), hipMemcpyDeviceToHost));
+  if (err) {
+    HIP_TRY(ctx, hipMemset(ctx->ws.err, 0, sizeof(uint32_t)));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    if (err & kErrKeyOverflow) return fail(ctx, DASS_E_CAPACITY, "tile-key buffer overflow (raise max_keys)");
+  }
+  return DASS_OK;
+}
+
+dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                       const float bg[3], dass_image* out, const dass_opts* opts, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if ((s = check_opts(ctx, opts)) != DASS_OK) return s;
+  if (!bg || !out) return fail(ctx, DASS_E_INVALID, "bg or out is NULL");
+  CamsK ck;
+  int64_t total_tiles = 0;
+  if ((s = make_cams(ctx, cams, n_views, ck, total_tiles)) != DASS_OK) return s;
+  if (g->n > ctx->lim.max_gaussians)
+    return fail(ctx, DASS_E_CAPACITY, "n=%d exceeds max_gaussians %d", g->n, ctx->lim.max_gaussians);
+  ViewsIO io;
+  std::memset(&io, 0, sizeof(io));
+  for (int v = 0; v < n_views; v++) {
+    if (!out[v].rgb || !out[v].t_final || !out[v].n_contrib)
+      return fail(ctx, DASS_E_INVALID, "out[%d] has a NULL buffer", v);
+    io.v[v].rgb = out[v].rgb;
+    io.v[v].t_final = out[v].t_final;
+    io.v[v].n_contrib = out[v].n_contrib;
+    io.v[v].dl = nullptr;
+    io.v[v].W = ck.c[v].W;
+    io.v[v].H = ck.c[v].H;
+    io.v[v].TX = ck.c[v].TX;
+    io.v[v].tile_base = ck.c[v].tile_base;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  const SceneK sc = scene_of(g);
+  const int64_t vn = (int64_t)n_views * g->n;
+  // 1. projection
+  launch_preprocess(sc, ck, n_views, ws, st);
+  // 2. per-view depth order: sort (view << 32 | depth bits, index)
+  launch_fill_u32(ws.counters + 2, (uint32_t)vn, 1, st);
+  const int dcur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 2, vn, 0, 32 + bit_width((uint64_t)(n_views - 1)),
+                                  ws.hist, sort_blocks_for(vn), st);
+  ws.gid_s = ws.dval[dcur];
+  // 3. records into depth order; tile keys in that order; stable sort on the tile id
+  launch_gather_sorted(g->n, vn, ws.gid_s, ws, st);
+  launch_emit_keys(g->n, vn, ck, ws, st);
+  const int kcur = radix_sort_u32(ws.keys, ws.vals, ws.counters, ws.cap_keys, 0,
+                                  bit_width((uint64_t)(total_tiles > 0 ? total_tiles - 1 : 0)), ws.hist,
+                                  sort_blocks_for(ws.cap_keys), st);
+  launch_ranges(ws.keys[kcur], total_tiles, ws, st);
+  // 4. blend
+  launch_blend_fwd(io, n_views, total_tiles, bg, ws, ws.vals[kcur], st);
+  if ((s = check_launch(ctx, "render_fwd")) != DASS_OK) return s;
+  ctx->have_fwd = true;
+  ctx->fwd_n = g->n;
+  ctx->fwd_nv = n_views;
+  ctx->fwd_stride = g->capacity;
+  ctx->fwd_tiles = total_tiles;
+  ctx->fwd_key_buf = kcur;
+  ctx->fwd_cams = ck;
+  return DASS_OK;
+}
+
+dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                       const float bg[3], const dass_image* fwd_out, const float* const* dl_drgb, dass_grads* grads,
+                       float* gradnorm_sum, int32_t* grad_count, const dass_opts* opts, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if ((s = check_opts(ctx, opts)) != DASS_OK) return s;
+  if (!bg || !fwd_out || !dl_drgb || !grads) return fail(ctx, DASS_E_INVALID, "NULL argument");
+  CamsK ck;
+  int64_t total_tiles = 0;
+  if ((s = make_cams(ctx, cams, n_views, ck, total_tiles)) != DASS_OK) return s;
+  if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
+      ctx->fwd_stride != g->capacity)
+    return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context");
+  ViewsIO io;
+  std::memset(&io, 0, sizeof(io));
+  for (int v = 0; v < n_views; v++) {
+    if (!fwd_out[v].t_final || !fwd_out[v].n_contrib || !dl_drgb[v])
+      return fail(ctx, DASS_E_INVALID, "view %d: NULL t_final, n_contrib or dl_drgb", v);
+    io.v[v].rgb = nullptr;
+    io.v[v].t_final = fwd_out[v].t_final;
+    io.v[v].n_contrib = fwd_out[v].n_contrib;
+    io.v[v].dl = dl_drgb[v];
+    io.v[v].W = ck.c[v].W;
+    io.v[v].H = ck.c[v].H;
+    io.v[v].TX = ck.c[v].TX;
+    io.v[v].tile_base = ck.c[v].tile_base;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  const int64_t vn = (int64_t)n_views * g->n;
+  launch_fill_u32(reinterpret_cast<uint32_t*>(ws.g2d), 0u, vn * 9, st);
+  launch_blend_bwd(io, n_views, total_tiles, bg, ws, ws.vals[ctx->fwd_key_buf], st);
+  launch_preprocess_bwd(scene_of(g), ck, n_views, ws, *grads, gradnorm_sum, grad_count, st);
+  return check_launch(ctx, "render_bwd");
+}
+
+dass_status shift_apply(dass_ctx ctx, int32_t mode, const int32_t* dyn_idx, int32_t n_dyn, const float* dpos,
+                        const float* drot, const dass_gaussians* in, dass_gaussians* out, const dass_grads* d_out,
+                        float* d_dpos, float* d_drot, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, in)) != DASS_OK) return s;
+  if (n_dyn < 0 || n_dyn > in->n) return fail(ctx, DASS_E_INVALID, "n_dyn %d outside [0, n]", n_dyn);
+  if (n_dyn > 0 && (!dyn_idx || !drot)) return fail(ctx, DASS_E_INVALID, "dyn_idx or drot is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const SceneK sc = scene_of(in);
+  if (mode == DASS_FWD) {
+    if (!out || !out->mean || !out->quat) return fail(ctx, DASS_E_INVALID, "out->mean/quat is NULL");
+    if (out->capacity != in->capacity) return fail(ctx, DASS_E_INVALID, "out and in capacities differ");
+    if (out->mean == in->mean || out->quat == in->quat) return fail(ctx, DASS_E_INVALID, "out may not alias in");
+    if (n_dyn > 0 && !dpos) return fail(ctx, DASS_E_INVALID, "dpos is NULL");
+    launch_shift_fwd(sc, out->mean, out->quat, dyn_idx, n_dyn, dpos, drot, st);
+  } else if (mode == DASS_ADJOINT) {
+    if (!d_out) return fail(ctx, DASS_E_INVALID, "d_out is NULL");
+    if (n_dyn > 0 && ((d_out->mean && !d_dpos) || (d_out->quat && !d_drot)))
+      return fail(ctx, DASS_E_INVALID, "d_dpos or d_drot is NULL");
+    launch_shift_adj(sc, d_out->mean, d_out->quat, dyn_idx, n_dyn, drot, d_dpos, d_drot, st);
+  } else {
+    return fail(ctx, DASS_E_INVALID, "mode must be DASS_FWD or DASS_ADJOINT");
+  }
+  return check_launch(ctx, "shift_apply");
+}
+
+dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,
+                      float eps, int32_t step, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!groups || n_groups < 1 || step < 1) return fail(ctx, DASS_E_INVALID, "need groups, n_groups >= 1, step >= 1");
+  for (int i = 0; i < n_groups; i++) {
+    const dass_adam_group& G = groups[i];
+    if (G.n < 0) return fail(ctx, DASS_E_INVALID, "group %d: n < 0", i);
+    if (G.n > 0 && (!G.param || !G.grad || !G.m || !G.v)) return fail(ctx, DASS_E_INVALID, "group %d: NULL", i);
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int per = adam_per_block();
+  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
+    AdamArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.bc1 = bc1;
+    a.bc2 = bc2;
+    int64_t blocks = 0;
+    int k = 0;
+    for (int i = base; i < n_groups && k < kAdamMaxGroups; i++) {
+      const dass_adam_group& G = groups[i];
+      if (G.n == 0) continue;
+      a.g[k].p = G.param;
+      a.g[k].g = G.grad;
+      a.g[k].m = G.m;
+      a.g[k].v = G.v;
+      a.g[k].n = G.n;
+      a.g[k].lr = G.lr;
+      a.g[k].block_begin = blocks;
+      blocks += (G.n + per - 1) / per;
+      k++;
+    }
+    a.n_groups = k;
+    if (k > 0) launch_adam(a, blocks, st);
+  }
+  return check_launch(ctx, "adam_step");
+}
+
+dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* render,
+                              const float* const* target, float* const* dl_drgb, float* const* err, float* loss,
+                              dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!cams || !render || !target || !dl_drgb || n_views < 1 || n_views > DASS_MAX_VIEWS)
+    return fail(ctx, DASS_E_INVALID, "bad arguments");
+  L1Args a;
+  std::memset(&a, 0, sizeof(a));
+  a.nv = n_views;
+  a.scale = 1.0f / (float)n_views;
+  int64_t blocks = 0;
+  const int per = l1_per_block();
+  for (int v = 0; v < n_views; v++) {
+    if (!render[v] || !target[v] || !dl_drgb[v]) return fail(ctx, DASS_E_INVALID, "view %d: NULL buffer", v);
+    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    a.v[v].render = render[v];
+    a.v[v].target = target[v];
+    a.v[v].dl = dl_drgb[v];
+    a.v[v].err = err ? err[v] : nullptr;
+    a.v[v].hw = (int64_t)cams[v].width * cams[v].height;
+    a.v[v].block_begin = blocks;
+    blocks += (a.v[v].hw + per - 1) / per;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  launch_l1(a, blocks, loss, (hipStream_t)stream);
+  return check_launch(ctx, "dass_l1_loss_grad");
+}
+
+dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* err_maps, const dass_camera* cams,
+                           int32_t n_views, const float* gradnorm_sum, const int32_t* grad_count, float gamma_err,
+                           float tau_pos, float tau_err, int32_t k_max, uint64_t seed, int32_t* n_appended,
+                           dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if (!err_maps || !cams || !n_appended || k_max < 0 || n_views < 1 || n_views > DASS_MAX_VIEWS)
+    return fail(ctx, DASS_E_INVALID, "bad arguments");
+  if (g->n_base > 0 && (!gradnorm_sum || !grad_count))
+    return fail(ctx, DASS_E_INVALID, "gradnorm_sum / grad_count is NULL");
+  if (g->n_base > ctx->ws.cap_vn) return fail(ctx, DASS_E_CAPACITY, "n_base exceeds the reserved workspace");
+  DensifyArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nv = n_views;
+  a.gamma_err = gamma_err;
+  a.tau_pos = tau_pos;
+  a.tau_err = tau_err;
+  for (int v = 0; v < n_views; v++) {
+    if (!err_maps[v]) return fail(ctx, DASS_E_INVALID, "err_maps[%d] is NULL", v);
+    const dass_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    a.err[v] = err_maps[v];
+    CamK& k = a.cams[v];
+    std::memcpy(k.R, c.R, sizeof(k.R));
+    std::memcpy(k.t, c.t, sizeof(k.t));
+    k.fx = c.fx;
+    k.fy = c.fy;
+    k.cx = c.cx;
+    k.cy = c.cy;
+    k.W = c.width;
+    k.H = c.height;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  const SceneK sc = scene_of(g);
+  launch_fill_u32(ws.counters + 1, 0u, 1, st);
+  launch_densify_select(sc, a, gradnorm_sum, grad_count, g->n_base, ws.dkey[0], ws.dval[0], ws.counters + 1, st);
+  const int cur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 1, g->n_base, 0, 64, ws.hist,
+                                 sort_blocks_for(g->n_base), st);
+  const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+  launch_densify_spawn(g->mean, g->quat, g->log_scale, g->opacity_logit, g->sh, 3 * K, g->capacity, g->n,
+                       g->capacity, ws.dkey[cur], ws.counters + 1, k_max, seed, n_appended, st);
+  ctx->have_fwd = false;  // the depth-order buffers were reused
+  return check_launch(ctx, "densify_append");
+}
+
+dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t* vals, int64_t max, int64_t* ranges,
+                            int64_t* count) {
+  if (!ctx || !count || !ranges) return DASS_E_INVALID;
+  if (!ctx->have_fwd || view < 0 || view >= ctx->fwd_nv) return fail(ctx, DASS_E_INVALID, "no such view");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  const CamK& c = ctx->fwd_cams.c[view];
+  const int nt = c.TX * c.TY;
+  std::vector<uint2> r(nt);
+  HIP_TRY(ctx, hipMemcpy(r.data(), ctx->ws.ranges + c.tile_base, nt * sizeof(uint2), hipMemcpyDeviceToHost));
+  uint32_t lo = 0xFFFFFFFFu, hi = 0;
+  for (const uint2& x : r)
+    if (x.y > x.x) {
+      lo = std::min(lo, x.x);
+      hi = std::max(hi, x.y);
+    }
+  if (hi == 0) lo = 0;
+  const uint32_t cnt = hi - lo;
+  *count = cnt;
+  if ((int64_t)cnt > max) return fail(ctx, DASS_E_CAPACITY, "view has %u keys", cnt);
+  if (cnt > 0 && (!keys || !vals)) return DASS_E_INVALID;
+  launch_debug_keys(view, ctx->fwd_n, ctx->ws, ctx->ws.keys[ctx->fwd_key_buf], ctx->ws.vals[ctx->fwd_key_buf], lo, cnt,
+                    c, keys, vals, ranges, nullptr);
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  return check_launch(ctx, "dass_debug_keys");
+}
+
+dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cam, double* out) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if (!out) return fail(ctx, DASS_E_INVALID, "out is NULL");
+  CamsK ck;
+  int64_t total = 0;
+  const int64_t keep = ctx->ws.cap_tiles;
+  ctx->ws.cap_tiles = INT64_MAX;  // the tile budget does not apply to this export
+  s = make_cams(ctx, cam, 1, ck, total);
+  ctx->ws.cap_tiles = keep;
+  if (s != DASS_OK) return s;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  launch_debug_projection(scene_of(g), ck, 0, out, nullptr);
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  return check_launch(ctx, "dass_debug_projection");
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// Internal declarations shared by the HIP translation units of libdass (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dass.h"
+
+namespace dass {
+
+// Blend thresholds (fp32 values; the kernels compare in fp32).
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTStop = 1e-4f;
+// Projection constants (fp32 values widened; the projection runs in fp64).
+constexpr double kDilation = (double)0.3f;
+constexpr double kNearZ = (double)0.2f;
+constexpr double kClip = (double)1.3f;
+
+constexpr int kTile = 16;          // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;
+constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// Device error bits (ctx->d_err)
+constexpr uint32_t kErrKeyOverflow = 1u;
+
+// Camera as the kernels see it (one per view, passed by value).
+struct CamK {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float campos[3];
+  int W, H, TX, TY;
+  int tile_base;  // first global tile index of this view
+};
+struct CamsK {
+  CamK c[DASS_MAX_VIEWS];
+};
+
+struct SceneK {
+  const float* mean;
+  const float* quat;
+  const float* log_scale;
+  const float* logit;
+  const float* sh;
+  int n, stride, deg;
+};
+
+// Per-view output pointers for the blend kernels.
+struct ViewIO {
+  float* rgb;
+  float* t_final;
+  int32_t* n_contrib;
+  const float* dl;  // upstream gradient (backward only)
+  int W, H, TX, tile_base;
+};
+struct ViewsIO {
+  ViewIO v[DASS_MAX_VIEWS];
+};
+
+// The projected record of one (view, Gaussian), as the blend consumes it (48 bytes).
+//   r0 = (u_hi, v_hi, u_lo, v_lo)   pixel-space mean as float hi + lo (fp64-accurate)
+//   r1 = (A, B, C, opacity)         inverse of the dilated 2D covariance
+//   r2 = (r, g, b, depth)
+struct Rec {
+  float4 r0, r1, r2;
+};
+
+// ---- workspace -------------------------------------------------------------------------
+struct Workspace {
+  int64_t cap_vn = 0;     // max views * max gaussians
+  int64_t cap_keys = 0;
+  int64_t cap_tiles = 0;
+  int sort_blocks = 0;
+  // per (view, gaussian), view-major, unsorted
+  Rec* rec_u = nullptr;
+  uint32_t* tt_u = nullptr;        // tiles touched
+  uint2* rect_u = nullptr;         // (x0 | y0 << 16, x1 | y1 << 16)
+  uint64_t* dkey[2] = {nullptr, nullptr};
+  uint32_t* dval[2] = {nullptr, nullptr};
+  // per sorted position p (view-major, depth order)
+  Rec* rec_s = nullptr;
+  uint2* rect_s = nullptr;
+  uint32_t* tt_s = nullptr;        // tiles touched, sorted order
+  uint64_t* off_s = nullptr;       // exclusive prefix of tiles touched, [cap_vn + 1]
+  uint32_t* inv = nullptr;         // inv[v*n + g] = p
+  uint32_t* gid_s = nullptr;       // gid of sorted position p
+  float* g2d = nullptr;            // [cap_vn][9]
+  // keys
+  uint32_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint2* ranges = nullptr;         // [cap_tiles]
+  // scratch
+  uint32_t* hist = nullptr;        // sort histograms
+  uint64_t* scan_tmp = nullptr;    // scan block sums
+  uint32_t* counters = nullptr;    // [0] = key count (clamped), [1] = densify |S|, ...
+  uint32_t* err = nullptr;         // device error bits
+};
+
+// ---- kernels launched by the host layer ------------------------------------------------
+// project.hip
+void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws, hipStream_t st);
+void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Workspace& ws,
+                           const dass_grads& grads, float* gradnorm, int32_t* gcount, hipStream_t st);
+void launch_debug_projection(const SceneK& s, const CamsK& cams, int view, double* out, hipStream_t st);
+
+// sort.hip
+// Exclusive scan of n uint32 values into uint64 out[0..n], out[n] = total.
+void scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, hipStream_t st);
+size_t scan_tmp_elems(int64_t n);
+// LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit); the element count is read
+// from device memory (*d_count) and must not exceed max_count.  Keys and values ping-pong
+// between buffer 0 and 1; returns the index of the buffer holding the result.
+int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count,
+                   int begin_bit, int end_bit, uint32_t* hist, int blocks, hipStream_t st);
+int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count,
+                   int begin_bit, int end_bit, uint32_t* hist, int blocks, hipStream_t st);
+int sort_blocks_for(int64_t max_count);
+
+// raster.hip
+void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspace& ws, hipStream_t st);
+// emits keys into ws.keys[0]/ws.vals[0] and writes the clamped key count to ws.counters[0]
+void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipStream_t st);
+void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
+void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
+                      const Workspace& ws, const uint32_t* vals, hipStream_t st);
+void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
+                      const Workspace& ws, const uint32_t* vals, hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted,
+                       const uint32_t* vals_sorted, uint32_t lo, uint32_t cnt, const CamK& cam,
+                       uint64_t* kout, uint32_t* vout, int64_t* rout, hipStream_t st);
+
+// update.hip
+void launch_shift_fwd(const SceneK& in, float* out_mean, float* out_quat, const int32_t* dyn_idx,
+                      int n_dyn, const float* dpos, const float* drot, hipStream_t st);
+void launch_shift_adj(const SceneK& in, const float* dmean, const float* dquat, const int32_t* dyn_idx,
+                      int n_dyn, const float* drot, float* d_dpos, float* d_drot, hipStream_t st);
+
+struct AdamGroupK {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  int64_t block_begin;  // first block index of this group
+  float lr;
+};
+constexpr int kAdamMaxGroups = 24;
+struct AdamArgs {
+  AdamGroupK g[kAdamMaxGroups];
+  int n_groups;
+  float b1, b2, eps, bc1, bc2;
+};
+void launch_adam(const AdamArgs& a, int64_t total_blocks, hipStream_t st);
+
+struct L1View {
+  const float* render;
+  const float* target;
+  float* dl;
+  float* err;
+  int64_t hw;
+  int64_t block_begin;
+};
+struct L1Args {
+  L1View v[DASS_MAX_VIEWS];
+  int nv;
+  float scale;  // 1 / (3 H W V) per view is computed per view; scale = 1/V
+};
+void launch_l1(const L1Args& a, int64_t total_blocks, float* loss, hipStream_t st);
+
+struct DensifyArgs {
+  const float* err[DASS_MAX_VIEWS];
+  CamK cams[DASS_MAX_VIEWS];
+  int nv;
+  float gamma_err, tau_pos, tau_err;
+};
+void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* gsum, const int32_t* gcnt,
+                           int n_base, uint64_t* sel_keys, uint32_t* sel_vals, uint32_t* d_count,
+                           hipStream_t st);
+void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
+                          int stride, int n, int capacity, const uint64_t* sel_keys, const uint32_t* d_count,
+                          int k_max, uint64_t seed, int32_t* n_appended, hipStream_t st);
+
+// error checking helper
+inline const char* hip_err_str(hipError_t e) { return hipGetErrorString(e); }
+
+}  // namespace dass

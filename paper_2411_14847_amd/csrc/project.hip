@@ -1,0 +1,452 @@
+// Projection of 3D Gaussians into every view (App. A.1) and its adjoint.
+//
+// One thread per Gaussian walks all views of the call, so the Gaussian's 59 parameters are
+// read from HBM once (coalesced structure-of-arrays planes) and kept in registers.  The
+// arithmetic is fp64: it is a few hundred flops per Gaussian-view (negligible next to the
+// blend), and it makes the integer decisions taken here -- cull, radius, tile rectangle,
+// float32 depth bits of the key -- agree with an fp64 definition except within ~1e-15 of a
+// boundary.  The pixel-space mean is handed to the fp32 blend as hi + lo floats.
+#include "dass_internal.h"
+
+namespace dass {
+namespace {
+
+// Real orthonormal spherical harmonics up to degree 3 (no Condon-Shortley sign), index
+// k = l*l + l + m, evaluated at a unit direction; optional gradient w.r.t. (x, y, z) of the
+// polynomial form.
+constexpr double kY0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+constexpr double kY1 = 0.4886025119029199;    // sqrt(3/(4 pi))
+constexpr double kY2a = 1.0925484305920792;   // sqrt(15/pi)/2
+constexpr double kY2b = 0.31539156525252005;  // sqrt(5/pi)/4
+constexpr double kY2c = 0.5462742152960396;   // sqrt(15/pi)/4
+constexpr double kY3a = 0.5900435899266435;   // sqrt(35/(2 pi))/4
+constexpr double kY3b = 2.890611442640554;    // sqrt(105/pi)/2
+constexpr double kY3c = 0.4570457994644658;   // sqrt(21/(2 pi))/4
+constexpr double kY3d = 0.3731763325901154;   // sqrt(7/pi)/4
+constexpr double kY3e = 1.445305721320277;    // sqrt(105/pi)/4
+
+template <int DEG, bool GRAD>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y, double* gx, double* gy,
+                                         double* gz) {
+  Y[0] = kY0;
+  if (GRAD) { gx[0] = gy[0] = gz[0] = 0.0; }
+  if (DEG >= 1) {
+    Y[1] = kY1 * y; Y[2] = kY1 * z; Y[3] = kY1 * x;
+    if (GRAD) {
+      gx[1] = 0.0; gy[1] = kY1; gz[1] = 0.0;
+      gx[2] = 0.0; gy[2] = 0.0; gz[2] = kY1;
+      gx[3] = kY1; gy[3] = 0.0; gz[3] = 0.0;
+    }
+  }
+  if (DEG >= 2) {
+    double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kY2a * x * y;
+    Y[5] = kY2a * y * z;
+    Y[6] = kY2b * (2.0 * zz - xx - yy);
+    Y[7] = kY2a * x * z;
+    Y[8] = kY2c * (xx - yy);
+    if (GRAD) {
+      gx[4] = kY2a * y; gy[4] = kY2a * x; gz[4] = 0.0;
+      gx[5] = 0.0; gy[5] = kY2a * z; gz[5] = kY2a * y;
+      gx[6] = -2.0 * kY2b * x; gy[6] = -2.0 * kY2b * y; gz[6] = 4.0 * kY2b * z;
+      gx[7] = kY2a * z; gy[7] = 0.0; gz[7] = kY2a * x;
+      gx[8] = 2.0 * kY2c * x; gy[8] = -2.0 * kY2c * y; gz[8] = 0.0;
+    }
+  }
+  if (DEG >= 3) {
+    double xx = x * x, yy = y * y, zz = z * z;
+    Y[9] = kY3a * y * (3.0 * xx - yy);
+    Y[10] = kY3b * x * y * z;
+    Y[11] = kY3c * y * (4.0 * zz - xx - yy);
+    Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = kY3c * x * (4.0 * zz - xx - yy);
+    Y[14] = kY3e * z * (xx - yy);
+    Y[15] = kY3a * x * (xx - 3.0 * yy);
+    if (GRAD) {
+      gx[9] = kY3a * 6.0 * x * y; gy[9] = kY3a * 3.0 * (xx - yy); gz[9] = 0.0;
+      gx[10] = kY3b * y * z; gy[10] = kY3b * x * z; gz[10] = kY3b * x * y;
+      gx[11] = -2.0 * kY3c * x * y; gy[11] = kY3c * (4.0 * zz - xx - 3.0 * yy); gz[11] = 8.0 * kY3c * y * z;
+      gx[12] = -6.0 * kY3d * x * z; gy[12] = -6.0 * kY3d * y * z; gz[12] = kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+      gx[13] = kY3c * (4.0 * zz - 3.0 * xx - yy); gy[13] = -2.0 * kY3c * x * y; gz[13] = 8.0 * kY3c * x * z;
+      gx[14] = 2.0 * kY3e * x * z; gy[14] = -2.0 * kY3e * y * z; gz[14] = kY3e * (xx - yy);
+      gx[15] = kY3a * 3.0 * (xx - yy); gy[15] = -6.0 * kY3a * x * y; gz[15] = 0.0;
+    }
+  }
+}
+
+// View-independent part of one Gaussian.
+struct GaussD {
+  double mu[3], qhat[4], qn, s[3], Rq[9], M[9], Sig[6], o;  // Sig: xx, xy, xz, yy, yz, zz
+  bool ok;
+};
+
+__device__ __forceinline__ void load_gaussian(const SceneK& sc, int g, GaussD& G) {
+  const int64_t st = sc.stride;
+  for (int i = 0; i < 3; i++) G.mu[i] = (double)sc.mean[i * st + g];
+  double q[4];
+  for (int i = 0; i < 4; i++) q[i] = (double)sc.quat[i * st + g];
+  G.qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  G.ok = G.qn > 0.0;
+  double inv = G.ok ? 1.0 / G.qn : 0.0;
+  for (int i = 0; i < 4; i++) G.qhat[i] = q[i] * inv;
+  for (int i = 0; i < 3; i++) G.s[i] = exp((double)sc.log_scale[i * st + g]);
+  double w = G.qhat[0], x = G.qhat[1], y = G.qhat[2], z = G.qhat[3];
+  double* R = G.Rq;
+  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) G.M[i * 3 + j] = R[i * 3 + j] * G.s[j];
+  const double* M = G.M;
+  G.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  G.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  G.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  G.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  G.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  G.o = 1.0 / (1.0 + exp(-(double)sc.logit[g]));
+}
+
+// View-dependent part.
+struct ViewD {
+  double t[3], limx, limy, txc, tyc, J0, J2, J4, J5;  // J = [[J0, 0, J2], [0, J4, J5]]
+  double T[6];                                      // J W
+  double a, b, c, det, A, B, C, u, v;
+  bool clipx, clipy, visible;
+  int radius, x0, y0, x1, y1;
+  uint32_t depth_bits;
+};
+
+__device__ __forceinline__ void project_view(const GaussD& G, const CamK& cam, ViewD& V) {
+#pragma clang fp contract(off)
+  double W[9];
+  for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
+  // camera space, fixed evaluation order, no fused multiply-add (compared bit-for-bit)
+  for (int i = 0; i < 3; i++)
+    V.t[i] = ((W[i * 3 + 0] * G.mu[0] + W[i * 3 + 1] * G.mu[1]) + W[i * 3 + 2] * G.mu[2]) + (double)cam.t[i];
+  const double tx = V.t[0], ty = V.t[1], tz = V.t[2];
+  V.visible = false;
+  V.radius = 0;
+  V.x0 = V.y0 = V.x1 = V.y1 = 0;
+  V.depth_bits = 0xFFFFFFFFu;
+  if (!G.ok || !(tz > kNearZ)) return;
+  const double fx = (double)cam.fx, fy = (double)cam.fy;
+  V.limx = kClip * ((double)cam.W / (2.0 * fx));
+  V.limy = kClip * ((double)cam.H / (2.0 * fy));
+  const double rx = tx / tz, ry = ty / tz;
+  V.clipx = (rx < -V.limx) || (rx > V.limx);
+  V.clipy = (ry < -V.limy) || (ry > V.limy);
+  V.txc = fmin(fmax(rx, -V.limx), V.limx) * tz;
+  V.tyc = fmin(fmax(ry, -V.limy), V.limy) * tz;
+  const double tz2 = tz * tz;
+  V.J0 = fx / tz;
+  V.J2 = -fx * V.txc / tz2;
+  V.J4 = fy / tz;
+  V.J5 = -fy * V.tyc / tz2;
+  for (int j = 0; j < 3; j++) {
+    V.T[j] = V.J0 * W[j] + V.J2 * W[6 + j];
+    V.T[3 + j] = V.J4 * W[3 + j] + V.J5 * W[6 + j];
+  }
+  // Sigma_2D = T Sigma T^T + dilation
+  const double* S = G.Sig;
+  double TS[6];
+  for (int i = 0; i < 2; i++) {
+    const double* Ti = V.T + 3 * i;
+    TS[3 * i + 0] = Ti[0] * S[0] + Ti[1] * S[1] + Ti[2] * S[2];
+    TS[3 * i + 1] = Ti[0] * S[1] + Ti[1] * S[3] + Ti[2] * S[4];
+    TS[3 * i + 2] = Ti[0] * S[2] + Ti[1] * S[4] + Ti[2] * S[5];
+  }
+  V.a = (TS[0] * V.T[0] + TS[1] * V.T[1] + TS[2] * V.T[2]) + kDilation;
+  V.b = TS[0] * V.T[3] + TS[1] * V.T[4] + TS[2] * V.T[5];
+  V.c = (TS[3] * V.T[3] + TS[4] * V.T[4] + TS[5] * V.T[5]) + kDilation;
+  V.det = V.a * V.c - V.b * V.b;
+  if (!(V.det > 0.0)) return;
+  V.A = V.c / V.det;
+  V.B = -V.b / V.det;
+  V.C = V.a / V.det;
+  const double mid = 0.5 * (V.a + V.c);
+  const double d = 0.5 * (V.a - V.c);
+  const double lmax = mid + sqrt(fmax(d * d + V.b * V.b, 0.0));
+  double r = ceil(3.0 * sqrt(lmax));
+  r = fmin(r, 1.0e7);
+  V.radius = (int)r;
+  V.u = ((fx * tx) / tz) + (double)cam.cx;
+  V.v = ((fy * ty) / tz) + (double)cam.cy;
+  const double fx0 = floor((V.u - r) / (double)kTile);
+  const double fx1 = floor(((V.u + r) + (double)(kTile - 1)) / (double)kTile);
+  const double fy0 = floor((V.v - r) / (double)kTile);
+  const double fy1 = floor(((V.v + r) + (double)(kTile - 1)) / (double)kTile);
+  V.x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.TX);
+  V.x1 = (int)fmin(fmax(fx1, 0.0), (double)cam.TX);
+  V.y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.TY);
+  V.y1 = (int)fmin(fmax(fy1, 0.0), (double)cam.TY);
+  V.visible = (V.radius > 0) && (V.x1 > V.x0) && (V.y1 > V.y0);
+  V.depth_bits = V.visible ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
+}
+
+template <int DEG>
+__device__ __forceinline__ void colour(const GaussD& G, const CamK& cam, const float* shc, double* rgb_pre,
+                                       double* dhat, double& dn) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  double dir[3];
+  for (int i = 0; i < 3; i++) dir[i] = G.mu[i] - (double)cam.campos[i];
+  dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
+  for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv;
+  double Y[16];
+  sh_basis<DEG, false>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
+#pragma unroll
+  for (int ch = 0; ch < 3; ch++) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; k++) acc += (double)shc[k * 3 + ch] * Y[k];
+    rgb_pre[ch] = acc + 0.5;
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int nv, Rec* __restrict__ rec,
+                                                    uint32_t* __restrict__ tt, uint2* __restrict__ rect,
+                                                    uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  GaussD G;
+  load_gaussian(sc, g, G);
+  float shc[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) shc[k] = sc.sh[(int64_t)k * sc.stride + g];
+  for (int v = 0; v < nv; v++) {
+    const CamK& cam = cams.c[v];
+    const int64_t i = (int64_t)v * sc.n + g;
+    ViewD V;
+    project_view(G, cam, V);
+    Rec r;
+    if (V.visible) {
+      double rgb_pre[3], dhat[3], dn;
+      colour<DEG>(G, cam, shc, rgb_pre, dhat, dn);
+      const float uh = (float)V.u, vh = (float)V.v;
+      r.r0 = make_float4(uh, vh, (float)(V.u - (double)uh), (float)(V.v - (double)vh));
+      r.r1 = make_float4((float)V.A, (float)V.B, (float)V.C, (float)G.o);
+      r.r2 = make_float4((float)fmax(rgb_pre[0], 0.0), (float)fmax(rgb_pre[1], 0.0),
+                         (float)fmax(rgb_pre[2], 0.0), (float)V.t[2]);
+      tt[i] = (uint32_t)((V.x1 - V.x0) * (V.y1 - V.y0));
+      rect[i] = make_uint2((uint32_t)V.x0 | ((uint32_t)V.y0 << 16), (uint32_t)V.x1 | ((uint32_t)V.y1 << 16));
+    } else {
+      r.r0 = r.r1 = r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      tt[i] = 0;
+      rect[i] = make_uint2(0, 0);
+    }
+    rec[i] = r;
+    dkey[i] = ((uint64_t)v << 32) | (uint64_t)V.depth_bits;
+    dval[i] = (uint32_t)g;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adjoint.  Per Gaussian: for every view where it is visible, read the per-view 2D gradient
+// (du, dv, dA, dB, dC, do, dr, dg, db) at its sorted position, chain it back through the
+// conic inverse, the EWA projection, the pixel mean, the colour and the opacity; quantities
+// linear in the view (dSigma, dlogit) are summed over views first and chained once.
+// ---------------------------------------------------------------------------------------------
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, int nv,
+                                                        const uint32_t* __restrict__ inv,
+                                                        const float* __restrict__ g2d, dass_grads gr,
+                                                        float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  GaussD G;
+  load_gaussian(sc, g, G);
+  float shc[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) shc[k] = sc.sh[(int64_t)k * sc.stride + g];
+  float dsh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) dsh[k] = 0.f;
+  double dmu[3] = {0.0, 0.0, 0.0};
+  double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double dop = 0.0, gnorm = 0.0;
+  int cnt = 0;
+  for (int v = 0; v < nv; v++) {
+    const CamK& cam = cams.c[v];
+    ViewD V;
+    project_view(G, cam, V);
+    if (!V.visible) continue;
+    const uint32_t p = inv[(int64_t)v * sc.n + g];
+    const float* gd = g2d + (int64_t)p * 9;
+    const double du = gd[0], dv = gd[1], dA = gd[2], dB = gd[3], dC = gd[4];
+    dop += (double)gd[5];
+    gnorm += sqrt(du * du + dv * dv);
+    cnt++;
+    // colour
+    {
+      double rgb_pre[3], dhat[3], dn;
+      colour<DEG>(G, cam, shc, rgb_pre, dhat, dn);
+      double Y[16], gx[16], gy[16], gz[16];
+      sh_basis<DEG, true>(dhat[0], dhat[1], dhat[2], Y, gx, gy, gz);
+      double dd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ch = 0; ch < 3; ch++) {
+        if (rgb_pre[ch] < 0.0) continue;
+        const double dc = (double)gd[6 + ch];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+          dsh[k * 3 + ch] += (float)(dc * Y[k]);
+          const double w = dc * (double)shc[k * 3 + ch];
+          dd[0] += w * gx[k];
+          dd[1] += w * gy[k];
+          dd[2] += w * gz[k];
+        }
+      }
+      if (dn > 0.0) {
+        const double dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
+        for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) / dn;
+      }
+    }
+    // conic (A, B, C) = inverse of [[a, b], [b, c]]: dSigma2D = -Q G Q with G = [[dA, dB/2], [dB/2, dC]]
+    const double A = V.A, B = V.B, C = V.C;
+    const double hB = 0.5 * dB;
+    // Q G
+    const double qg00 = A * dA + B * hB, qg01 = A * hB + B * dC;
+    const double qg10 = B * dA + C * hB, qg11 = B * hB + C * dC;
+    const double da = -(qg00 * A + qg01 * B);
+    const double db2 = -(qg00 * B + qg01 * C);  // (0,1) entry of the symmetric matrix gradient
+    const double dc = -(qg10 * B + qg11 * C);
+    // Sigma_2D = T Sigma T^T: dSigma += T^T G2 T, dT = 2 G2 T Sigma, with G2 = [[da, db2], [db2, dc]]
+    const double* T = V.T;
+    double G2T[6];
+    for (int j = 0; j < 3; j++) {
+      G2T[j] = da * T[j] + db2 * T[3 + j];
+      G2T[3 + j] = db2 * T[j] + dc * T[3 + j];
+    }
+    dSig[0] += T[0] * G2T[0] + T[3] * G2T[3];
+    dSig[1] += T[0] * G2T[1] + T[3] * G2T[4];
+    dSig[2] += T[0] * G2T[2] + T[3] * G2T[5];
+    dSig[3] += T[1] * G2T[1] + T[4] * G2T[4];
+    dSig[4] += T[1] * G2T[2] + T[4] * G2T[5];
+    dSig[5] += T[2] * G2T[2] + T[5] * G2T[5];
+    const double* S = G.Sig;
+    double dT[6];
+    for (int i = 0; i < 2; i++) {
+      const double* r = G2T + 3 * i;
+      dT[3 * i + 0] = 2.0 * (r[0] * S[0] + r[1] * S[1] + r[2] * S[2]);
+      dT[3 * i + 1] = 2.0 * (r[0] * S[1] + r[1] * S[3] + r[2] * S[4]);
+      dT[3 * i + 2] = 2.0 * (r[0] * S[2] + r[1] * S[4] + r[2] * S[5]);
+    }
+    // T = J W: dJ_ij = sum_k dT_ik W_jk
+    double W[9];
+    for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
+    const double dJ0 = dT[0] * W[0] + dT[1] * W[1] + dT[2] * W[2];
+    const double dJ2 = dT[0] * W[6] + dT[1] * W[7] + dT[2] * W[8];
+    const double dJ4 = dT[3] * W[3] + dT[4] * W[4] + dT[5] * W[5];
+    const double dJ5 = dT[3] * W[6] + dT[4] * W[7] + dT[5] * W[8];
+    const double fx = (double)cam.fx, fy = (double)cam.fy;
+    const double tx = V.t[0], ty = V.t[1], tz = V.t[2];
+    const double tz2 = tz * tz, tz3 = tz2 * tz;
+    double dt[3] = {0.0, 0.0, 0.0};
+    dt[2] += -dJ0 * fx / tz2 - dJ4 * fy / tz2;
+    dt[2] += 2.0 * dJ2 * fx * V.txc / tz3 + 2.0 * dJ5 * fy * V.tyc / tz3;
+    const double dtxc = -dJ2 * fx / tz2, dtyc = -dJ5 * fy / tz2;
+    if (!V.clipx) dt[0] += dtxc; else dt[2] += dtxc * (tx > 0.0 ? V.limx : -V.limx);
+    if (!V.clipy) dt[1] += dtyc; else dt[2] += dtyc * (ty > 0.0 ? V.limy : -V.limy);
+    // pixel-space mean
+    dt[0] += du * fx / tz;
+    dt[1] += dv * fy / tz;
+    dt[2] -= (du * fx * tx + dv * fy * ty) / tz2;
+    for (int i = 0; i < 3; i++) dmu[i] += W[i] * dt[0] + W[3 + i] * dt[1] + W[6 + i] * dt[2];
+  }
+  if (cnt == 0) return;
+  // Sigma = M M^T -> dM = 2 dSigma M (dSigma symmetric)
+  const double* M = G.M;
+  const double dS[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
+  double dM[9];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      dM[i * 3 + j] = 2.0 * (dS[i * 3 + 0] * M[0 * 3 + j] + dS[i * 3 + 1] * M[1 * 3 + j] + dS[i * 3 + 2] * M[2 * 3 + j]);
+  double dR[9], dls[3];
+  for (int j = 0; j < 3; j++) {
+    double acc = 0.0;
+    for (int i = 0; i < 3; i++) {
+      dR[i * 3 + j] = dM[i * 3 + j] * G.s[j];
+      acc += dM[i * 3 + j] * G.Rq[i * 3 + j];
+    }
+    dls[j] = acc * G.s[j];
+  }
+  const double w = G.qhat[0], x = G.qhat[1], y = G.qhat[2], z = G.qhat[3];
+  double dw = 2.0 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  double dx = 2.0 * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                     2.0 * x * dR[8]);
+  double dy = 2.0 * (-2.0 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                     2.0 * y * dR[8]);
+  double dz = 2.0 * (-2.0 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0 * z * dR[4] + y * dR[5] + x * dR[6] +
+                     y * dR[7]);
+  const double dot = w * dw + x * dx + y * dy + z * dz;
+  const double dq[4] = {(dw - w * dot) / G.qn, (dx - x * dot) / G.qn, (dy - y * dot) / G.qn, (dz - z * dot) / G.qn};
+  const int64_t st = sc.stride;
+  if (gr.mean)
+    for (int i = 0; i < 3; i++) gr.mean[i * st + g] += (float)dmu[i];
+  if (gr.quat)
+    for (int i = 0; i < 4; i++) gr.quat[i * st + g] += (float)dq[i];
+  if (gr.log_scale)
+    for (int i = 0; i < 3; i++) gr.log_scale[i * st + g] += (float)dls[i];
+  if (gr.opacity_logit) gr.opacity_logit[g] += (float)(dop * G.o * (1.0 - G.o));
+  if (gr.sh) {
+#pragma unroll
+    for (int k = 0; k < 3 * K; k++) gr.sh[(int64_t)k * st + g] += dsh[k];
+  }
+  if (gradnorm) gradnorm[g] += (float)gnorm;
+  if (gcount) gcount[g] += cnt;
+}
+
+__global__ void k_debug_projection(SceneK sc, CamK cam, double* out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= sc.n) return;
+  GaussD G;
+  load_gaussian(sc, g, G);
+  ViewD V;
+  project_view(G, cam, V);
+  double* o = out + (int64_t)g * 16;
+  double rgb_pre[3] = {0, 0, 0}, dhat[3], dn;
+  float shc[48];
+  const int K = (sc.deg + 1) * (sc.deg + 1);
+  for (int k = 0; k < 48; k++) shc[k] = k < 3 * K ? sc.sh[(int64_t)k * sc.stride + g] : 0.f;
+  colour<3>(G, cam, shc, rgb_pre, dhat, dn);
+  o[0] = V.u; o[1] = V.v; o[2] = V.A; o[3] = V.B; o[4] = V.C; o[5] = G.o;
+  for (int c = 0; c < 3; c++) o[6 + c] = fmax(rgb_pre[c], 0.0);
+  o[9] = V.t[2]; o[10] = V.radius; o[11] = V.x0; o[12] = V.y0; o[13] = V.x1; o[14] = V.y1;
+  o[15] = V.visible ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws, hipStream_t st) {
+  if (s.n == 0) return;
+  dim3 grid((s.n + 255) / 256), block(256);
+  switch (s.deg) {
+    case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
+    case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
+    case 2: k_preprocess<2><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
+    default: k_preprocess<3><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
+  }
+}
+
+void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Workspace& ws, const dass_grads& grads,
+                           float* gradnorm, int32_t* gcount, hipStream_t st) {
+  if (s.n == 0) return;
+  dim3 grid((s.n + 255) / 256), block(256);
+  switch (s.deg) {
+    case 0: k_preprocess_bwd<0><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
+    case 1: k_preprocess_bwd<1><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
+    case 2: k_preprocess_bwd<2><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
+    default: k_preprocess_bwd<3><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
+  }
+}
+
+void launch_debug_projection(const SceneK& s, const CamsK& cams, int view, double* out, hipStream_t st) {
+  if (s.n == 0) return;
+  k_debug_projection<<<(s.n + 255) / 256, 256, 0, st>>>(s, cams.c[view], out);
+}
+
+}  // namespace dass

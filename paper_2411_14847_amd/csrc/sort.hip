@@ -1,0 +1,328 @@
+// Prefix scan and LSD radix sort for wave64 (gfx950).
+//
+// Radix sort: reduce-then-scan with a fixed grid, so that the element count can stay on the
+// device (no host round trip inside a render; the launch sequence is graph-capturable).
+// Each pass over an 8-bit digit is
+//   (1) upsweep: every block histograms its contiguous chunk into LDS (per-wave
+//       sub-histograms to spread LDS atomics), written digit-major to global memory;
+//   (2) scan: one workgroup turns the [256][blocks] counts into global write offsets;
+//   (3) scatter: every block re-reads its chunk in batches of 2048 pairs, ranks them stably
+//       with wave ballots (8 ballots give each lane the mask of lanes holding the same
+//       digit), orders the batch by digit in LDS and writes each digit's run contiguously.
+// A pass never depends on forward progress between workgroups.
+#include "dass_internal.h"
+
+namespace dass {
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;                      // items per thread per batch
+constexpr int kBatch = kSortThreads * kSortItems;  // 2048
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive scan within a wave of 64 lanes (shuffle-up steps).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan across a 256-thread block; returns the exclusive prefix, *total the sum.
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_wave, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x);
+  if (lane == 63) s_wave[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    uint32_t s = s_wave[w];
+    if (w < wave) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  if (total) *total = tot;
+  return base + inc - x;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K k, int shift) {
+  return (uint32_t)(k >> shift) & (kRadix - 1);
+}
+
+__device__ __forceinline__ void chunk_of(uint32_t count, int blocks, uint32_t& lo, uint32_t& hi) {
+  const uint32_t chunk = (uint32_t)(((uint64_t)count + blocks - 1) / blocks);
+  const uint64_t l = (uint64_t)blockIdx.x * chunk;
+  lo = (uint32_t)(l < count ? l : count);
+  const uint64_t h = l + chunk;
+  hi = (uint32_t)(h < count ? h : count);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_upsweep(const K* __restrict__ keys, const uint32_t* __restrict__ d_count,
+                                                          int shift, int blocks, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[4][kRadix];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int i = tid; i < 4 * kRadix; i += kSortThreads) (&s_h[0][0])[i] = 0;
+  __syncthreads();
+  uint32_t lo, hi;
+  chunk_of(*d_count, blocks, lo, hi);
+  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&s_h[wave][digit_of(keys[i], shift)], 1u);
+  __syncthreads();
+  hist[(int64_t)tid * blocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+}
+
+// Exclusive scan of n = 256 * blocks counts (digit-major), one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_hist(uint32_t* __restrict__ hist, int n) {
+  __shared__ uint32_t s_w[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (n + 1023) / 1024;
+  const int b = tid * per, e = min(b + per, n);
+  uint32_t sum = 0;
+  for (int i = b; i < e; i++) sum += hist[i];
+  uint32_t inc = wave_incl_scan(sum);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wave; w++) base += s_w[w];
+  uint32_t run = base + inc - sum;
+  for (int i = b; i < e; i++) {
+    uint32_t c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                          K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          const uint32_t* __restrict__ d_count, int shift, int blocks,
+                                                          const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_base[kRadix];       // global write position of the next item of each digit
+  __shared__ uint32_t s_cnt[kRadix];        // items of each digit seen so far in this batch
+  __shared__ uint32_t s_boff[kRadix];       // exclusive digit offsets within the batch
+  __shared__ uint32_t s_wcnt[2][4][kRadix];  // per-wave digit counts (double-buffered by sub-round)
+  __shared__ uint32_t s_tmp[4];
+  __shared__ K s_k[kBatch];
+  __shared__ uint32_t s_v[kBatch];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t lo, hi;
+  chunk_of(*d_count, blocks, lo, hi);
+  s_base[tid] = hist[(int64_t)tid * blocks + blockIdx.x];
+  const uint64_t lt = lanemask_lt();
+
+  for (uint32_t batch = lo; batch < hi; batch += kBatch) {
+    const uint32_t nb = min((uint32_t)kBatch, hi - batch);
+    s_cnt[tid] = 0;
+    K key[kSortItems];
+    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+#pragma unroll
+    for (int s = 0; s < kSortItems; s++) {
+      uint32_t (*wc)[kRadix] = s_wcnt[s & 1];
+#pragma unroll
+      for (int w = 0; w < 4; w++) wc[w][tid] = 0;
+      const uint32_t idx = batch + s * kSortThreads + tid;
+      const bool valid = idx < hi;
+      uint32_t d = 0;
+      if (valid) {
+        key[s] = kin[idx];
+        val[s] = vin[idx];
+        d = digit_of(key[s], shift);
+      }
+      dig[s] = d;
+      __syncthreads();
+      // lanes of this wave holding the same digit
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; b++) {
+        const uint64_t m = __ballot((d >> b) & 1);
+        peers &= ((d >> b) & 1) ? m : ~m;
+      }
+      const uint32_t rw = __popcll(peers & lt);
+      if (valid && rw == 0) wc[wave][d] = __popcll(peers);
+      __syncthreads();
+      {  // thread tid owns digit tid: exclusive prefix over waves, running count
+        uint32_t run = s_cnt[tid];
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+          const uint32_t c = wc[w][tid];
+          wc[w][tid] = run;
+          run += c;
+        }
+        s_cnt[tid] = run;
+      }
+      __syncthreads();
+      rank[s] = valid ? wc[wave][d] + rw : 0;
+    }
+    // digit offsets within the batch
+    const uint32_t c = s_cnt[tid];
+    s_boff[tid] = block_excl_scan256(c, s_tmp, nullptr);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSortItems; s++) {
+      const uint32_t idx = batch + s * kSortThreads + tid;
+      if (idx < hi) {
+        const uint32_t pos = s_boff[dig[s]] + rank[s];
+        s_k[pos] = key[s];
+        s_v[pos] = val[s];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kSortItems; s++) {
+      const uint32_t j = s * kSortThreads + tid;
+      if (j < nb) {
+        const K k = s_k[j];
+        const uint32_t d = digit_of(k, shift);
+        const uint32_t o = s_base[d] + (j - s_boff[d]);
+        kout[o] = k;
+        vout[o] = s_v[j];
+      }
+    }
+    __syncthreads();
+    s_base[tid] += c;
+    __syncthreads();
+  }
+  (void)lane;
+}
+
+// ---- scan of uint32 -> uint64 (exclusive), 3 phases ----------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                              uint64_t* __restrict__ sums) {
+  __shared__ uint64_t s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t acc = 0;
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
+    const int64_t j = base + i;
+    if (j < n) acc += in[j];
+  }
+  // wave reduce
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// exclusive scan of nb block sums in place (single workgroup of 1024), nb <= 1024 * 64
+__global__ __launch_bounds__(1024) void k_scan_sums(uint64_t* __restrict__ sums, int nb) {
+  __shared__ uint64_t s_w[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (nb + 1023) / 1024;
+  const int b = tid * per, e = min(b + per, nb);
+  uint64_t sum = 0;
+  for (int i = b; i < e; i++) sum += sums[i];
+  uint64_t inc = wave_incl_scan64(sum);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint64_t base = 0;
+  for (int w = 0; w < wave; w++) base += s_w[w];
+  uint64_t run = base + inc - sum;
+  for (int i = b; i < e; i++) {
+    uint64_t c = sums[i];
+    sums[i] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __restrict__ in, int64_t n,
+                                                             const uint64_t* __restrict__ sums,
+                                                             uint64_t* __restrict__ out) {
+  __shared__ uint64_t s_w[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;  // blocked layout
+  uint32_t x[kScanItems];
+  uint64_t local = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    const int64_t j = base + i;
+    x[i] = j < n ? in[j] : 0u;
+    local += x[i];
+  }
+  uint64_t inc = wave_incl_scan64(local);
+  if (lane == 63) s_w[wave] = inc;
+  __syncthreads();
+  uint64_t run = sums[blockIdx.x] + inc - local;
+  for (int w = 0; w < wave; w++) run += s_w[w];
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    const int64_t j = base + i;
+    if (j < n) out[j] = run;
+    run += x[i];
+  }
+  if (base <= n - 1 && n - 1 < base + kScanItems) out[n] = run;  // holder of the last element
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
+
+template <typename K>
+int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
+                    int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
+  int cur = 0;
+  if (max_count == 0) return cur;
+  for (int shift = begin_bit; shift < end_bit; shift += 8) {
+    k_upsweep<K><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
+    k_scan_hist<<<1, 1024, 0, st>>>(hist, kRadix * blocks);
+    k_scatter<K><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count, shift,
+                                                  blocks, hist);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+}  // namespace
+
+int sort_blocks_for(int64_t max_count) {
+  int64_t b = (max_count + 4 * kBatch - 1) / (4 * kBatch);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
+                   int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
+  return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st);
+}
+
+int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
+                   int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
+  return radix_sort_impl<uint32_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st);
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+void scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* tmp, hipStream_t st) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (n == 0) {
+    k_set_u64<<<1, 1, 0, st>>>(out, 0);
+    return;
+  }
+  k_scan_reduce<<<(unsigned)nb, kScanThreads, 0, st>>>(in, n, tmp);
+  k_scan_sums<<<1, 1024, 0, st>>>(tmp, (int)nb);
+  k_scan_final<<<(unsigned)nb, kScanThreads, 0, st>>>(in, n, tmp, out);
+}
+
+}  // namespace dass
