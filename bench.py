@@ -1,0 +1,262 @@
+#!/usr/bin/env python
+"""Benchmark of the streaming Gaussian-splatting hot path on one MI355X.
+
+One step = one optimisation iteration of the shift stage over every view of a timestep:
+  shift_apply (forward) -> render_fwd (all views, one launch sequence) -> L1 loss gradient and
+  error maps -> render_bwd (full parameter gradients + historical positional gradient) ->
+  shift_apply (adjoint) -> adam_step -> densify_append (children written into spare rows;
+  the live count is not advanced, so every step sees the same scene size).
+Inputs are synthetic and resident in device memory before timing starts.
+
+Prints one JSON line (rank 0).  `python bench.py` defaults to one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_FLOPS = 157.3e12   # MI355X fp32 vector, published
+PEAK_HBM_BPS = 8.0e12        # MI355X HBM3E, published
+# Algorithmic flops per (pixel, list entry) pair of the blend (counted from its definition):
+#   alpha test of an entry: pixel offset (2), quadratic form (8), exp (1), opacity scale, clamp,
+#   skip test (3) = 14; compositing a blended entry: transmittance update and stop test (3),
+#   weight (1), three colour multiply-adds (6) = 10.
+FWD_FLOPS_TEST, FWD_FLOPS_BLEND = 14, 10
+# Backward, per entry walked from the pixel's last blended entry: alpha recomputed (14); for a
+#   blended entry also transmittance recovery (2), colour gradient (4), alpha gradient (9),
+#   colour-behind update (12), exponent / opacity gradient (2), mean and conic gradients (17) = 46.
+BWD_FLOPS_TEST, BWD_FLOPS_BLEND = 14, 46
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(args):
+    import torch
+
+    import synth
+    from paper_2411_14847_amd import Context, GaussianBuffers, RenderOut
+
+    if args.workload == "multiview":
+        scene, cams, _ = synth.multiview_scene(args.seed, n=args.n, n_views=args.views, width=args.width,
+                                               height=args.height, with_grads=False)
+        name = f"multiview_{args.n // 1000}k_sh3_{args.views}x{args.width}x{args.height}"
+    else:
+        scene, cams, _ = synth.single_view_scene(args.seed)
+        name = "single_view_2k_sh0_128x128"
+    N = scene.n
+    cap = N + args.densify_k
+    g = GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh,
+                                    scene.sh_degree, capacity=cap)
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=args.max_keys or int(N * len(cams) * 24) + (1 << 20),
+                  max_tiles=tiles)
+    dev = "cuda"
+    # dynamic group and its ground-truth motion (10% of the base Gaussians)
+    motion = synth.timestep_motion(args.seed, 1, N)
+    dyn = torch.as_tensor(motion.dynamic, device=dev)
+    nd = int(dyn.numel())
+    # shifted copy: separate mean/quat planes, the other planes alias the scene's
+    gs = GaussianBuffers(torch.zeros_like(g.mean), torch.zeros_like(g.quat), g.log_scale, g.logit, g.sh, g.n,
+                         g.n_base, g.sh_degree)
+    # targets: the ground truth moved by its motion, rendered once
+    ctx.shift_fwd(g, gs, dyn, torch.as_tensor(motion.dpos, device=dev), torch.as_tensor(motion.dquat, device=dev))
+    targets = [o.rgb.clone() for o in ctx.render_fwd(gs, cams, args.bg)]
+    ctx.sync()
+    st = dict(
+        torch=torch, ctx=ctx, g=g, gs=gs, cams=cams, dyn=dyn, targets=targets, name=name, scene=scene,
+        outs=[RenderOut.allocate(c) for c in cams],
+        dls=[torch.zeros(3, c.height, c.width, device=dev) for c in cams],
+        errs=[torch.zeros(c.height, c.width, device=dev) for c in cams],
+        grads=g.zeros_like(), loss=torch.zeros(1, device=dev),
+        gn=torch.zeros(cap, device=dev), cnt=torch.zeros(cap, dtype=torch.int32, device=dev),
+        dpos=torch.zeros(3, nd, device=dev), drot=torch.cat([torch.ones(1, nd), torch.zeros(3, nd)]).to(dev),
+        d_dpos=torch.zeros(3, nd, device=dev), d_drot=torch.zeros(4, nd, device=dev),
+        m=[torch.zeros(3, nd, device=dev), torch.zeros(4, nd, device=dev)],
+        v=[torch.zeros(3, nd, device=dev), torch.zeros(4, nd, device=dev)],
+        n_app=torch.zeros(1, dtype=torch.int32, device=dev), nd=nd, N=N, cap=cap,
+    )
+    return st
+
+
+def train_step(s, it, args, per_view=False):
+    ctx, g, gs, cams = s["ctx"], s["g"], s["gs"], s["cams"]
+    ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
+    for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
+        t.zero_()
+    if not per_view:
+        ctx.render_fwd(gs, cams, args.bg, out=s["outs"])
+        ctx.l1_loss_grad(cams, [o.rgb for o in s["outs"]], s["targets"], s["dls"], s["errs"], s["loss"])
+        ctx.render_bwd(gs, cams, args.bg, s["outs"], s["dls"], s["grads"], s["gn"], s["cnt"])
+    else:
+        # plain per-view path: one render_fwd / loss / render_bwd per camera
+        V = len(cams)
+        for v in range(V):
+            ctx.render_fwd(gs, cams[v:v + 1], args.bg, out=s["outs"][v:v + 1])
+            ctx.l1_loss_grad(cams[v:v + 1], [s["outs"][v].rgb], s["targets"][v:v + 1], s["dls"][v:v + 1],
+                             s["errs"][v:v + 1], s["loss"])
+            s["dls"][v].mul_(1.0 / V)
+            ctx.render_bwd(gs, cams[v:v + 1], args.bg, s["outs"][v:v + 1], s["dls"][v:v + 1], s["grads"], s["gn"],
+                           s["cnt"])
+    ctx.shift_adjoint(g, s["dyn"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
+    ctx.adam_step([(s["dpos"], s["d_dpos"], s["m"][0], s["v"][0], args.lr_pos),
+                   (s["drot"], s["d_drot"], s["m"][1], s["v"][1], args.lr_rot)], step=it)
+    ctx.densify_append(g, s["errs"], cams, s["gn"], s["cnt"], 0.0, 0.0, 0.0, args.densify_k, it, s["n_app"])
+
+
+def time_steps(s, args, k, warm, per_view=False):
+    torch = s["torch"]
+    for i in range(warm):
+        train_step(s, i + 1, args, per_view)
+    torch.cuda.synchronize()
+    s["ctx"].sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(k):
+        train_step(s, warm + i + 1, args, per_view)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s["ctx"].sync()
+    return e0.elapsed_time(e1) / k, wall
+
+
+def render_latency(s, args, reps):
+    """Latency of one full-resolution novel-view render (view 0) on an idle GPU."""
+    torch = s["torch"]
+    ctx, gs, cam = s["ctx"], s["gs"], s["cams"][0]
+    out = s["outs"][0:1]
+    times = []
+    for _ in range(5):
+        ctx.render_fwd(gs, [cam], args.bg, out=out)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.render_fwd(gs, [cam], args.bg, out=out)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.percentile(times, 50)), float(np.percentile(times, 99))
+
+
+def cpu_baseline(s, args):
+    """The oracle (single-threaded float64 C) on a bounded sample: view 0 of the same scene,
+    forward + backward with a seeded upstream gradient; scaled to iterations of all views."""
+    import oracle
+    scene, cam = s["scene"], s["cams"][0]
+    rng = np.random.default_rng(args.seed + 7)
+    dl = rng.normal(0, 1, size=(3, cam.height, cam.width)).astype(np.float32)
+    oracle.lib()
+    t0 = time.perf_counter()
+    vr = oracle.render_view(scene, cam, bg=args.bg)
+    oracle.render_backward(scene, [cam], [dl], bg=args.bg, renders=[vr])
+    dt = time.perf_counter() - t0
+    per_iter = dt * len(s["cams"])
+    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"view 0 of {len(s['cams'])} ({cam.width}x{cam.height}, {scene.n} Gaussians), fwd+bwd, "
+                      f"{dt:.1f} s; value = 1 / ({len(s['cams'])} x that time)",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["multiview", "single"], default="multiview")
+    ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--views", type=int, default=20)
+    ap.add_argument("--width", type=int, default=1352)
+    ap.add_argument("--height", type=int, default=1014)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--densify-k", type=int, default=5000)
+    ap.add_argument("--max-keys", type=int, default=0)
+    ap.add_argument("--lr-pos", type=float, default=1e-3)
+    ap.add_argument("--lr-rot", type=float, default=1e-3)
+    ap.add_argument("--render-reps", type=int, default=100)
+    ap.add_argument("--per-view-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    args.bg = (0.0, 0.0, 0.0)
+    rank = int(os.environ.get("RANK", "0"))
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        if rank == 0:
+            print("bench.py measures one GPU only: this build has no multi-GPU path (views would shard "
+                  "across GPUs with one gradient all-reduce; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    log(f"[bench] building workload {args.workload}")
+    s = build_workload(args)
+    ctx = s["ctx"]
+    # pair counts of the blend (outside the timed region)
+    train_step(s, 1, args)
+    ctx.render_fwd(s["gs"], s["cams"], args.bg, out=s["outs"], count_pairs=True)
+    ctx.sync()
+    evaluated, blended = ctx.pair_counts()
+    walked = int(sum(int(o.n_contrib.sum().item()) for o in s["outs"]))
+    log(f"[bench] pairs evaluated {evaluated:.3e} blended {blended:.3e} walked-bwd {walked:.3e}")
+    # timed steps with live stage timers
+    log(f"[bench] warmup {args.warmup}, timing {args.steps} steps")
+    for i in range(args.warmup):
+        train_step(s, i + 2, args)
+    ctx.profile_begin(max_records=args.steps + 1)
+    ms, wall = time_steps(s, args, args.steps, 0)
+    stages = ctx.profile_end()
+    log(f"[bench] {ms:.2f} ms/step ({1000.0 / ms:.2f} iters/s), wall {wall:.2f}s")
+    per_stage = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    # dominant kernel roofline
+    fwd_flops = FWD_FLOPS_TEST * evaluated + FWD_FLOPS_BLEND * blended
+    bwd_flops = BWD_FLOPS_TEST * walked + BWD_FLOPS_BLEND * blended
+    cand = {"blend_bwd": bwd_flops, "blend_fwd": fwd_flops}
+    dom = max(cand, key=lambda k: per_stage.get(k, 0.0))
+    dom_ms = per_stage[dom]
+    achieved = cand[dom] / (dom_ms * 1e-3) / 1e12
+    roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_FLOPS / 1e12,
+            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": None,
+            "flops_per_launch": float(cand[dom]), "avg_launch_ms": round(dom_ms, 4)}
+    p50, p99 = render_latency(s, args, args.render_reps)
+    log(f"[bench] render p50 {p50:.3f} ms p99 {p99:.3f} ms")
+    pv_ms = None
+    if args.per_view_steps > 0:
+        pv_ms, _ = time_steps(s, args, args.per_view_steps, 1, per_view=True)
+        log(f"[bench] per-view loop {pv_ms:.2f} ms/step")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        cpu = cpu_baseline(s, args)
+        log(f"[bench] cpu baseline {cpu['value']:.3e} iters/s")
+    cams = s["cams"]
+    line = {
+        "metric": "fwd+bwd iters/s @200k Gaussians x 20 views 1352x1014; render p50/p99 ms",
+        "value": round(1000.0 / ms, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": s["name"], "n_gaussians": s["N"], "sh_degree": int(s["g"].sh_degree),
+                   "views": len(cams), "width": cams[0].width, "height": cams[0].height, "tile": "16x16",
+                   "n_dynamic": s["nd"], "densify_k": args.densify_k, "parallelism": "single GPU"},
+        "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
+        "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
+        "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
+        "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

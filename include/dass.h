@@ -97,9 +97,11 @@ typedef struct {
 } dass_grads;
 
 /* Render options.  tile_w x tile_h must be 16x16 in this build. */
+#define DASS_FLAG_COUNT_PAIRS 1u /* render_fwd also counts evaluated / blended (pixel, entry)
+                                    pairs (read with dass_debug_pair_counts); slower */
 typedef struct {
   int32_t tile_w, tile_h;
-  uint32_t flags; /* reserved, 0 */
+  uint32_t flags; /* DASS_FLAG_* bits */
 } dass_opts;
 
 /* Sizes the context reserves device memory for. */
@@ -222,7 +224,38 @@ dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_v
                               float* const* dl_drgb, float* const* err, float* loss,
                               dass_stream stream);
 
+/* ---- stage timers --------------------------------------------------------------------- */
+
+/* Stages timed with HIP events on the stream of each call while profiling is on. */
+typedef enum {
+  DASS_STAGE_PROJECT = 0,     /* per-Gaussian projection, all views                 */
+  DASS_STAGE_DEPTH_SORT = 1,  /* per-view depth order                                */
+  DASS_STAGE_BINNING = 2,     /* records into depth order, scan, tile-key emission   */
+  DASS_STAGE_KEY_SORT = 3,    /* stable sort of tile keys                            */
+  DASS_STAGE_RANGES = 4,      /* per-tile ranges                                     */
+  DASS_STAGE_BLEND_FWD = 5,   /* front-to-back blend                                 */
+  DASS_STAGE_BLEND_BWD = 6,   /* adjoint of the blend                                */
+  DASS_STAGE_PROJECT_BWD = 7, /* adjoint of the projection                           */
+  DASS_STAGE_SHIFT = 8,       /* shift_apply (either mode)                           */
+  DASS_STAGE_ADAM = 9,        /* adam_step                                           */
+  DASS_STAGE_L1 = 10,         /* dass_l1_loss_grad                                   */
+  DASS_STAGE_DENSIFY = 11,    /* densify_append                                      */
+  DASS_NUM_STAGES = 12
+} dass_stage;
+
+/* Starts recording: up to max_records intervals per stage (allocates the events). */
+dass_status dass_profile_begin(dass_ctx ctx, int32_t max_records);
+
+/* Stops recording, waits for the device, and writes per stage the summed duration in
+ * milliseconds and the number of intervals (host arrays of DASS_NUM_STAGES; either may be NULL). */
+dass_status dass_profile_end(dass_ctx ctx, double* total_ms, int32_t* records);
+
 /* ---- debug exports (synchronise; for parity tests) ------------------------------------- */
+
+/* Pair counts of the last render_fwd run with DASS_FLAG_COUNT_PAIRS: evaluated = (pixel, list
+ * entry) pairs whose alpha was computed, blended = pairs composited (host outputs). */
+dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* blended);
+
 
 /* Sorted tile keys of view `view` of the last render_fwd: copies up to `max` keys
  * ((tile << 32) | float32 depth bits, tile = ty*tiles_x + tx) and values (Gaussian index) into

@@ -16,7 +16,10 @@ MAX_VIEWS = 32
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
            "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
-           "dass_debug_projection")
+           "dass_debug_projection", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts")
+FLAG_COUNT_PAIRS = 1
+STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
+          "shift", "adam", "l1", "densify")
 
 
 class Gaussians(C.Structure):
@@ -87,6 +90,9 @@ def lib():
             "dass_l1_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), P(vp), P(vp), vp, vp]),
             "dass_debug_keys": (i32, [vp, i32, vp, vp, i64, vp, P(i64)]),
             "dass_debug_projection": (i32, [vp, P(Gaussians), P(Camera), vp]),
+            "dass_profile_begin": (i32, [vp, i32]),
+            "dass_profile_end": (i32, [vp, P(C.c_double), P(i32)]),
+            "dass_debug_pair_counts": (i32, [vp, P(u64), P(u64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

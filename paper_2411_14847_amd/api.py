@@ -174,12 +174,13 @@ class Context:
         self._check(self._lib.dass_sync(self._h, _stream(stream)))
 
     # ---- hot path --------------------------------------------------------------------------
-    def render_fwd(self, g: GaussianBuffers, cams: Sequence, bg=(0.0, 0.0, 0.0), out=None, stream=None):
+    def render_fwd(self, g: GaussianBuffers, cams: Sequence, bg=(0.0, 0.0, 0.0), out=None, stream=None,
+                   count_pairs: bool = False):
         out = out if out is not None else [RenderOut.allocate(c, g.mean.device) for c in cams]
         imgs = (F.Image * len(cams))(*[o.struct() for o in out])
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
-        opts = F.Opts(16, 16, 0)
+        opts = F.Opts(16, 16, F.FLAG_COUNT_PAIRS if count_pairs else 0)
         self._check(self._lib.render_fwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs,
                                          C.byref(opts), _stream(stream)))
         return out
@@ -236,7 +237,22 @@ class Context:
                                              _ptr(count), float(gamma_err), float(tau_pos), float(tau_err),
                                              int(k_max), int(seed), _ptr(n_appended), _stream(stream)))
 
+    # ---- stage timers ----------------------------------------------------------------------
+    def profile_begin(self, max_records: int = 256):
+        self._check(self._lib.dass_profile_begin(self._h, int(max_records)))
+
+    def profile_end(self) -> dict:
+        ms = (C.c_double * len(F.STAGES))()
+        rec = (C.c_int32 * len(F.STAGES))()
+        self._check(self._lib.dass_profile_end(self._h, ms, rec))
+        return {name: (ms[i], rec[i]) for i, name in enumerate(F.STAGES)}
+
     # ---- debug -----------------------------------------------------------------------------
+    def pair_counts(self):
+        ev, bl = C.c_uint64(), C.c_uint64()
+        self._check(self._lib.dass_debug_pair_counts(self._h, C.byref(ev), C.byref(bl)))
+        return ev.value, bl.value
+
     def debug_keys(self, view: int, max_keys: int, n_tiles: int, device="cuda"):
         keys = torch.empty(max(max_keys, 1), dtype=torch.int64, device=device)
         vals = torch.empty(max(max_keys, 1), dtype=torch.int32, device=device)

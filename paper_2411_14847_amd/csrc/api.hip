@@ -17,8 +17,16 @@ int l1_per_block();
 
 using namespace dass;
 
+struct Profiler {
+  bool on = false;
+  int max = 0;
+  std::vector<hipEvent_t> ev[DASS_NUM_STAGES];  // 2 per record (start, end)
+  int used[DASS_NUM_STAGES] = {};
+};
+
 struct dass_ctx_s {
   int device = 0;
+  Profiler prof;
   dass_limits lim{};
   Workspace ws;
   std::vector<void*> allocs;
@@ -50,6 +58,30 @@ dass_status fail(dass_ctx ctx, dass_status st, const char* fmt, ...) {
     hipError_t _e = (expr);                                                                  \
     if (_e != hipSuccess) return fail(ctx, DASS_E_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
   } while (0)
+
+// Records the start / end of a stage interval on `st` while profiling is on.
+void stage_begin(dass_ctx ctx, int stage, hipStream_t st) {
+  Profiler& p = ctx->prof;
+  if (!p.on || p.used[stage] >= p.max) return;
+  (void)hipEventRecord(p.ev[stage][2 * p.used[stage]], st);
+}
+void stage_end(dass_ctx ctx, int stage, hipStream_t st) {
+  Profiler& p = ctx->prof;
+  if (!p.on || p.used[stage] >= p.max) return;
+  (void)hipEventRecord(p.ev[stage][2 * p.used[stage] + 1], st);
+  p.used[stage]++;
+}
+
+void profile_free(dass_ctx ctx) {
+  Profiler& p = ctx->prof;
+  for (int s = 0; s < DASS_NUM_STAGES; s++) {
+    for (hipEvent_t e : p.ev[s]) (void)hipEventDestroy(e);
+    p.ev[s].clear();
+    p.used[s] = 0;
+  }
+  p.on = false;
+  p.max = 0;
+}
 
 dass_status check_launch(dass_ctx ctx, const char* what) {
   hipError_t e = hipGetLastError();
@@ -129,11 +161,13 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.hist, 256 * 1024);
   ALLOC(w.scan_tmp, scan_tmp_elems(vn));
   ALLOC(w.counters, 16);
+  ALLOC(w.pairs, 2);
   ALLOC(w.err, 1);
 #undef ALLOC
   w.gid_s = w.dval[0];
   HIP_TRY(ctx, hipMemset(w.counters, 0, 16 * sizeof(uint32_t)));
   HIP_TRY(ctx, hipMemset(w.err, 0, sizeof(uint32_t)));
+  HIP_TRY(ctx, hipMemset(w.pairs, 0, 2 * sizeof(unsigned long long)));
   HIP_TRY(ctx, hipDeviceSynchronize());
   ctx->lim = l;
   ctx->have_fwd = false;
@@ -188,6 +222,7 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, CamsK& out,
 dass_status check_opts(dass_ctx ctx, const dass_opts* o) {
   if (o && (o->tile_w != kTile || o->tile_h != kTile))
     return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (16x16 only)", o->tile_w, o->tile_h);
+  if (o && (o->flags & ~DASS_FLAG_COUNT_PAIRS)) return fail(ctx, DASS_E_INVALID, "unknown option flags");
   return DASS_OK;
 }
 
@@ -262,6 +297,7 @@ void dass_destroy(dass_ctx ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  profile_free(ctx);
   free_all(ctx);
   delete ctx;
 }
@@ -313,22 +349,36 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   Workspace& ws = ctx->ws;
   const SceneK sc = scene_of(g);
   const int64_t vn = (int64_t)n_views * g->n;
+  const bool count_pairs = opts && (opts->flags & DASS_FLAG_COUNT_PAIRS);
   // 1. projection
+  stage_begin(ctx, DASS_STAGE_PROJECT, st);
   launch_preprocess(sc, ck, n_views, ws, st);
+  stage_end(ctx, DASS_STAGE_PROJECT, st);
   // 2. per-view depth order: sort (view << 32 | depth bits, index)
+  stage_begin(ctx, DASS_STAGE_DEPTH_SORT, st);
   launch_fill_u32(ws.counters + 2, (uint32_t)vn, 1, st);
   const int dcur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 2, vn, 0, 32 + bit_width((uint64_t)(n_views - 1)),
                                   ws.hist, sort_blocks_for(vn), st);
   ws.gid_s = ws.dval[dcur];
+  stage_end(ctx, DASS_STAGE_DEPTH_SORT, st);
   // 3. records into depth order; tile keys in that order; stable sort on the tile id
+  stage_begin(ctx, DASS_STAGE_BINNING, st);
   launch_gather_sorted(g->n, vn, ws.gid_s, ws, st);
   launch_emit_keys(g->n, vn, ck, ws, st);
+  stage_end(ctx, DASS_STAGE_BINNING, st);
+  stage_begin(ctx, DASS_STAGE_KEY_SORT, st);
   const int kcur = radix_sort_u32(ws.keys, ws.vals, ws.counters, ws.cap_keys, 0,
                                   bit_width((uint64_t)(total_tiles > 0 ? total_tiles - 1 : 0)), ws.hist,
                                   sort_blocks_for(ws.cap_keys), st);
+  stage_end(ctx, DASS_STAGE_KEY_SORT, st);
+  stage_begin(ctx, DASS_STAGE_RANGES, st);
   launch_ranges(ws.keys[kcur], total_tiles, ws, st);
+  stage_end(ctx, DASS_STAGE_RANGES, st);
   // 4. blend
-  launch_blend_fwd(io, n_views, total_tiles, bg, ws, ws.vals[kcur], st);
+  if (count_pairs) launch_fill_u32(reinterpret_cast<uint32_t*>(ws.pairs), 0u, 4, st);
+  stage_begin(ctx, DASS_STAGE_BLEND_FWD, st);
+  launch_blend_fwd(io, n_views, total_tiles, bg, ws, ws.vals[kcur], count_pairs, st);
+  stage_end(ctx, DASS_STAGE_BLEND_FWD, st);
   if ((s = check_launch(ctx, "render_fwd")) != DASS_OK) return s;
   ctx->have_fwd = true;
   ctx->fwd_n = g->n;
@@ -373,8 +423,12 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   Workspace& ws = ctx->ws;
   const int64_t vn = (int64_t)n_views * g->n;
   launch_fill_u32(reinterpret_cast<uint32_t*>(ws.g2d), 0u, vn * 9, st);
+  stage_begin(ctx, DASS_STAGE_BLEND_BWD, st);
   launch_blend_bwd(io, n_views, total_tiles, bg, ws, ws.vals[ctx->fwd_key_buf], st);
+  stage_end(ctx, DASS_STAGE_BLEND_BWD, st);
+  stage_begin(ctx, DASS_STAGE_PROJECT_BWD, st);
   launch_preprocess_bwd(scene_of(g), ck, n_views, ws, *grads, gradnorm_sum, grad_count, st);
+  stage_end(ctx, DASS_STAGE_PROJECT_BWD, st);
   return check_launch(ctx, "render_bwd");
 }
 
@@ -394,12 +448,16 @@ dass_status shift_apply(dass_ctx ctx, int32_t mode, const int32_t* dyn_idx, int3
     if (out->capacity != in->capacity) return fail(ctx, DASS_E_INVALID, "out and in capacities differ");
     if (out->mean == in->mean || out->quat == in->quat) return fail(ctx, DASS_E_INVALID, "out may not alias in");
     if (n_dyn > 0 && !dpos) return fail(ctx, DASS_E_INVALID, "dpos is NULL");
+    stage_begin(ctx, DASS_STAGE_SHIFT, st);
     launch_shift_fwd(sc, out->mean, out->quat, dyn_idx, n_dyn, dpos, drot, st);
+    stage_end(ctx, DASS_STAGE_SHIFT, st);
   } else if (mode == DASS_ADJOINT) {
     if (!d_out) return fail(ctx, DASS_E_INVALID, "d_out is NULL");
     if (n_dyn > 0 && ((d_out->mean && !d_dpos) || (d_out->quat && !d_drot)))
       return fail(ctx, DASS_E_INVALID, "d_dpos or d_drot is NULL");
+    stage_begin(ctx, DASS_STAGE_SHIFT, st);
     launch_shift_adj(sc, d_out->mean, d_out->quat, dyn_idx, n_dyn, drot, d_dpos, d_drot, st);
+    stage_end(ctx, DASS_STAGE_SHIFT, st);
   } else {
     return fail(ctx, DASS_E_INVALID, "mode must be DASS_FWD or DASS_ADJOINT");
   }
@@ -420,6 +478,7 @@ dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_gro
   const int per = adam_per_block();
   const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
   const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  stage_begin(ctx, DASS_STAGE_ADAM, st);
   for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
     AdamArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -446,6 +505,7 @@ dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_gro
     a.n_groups = k;
     if (k > 0) launch_adam(a, blocks, st);
   }
+  stage_end(ctx, DASS_STAGE_ADAM, st);
   return check_launch(ctx, "adam_step");
 }
 
@@ -473,7 +533,9 @@ dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_v
     blocks += (a.v[v].hw + per - 1) / per;
   }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  stage_begin(ctx, DASS_STAGE_L1, (hipStream_t)stream);
   launch_l1(a, blocks, loss, (hipStream_t)stream);
+  stage_end(ctx, DASS_STAGE_L1, (hipStream_t)stream);
   return check_launch(ctx, "dass_l1_loss_grad");
 }
 
@@ -514,6 +576,7 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
   hipStream_t st = (hipStream_t)stream;
   Workspace& ws = ctx->ws;
   const SceneK sc = scene_of(g);
+  stage_begin(ctx, DASS_STAGE_DENSIFY, st);
   launch_fill_u32(ws.counters + 1, 0u, 1, st);
   launch_densify_select(sc, a, gradnorm_sum, grad_count, g->n_base, ws.dkey[0], ws.dval[0], ws.counters + 1, st);
   const int cur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 1, g->n_base, 0, 64, ws.hist,
@@ -521,6 +584,7 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
   const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
   launch_densify_spawn(g->mean, g->quat, g->log_scale, g->opacity_logit, g->sh, 3 * K, g->capacity, g->n,
                        g->capacity, ws.dkey[cur], ws.counters + 1, k_max, seed, n_appended, st);
+  stage_end(ctx, DASS_STAGE_DENSIFY, st);
   ctx->have_fwd = false;  // the depth-order buffers were reused
   return check_launch(ctx, "densify_append");
 }
@@ -568,6 +632,50 @@ dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const d
   launch_debug_projection(scene_of(g), ck, 0, out, nullptr);
   HIP_TRY(ctx, hipDeviceSynchronize());
   return check_launch(ctx, "dass_debug_projection");
+}
+
+dass_status dass_profile_begin(dass_ctx ctx, int32_t max_records) {
+  if (!ctx || max_records < 1) return DASS_E_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  profile_free(ctx);
+  Profiler& p = ctx->prof;
+  for (int s = 0; s < DASS_NUM_STAGES; s++) {
+    p.ev[s].resize(2 * (size_t)max_records);
+    for (auto& e : p.ev[s]) HIP_TRY(ctx, hipEventCreate(&e));
+  }
+  p.max = max_records;
+  p.on = true;
+  return DASS_OK;
+}
+
+dass_status dass_profile_end(dass_ctx ctx, double* total_ms, int32_t* records) {
+  if (!ctx) return DASS_E_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  Profiler& p = ctx->prof;
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  for (int s = 0; s < DASS_NUM_STAGES; s++) {
+    double acc = 0.0;
+    for (int i = 0; i < p.used[s]; i++) {
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, p.ev[s][2 * i], p.ev[s][2 * i + 1]));
+      acc += ms;
+    }
+    if (total_ms) total_ms[s] = acc;
+    if (records) records[s] = p.used[s];
+  }
+  profile_free(ctx);
+  return DASS_OK;
+}
+
+dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* blended) {
+  if (!ctx || !evaluated || !blended) return DASS_E_INVALID;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipDeviceSynchronize());
+  unsigned long long h[2];
+  HIP_TRY(ctx, hipMemcpy(h, ctx->ws.pairs, sizeof(h), hipMemcpyDeviceToHost));
+  *evaluated = h[0];
+  *blended = h[1];
+  return DASS_OK;
 }
 
 }  // extern "C"

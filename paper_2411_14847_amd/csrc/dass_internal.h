@@ -93,7 +93,8 @@ struct Workspace {
   // scratch
   uint32_t* hist = nullptr;        // sort histograms
   uint64_t* scan_tmp = nullptr;    // scan block sums
-  uint32_t* counters = nullptr;    // [0] = key count (clamped), [1] = densify |S|, ...
+  uint32_t* counters = nullptr;    // [0] = key count (clamped), [1] = densify |S|, [2] = depth-sort count
+  unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
   uint32_t* err = nullptr;         // device error bits
 };
 
@@ -123,7 +124,7 @@ void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspa
 void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipStream_t st);
 void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
-                      const Workspace& ws, const uint32_t* vals, hipStream_t st);
+                      const Workspace& ws, const uint32_t* vals, bool count_pairs, hipStream_t st);
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -90,10 +90,12 @@ __device__ __forceinline__ int view_of(const ViewsIO& io, int nv, int b) {
   return v;
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
                                                         float bg1, float bg2, const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ vals,
-                                                        const Rec* __restrict__ rec_s) {
+                                                        const Rec* __restrict__ rec_s,
+                                                        unsigned long long* __restrict__ pairs) {
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];
   __shared__ float4 s_rgb[kBatchB];
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int 
   float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
   int last = 0;
   bool done = !inside;
+  uint32_t n_eval = 0, n_blend = 0;
   for (uint32_t start = r.x; start < r.y; start += kBatchB) {
     const int n_in = (int)min((uint32_t)kBatchB, r.y - start);
     if (tid < n_in) {
@@ -130,6 +133,7 @@ __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int 
         const float4 co = s_co[j];
         const float dx = xy.x - flx, dy = xy.y - fly;
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
+        if (COUNT) n_eval++;
         if (pw > 0.f) continue;
         const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
         if (a < kAlphaMin) continue;
@@ -138,6 +142,7 @@ __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int 
           done = true;
           break;
         }
+        if (COUNT) n_blend++;
         const float4 c = s_rgb[j];
         const float w = a * T;
         c0 += c.x * w;
@@ -157,6 +162,10 @@ __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int 
     V.rgb[2 * hw + pix] = c2 + T * bg2;
     V.t_final[pix] = T;
     V.n_contrib[pix] = last;
+  }
+  if (COUNT) {
+    atomicAdd(&pairs[0], (unsigned long long)n_eval);
+    atomicAdd(&pairs[1], (unsigned long long)n_blend);
   }
 }
 
@@ -324,11 +333,15 @@ void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hip
 static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNumXcd - 1) / kNumXcd); }
 
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
-                      const uint32_t* vals, hipStream_t st) {
+                      const uint32_t* vals, bool count_pairs, hipStream_t st) {
   if (total_tiles == 0) return;
   const int per = per_xcd(total_tiles);
-  k_blend_fwd<<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_s);
+  if (count_pairs)
+    k_blend_fwd<true><<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+                                                           ws.ranges, vals, ws.rec_s, ws.pairs);
+  else
+    k_blend_fwd<false><<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+                                                            ws.ranges, vals, ws.rec_s, nullptr);
 }
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
