@@ -249,14 +249,30 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
 // conic inverse, the EWA projection, the pixel mean, the colour and the opacity; quantities
 // linear in the view (dSigma, dlogit) are summed over views first and chained once.
 // ---------------------------------------------------------------------------------------------
+constexpr int kBwdSplit = 4;  // lanes per Gaussian in the adjoint (views split round-robin)
+
+__device__ __forceinline__ double quad_sum(double x) {
+  x += __shfl_xor(x, 1, 64);
+  x += __shfl_xor(x, 2, 64);
+  return x;
+}
+__device__ __forceinline__ float quad_sumf(float x) {
+  x += __shfl_xor(x, 1, 64);
+  x += __shfl_xor(x, 2, 64);
+  return x;
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, int nv,
                                                         const uint32_t* __restrict__ inv,
                                                         const float* __restrict__ g2d, dass_grads gr,
                                                         float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= sc.n) return;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g_raw = tid / kBwdSplit, r = tid % kBwdSplit;
+  // every lane of a quad stays to the end (the quad shuffles need all four)
+  const bool live = g_raw < sc.n;
+  const int g = live ? g_raw : sc.n - 1;
   GaussD G;
   load_gaussian(sc, g, G);
   float shc[3 * K];
@@ -269,7 +285,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
   double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double dop = 0.0, gnorm = 0.0;
   int cnt = 0;
-  for (int v = 0; v < nv; v++) {
+  for (int v = r; v < nv && live; v += kBwdSplit) {
     const CamK& cam = cams.c[v];
     ViewD V;
     project_view(G, cam, V);
@@ -357,7 +373,16 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
     dt[2] -= (du * fx * tx + dv * fy * ty) / tz2;
     for (int i = 0; i < 3; i++) dmu[i] += W[i] * dt[0] + W[3 + i] * dt[1] + W[6 + i] * dt[2];
   }
-  if (cnt == 0) return;
+  // combine the four lanes of this Gaussian
+  for (int i = 0; i < 3; i++) dmu[i] = quad_sum(dmu[i]);
+  for (int i = 0; i < 6; i++) dSig[i] = quad_sum(dSig[i]);
+  dop = quad_sum(dop);
+  gnorm = quad_sum(gnorm);
+  cnt += __shfl_xor(cnt, 1, 64);
+  cnt += __shfl_xor(cnt, 2, 64);
+#pragma unroll
+  for (int k = 0; k < 3 * K; k++) dsh[k] = quad_sumf(dsh[k]);
+  if (!live || r != 0 || cnt == 0) return;
   // Sigma = M M^T -> dM = 2 dSigma M (dSigma symmetric)
   const double* M = G.M;
   const double dS[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
@@ -435,7 +460,8 @@ void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws
 void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Workspace& ws, const dass_grads& grads,
                            float* gradnorm, int32_t* gcount, hipStream_t st) {
   if (s.n == 0) return;
-  dim3 grid((s.n + 255) / 256), block(256);
+  const int64_t threads = (int64_t)s.n * kBwdSplit;
+  dim3 grid((unsigned)((threads + 255) / 256)), block(256);
   switch (s.deg) {
     case 0: k_preprocess_bwd<0><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
     case 1: k_preprocess_bwd<1><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;

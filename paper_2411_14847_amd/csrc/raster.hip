@@ -17,7 +17,7 @@
 namespace dass {
 namespace {
 
-constexpr int kBatchB = 256;
+constexpr int kBatchB = 128;  // list entries staged in LDS per batch
 constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ __forceinline__ int xcd_logical(int bid, int per) {
@@ -46,26 +46,45 @@ __global__ __launch_bounds__(256) void k_gather_sorted(int n, int64_t vn, const 
   inv[i] = (uint32_t)p;
 }
 
+// Each wave takes 64 consecutive sorted positions and writes their keys one Gaussian at a time
+// with all 64 lanes, so consecutive lanes write consecutive keys.
 __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams, const uint32_t* __restrict__ tt_s,
                                                    const uint2* __restrict__ rect_s, const uint64_t* __restrict__ off,
                                                    int64_t cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ err) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= vn) return;
-  const uint32_t tt = tt_s[p];
-  if (tt == 0) return;
-  const int v = (int)(p / n);
-  const CamK& c = cams.c[v];
-  const uint2 r = rect_s[p];
-  const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
-  uint64_t k = off[p];
-  if (k + tt > (uint64_t)cap) atomicOr(err, kErrKeyOverflow);
-  for (int ty = y0; ty < y1; ty++)
-    for (int tx = x0; tx < x1; tx++, k++)
+  const int lane = threadIdx.x & 63;
+  const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first position of this wave
+  const int64_t pm = p0 + lane;
+  uint32_t my_tt = 0;
+  uint2 my_r = make_uint2(0, 0);
+  uint64_t my_off = 0;
+  if (pm < vn) {
+    my_tt = tt_s[pm];
+    my_r = rect_s[pm];
+    my_off = off[pm];
+    if (my_off + my_tt > (uint64_t)cap) atomicOr(err, kErrKeyOverflow);
+  }
+  uint64_t pending = __ballot(my_tt > 0);
+  while (pending) {
+    const int src = __ffsll((unsigned long long)pending) - 1;
+    pending &= pending - 1;
+    const uint32_t tt = __shfl(my_tt, src, 64);
+    const uint32_t rx = __shfl(my_r.x, src, 64), ry = __shfl(my_r.y, src, 64);
+    const uint64_t base = __shfl(my_off, src, 64);
+    const int64_t p = p0 + src;
+    const int v = (int)(p / n);
+    const int x0 = rx & 0xFFFF, y0 = rx >> 16, x1 = ry & 0xFFFF;
+    const int w = x1 - x0;
+    const int tile0 = cams.c[v].tile_base, TX = cams.c[v].TX;
+    for (uint32_t i = lane; i < tt; i += 64) {
+      const uint64_t k = base + i;
       if (k < (uint64_t)cap) {
-        keys[k] = (uint32_t)(c.tile_base + ty * c.TX + tx);
+        const int ty = y0 + (int)(i / (uint32_t)w), tx = x0 + (int)(i % (uint32_t)w);
+        keys[k] = (uint32_t)(tile0 + ty * TX + tx);
         vals[k] = (uint32_t)p;
       }
+    }
+  }
 }
 
 __global__ void k_clamp_count(const uint64_t* __restrict__ total, int64_t cap, uint32_t* __restrict__ count) {
@@ -90,78 +109,187 @@ __device__ __forceinline__ int view_of(const ViewsIO& io, int nv, int b) {
   return v;
 }
 
+// ---- blend ------------------------------------------------------------------------------------
+// One wave per 16x16 tile; lane (qx, qy) of the 8x8 lane grid owns the 2x2 pixel block at
+// (2qx, 2qy).  Batches of up to 256 list entries are loaded by the wave, culled against the
+// tile and compacted into LDS in list order.  The cull drops an entry only if the minimum of its
+// quadratic form over the tile's pixel rectangle exceeds the alpha >= 1/255 level by a margin,
+// i.e. when every pixel of the tile would skip it anyway; the list position of every kept entry
+// is carried along, so n_contrib still counts positions in the full list.
+constexpr int kLanes = 64;
+constexpr int kCullPad = 0;
+
+__device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// true if the entry cannot reach alpha >= 1/255 at any pixel centre of [0,15]^2 (tile-relative)
+__device__ __forceinline__ bool cull_entry(float mx, float my, float A, float B, float C, float o) {
+  if (!(o * 255.0f > 0.999f)) return true;  // alpha <= o < 1/255 everywhere (with margin)
+  const float thr = 2.0f * __logf(255.0f * o);  // q <= thr  <=>  o exp(-q/2) >= 1/255
+  const float lo = 0.0f, hi = (float)(kTile - 1);
+  if (mx >= lo && mx <= hi && my >= lo && my <= hi) return false;
+  float qmin = 3.0e38f;
+  // vertical edges x = lo, hi
+#pragma unroll
+  for (int e = 0; e < 2; e++) {
+    const float dx = (e ? hi : lo) - mx;
+    float dy = C > 0.f ? -B * dx / C : 0.f;
+    dy = fminf(fmaxf(dy, lo - my), hi - my);
+    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
+  }
+#pragma unroll
+  for (int e = 0; e < 2; e++) {
+    const float dy = (e ? hi : lo) - my;
+    float dx = A > 0.f ? -B * dy / A : 0.f;
+    dx = fminf(fmaxf(dx, lo - mx), hi - mx);
+    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
+  }
+  return qmin > thr * 1.001f + 1e-3f;
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// One halving step of the transposed reduction: lanes with the step's bit clear keep slots
+// [0, H), lanes with it set keep slots [H, 2H) (slots >= N are zero); each adds its partner's copy.
+template <int N, int H, int CTRL>
+__device__ __forceinline__ void tstep(float* v, bool upper) {
+  float out[H];
+#pragma unroll
+  for (int k = 0; k < H; k++) {
+    const float hiv = (H + k < N) ? v[H + k] : 0.f;
+    const float keep = upper ? hiv : v[k];
+    const float send = upper ? v[k] : hiv;
+    out[k] = keep + dppf<CTRL>(send);
+  }
+#pragma unroll
+  for (int k = 0; k < H; k++) v[k] = out[k];
+}
+
+// Sums 9 per-lane values over the wave.  Afterwards lane l (l < 16) holds the total of value
+// kRedSlot[l] (-1: none); lanes l + 16, l + 32, l + 48 hold the same total.
+__device__ __forceinline__ float wave_reduce9(float* v, int lane) {
+  tstep<9, 5, 0xB1>(v, lane & 1);         // xor 1 (quad_perm 1,0,3,2)
+  tstep<5, 3, 0x4E>(v, (lane >> 1) & 1);  // xor 2 (quad_perm 2,3,0,1)
+  tstep<3, 2, 0x128>(v, (lane >> 3) & 1); // xor 8 (row_ror 8)
+  {                                       // xor 4 (row_shl 4 / row_shr 4)
+    const bool up = (lane >> 2) & 1;
+    const float keep = up ? v[1] : v[0];
+    const float send = up ? v[0] : v[1];
+    const float a = dppf<0x104>(send), b = dppf<0x114>(send);
+    v[0] = keep + (up ? b : a);
+  }
+  float x = v[0];
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+// value index held by lanes 0..15 after wave_reduce9 (bits 0,1,3,2 halve 9 -> 5 -> 3 -> 2 -> 1)
+__constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, -1, -1};
+
 template <bool COUNT>
-__global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
-                                                        float bg1, float bg2, const uint2* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ vals,
-                                                        const Rec* __restrict__ rec_s,
-                                                        unsigned long long* __restrict__ pairs) {
+__global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
+                                                      float bg1, float bg2, const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
+                                                      unsigned long long* __restrict__ pairs) {
   __shared__ float2 s_xy[kBatchB];
-  __shared__ float4 s_co[kBatchB];
-  __shared__ float4 s_rgb[kBatchB];
+  __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
+  __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
   const int b = xcd_logical(blockIdx.x, per);
   if (b >= total_tiles) return;
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
-  const int px = tx * kTile + lx, py = ty * kTile + ly;
-  const bool inside = px < V.W && py < V.H;
+  const int lane = threadIdx.x;
+  const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
   const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
-  const float flx = (float)lx, fly = (float)ly;
+  const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
-  float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-  int last = 0;
-  bool done = !inside;
+  float T[4], c0[4], c1[4], c2[4];
+  int last[4];
+  bool done[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    T[k] = 1.f;
+    c0[k] = c1[k] = c2[k] = 0.f;
+    last[k] = 0;
+    done[k] = !(px < V.W && py < V.H);
+  }
   uint32_t n_eval = 0, n_blend = 0;
   for (uint32_t start = r.x; start < r.y; start += kBatchB) {
     const int n_in = (int)min((uint32_t)kBatchB, r.y - start);
-    if (tid < n_in) {
-      const uint32_t p = vals[start + tid];
-      const Rec R = rec_s[p];
-      s_xy[tid] = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
-      s_co[tid] = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
-      s_rgb[tid] = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.f);
+    int n_kept = 0;
+#pragma unroll
+    for (int k = 0; k < kBatchB / kLanes; k++) {
+      const int e = k * kLanes + lane;
+      bool keep = false;
+      float2 xy;
+      float4 co, rgb;
+      if (e < n_in) {
+        const Rec R = rec_s[vals[start + e]];
+        xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
+        keep = !cull_entry(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
+        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((int)(start - r.x) + e));
+      }
+      const uint64_t m = __ballot(keep);
+      if (keep) {
+        const int pos = n_kept + __popcll(m & lt);
+        s_xy[pos] = xy;
+        s_co[pos] = co;
+        s_rgb[pos] = rgb;
+      }
+      n_kept += __popcll(m);
     }
     __syncthreads();
-    if (!done) {
-      const int base = (int)(start - r.x);
-      for (int j = 0; j < n_in; j++) {
-        const float2 xy = s_xy[j];
-        const float4 co = s_co[j];
-        const float dx = xy.x - flx, dy = xy.y - fly;
+    for (int j = 0; j < n_kept; j++) {
+      const float2 xy = s_xy[j];
+      const float4 co = s_co[j];
+      const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
+      const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (done[k]) continue;
+        const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
         if (COUNT) n_eval++;
         if (pw > 0.f) continue;
         const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
         if (a < kAlphaMin) continue;
-        const float Tn = T * (1.f - a);
+        const float Tn = T[k] * (1.f - a);
         if (Tn < kTStop) {
-          done = true;
-          break;
+          done[k] = true;
+          continue;
         }
         if (COUNT) n_blend++;
         const float4 c = s_rgb[j];
-        const float w = a * T;
-        c0 += c.x * w;
-        c1 += c.y * w;
-        c2 += c.z * w;
-        T = Tn;
-        last = base + j + 1;
+        const float w = a * T[k];
+        c0[k] += c.x * w;
+        c1[k] += c.y * w;
+        c2[k] += c.z * w;
+        T[k] = Tn;
+        last[k] = __float_as_int(c.w) + 1;
       }
     }
-    if (__syncthreads_count(done) == kTilePix) break;
+    const bool alive = !(done[0] && done[1] && done[2] && done[3]);
+    if (__ballot(alive) == 0) break;
+    __syncthreads();
   }
-  if (inside) {
-    const int64_t hw = (int64_t)V.W * V.H;
-    const int64_t pix = (int64_t)py * V.W + px;
-    V.rgb[pix] = c0 + T * bg0;
-    V.rgb[hw + pix] = c1 + T * bg1;
-    V.rgb[2 * hw + pix] = c2 + T * bg2;
-    V.t_final[pix] = T;
-    V.n_contrib[pix] = last;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    if (px < V.W && py < V.H) {
+      const int64_t hw = (int64_t)V.W * V.H;
+      const int64_t pix = (int64_t)py * V.W + px;
+      V.rgb[pix] = c0[k] + T[k] * bg0;
+      V.rgb[hw + pix] = c1[k] + T[k] * bg1;
+      V.rgb[2 * hw + pix] = c2[k] + T[k] * bg2;
+      V.t_final[pix] = T[k];
+      V.n_contrib[pix] = last[k];
+    }
   }
   if (COUNT) {
     atomicAdd(&pairs[0], (unsigned long long)n_eval);
@@ -169,110 +297,129 @@ __global__ __launch_bounds__(kTilePix) void k_blend_fwd(ViewsIO io, int nv, int 
   }
 }
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-
-__global__ __launch_bounds__(kTilePix) void k_blend_bwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
-                                                        float bg1, float bg2, const uint2* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ vals,
-                                                        const Rec* __restrict__ rec_s, float* __restrict__ g2d) {
+__global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
+                                                      float bg1, float bg2, const uint2* __restrict__ ranges,
+                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
+                                                      float* __restrict__ g2d) {
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
-  __shared__ float4 s_cn[kBatchB];   // conic A, B, C
-  __shared__ float4 s_rgb[kBatchB];
+  __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
   __shared__ uint32_t s_p[kBatchB];
-  __shared__ int s_max;
   const int b = xcd_logical(blockIdx.x, per);
   if (b >= total_tiles) return;
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
-  const int px = tx * kTile + lx, py = ty * kTile + ly;
-  const bool inside = px < V.W && py < V.H;
+  const int lane = threadIdx.x;
+  const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
   const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
-  const float flx = (float)lx, fly = (float)ly;
+  const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const int64_t hw = (int64_t)V.W * V.H;
-  const int64_t pix = (int64_t)py * V.W + px;
-  float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
-  int last = 0;
-  if (inside) {
-    T = V.t_final[pix];
-    last = V.n_contrib[pix];
-    dC0 = V.dl[pix];
-    dC1 = V.dl[hw + pix];
-    dC2 = V.dl[2 * hw + pix];
+  float T[4], dC0[4], dC1[4], dC2[4], B0[4], B1[4], B2[4];
+  int last[4];
+  int my_max = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    T[k] = 1.f;
+    dC0[k] = dC1[k] = dC2[k] = 0.f;
+    last[k] = 0;
+    B0[k] = bg0;
+    B1[k] = bg1;
+    B2[k] = bg2;
+    if (px < V.W && py < V.H) {
+      const int64_t pix = (int64_t)py * V.W + px;
+      T[k] = V.t_final[pix];
+      last[k] = V.n_contrib[pix];
+      dC0[k] = V.dl[pix];
+      dC1[k] = V.dl[hw + pix];
+      dC2[k] = V.dl[2 * hw + pix];
+    }
+    my_max = max(my_max, last[k]);
   }
-  float B0 = bg0, B1 = bg1, B2 = bg2;  // colour behind the current entry
-  if (tid == 0) s_max = 0;
-  __syncthreads();
-  atomicMax(&s_max, last);
-  __syncthreads();
-  const int max_last = min(s_max, (int)(r.y - r.x));  // n_contrib never exceeds the list length
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) my_max = max(my_max, __shfl_xor(my_max, d, 64));
+  const int max_last = min(my_max, (int)(r.y - r.x));  // n_contrib never exceeds the list length
   if (max_last <= 0) return;
+  const int slot = kRedSlot[lane & 15];
   const int nbatch = (max_last + kBatchB - 1) / kBatchB;
   for (int bi = nbatch - 1; bi >= 0; bi--) {
     const uint32_t start = r.x + (uint32_t)bi * kBatchB;
     const int n_in = min(kBatchB, max_last - bi * kBatchB);
     __syncthreads();
-    if (tid < n_in) {
-      const uint32_t p = vals[start + tid];
-      const Rec R = rec_s[p];
-      s_xy[tid] = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
-      s_co[tid] = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
-      s_cn[tid] = make_float4(R.r1.x, R.r1.y, R.r1.z, 0.f);
-      s_rgb[tid] = make_float4(R.r2.x, R.r2.y, R.r2.z, 0.f);
-      s_p[tid] = p;
+    int n_kept = 0;
+#pragma unroll
+    for (int k = 0; k < kBatchB / kLanes; k++) {
+      const int e = k * kLanes + lane;
+      bool keep = false;
+      float2 xy;
+      float4 cn, rgb;
+      uint32_t p = 0;
+      if (e < n_in) {
+        p = vals[start + e];
+        const Rec R = rec_s[p];
+        xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
+        cn = R.r1;
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(bi * kBatchB + e));
+        keep = !cull_entry(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
+      }
+      const uint64_t m = __ballot(keep);
+      if (keep) {
+        const int pos = n_kept + __popcll(m & lt);
+        s_xy[pos] = xy;
+        s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, cn.w);
+        s_rgb[pos] = rgb;
+        s_p[pos] = p;
+      }
+      n_kept += __popcll(m);
     }
     __syncthreads();
-    for (int j = n_in - 1; j >= 0; j--) {
-      const int idx = bi * kBatchB + j;
+    for (int j = n_kept - 1; j >= 0; j--) {
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
-      const float dx = xy.x - flx, dy = xy.y - fly;
-      const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-      const float G = __builtin_amdgcn_exp2f(pw);
-      const float araw = co.w * G;
-      const float a = fminf(kAlphaMax, araw);
-      const bool valid = (idx < last) && (pw <= 0.f) && (a >= kAlphaMin);
-      float g[9];
-      if (valid) {
-        T = T / (1.f - a);
-        const float4 c = s_rgb[j];
-        const float w = a * T;
-        g[6] = w * dC0;
-        g[7] = w * dC1;
-        g[8] = w * dC2;
-        const float da = T * ((c.x - B0) * dC0 + (c.y - B1) * dC1 + (c.z - B2) * dC2);
-        B0 = a * c.x + (1.f - a) * B0;
-        B1 = a * c.y + (1.f - a) * B1;
-        B2 = a * c.z + (1.f - a) * B2;
-        const bool clamped = araw >= kAlphaMax;
-        const float dP = clamped ? 0.f : da * a;
-        g[5] = clamped ? 0.f : da * G;
-        const float4 cn = s_cn[j];
-        g[0] = dP * (-cn.x * dx - cn.y * dy);
-        g[1] = dP * (-cn.z * dy - cn.y * dx);
-        g[2] = -0.5f * dP * dx * dx;
-        g[3] = -dP * dx * dy;
-        g[4] = -0.5f * dP * dy * dy;
-      } else {
+      const float4 c = s_rgb[j];
+      const int idx = __float_as_int(c.w);
+      // natural conic from the scaled one: A = -2 co.x / log2 e, B = -co.y / log2 e, C = -2 co.z / log2 e
+      const float cnx = co.x * (-2.f / kLog2e), cny = co.y * (-1.f / kLog2e), cnz = co.z * (-2.f / kLog2e);
+      const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
+      const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
+      float gsum[9];
 #pragma unroll
-        for (int k = 0; k < 9; k++) g[k] = 0.f;
+      for (int q = 0; q < 9; q++) gsum[q] = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
+        const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
+        const float G = __builtin_amdgcn_exp2f(pw);
+        const float araw = co.w * G;
+        const float a = fminf(kAlphaMax, araw);
+        if (!((idx < last[k]) && (pw <= 0.f) && (a >= kAlphaMin))) continue;
+        any = true;
+        T[k] = T[k] * __builtin_amdgcn_rcpf(1.f - a);  // transmittance before this entry
+        const float w = a * T[k];
+        gsum[6] += w * dC0[k];
+        gsum[7] += w * dC1[k];
+        gsum[8] += w * dC2[k];
+        const float da = T[k] * ((c.x - B0[k]) * dC0[k] + (c.y - B1[k]) * dC1[k] + (c.z - B2[k]) * dC2[k]);
+        B0[k] = a * c.x + (1.f - a) * B0[k];
+        B1[k] = a * c.y + (1.f - a) * B1[k];
+        B2[k] = a * c.z + (1.f - a) * B2[k];
+        if (araw < kAlphaMax) {
+          const float dP = da * a;
+          gsum[5] += da * G;
+          gsum[0] += dP * (-cnx * dx - cny * dy);
+          gsum[1] += dP * (-cnz * dy - cny * dx);
+          gsum[2] += -0.5f * dP * dx * dx;
+          gsum[3] += -dP * dx * dy;
+          gsum[4] += -0.5f * dP * dy * dy;
+        }
       }
-      if (__ballot(valid) != 0) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) g[k] = wave_sum(g[k]);
-        float mine = g[0];
-#pragma unroll
-        for (int k = 1; k < 9; k++) mine = (lane == k) ? g[k] : mine;
-        if (lane < 9) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + lane], mine);
+      if (__ballot(any) != 0) {
+        const float tot = wave_reduce9(gsum, lane);
+        if (lane < 16 && slot >= 0) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], tot);
       }
     }
   }
@@ -337,10 +484,10 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   if (total_tiles == 0) return;
   const int per = per_xcd(total_tiles);
   if (count_pairs)
-    k_blend_fwd<true><<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+    k_blend_fwd<true><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
                                                            ws.ranges, vals, ws.rec_s, ws.pairs);
   else
-    k_blend_fwd<false><<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+    k_blend_fwd<false><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
                                                             ws.ranges, vals, ws.rec_s, nullptr);
 }
 
@@ -348,7 +495,7 @@ void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
                       const uint32_t* vals, hipStream_t st) {
   if (total_tiles == 0) return;
   const int per = per_xcd(total_tiles);
-  k_blend_bwd<<<per * kNumXcd, kTilePix, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+  k_blend_bwd<<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2], ws.ranges, vals,
                                                    ws.rec_s, ws.g2d);
 }
 

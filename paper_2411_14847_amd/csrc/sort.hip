@@ -18,7 +18,9 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;                      // items per thread per batch
 constexpr int kBatch = kSortThreads * kSortItems;  // 2048
-constexpr int kRadix = 256;
+constexpr int kMaxRadixBits = 9;
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
+constexpr int kMaxSortBlocks = 1024;
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
@@ -64,9 +66,9 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t x, uint32_t* s_w
   return base + inc - x;
 }
 
-template <typename K>
+template <int RB, typename K>
 __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
-  return (uint32_t)(k >> shift) & (kRadix - 1);
+  return (uint32_t)(k >> shift) & ((1u << RB) - 1);
 }
 
 __device__ __forceinline__ void chunk_of(uint32_t count, int blocks, uint32_t& lo, uint32_t& hi) {
@@ -77,106 +79,145 @@ __device__ __forceinline__ void chunk_of(uint32_t count, int blocks, uint32_t& l
   hi = (uint32_t)(h < count ? h : count);
 }
 
-template <typename K>
+template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void k_upsweep(const K* __restrict__ keys, const uint32_t* __restrict__ d_count,
                                                           int shift, int blocks, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_h[4][kRadix];
+  constexpr int R = 1 << RB;
+  __shared__ uint32_t s_h[4][R];
   const int tid = threadIdx.x, wave = tid >> 6;
-  for (int i = tid; i < 4 * kRadix; i += kSortThreads) (&s_h[0][0])[i] = 0;
+  for (int i = tid; i < 4 * R; i += kSortThreads) (&s_h[0][0])[i] = 0;
   __syncthreads();
   uint32_t lo, hi;
   chunk_of(*d_count, blocks, lo, hi);
-  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&s_h[wave][digit_of(keys[i], shift)], 1u);
+  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&s_h[wave][digit_of<RB>(keys[i], shift)], 1u);
   __syncthreads();
-  hist[(int64_t)tid * blocks + blockIdx.x] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+  for (int d = tid; d < R; d += kSortThreads)
+    hist[(int64_t)d * blocks + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
 }
 
-// Exclusive scan of n = 256 * blocks counts (digit-major), one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_hist(uint32_t* __restrict__ hist, int n) {
-  __shared__ uint32_t s_w[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (n + 1023) / 1024;
-  const int b = tid * per, e = min(b + per, n);
+// Exclusive scan of each digit's row of block counts (one workgroup per digit); the row total
+// goes to totals[digit].  The scatter adds the exclusive scan of the totals.
+__global__ __launch_bounds__(kSortThreads) void k_scan_rows(uint32_t* __restrict__ hist, int blocks,
+                                                            uint32_t* __restrict__ totals) {
+  __shared__ uint32_t s_w[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * blocks;
+  const int per = (blocks + kSortThreads - 1) / kSortThreads;
+  const int b = threadIdx.x * per, e = min(b + per, blocks);
   uint32_t sum = 0;
-  for (int i = b; i < e; i++) sum += hist[i];
-  uint32_t inc = wave_incl_scan(sum);
-  if (lane == 63) s_w[wave] = inc;
-  __syncthreads();
-  uint32_t base = 0;
-  for (int w = 0; w < wave; w++) base += s_w[w];
-  uint32_t run = base + inc - sum;
+  for (int i = b; i < e; i++) sum += row[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan256(sum, s_w, &tot);
   for (int i = b; i < e; i++) {
-    uint32_t c = hist[i];
-    hist[i] = run;
+    const uint32_t c = row[i];
+    row[i] = run;
     run += c;
   }
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-template <typename K>
+// Exclusive scan over R digits held D = R/256 per thread (consecutive); returns per-thread
+// prefix base (the thread's first digit's offset); *total is the sum of all.
+template <int D>
+__device__ __forceinline__ uint32_t block_excl_scan_digits(const uint32_t* c, uint32_t* s_tmp, uint32_t* total) {
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < D; i++) sum += c[i];
+  return block_excl_scan256(sum, s_tmp, total);
+}
+
+template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                           K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                           const uint32_t* __restrict__ d_count, int shift, int blocks,
-                                                          const uint32_t* __restrict__ hist) {
-  __shared__ uint32_t s_base[kRadix];       // global write position of the next item of each digit
-  __shared__ uint32_t s_cnt[kRadix];        // items of each digit seen so far in this batch
-  __shared__ uint32_t s_boff[kRadix];       // exclusive digit offsets within the batch
-  __shared__ uint32_t s_wcnt[2][4][kRadix];  // per-wave digit counts (double-buffered by sub-round)
+                                                          const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ totals) {
+  constexpr int R = 1 << RB;
+  constexpr int D = R / kSortThreads;        // digits owned per thread
+  __shared__ uint32_t s_base[R];             // global write position of the next item of each digit
+  __shared__ uint32_t s_cnt[R];              // items of each digit seen so far in this batch
+  __shared__ uint32_t s_boff[R];             // exclusive digit offsets within the batch
+  __shared__ uint32_t s_wcnt[2][4][R];       // per-wave digit counts (double-buffered by sub-round)
   __shared__ uint32_t s_tmp[4];
   __shared__ K s_k[kBatch];
   __shared__ uint32_t s_v[kBatch];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6;
   uint32_t lo, hi;
   chunk_of(*d_count, blocks, lo, hi);
-  s_base[tid] = hist[(int64_t)tid * blocks + blockIdx.x];
+  {  // global base of each digit for this block: row prefix + exclusive scan of the digit totals
+    uint32_t tv[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) tv[i] = totals[tid * D + i];
+    uint32_t run = block_excl_scan_digits<D>(tv, s_tmp, nullptr);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      const int d = tid * D + i;
+      s_base[d] = hist[(int64_t)d * blocks + blockIdx.x] + run;
+      run += tv[i];
+    }
+  }
   const uint64_t lt = lanemask_lt();
 
   for (uint32_t batch = lo; batch < hi; batch += kBatch) {
     const uint32_t nb = min((uint32_t)kBatch, hi - batch);
-    s_cnt[tid] = 0;
+#pragma unroll
+    for (int i = 0; i < D; i++) s_cnt[tid * D + i] = 0;
     K key[kSortItems];
     uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
     for (int s = 0; s < kSortItems; s++) {
-      uint32_t (*wc)[kRadix] = s_wcnt[s & 1];
+      uint32_t (*wc)[R] = s_wcnt[s & 1];
 #pragma unroll
-      for (int w = 0; w < 4; w++) wc[w][tid] = 0;
+      for (int w = 0; w < 4; w++)
+#pragma unroll
+        for (int i = 0; i < D; i++) wc[w][tid * D + i] = 0;
       const uint32_t idx = batch + s * kSortThreads + tid;
       const bool valid = idx < hi;
       uint32_t d = 0;
       if (valid) {
         key[s] = kin[idx];
         val[s] = vin[idx];
-        d = digit_of(key[s], shift);
+        d = digit_of<RB>(key[s], shift);
       }
       dig[s] = d;
       __syncthreads();
       // lanes of this wave holding the same digit
       uint64_t peers = __ballot(valid);
 #pragma unroll
-      for (int b = 0; b < 8; b++) {
+      for (int b = 0; b < RB; b++) {
         const uint64_t m = __ballot((d >> b) & 1);
         peers &= ((d >> b) & 1) ? m : ~m;
       }
       const uint32_t rw = __popcll(peers & lt);
       if (valid && rw == 0) wc[wave][d] = __popcll(peers);
       __syncthreads();
-      {  // thread tid owns digit tid: exclusive prefix over waves, running count
-        uint32_t run = s_cnt[tid];
+#pragma unroll
+      for (int i = 0; i < D; i++) {  // thread owns digits tid*D..: prefix over waves, running count
+        const int dd = tid * D + i;
+        uint32_t run = s_cnt[dd];
 #pragma unroll
         for (int w = 0; w < 4; w++) {
-          const uint32_t c = wc[w][tid];
-          wc[w][tid] = run;
+          const uint32_t c = wc[w][dd];
+          wc[w][dd] = run;
           run += c;
         }
-        s_cnt[tid] = run;
+        s_cnt[dd] = run;
       }
       __syncthreads();
       rank[s] = valid ? wc[wave][d] + rw : 0;
     }
     // digit offsets within the batch
-    const uint32_t c = s_cnt[tid];
-    s_boff[tid] = block_excl_scan256(c, s_tmp, nullptr);
+    uint32_t c[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) c[i] = s_cnt[tid * D + i];
+    {
+      uint32_t run = block_excl_scan_digits<D>(c, s_tmp, nullptr);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        s_boff[tid * D + i] = run;
+        run += c[i];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < kSortItems; s++) {
@@ -193,17 +234,17 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
       const uint32_t j = s * kSortThreads + tid;
       if (j < nb) {
         const K k = s_k[j];
-        const uint32_t d = digit_of(k, shift);
+        const uint32_t d = digit_of<RB>(k, shift);
         const uint32_t o = s_base[d] + (j - s_boff[d]);
         kout[o] = k;
         vout[o] = s_v[j];
       }
     }
     __syncthreads();
-    s_base[tid] += c;
+#pragma unroll
+    for (int i = 0; i < D; i++) s_base[tid * D + i] += c[i];
     __syncthreads();
   }
-  (void)lane;
 }
 
 // ---- scan of uint32 -> uint64 (exclusive), 3 phases ----------------------------------------
@@ -282,12 +323,24 @@ template <typename K>
 int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
                     int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
   int cur = 0;
-  if (max_count == 0) return cur;
-  for (int shift = begin_bit; shift < end_bit; shift += 8) {
-    k_upsweep<K><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
-    k_scan_hist<<<1, 1024, 0, st>>>(hist, kRadix * blocks);
-    k_scatter<K><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count, shift,
-                                                  blocks, hist);
+  if (max_count == 0 || end_bit <= begin_bit) return cur;
+  // fewest passes of at most kMaxRadixBits; 8-bit digits when that costs no extra pass
+  const int bits = end_bit - begin_bit;
+  const int passes = (bits + kMaxRadixBits - 1) / kMaxRadixBits;
+  const int rb = ((bits + 7) / 8 == passes) ? 8 : kMaxRadixBits;
+  uint32_t* totals = hist + (int64_t)kMaxRadix * kMaxSortBlocks;
+  for (int shift = begin_bit; shift < end_bit; shift += rb) {
+    if (rb == 8) {
+      k_upsweep<K, 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
+      k_scan_rows<<<256, kSortThreads, 0, st>>>(hist, blocks, totals);
+      k_scatter<K, 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
+                                                       shift, blocks, hist, totals);
+    } else {
+      k_upsweep<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
+      k_scan_rows<<<512, kSortThreads, 0, st>>>(hist, blocks, totals);
+      k_scatter<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
+                                                       shift, blocks, hist, totals);
+    }
     cur ^= 1;
   }
   return cur;
@@ -298,7 +351,7 @@ int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int6
 int sort_blocks_for(int64_t max_count) {
   int64_t b = (max_count + 4 * kBatch - 1) / (4 * kBatch);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > kMaxSortBlocks) b = kMaxSortBlocks;
   return (int)b;
 }
 
