@@ -74,6 +74,35 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y
   }
 }
 
+// d/d(x,y,z) of sum_k w_k Y_k(x,y,z) (the polynomial forms above), without materialising the
+// per-basis gradient arrays.
+template <int DEG>
+__device__ __forceinline__ void sh_weighted_grad(double x, double y, double z, const double* w, double& gx,
+                                                 double& gy, double& gz) {
+  gx = gy = gz = 0.0;
+  if (DEG >= 1) {
+    gy += w[1] * kY1;
+    gz += w[2] * kY1;
+    gx += w[3] * kY1;
+  }
+  if (DEG >= 2) {
+    gx += w[4] * kY2a * y + w[6] * (-2.0 * kY2b * x) + w[7] * kY2a * z + w[8] * (2.0 * kY2c * x);
+    gy += w[4] * kY2a * x + w[5] * kY2a * z + w[6] * (-2.0 * kY2b * y) + w[8] * (-2.0 * kY2c * y);
+    gz += w[5] * kY2a * y + w[6] * (4.0 * kY2b * z) + w[7] * kY2a * x;
+  }
+  if (DEG >= 3) {
+    const double xx = x * x, yy = y * y, zz = z * z;
+    gx += w[9] * (6.0 * kY3a * x * y) + w[10] * (kY3b * y * z) + w[11] * (-2.0 * kY3c * x * y) +
+          w[12] * (-6.0 * kY3d * x * z) + w[13] * (kY3c * (4.0 * zz - 3.0 * xx - yy)) +
+          w[14] * (2.0 * kY3e * x * z) + w[15] * (3.0 * kY3a * (xx - yy));
+    gy += w[9] * (3.0 * kY3a * (xx - yy)) + w[10] * (kY3b * x * z) + w[11] * (kY3c * (4.0 * zz - xx - 3.0 * yy)) +
+          w[12] * (-6.0 * kY3d * y * z) + w[13] * (-2.0 * kY3c * x * y) + w[14] * (-2.0 * kY3e * y * z) +
+          w[15] * (-6.0 * kY3a * x * y);
+    gz += w[10] * (kY3b * x * y) + w[11] * (8.0 * kY3c * y * z) + w[12] * (kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy)) +
+          w[13] * (8.0 * kY3c * x * z) + w[14] * (kY3e * (xx - yy));
+  }
+}
+
 // View-independent part of one Gaussian.
 struct GaussD {
   double mu[3], qhat[4], qn, s[3], Rq[9], M[9], Sig[6], o;  // Sig: xx, xy, xz, yy, yz, zz
@@ -107,6 +136,12 @@ __device__ __forceinline__ void load_gaussian(const SceneK& sc, int g, GaussD& G
   G.o = 1.0 / (1.0 + exp(-(double)sc.logit[g]));
 }
 
+// What the per-view projection needs of a Gaussian.
+struct GaussLite {
+  double mu[3], Sig[6];
+  bool ok;
+};
+
 // View-dependent part.
 struct ViewD {
   double t[3], limx, limy, txc, tyc, J0, J2, J4, J5;  // J = [[J0, 0, J2], [0, J4, J5]]
@@ -117,7 +152,8 @@ struct ViewD {
   uint32_t depth_bits;
 };
 
-__device__ __forceinline__ void project_view(const GaussD& G, const CamK& cam, ViewD& V) {
+template <typename GT>
+__device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD& V) {
 #pragma clang fp contract(off)
   double W[9];
   for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
@@ -184,8 +220,8 @@ __device__ __forceinline__ void project_view(const GaussD& G, const CamK& cam, V
   V.depth_bits = V.visible ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
 }
 
-template <int DEG>
-__device__ __forceinline__ void colour(const GaussD& G, const CamK& cam, const float* shc, double* rgb_pre,
+template <int DEG, typename GT>
+__device__ __forceinline__ void colour(const GT& G, const CamK& cam, const float* shc, double* rgb_pre,
                                        double* dhat, double& dn) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   double dir[3];
@@ -262,25 +298,26 @@ __device__ __forceinline__ float quad_sumf(float x) {
   return x;
 }
 
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, int nv,
-                                                        const uint32_t* __restrict__ inv,
-                                                        const float* __restrict__ g2d, dass_grads gr,
-                                                        float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
-  constexpr int K = (DEG + 1) * (DEG + 1);
+// Geometry part: pixel mean and conic back to mean, quaternion and log-scale; opacity.
+__global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK cams, int nv,
+                                                             const uint32_t* __restrict__ inv,
+                                                             const float* __restrict__ g2d, dass_grads gr,
+                                                             float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int g_raw = tid / kBwdSplit, r = tid % kBwdSplit;
   // every lane of a quad stays to the end (the quad shuffles need all four)
   const bool live = g_raw < sc.n;
   const int g = live ? g_raw : sc.n - 1;
-  GaussD G;
-  load_gaussian(sc, g, G);
-  float shc[3 * K];
-#pragma unroll
-  for (int k = 0; k < 3 * K; k++) shc[k] = sc.sh[(int64_t)k * sc.stride + g];
-  float dsh[3 * K];
-#pragma unroll
-  for (int k = 0; k < 3 * K; k++) dsh[k] = 0.f;
+  GaussLite L;
+  double o;
+  {
+    GaussD G;
+    load_gaussian(sc, g, G);
+    for (int i = 0; i < 3; i++) L.mu[i] = G.mu[i];
+    for (int i = 0; i < 6; i++) L.Sig[i] = G.Sig[i];
+    L.ok = G.ok;
+    o = G.o;
+  }
   double dmu[3] = {0.0, 0.0, 0.0};
   double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double dop = 0.0, gnorm = 0.0;
@@ -288,7 +325,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
   for (int v = r; v < nv && live; v += kBwdSplit) {
     const CamK& cam = cams.c[v];
     ViewD V;
-    project_view(G, cam, V);
+    project_view(L, cam, V);
     if (!V.visible) continue;
     const uint32_t p = inv[(int64_t)v * sc.n + g];
     const float* gd = g2d + (int64_t)p * 9;
@@ -296,35 +333,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
     dop += (double)gd[5];
     gnorm += sqrt(du * du + dv * dv);
     cnt++;
-    // colour
-    {
-      double rgb_pre[3], dhat[3], dn;
-      colour<DEG>(G, cam, shc, rgb_pre, dhat, dn);
-      double Y[16], gx[16], gy[16], gz[16];
-      sh_basis<DEG, true>(dhat[0], dhat[1], dhat[2], Y, gx, gy, gz);
-      double dd[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ch = 0; ch < 3; ch++) {
-        if (rgb_pre[ch] < 0.0) continue;
-        const double dc = (double)gd[6 + ch];
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-          dsh[k * 3 + ch] += (float)(dc * Y[k]);
-          const double w = dc * (double)shc[k * 3 + ch];
-          dd[0] += w * gx[k];
-          dd[1] += w * gy[k];
-          dd[2] += w * gz[k];
-        }
-      }
-      if (dn > 0.0) {
-        const double dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
-        for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) / dn;
-      }
-    }
     // conic (A, B, C) = inverse of [[a, b], [b, c]]: dSigma2D = -Q G Q with G = [[dA, dB/2], [dB/2, dC]]
     const double A = V.A, B = V.B, C = V.C;
     const double hB = 0.5 * dB;
-    // Q G
     const double qg00 = A * dA + B * hB, qg01 = A * hB + B * dC;
     const double qg10 = B * dA + C * hB, qg11 = B * hB + C * dC;
     const double da = -(qg00 * A + qg01 * B);
@@ -343,13 +354,13 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
     dSig[3] += T[1] * G2T[1] + T[4] * G2T[4];
     dSig[4] += T[1] * G2T[2] + T[4] * G2T[5];
     dSig[5] += T[2] * G2T[2] + T[5] * G2T[5];
-    const double* S = G.Sig;
+    const double* S = L.Sig;
     double dT[6];
     for (int i = 0; i < 2; i++) {
-      const double* r = G2T + 3 * i;
-      dT[3 * i + 0] = 2.0 * (r[0] * S[0] + r[1] * S[1] + r[2] * S[2]);
-      dT[3 * i + 1] = 2.0 * (r[0] * S[1] + r[1] * S[3] + r[2] * S[4]);
-      dT[3 * i + 2] = 2.0 * (r[0] * S[2] + r[1] * S[4] + r[2] * S[5]);
+      const double* rr = G2T + 3 * i;
+      dT[3 * i + 0] = 2.0 * (rr[0] * S[0] + rr[1] * S[1] + rr[2] * S[2]);
+      dT[3 * i + 1] = 2.0 * (rr[0] * S[1] + rr[1] * S[3] + rr[2] * S[4]);
+      dT[3 * i + 2] = 2.0 * (rr[0] * S[2] + rr[1] * S[4] + rr[2] * S[5]);
     }
     // T = J W: dJ_ij = sum_k dT_ik W_jk
     double W[9];
@@ -380,9 +391,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
   gnorm = quad_sum(gnorm);
   cnt += __shfl_xor(cnt, 1, 64);
   cnt += __shfl_xor(cnt, 2, 64);
-#pragma unroll
-  for (int k = 0; k < 3 * K; k++) dsh[k] = quad_sumf(dsh[k]);
   if (!live || r != 0 || cnt == 0) return;
+  GaussD G;
+  load_gaussian(sc, g, G);
   // Sigma = M M^T -> dM = 2 dSigma M (dSigma symmetric)
   const double* M = G.M;
   const double dS[9] = {dSig[0], dSig[1], dSig[2], dSig[1], dSig[3], dSig[4], dSig[2], dSig[4], dSig[5]};
@@ -416,13 +427,75 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(SceneK sc, CamsK cams, i
     for (int i = 0; i < 4; i++) gr.quat[i * st + g] += (float)dq[i];
   if (gr.log_scale)
     for (int i = 0; i < 3; i++) gr.log_scale[i * st + g] += (float)dls[i];
-  if (gr.opacity_logit) gr.opacity_logit[g] += (float)(dop * G.o * (1.0 - G.o));
-  if (gr.sh) {
-#pragma unroll
-    for (int k = 0; k < 3 * K; k++) gr.sh[(int64_t)k * st + g] += dsh[k];
-  }
+  if (gr.opacity_logit) gr.opacity_logit[g] += (float)(dop * o * (1.0 - o));
   if (gradnorm) gradnorm[g] += (float)gnorm;
   if (gcount) gcount[g] += cnt;
+}
+
+// Colour part: rgb_c = max(0, sum_k sh[k,c] Y_k(dhat) + 0.5), dhat = normalise(mu - campos).
+// Four lanes per Gaussian: lane c < 3 owns channel c (its K coefficients and their gradients,
+// over all views); the direction gradients of the three channels are summed at the end.
+// Visibility in a view is read from the forward's tile counts (a visible Gaussian touches >= 1
+// tile), so no projection is recomputed here.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK cams, int nv,
+                                                               const uint32_t* __restrict__ inv,
+                                                               const uint32_t* __restrict__ tt_s,
+                                                               const float* __restrict__ g2d, dass_grads gr) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g_raw = tid / kBwdSplit, ch = tid % kBwdSplit;
+  const bool live = g_raw < sc.n && ch < 3;
+  const int g = g_raw < sc.n ? g_raw : sc.n - 1;
+  const int c = ch < 3 ? ch : 2;
+  double mu[3];
+  for (int i = 0; i < 3; i++) mu[i] = (double)sc.mean[(int64_t)i * sc.stride + g];
+  float shc[K], dsh[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    shc[k] = sc.sh[(int64_t)(k * 3 + c) * sc.stride + g];
+    dsh[k] = 0.f;
+  }
+  double dmu[3] = {0.0, 0.0, 0.0};
+  for (int v = 0; v < nv && live; v++) {
+    const uint32_t p = inv[(int64_t)v * sc.n + g];
+    if (tt_s[p] == 0) continue;
+    const CamK& cam = cams.c[v];
+    double dir[3];
+    for (int i = 0; i < 3; i++) dir[i] = mu[i] - (double)cam.campos[i];
+    const double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    const double inv_dn = dn > 0.0 ? 1.0 / dn : 0.0;
+    double dhat[3];
+    for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv_dn;
+    double Y[16];
+    sh_basis<DEG, false>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; k++) acc += (double)shc[k] * Y[k];
+    if (acc + 0.5 < 0.0) continue;  // clamped channel: no derivative
+    const double d = (double)g2d[(int64_t)p * 9 + 6 + c];
+    double w[16];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      dsh[k] += (float)(d * Y[k]);
+      w[k] = d * (double)shc[k];
+    }
+    double dd[3];
+    sh_weighted_grad<DEG>(dhat[0], dhat[1], dhat[2], w, dd[0], dd[1], dd[2]);
+    if (dn > 0.0) {
+      const double dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
+      for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) * inv_dn;
+    }
+  }
+  for (int i = 0; i < 3; i++) dmu[i] = quad_sum(dmu[i]);
+  if (g_raw >= sc.n) return;
+  const int64_t st = sc.stride;
+  if (live && gr.sh) {
+#pragma unroll
+    for (int k = 0; k < K; k++) gr.sh[(int64_t)(k * 3 + c) * st + g] += dsh[k];
+  }
+  if (ch == 0 && gr.mean)
+    for (int i = 0; i < 3; i++) gr.mean[i * st + g] += (float)dmu[i];
 }
 
 __global__ void k_debug_projection(SceneK sc, CamK cam, double* out) {
@@ -462,11 +535,13 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   if (s.n == 0) return;
   const int64_t threads = (int64_t)s.n * kBwdSplit;
   dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+  k_preprocess_bwd_geom<<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount);
+  if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
-    case 0: k_preprocess_bwd<0><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
-    case 1: k_preprocess_bwd<1><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
-    case 2: k_preprocess_bwd<2><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
-    default: k_preprocess_bwd<3><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount); break;
+    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
+    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
+    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
+    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
   }
 }
 

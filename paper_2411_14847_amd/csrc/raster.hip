@@ -248,30 +248,31 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     for (int j = 0; j < n_kept; j++) {
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
+      const float4 c = s_rgb[j];
+      const int pos1 = __float_as_int(c.w) + 1;
       const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
       const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
+      // branch-free: every pixel evaluates the entry; selects keep skipped / stopped pixels unchanged
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        if (done[k]) continue;
         const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        if (COUNT) n_eval++;
-        if (pw > 0.f) continue;
         const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
-        if (a < kAlphaMin) continue;
-        const float Tn = T[k] * (1.f - a);
-        if (Tn < kTStop) {
-          done[k] = true;
-          continue;
-        }
-        if (COUNT) n_blend++;
-        const float4 c = s_rgb[j];
-        const float w = a * T[k];
+        const bool ok = !done[k] && (pw <= 0.f) && (a >= kAlphaMin);
+        const float Tn = T[k] - T[k] * a;
+        const bool stop = ok && (Tn < kTStop);
+        const bool blend = ok && !stop;
+        done[k] = done[k] || stop;
+        const float w = blend ? a * T[k] : 0.f;
         c0[k] += c.x * w;
         c1[k] += c.y * w;
         c2[k] += c.z * w;
-        T[k] = Tn;
-        last[k] = __float_as_int(c.w) + 1;
+        T[k] = blend ? Tn : T[k];
+        last[k] = blend ? pos1 : last[k];
+        if (COUNT) {
+          n_eval += (!done[k] || stop) ? 1u : 0u;
+          n_blend += blend ? 1u : 0u;
+        }
       }
     }
     const bool alive = !(done[0] && done[1] && done[2] && done[3]);
@@ -381,13 +382,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
       const int idx = __float_as_int(c.w);
-      // natural conic from the scaled one: A = -2 co.x / log2 e, B = -co.y / log2 e, C = -2 co.z / log2 e
-      const float cnx = co.x * (-2.f / kLog2e), cny = co.y * (-1.f / kLog2e), cnz = co.z * (-2.f / kLog2e);
       const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
       const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
-      float gsum[9];
+      // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
+      // sum dP dy^2, d opacity, d rgb); the conic is applied after the wave reduction
+      float m[9];
 #pragma unroll
-      for (int q = 0; q < 9; q++) gsum[q] = 0.f;
+      for (int q = 0; q < 9; q++) m[q] = 0.f;
       bool any = false;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
@@ -400,26 +401,38 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         any = true;
         T[k] = T[k] * __builtin_amdgcn_rcpf(1.f - a);  // transmittance before this entry
         const float w = a * T[k];
-        gsum[6] += w * dC0[k];
-        gsum[7] += w * dC1[k];
-        gsum[8] += w * dC2[k];
-        const float da = T[k] * ((c.x - B0[k]) * dC0[k] + (c.y - B1[k]) * dC1[k] + (c.z - B2[k]) * dC2[k]);
-        B0[k] = a * c.x + (1.f - a) * B0[k];
-        B1[k] = a * c.y + (1.f - a) * B1[k];
-        B2[k] = a * c.z + (1.f - a) * B2[k];
-        if (araw < kAlphaMax) {
+        m[6] += w * dC0[k];
+        m[7] += w * dC1[k];
+        m[8] += w * dC2[k];
+        const float e0 = c.x - B0[k], e1 = c.y - B1[k], e2 = c.z - B2[k];
+        const float da = T[k] * (e0 * dC0[k] + e1 * dC1[k] + e2 * dC2[k]);
+        B0[k] += a * e0;
+        B1[k] += a * e1;
+        B2[k] += a * e2;
+        if (araw < kAlphaMax) {  // no derivative through an active clamp
           const float dP = da * a;
-          gsum[5] += da * G;
-          gsum[0] += dP * (-cnx * dx - cny * dy);
-          gsum[1] += dP * (-cnz * dy - cny * dx);
-          gsum[2] += -0.5f * dP * dx * dx;
-          gsum[3] += -dP * dx * dy;
-          gsum[4] += -0.5f * dP * dy * dy;
+          m[5] += da * G;
+          const float pdx = dP * dx, pdy = dP * dy;
+          m[0] += pdx;
+          m[1] += pdy;
+          m[2] += pdx * dx;
+          m[3] += pdx * dy;
+          m[4] += pdy * dy;
         }
       }
       if (__ballot(any) != 0) {
-        const float tot = wave_reduce9(gsum, lane);
-        if (lane < 16 && slot >= 0) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], tot);
+        const float tot = wave_reduce9(m, lane);
+        // lanes 0..15 hold the totals; lane 4 (slot 1) needs slot 0's partner values, so the
+        // mean / conic terms are formed by the lane holding each output from the moments.
+        const float s0 = __shfl(tot, 0, 64), s1 = __shfl(tot, 4, 64);  // sum dP dx, sum dP dy
+        const float cnx = co.x * (-2.f / kLog2e), cny = co.y * (-1.f / kLog2e), cnz = co.z * (-2.f / kLog2e);
+        float out = tot;
+        if (slot == 0) out = -cnx * s0 - cny * s1;           // d u
+        else if (slot == 1) out = -cnz * s1 - cny * s0;      // d v
+        else if (slot == 2) out = -0.5f * tot;               // d A
+        else if (slot == 3) out = -tot;                      // d B
+        else if (slot == 4) out = -0.5f * tot;               // d C
+        if (lane < 16 && slot >= 0) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], out);
       }
     }
   }
