@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--render-reps", type=int, default=100)
     ap.add_argument("--per-view-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     args.bg = (0.0, 0.0, 0.0)
     rank = int(os.environ.get("RANK", "0"))
@@ -199,6 +201,16 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
     log(f"[bench] building workload {args.workload}")
     s = build_workload(args)
     ctx = s["ctx"]

@@ -196,6 +196,13 @@ typedef struct {
 dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1,
                       float beta2, float eps, int32_t step, dass_stream stream);
 
+/* adam_step with the 1-based step count in device memory: *d_step is incremented by one on the
+ * device and the incremented value is used for the bias correction.  For launch sequences
+ * captured once and replayed (a HIP graph), where a host-side step would be frozen. */
+dass_status adam_step_device_count(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups,
+                                   float beta1, float beta2, float eps, int32_t* d_step,
+                                   dass_stream stream);
+
 /* Error-guided densification (Sec. 3.4, Alg. 1, Eq. 4).  For every base Gaussian n in
  * [0, g->n_base): its Alg. 1 pixel in each view (full projection, Round(z) = floor(z+0.5),
  * x from x_norm and W, y from y_norm and H; points behind a camera or off the image are not

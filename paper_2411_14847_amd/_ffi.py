@@ -16,7 +16,8 @@ MAX_VIEWS = 32
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
            "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
-           "dass_debug_projection", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts")
+           "dass_debug_projection", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
+           "adam_step_device_count")
 FLAG_COUNT_PAIRS = 1
 STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
           "shift", "adam", "l1", "densify")
@@ -85,6 +86,7 @@ def lib():
                                  P(Opts), vp]),
             "shift_apply": (i32, [vp, i32, vp, i32, vp, vp, P(Gaussians), P(Gaussians), P(Grads), vp, vp, vp]),
             "adam_step": (i32, [vp, P(AdamGroup), i32, f32, f32, f32, i32, vp]),
+            "adam_step_device_count": (i32, [vp, P(AdamGroup), i32, f32, f32, f32, vp, vp]),
             "densify_append": (i32, [vp, P(Gaussians), P(vp), P(Camera), i32, vp, vp, f32, f32, f32, i32, u64, vp,
                                      vp]),
             "dass_l1_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), P(vp), P(vp), vp, vp]),

@@ -148,6 +148,7 @@ class Context:
         if st != F.DASS_OK:
             raise DassError(st, "dass_create failed")
         self.limits = lim
+        self.generation = 0  # bumped by every call that replaces the state kept for render_bwd
 
     def close(self):
         if self._h:
@@ -181,6 +182,7 @@ class Context:
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
         opts = F.Opts(16, 16, F.FLAG_COUNT_PAIRS if count_pairs else 0)
+        self.generation += 1
         self._check(self._lib.render_fwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs,
                                          C.byref(opts), _stream(stream)))
         return out
@@ -210,12 +212,23 @@ class Context:
                                           _ptr(drot), C.byref(gs), None, C.byref(gr), _ptr(d_dpos), _ptr(d_drot),
                                           _stream(stream)))
 
-    def adam_step(self, groups, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None):
-        """groups: sequence of (param, grad, m, v, lr) with equal-length contiguous float32 tensors."""
+    @staticmethod
+    def _adam_groups(groups):
         arr = (F.AdamGroup * len(groups))()
         for i, (p, g, m, v, lr) in enumerate(groups):
             arr[i] = F.AdamGroup(_ptr(p), _ptr(g), _ptr(m), _ptr(v), int(p.numel()), float(lr))
-        self._check(self._lib.adam_step(self._h, arr, len(groups), beta1, beta2, eps, int(step), _stream(stream)))
+        return arr
+
+    def adam_step(self, groups, beta1=0.9, beta2=0.999, eps=1e-15, step=1, stream=None, d_step=None):
+        """groups: sequence of (param, grad, m, v, lr) with equal-length contiguous float32 tensors.
+        With d_step (device int32 tensor) the step count lives on the device and is incremented."""
+        arr = self._adam_groups(groups)
+        if d_step is not None:
+            self._check(self._lib.adam_step_device_count(self._h, arr, len(groups), beta1, beta2, eps, _ptr(d_step),
+                                                         _stream(stream)))
+        else:
+            self._check(self._lib.adam_step(self._h, arr, len(groups), beta1, beta2, eps, int(step),
+                                            _stream(stream)))
 
     def l1_loss_grad(self, cams, renders, targets, dl_out, err_out=None, loss: Optional[torch.Tensor] = None,
                      stream=None):
@@ -232,6 +245,7 @@ class Context:
         """Appends children in rows [g.n, g.n + K); K lands in n_appended (device int32); the caller
         reads it and advances g.n."""
         gs = g.struct()
+        self.generation += 1
         E = (C.c_void_p * len(cams))(*[_ptr(e) for e in err_maps])
         self._check(self._lib.densify_append(self._h, C.byref(gs), E, cameras_array(cams), len(cams), _ptr(gradnorm),
                                              _ptr(count), float(gamma_err), float(tau_pos), float(tau_err),

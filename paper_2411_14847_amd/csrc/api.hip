@@ -424,7 +424,7 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   const int64_t vn = (int64_t)n_views * g->n;
   launch_fill_u32(reinterpret_cast<uint32_t*>(ws.g2d), 0u, vn * 9, st);
   stage_begin(ctx, DASS_STAGE_BLEND_BWD, st);
-  launch_blend_bwd(io, n_views, total_tiles, bg, ws, ws.vals[ctx->fwd_key_buf], st);
+  launch_blend_bwd(io, n_views, total_tiles, bg, ws, ws.vals[ctx->fwd_key_buf], g->n, st);
   stage_end(ctx, DASS_STAGE_BLEND_BWD, st);
   stage_begin(ctx, DASS_STAGE_PROJECT_BWD, st);
   launch_preprocess_bwd(scene_of(g), ck, n_views, ws, *grads, gradnorm_sum, grad_count, st);
@@ -464,10 +464,11 @@ dass_status shift_apply(dass_ctx ctx, int32_t mode, const int32_t* dyn_idx, int3
   return check_launch(ctx, "shift_apply");
 }
 
-dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,
-                      float eps, int32_t step, dass_stream stream) {
+static dass_status adam_impl(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,
+                             float eps, int32_t step, int32_t* d_step, dass_stream stream) {
   if (!ctx) return DASS_E_INVALID;
-  if (!groups || n_groups < 1 || step < 1) return fail(ctx, DASS_E_INVALID, "need groups, n_groups >= 1, step >= 1");
+  if (!groups || n_groups < 1 || (!d_step && step < 1))
+    return fail(ctx, DASS_E_INVALID, "need groups, n_groups >= 1, step >= 1");
   for (int i = 0; i < n_groups; i++) {
     const dass_adam_group& G = groups[i];
     if (G.n < 0) return fail(ctx, DASS_E_INVALID, "group %d: n < 0", i);
@@ -476,9 +477,10 @@ dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_gro
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int per = adam_per_block();
-  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)step));
-  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+  const float bc1 = d_step ? 1.f : (float)(1.0 - std::pow((double)beta1, (double)step));
+  const float bc2 = d_step ? 1.f : (float)(1.0 - std::pow((double)beta2, (double)step));
   stage_begin(ctx, DASS_STAGE_ADAM, st);
+  if (d_step) launch_step_increment(d_step, st);
   for (int base = 0; base < n_groups; base += kAdamMaxGroups) {
     AdamArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -487,9 +489,10 @@ dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_gro
     a.eps = eps;
     a.bc1 = bc1;
     a.bc2 = bc2;
+    a.d_step = d_step;
     int64_t blocks = 0;
     int k = 0;
-    for (int i = base; i < n_groups && k < kAdamMaxGroups; i++) {
+    for (int i = base; i < n_groups && i < base + kAdamMaxGroups; i++) {
       const dass_adam_group& G = groups[i];
       if (G.n == 0) continue;
       a.g[k].p = G.param;
@@ -507,6 +510,17 @@ dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_gro
   }
   stage_end(ctx, DASS_STAGE_ADAM, st);
   return check_launch(ctx, "adam_step");
+}
+
+dass_status adam_step(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,
+                      float eps, int32_t step, dass_stream stream) {
+  return adam_impl(ctx, groups, n_groups, beta1, beta2, eps, step, nullptr, stream);
+}
+
+dass_status adam_step_device_count(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1,
+                                   float beta2, float eps, int32_t* d_step, dass_stream stream) {
+  if (!d_step) return fail(ctx, DASS_E_INVALID, "d_step is NULL");
+  return adam_impl(ctx, groups, n_groups, beta1, beta2, eps, 0, d_step, stream);
 }
 
 dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* render,

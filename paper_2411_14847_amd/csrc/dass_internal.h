@@ -85,7 +85,7 @@ struct Workspace {
   uint64_t* off_s = nullptr;       // exclusive prefix of tiles touched, [cap_vn + 1]
   uint32_t* inv = nullptr;         // inv[v*n + g] = p
   uint32_t* gid_s = nullptr;       // gid of sorted position p
-  float* g2d = nullptr;            // [cap_vn][9]
+  float* g2d = nullptr;            // [cap_vn][9], row v * n + g
   // keys
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
@@ -125,8 +125,9 @@ void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipSt
 void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, bool count_pairs, hipStream_t st);
+// accumulates the per-(view, Gaussian) 2D gradients into ws.g2d[(v * n + g) * 9 + k]
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
-                      const Workspace& ws, const uint32_t* vals, hipStream_t st);
+                      const Workspace& ws, const uint32_t* vals, int n, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted,
                        const uint32_t* vals_sorted, uint32_t lo, uint32_t cnt, const CamK& cam,
@@ -152,8 +153,10 @@ struct AdamArgs {
   AdamGroupK g[kAdamMaxGroups];
   int n_groups;
   float b1, b2, eps, bc1, bc2;
+  const int32_t* d_step;  // if set, the bias corrections come from this device step count
 };
 void launch_adam(const AdamArgs& a, int64_t total_blocks, hipStream_t st);
+void launch_step_increment(int32_t* d_step, hipStream_t st);
 
 struct L1View {
   const float* render;

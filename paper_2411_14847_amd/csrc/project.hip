@@ -300,7 +300,6 @@ __device__ __forceinline__ float quad_sumf(float x) {
 
 // Geometry part: pixel mean and conic back to mean, quaternion and log-scale; opacity.
 __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK cams, int nv,
-                                                             const uint32_t* __restrict__ inv,
                                                              const float* __restrict__ g2d, dass_grads gr,
                                                              float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,8 +326,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
     ViewD V;
     project_view(L, cam, V);
     if (!V.visible) continue;
-    const uint32_t p = inv[(int64_t)v * sc.n + g];
-    const float* gd = g2d + (int64_t)p * 9;
+    const float* gd = g2d + ((int64_t)v * sc.n + g) * 9;
     const double du = gd[0], dv = gd[1], dA = gd[2], dB = gd[3], dC = gd[4];
     dop += (double)gd[5];
     gnorm += sqrt(du * du + dv * dv);
@@ -435,12 +433,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
 // Colour part: rgb_c = max(0, sum_k sh[k,c] Y_k(dhat) + 0.5), dhat = normalise(mu - campos).
 // Four lanes per Gaussian: lane c < 3 owns channel c (its K coefficients and their gradients,
 // over all views); the direction gradients of the three channels are summed at the end.
-// Visibility in a view is read from the forward's tile counts (a visible Gaussian touches >= 1
-// tile), so no projection is recomputed here.
+// Visibility in a view is read from the forward's per-(view, Gaussian) tile counts (a visible
+// Gaussian touches >= 1 tile), so no projection is recomputed here.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK cams, int nv,
-                                                               const uint32_t* __restrict__ inv,
-                                                               const uint32_t* __restrict__ tt_s,
+                                                               const uint32_t* __restrict__ tt_u,
                                                                const float* __restrict__ g2d, dass_grads gr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,8 +455,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
   }
   double dmu[3] = {0.0, 0.0, 0.0};
   for (int v = 0; v < nv && live; v++) {
-    const uint32_t p = inv[(int64_t)v * sc.n + g];
-    if (tt_s[p] == 0) continue;
+    const int64_t row = (int64_t)v * sc.n + g;
+    if (tt_u[row] == 0) continue;  // not visible in this view
     const CamK& cam = cams.c[v];
     double dir[3];
     for (int i = 0; i < 3; i++) dir[i] = mu[i] - (double)cam.campos[i];
@@ -473,7 +470,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
 #pragma unroll
     for (int k = 0; k < K; k++) acc += (double)shc[k] * Y[k];
     if (acc + 0.5 < 0.0) continue;  // clamped channel: no derivative
-    const double d = (double)g2d[(int64_t)p * 9 + 6 + c];
+    const double d = (double)g2d[row * 9 + 6 + c];
     double w[16];
 #pragma unroll
     for (int k = 0; k < K; k++) {
@@ -535,13 +532,13 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   if (s.n == 0) return;
   const int64_t threads = (int64_t)s.n * kBwdSplit;
   dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  k_preprocess_bwd_geom<<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.g2d, grads, gradnorm, gcount);
+  k_preprocess_bwd_geom<<<grid, block, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
   if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
-    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
-    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
-    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
-    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.inv, ws.tt_s, ws.g2d, grads); break;
+    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
+    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
+    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
+    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
   }
 }
 

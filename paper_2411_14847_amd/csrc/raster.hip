@@ -301,6 +301,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
 __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
+                                                      const uint32_t* __restrict__ gid_s, int n,
                                                       float* __restrict__ g2d) {
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
@@ -372,7 +373,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         s_xy[pos] = xy;
         s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, cn.w);
         s_rgb[pos] = rgb;
-        s_p[pos] = p;
+        s_p[pos] = (uint32_t)v * (uint32_t)n + gid_s[p];  // gradient row: (view, Gaussian)
       }
       n_kept += __popcll(m);
     }
@@ -505,11 +506,11 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
 }
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
-                      const uint32_t* vals, hipStream_t st) {
+                      const uint32_t* vals, int n, hipStream_t st) {
   if (total_tiles == 0) return;
   const int per = per_xcd(total_tiles);
   k_blend_bwd<<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_s, ws.g2d);
+                                                   ws.rec_s, ws.gid_s, n, ws.g2d);
 }
 
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,

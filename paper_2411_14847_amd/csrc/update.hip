@@ -87,6 +87,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
   const AdamGroupK& G = a.g[gi];
   const int64_t base = (blk - G.block_begin) * kAdamPerBlock;
   const float omb1 = 1.f - a.b1, omb2 = 1.f - a.b2;
+  float bc1 = a.bc1, bc2 = a.bc2;
+  if (a.d_step) {
+    const double st = (double)*a.d_step;
+    bc1 = (float)(1.0 - pow((double)a.b1, st));
+    bc2 = (float)(1.0 - pow((double)a.b2, st));
+  }
   for (int k = threadIdx.x; k < kAdamPerBlock; k += blockDim.x) {
     const int64_t i = base + k;
     if (i >= G.n) break;
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
     const float v = a.b2 * G.v[i] + omb2 * g * g;
     G.m[i] = m;
     G.v[i] = v;
-    const float mh = m / a.bc1, vh = v / a.bc2;
+    const float mh = m / bc1, vh = v / bc2;
     G.p[i] -= G.lr * mh / (sqrtf(vh) + a.eps);
   }
 }
@@ -260,6 +266,10 @@ void launch_shift_adj(const SceneK& in, const float* dmean, const float* dquat, 
     k_shift_adj<<<(n_dyn + 255) / 256, 256, 0, st>>>(in.quat, dmean, dquat, in.stride, in.n, dyn_idx, n_dyn, drot,
                                                       d_dpos, d_drot);
 }
+
+__global__ void k_step_increment(int32_t* s) { *s += 1; }
+
+void launch_step_increment(int32_t* d_step, hipStream_t st) { k_step_increment<<<1, 1, 0, st>>>(d_step); }
 
 void launch_adam(const AdamArgs& a, int64_t total_blocks, hipStream_t st) {
   if (total_blocks > 0) k_adam<<<(unsigned)total_blocks, 256, 0, st>>>(a);

@@ -1,0 +1,195 @@
+"""Per-timestep streaming optimisation over the C ABI (Sec. 3.1-3.4).
+
+A timestep starts from the previous timestep's Gaussians G = {G^base, G^var}.  With a dynamics
+mask (the dynamic Gaussians' indices) it runs `iters` iterations of
+
+    shift_apply(FWD) -> render_fwd (all views) -> L1 gradient + error maps -> render_bwd
+    -> shift_apply(ADJOINT) -> adam_step over {dpos, drot} and every parameter of G^var,
+
+bakes the shift into G, and appends Gaussians where the error is large (densify_append).  The
+densified set G^var is kept between timesteps and erased every `erase_every` timesteps (App. B).
+The iteration can be captured once per timestep in a HIP graph and replayed (device-side Adam
+step count; every buffer is preallocated, nothing in the loop allocates or synchronises).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Dict, List
+
+import torch
+
+from .api import Context, GaussianBuffers, RenderOut
+
+
+@dataclass
+class StreamConfig:
+    iters: int = 100              # shift-stage steps per timestep (s2 = 100, Sec. 4.1)
+    k_append: int = 5000          # Gaussians appended per timestep
+    erase_every: int = 20         # G^var erased every 20 timesteps (App. B)
+    gamma_err: float = 0.0        # error threshold of D_err (Sec. 3.4)
+    tau_pos: float = 0.0          # historical-gradient thresholds of Eq. (4)
+    tau_err: float = 0.0
+    lr_dpos: float = 1e-3
+    lr_drot: float = 1e-3
+    lr_var: Dict[str, float] = field(default_factory=lambda: {
+        "mean": 1e-3, "quat": 1e-3, "log_scale": 5e-3, "logit": 5e-2, "sh0": 2.5e-3, "sh_rest": 1.25e-4})
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    bg: tuple = (0.0, 0.0, 0.0)
+    use_graph: bool = False
+    seed: int = 0
+
+
+class Trainer:
+    """Owns every device buffer of the loop; `g` is the live scene (capacity-sized planes)."""
+
+    def __init__(self, ctx: Context, g: GaussianBuffers, cams, max_dynamic: int, cfg: StreamConfig):
+        self.ctx, self.g, self.cams, self.cfg = ctx, g, list(cams), cfg
+        dev = g.mean.device
+        cap = g.capacity
+        self.dev = dev
+        # shifted scene: its own mean / quat planes, the other planes alias the live scene's
+        self.gs = GaussianBuffers(torch.zeros_like(g.mean), torch.zeros_like(g.quat), g.log_scale, g.logit, g.sh,
+                                  g.n, g.n_base, g.sh_degree)
+        self.outs = [RenderOut.allocate(c, dev) for c in self.cams]
+        self.dls = [torch.zeros(3, c.height, c.width, device=dev) for c in self.cams]
+        self.errs = [torch.zeros(c.height, c.width, device=dev) for c in self.cams]
+        self.targets = [torch.zeros(3, c.height, c.width, device=dev) for c in self.cams]
+        self.grads = g.zeros_like()
+        self.loss = torch.zeros(1, device=dev)
+        self.gn = torch.zeros(cap, device=dev)
+        self.cnt = torch.zeros(cap, dtype=torch.int32, device=dev)
+        self.n_app = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.d_step = torch.zeros(1, dtype=torch.int32, device=dev)
+        md = max(1, max_dynamic)
+        self.dyn_buf = torch.zeros(md, dtype=torch.int32, device=dev)
+        self.dpos_buf = torch.zeros(3, md, device=dev)
+        self.drot_buf = torch.zeros(4, md, device=dev)
+        self.d_dpos_buf = torch.zeros(3, md, device=dev)
+        self.d_drot_buf = torch.zeros(4, md, device=dev)
+        self.mv_dyn = [torch.zeros(3, md, device=dev), torch.zeros(3, md, device=dev),
+                       torch.zeros(4, md, device=dev), torch.zeros(4, md, device=dev)]
+        self.m_var = g.zeros_like()
+        self.v_var = g.zeros_like()
+        self.nd = 0
+        self.graph = None
+        self.graph_key = None
+
+    # ---- one iteration --------------------------------------------------------------------
+    def _adam_groups(self):
+        cfg, g = self.cfg, self.g
+        nd = self.nd
+        groups = []
+        if nd > 0:
+            groups.append((self._dpos, self._d_dpos, self._m_dpos, self._v_dpos, cfg.lr_dpos))
+            groups.append((self._drot, self._d_drot, self._m_drot, self._v_drot, cfg.lr_drot))
+        lo, hi = g.n_base, g.n
+        if hi > lo:
+            lr = cfg.lr_var
+            for name in ("mean", "quat", "log_scale"):
+                P, Gr, M, V = (getattr(x, name) for x in (g, self.grads, self.m_var, self.v_var))
+                for i in range(P.shape[0]):
+                    groups.append((P[i, lo:hi], Gr[i, lo:hi], M[i, lo:hi], V[i, lo:hi], lr[name]))
+            groups.append((g.logit[lo:hi], self.grads.logit[lo:hi], self.m_var.logit[lo:hi], self.v_var.logit[lo:hi],
+                           lr["logit"]))
+            for i in range(g.sh.shape[0]):
+                groups.append((g.sh[i, lo:hi], self.grads.sh[i, lo:hi], self.m_var.sh[i, lo:hi],
+                               self.v_var.sh[i, lo:hi], lr["sh0"] if i < 3 else lr["sh_rest"]))
+        return groups
+
+    def iteration(self, stream=None):
+        ctx, g, gs, cfg = self.ctx, self.g, self.gs, self.cfg
+        gs.n, gs.n_base = g.n, g.n_base
+        ctx.shift_fwd(g, gs, self._dyn, self._dpos, self._drot, stream=stream)
+        for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
+            t.zero_()
+        ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
+        ctx.l1_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, self.dls, self.errs, self.loss,
+                         stream=stream)
+        ctx.render_bwd(gs, self.cams, cfg.bg, self.outs, self.dls, self.grads, self.gn, self.cnt, stream=stream)
+        if self.nd > 0:
+            ctx.shift_adjoint(g, self._dyn, self._drot, self.grads, self._d_dpos, self._d_drot, stream=stream)
+        groups = self._adam_groups()
+        if groups:
+            ctx.adam_step(groups, cfg.beta1, cfg.beta2, cfg.eps, stream=stream, d_step=self.d_step)
+
+    # ---- one timestep -----------------------------------------------------------------------
+    def begin_timestep(self, t: int, dyn_idx: torch.Tensor):
+        cfg, g = self.cfg, self.g
+        if t % cfg.erase_every == 0:
+            g.n = g.n_base  # erase G^var
+        nd = int(dyn_idx.numel())
+        self.nd = nd
+        self.dyn_buf[:nd] = dyn_idx
+        for t_ in self.mv_dyn:
+            t_.zero_()
+        for t_ in (*self.m_var.planes(), *self.v_var.planes()):
+            t_.zero_()
+        self.d_step.zero_()
+        # contiguous views of the preallocated buffers used by the kernels for this timestep
+        flat = lambda buf, rows: buf.view(-1)[:rows * nd].view(rows, nd)
+        self._dyn = self.dyn_buf[:nd]
+        self._dpos, self._drot = flat(self.dpos_buf, 3), flat(self.drot_buf, 4)
+        self._dpos.zero_()
+        self._drot.zero_()
+        self._drot[0] = 1.0
+        self._d_dpos, self._d_drot = flat(self.d_dpos_buf, 3), flat(self.d_drot_buf, 4)
+        self._m_dpos, self._v_dpos = flat(self.mv_dyn[0], 3), flat(self.mv_dyn[1], 3)
+        self._m_drot, self._v_drot = flat(self.mv_dyn[2], 4), flat(self.mv_dyn[3], 4)
+
+    def set_targets(self, images: List[torch.Tensor]):
+        for dst, src in zip(self.targets, images):
+            dst.copy_(src)
+
+    def run_iterations(self, k: int):
+        if not self.cfg.use_graph:
+            for _ in range(k):
+                self.iteration()
+            return
+        key = (self.g.n, self.nd)
+        if self.graph is None or self.graph_key != key:
+            # warm up on a side stream, then capture one iteration
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            step0 = self.d_step.clone()
+            with torch.cuda.stream(s):
+                self.iteration(stream=s)
+            torch.cuda.current_stream().wait_stream(s)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self.iteration(stream=torch.cuda.current_stream())
+            self.graph_key = key
+            k -= 1  # the warm-up ran one real iteration; capture itself does not execute
+            del step0
+        for _ in range(k):
+            self.graph.replay()
+
+    def end_timestep(self, t: int) -> int:
+        """Bakes the shift into G and appends Gaussians; returns the number appended."""
+        cfg, g, gs = self.cfg, self.g, self.gs
+        n = g.n
+        g.mean[:, :n].copy_(gs.mean[:, :n])
+        g.quat[:, :n].copy_(gs.quat[:, :n])
+        self.ctx.densify_append(g, self.errs, self.cams, self.gn, self.cnt, cfg.gamma_err, cfg.tau_pos, cfg.tau_err,
+                                cfg.k_append, cfg.seed * 1_000_003 + t, self.n_app)
+        k = int(self.n_app.item())
+        g.n += k
+        self.graph = None
+        return k
+
+    def timestep(self, t: int, dyn_idx: torch.Tensor, targets: List[torch.Tensor]) -> dict:
+        t0 = time.perf_counter()
+        self.begin_timestep(t, dyn_idx)
+        self.set_targets(targets)
+        first = None
+        if self.cfg.iters > 0:
+            self.iteration()
+            first = float(self.loss.item())
+            self.run_iterations(self.cfg.iters - 1)
+        last = float(self.loss.item())
+        appended = self.end_timestep(t)
+        torch.cuda.synchronize()
+        return {"t": t, "ms": (time.perf_counter() - t0) * 1e3, "loss_first": first, "loss_last": last,
+                "appended": appended, "n": self.g.n}
