@@ -171,12 +171,197 @@ def cpu_baseline(s, args):
             "cpu": platform.processor() or platform.machine()}
 
 
+def _scene_buffers(scene, capacity):
+    from paper_2411_14847_amd import GaussianBuffers
+    return GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh,
+                                       scene.sh_degree, capacity=capacity)
+
+
+def _gt_targets(ctx, gt, gt_next, cams, seed, t, bg):
+    """Advances the ground-truth trajectory to timestep t (10% of the base Gaussians moved by a
+    seeded position and small-angle rotation delta) and renders its target images once."""
+    import torch
+    import synth
+    m = synth.timestep_motion(seed, t, gt.n_base)
+    dyn = torch.as_tensor(m.dynamic, device="cuda")
+    ctx.shift_fwd(gt, gt_next, dyn, torch.as_tensor(m.dpos, device="cuda"), torch.as_tensor(m.dquat, device="cuda"))
+    for d, s_ in zip(gt.planes(), gt_next.planes()):
+        d.copy_(s_)
+    imgs = [o.rgb.clone() for o in ctx.render_fwd(gt, cams, bg)]
+    return dyn, imgs
+
+
+def _psnr(outs, targets):
+    import math
+    mse = sum(float(((o.rgb - t) ** 2).mean().item()) for o, t in zip(outs, targets)) / len(outs)
+    return 10.0 * math.log10(1.0 / max(mse, 1e-20))
+
+
+def bench_streaming(args):
+    """Per-timestep streaming optimisation on the 2,000-Gaussian SH0 scene seen by a 20-camera rig
+    at 128x128: each timestep moves 10% of the Gaussians, runs `iters` shift/render/loss/adjoint/
+    Adam iterations against that timestep's ground-truth renders, then appends up to densify_k
+    Gaussians; G^var is erased every 20 timesteps.  Targets are rendered before each timestep's
+    timer starts.  Reports ms/timestep for the batched path (HIP-graph replay and eager) and for
+    the plain per-view loop."""
+    import torch
+    import synth
+    from paper_2411_14847_amd import Context
+    from paper_2411_14847_amd.streaming import StreamConfig, Trainer
+
+    scene, cam1, _ = synth.single_view_scene(args.seed)
+    cams = synth.streaming_rig(128, 128) if args.stream_views == 20 else cam1
+    N = scene.n
+    cap = N + 20 * args.densify_k
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    gctx = Context(max_gaussians=N, max_views=len(cams), max_keys=N * len(cams) * 64 + (1 << 20), max_tiles=tiles)
+    gt = _scene_buffers(scene, N)
+    gt_next = gt.clone()
+    targets, dyns = [], []
+    for t in range(1, args.timesteps + 1):
+        dyn, imgs = _gt_targets(gctx, gt, gt_next, cams, args.seed, t, args.bg)
+        dyns.append(dyn)
+        targets.append(imgs)
+    gctx.sync()
+    variants = [("batched_graph", dict(use_graph=True)), ("batched_eager", dict(use_graph=False))]
+    if args.per_view_steps > 0:
+        variants.append(("per_view_eager", dict(use_graph=False, per_view=True)))
+    res = {}
+    for name, kw in variants:
+        g = _scene_buffers(scene, cap)
+        ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 8 + (1 << 20),
+                      max_tiles=tiles)
+        cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, **kw)
+        tr = Trainer(ctx, g, cams, max_dynamic=int(dyns[0].numel()), cfg=cfg)
+        T = args.timesteps if name != "per_view_eager" else min(args.timesteps, args.per_view_timesteps)
+        rows = []
+        for t in range(1, T + 1):
+            r = tr.timestep(t, dyns[t - 1], targets[t - 1])
+            r["psnr"] = _psnr(tr.outs, targets[t - 1])
+            rows.append(r)
+        ctx.sync()
+        ms = [r["ms"] for r in rows]
+        steady = ms[1:] if len(ms) > 1 else ms
+        res[name] = {"timesteps": T, "ms_per_timestep": round(float(np.mean(steady)), 3),
+                     "ms_first_timestep": round(ms[0], 3), "n_final": rows[-1]["n"],
+                     "loss_first_last_final_t": [rows[-1]["loss_first"], rows[-1]["loss_last"]],
+                     "psnr_final_t": round(rows[-1]["psnr"], 2),
+                     "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows]))}
+        log(f"[bench] streaming {name}: {res[name]}")
+        del tr, ctx, g
+        torch.cuda.empty_cache()
+    main_ = res["batched_graph"]
+    line = {
+        "metric": "streaming ms/timestep (100 iterations + append) on the 2k-Gaussian scene, 20-view rig 128x128",
+        "value": main_["ms_per_timestep"], "unit": "ms/timestep", "n_gpus": 1, "steps": args.timesteps,
+        "warmup": 1, "ms_per_step": round(main_["ms_per_timestep"] / max(1, args.iters), 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"streaming_2k_sh0_{len(cams)}x128x128", "iters_per_timestep": args.iters,
+                   "densify_k": args.densify_k, "erase_every": 20, "dynamic_fraction": 0.1},
+        "variants": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args):
+    """Continuous-batching render serving of the 200k-Gaussian SH3 scene while a training thread
+    runs timesteps of the streaming loop on the 20-view 1352x1014 rig (its own stream) and
+    publishes each finished timestep.  Requests arrive Poisson at `rate` from 64 viewers, at
+    640x480, 1280x720 or 1920x1080; latency is arrival to completion event."""
+    import threading
+    import torch
+    import synth
+    from paper_2411_14847_amd import Context
+    from paper_2411_14847_amd.serving import RenderServer, Request, SceneSnapshots, serve_requests
+    from paper_2411_14847_amd.streaming import StreamConfig, Trainer
+
+    scene, cams, _ = synth.multiview_scene(args.seed, n=args.n, n_views=args.views, width=args.width,
+                                           height=args.height, with_grads=False)
+    N = scene.n
+    cap = N + 20 * args.densify_k
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=int(cap * len(cams) * 24) + (1 << 20),
+                  max_tiles=tiles)
+    g = _scene_buffers(scene, cap)
+    gt = _scene_buffers(scene, N)
+    gt_next = gt.clone()
+    cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, use_graph=True)
+    tr = Trainer(ctx, g, cams, max_dynamic=int(round(0.1 * N)), cfg=cfg)
+    snaps = SceneSnapshots(g)
+    snaps.publish(g)
+    server = RenderServer(snaps, max_gaussians=cap, n_slots=args.slots, max_batch=args.max_batch,
+                          max_tiles=args.max_batch * 8160, keys_per_tile=args.keys_per_tile)
+    reqs = [Request(i, r.arrival_s, r.camera)
+            for i, r in enumerate(synth.serving_requests(args.seed, n_requests=args.requests, rate_hz=args.rate))]
+    train_stream = torch.cuda.Stream()
+    t_state = {"t": 0}
+
+    def train_one():
+        t_state["t"] += 1
+        t = t_state["t"]
+        dyn, imgs = _gt_targets(ctx, gt, gt_next, cams, args.seed, t, args.bg)
+        r = tr.timestep(t, dyn, imgs)
+        snaps.publish(g, torch.cuda.current_stream())
+        return r
+
+    # warm-up: one training timestep alone, then one batch per slot
+    with torch.cuda.stream(train_stream):
+        alone = [train_one() for _ in range(args.train_alone)]
+    torch.cuda.synchronize()
+    for slot in server.slots:
+        server.launch(slot, reqs[:min(3, len(reqs))])
+    torch.cuda.synchronize()
+    for slot in server.slots:
+        slot.ctx.sync(slot.stream)
+        slot.busy, slot.event, slot.batch = False, None, []
+    # capacity: every request of a closed batch submitted at t = 0, no training
+    cap_reqs = [Request(i, 0.0, r.camera) for i, r in enumerate(reqs[:args.capacity_requests])]
+    st_cap = serve_requests(server, cap_reqs)
+    server.latencies.clear()
+    server.completed = server.retried = 0
+    log(f"[bench] serving capacity (closed batch of {len(cap_reqs)}, no training): {st_cap}")
+    # open loop with concurrent training
+    stop = threading.Event()
+    during = []
+
+    def trainer_loop():
+        with torch.cuda.stream(train_stream):
+            while not stop.is_set():
+                during.append(train_one())
+
+    th = threading.Thread(target=trainer_loop)
+    th.start()
+    st = serve_requests(server, reqs)
+    stop.set()
+    th.join()
+    torch.cuda.synchronize()
+    log(f"[bench] serving with training: {st}; training ms/timestep {[round(d['ms'], 1) for d in during]}")
+    train_alone_ms = float(np.mean([a["ms"] for a in alone[1:]] or [a["ms"] for a in alone]))
+    line = {
+        "metric": "serving frames/s and p50/p99 latency (Poisson 500/s, mixed 640x480..1920x1080, 200k Gaussians) "
+                  "with concurrent training",
+        "value": round(st["frames_per_s"], 2), "unit": "frames/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"serving_{N // 1000}k_sh3_poisson{int(args.rate)}_64viewers_mixedres",
+                   "requests": len(reqs), "slots": args.slots, "max_batch": args.max_batch,
+                   "training": f"{len(cams)} views {args.width}x{args.height}, {args.iters} iters/timestep"},
+        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "retried": st["retried"],
+        "train_ms_per_timestep_concurrent": round(float(np.mean([d["ms"] for d in during])), 2) if during else None,
+        "timesteps_during_serving": len(during),
+        "train_ms_per_timestep_alone": round(train_alone_ms, 2),
+        "capacity_frames_per_s": round(st_cap["frames_per_s"], 2),
+        "capacity_p50_ms": round(st_cap["p50_ms"], 3), "capacity_p99_ms": round(st_cap["p99_ms"], 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["multiview", "single"], default="multiview")
+    ap.add_argument("--workload", choices=["multiview", "single", "streaming", "serving"], default="multiview")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--width", type=int, default=1352)
@@ -189,6 +374,17 @@ def main():
     ap.add_argument("--render-reps", type=int, default=100)
     ap.add_argument("--per-view-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=100, help="iterations per timestep (streaming, serving)")
+    ap.add_argument("--timesteps", type=int, default=40, help="timesteps (streaming)")
+    ap.add_argument("--per-view-timesteps", type=int, default=10)
+    ap.add_argument("--stream-views", type=int, choices=[1, 20], default=20)
+    ap.add_argument("--requests", type=int, default=3000, help="requests (serving)")
+    ap.add_argument("--rate", type=float, default=500.0)
+    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--keys-per-tile", type=int, default=1200)
+    ap.add_argument("--train-alone", type=int, default=2)
+    ap.add_argument("--capacity-requests", type=int, default=500)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -211,6 +407,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
         return
+    if args.workload == "streaming":
+        return bench_streaming(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     log(f"[bench] building workload {args.workload}")
     s = build_workload(args)
     ctx = s["ctx"]

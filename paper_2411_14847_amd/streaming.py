@@ -39,6 +39,7 @@ class StreamConfig:
     eps: float = 1e-15
     bg: tuple = (0.0, 0.0, 0.0)
     use_graph: bool = False
+    per_view: bool = False        # plain per-view loop (one render_fwd / render_bwd per camera)
     seed: int = 0
 
 
@@ -105,10 +106,22 @@ class Trainer:
         ctx.shift_fwd(g, gs, self._dyn, self._dpos, self._drot, stream=stream)
         for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
             t.zero_()
-        ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
-        ctx.l1_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, self.dls, self.errs, self.loss,
-                         stream=stream)
-        ctx.render_bwd(gs, self.cams, cfg.bg, self.outs, self.dls, self.grads, self.gn, self.cnt, stream=stream)
+        if not cfg.per_view:
+            ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
+            ctx.l1_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, self.dls, self.errs, self.loss,
+                             stream=stream)
+            ctx.render_bwd(gs, self.cams, cfg.bg, self.outs, self.dls, self.grads, self.gn, self.cnt, stream=stream)
+        else:
+            V = len(self.cams)
+            for v in range(V):
+                sl = slice(v, v + 1)
+                ctx.render_fwd(gs, self.cams[sl], cfg.bg, out=self.outs[sl], stream=stream)
+                ctx.l1_loss_grad(self.cams[sl], [self.outs[v].rgb], self.targets[sl], self.dls[sl], self.errs[sl],
+                                 self.loss, stream=stream)
+                with torch.cuda.stream(stream or torch.cuda.current_stream()):
+                    self.dls[v].mul_(1.0 / V)
+                ctx.render_bwd(gs, self.cams[sl], cfg.bg, self.outs[sl], self.dls[sl], self.grads, self.gn, self.cnt,
+                               stream=stream)
         if self.nd > 0:
             ctx.shift_adjoint(g, self._dyn, self._drot, self.grads, self._d_dpos, self._d_drot, stream=stream)
         groups = self._adam_groups()
@@ -158,7 +171,8 @@ class Trainer:
                 self.iteration(stream=s)
             torch.cuda.current_stream().wait_stream(s)
             self.graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(self.graph):
+            # thread-local capture: a serving thread may keep using the device meanwhile
+            with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
                 self.iteration(stream=torch.cuda.current_stream())
             self.graph_key = key
             k -= 1  # the warm-up ran one real iteration; capture itself does not execute
@@ -184,12 +198,13 @@ class Trainer:
         self.begin_timestep(t, dyn_idx)
         self.set_targets(targets)
         first = None
+        scale = 1.0 / len(self.cams) if self.cfg.per_view else 1.0  # per-view calls each add a view's mean
         if self.cfg.iters > 0:
             self.iteration()
-            first = float(self.loss.item())
+            first = float(self.loss.item()) * scale
             self.run_iterations(self.cfg.iters - 1)
-        last = float(self.loss.item())
+        last = float(self.loss.item()) * scale
         appended = self.end_timestep(t)
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         return {"t": t, "ms": (time.perf_counter() - t0) * 1e3, "loss_first": first, "loss_last": last,
                 "appended": appended, "n": self.g.n}
