@@ -235,10 +235,14 @@ def bench_streaming(args):
         tr = Trainer(ctx, g, cams, max_dynamic=int(dyns[0].numel()), cfg=cfg)
         T = args.timesteps if name != "per_view_eager" else min(args.timesteps, args.per_view_timesteps)
         rows = []
+        prof_from = T - 2 if name == "batched_eager" and T >= 3 else None
         for t in range(1, T + 1):
+            if t == prof_from:
+                ctx.profile_begin(max_records=3 * (args.iters + 2))
             r = tr.timestep(t, dyns[t - 1], targets[t - 1])
             r["psnr"] = _psnr(tr.outs, targets[t - 1])
             rows.append(r)
+        stages = ctx.profile_end() if prof_from is not None else None
         ctx.sync()
         ms = [r["ms"] for r in rows]
         steady = ms[1:] if len(ms) > 1 else ms
@@ -246,7 +250,10 @@ def bench_streaming(args):
                      "ms_first_timestep": round(ms[0], 3), "n_final": rows[-1]["n"],
                      "loss_first_last_final_t": [rows[-1]["loss_first"], rows[-1]["loss_last"]],
                      "psnr_final_t": round(rows[-1]["psnr"], 2),
-                     "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows]))}
+                     "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows])),
+                     "ms_series": [round(r["ms"], 1) for r in rows], "n_series": [r["n"] for r in rows]}
+        if stages is not None:
+            res[name]["stage_ms_per_timestep_last3"] = {k: round(v[0] / 3.0, 3) for k, v in stages.items()}
         log(f"[bench] streaming {name}: {res[name]}")
         del tr, ctx, g
         torch.cuda.empty_cache()
@@ -356,12 +363,105 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_stress(args):
+    """Large-footprint stress: 1,000,000 Gaussians (SH3, log-scales N(-2, 0.5), about 680 tiles
+    per Gaussian), four 1920x1080 views; one step = zero gradients + render_fwd + render_bwd with
+    upstream gradients N(0, 1), captured once in a HIP graph and replayed."""
+    import torch
+    import synth
+    from paper_2411_14847_amd import Context, RenderOut
+
+    t0 = time.perf_counter()
+    scene, cams = synth.large_footprint_scene(args.seed, n=args.stress_n)
+    log(f"[bench] stress scene generated in {time.perf_counter() - t0:.1f}s")
+    N = scene.n
+    g = _scene_buffers(scene, N)
+    del scene
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    max_keys = args.max_keys or 0xFFFF0000
+    ctx = Context(max_gaussians=N, max_views=len(cams), max_keys=max_keys, max_tiles=tiles)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(args.seed)
+    dls = [torch.randn(3, c.height, c.width, device="cuda", generator=gen) for c in cams]
+    outs = [RenderOut.allocate(c) for c in cams]
+    grads = g.zeros_like()
+
+    def step():
+        for t in grads.planes():
+            t.zero_()
+        ctx.render_fwd(g, cams, args.bg, out=outs)
+        ctx.render_bwd(g, cams, args.bg, outs, dls, grads)
+
+    step()
+    ctx.render_fwd(g, cams, args.bg, out=outs, count_pairs=True)
+    ctx.sync()
+    evaluated, blended = ctx.pair_counts()
+    walked = int(sum(int(o.n_contrib.sum().item()) for o in outs))
+    total_keys = 0
+    for c in cams:
+        pr = ctx.debug_projection(g, c)  # [n][16]: ..., x0, y0, x1, y1, visible
+        vis = pr[:, 15] > 0.5
+        total_keys += int(((pr[vis, 13] - pr[vis, 11]) * (pr[vis, 14] - pr[vis, 12])).sum().item())
+        del pr
+    log(f"[bench] stress pairs evaluated {evaluated:.3e} blended {blended:.3e} walked {walked:.3e} keys {total_keys}")
+    # eager, with stage timers
+    for _ in range(args.warmup):
+        step()
+    ctx.sync()
+    ctx.profile_begin(max_records=args.steps + 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    stages = ctx.profile_end()
+    ctx.sync()
+    eager_ms = e0.elapsed_time(e1) / args.steps
+    per_stage = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    # HIP graph of one step, replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    log(f"[bench] stress eager {eager_ms:.2f} ms/step, graph {graph_ms:.2f} ms/step")
+    bwd_flops = BWD_FLOPS_TEST * walked + BWD_FLOPS_BLEND * blended
+    fwd_flops = FWD_FLOPS_TEST * evaluated + FWD_FLOPS_BLEND * blended
+    line = {
+        "metric": "large-footprint fwd+bwd iters/s @1M Gaussians x 4 views 1920x1080 (HIP graph)",
+        "value": round(1000.0 / graph_ms, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(graph_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": "16x16"},
+        "eager_ms_per_step": round(eager_ms, 3),
+        "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
+        "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
+        "tile_keys": total_keys,
+        "blend_tflops": {"fwd": round(fwd_flops / (per_stage.get("blend_fwd", 0) or 1) * 1e-9, 3),
+                         "bwd": round(bwd_flops / (per_stage.get("blend_bwd", 0) or 1) * 1e-9, 3)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["multiview", "single", "streaming", "serving"], default="multiview")
+    ap.add_argument("--workload", choices=["multiview", "single", "streaming", "serving", "stress"], default="multiview")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--width", type=int, default=1352)
@@ -385,6 +485,7 @@ def main():
     ap.add_argument("--keys-per-tile", type=int, default=1200)
     ap.add_argument("--train-alone", type=int, default=2)
     ap.add_argument("--capacity-requests", type=int, default=500)
+    ap.add_argument("--stress-n", type=int, default=1_000_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -411,6 +512,8 @@ def main():
         return bench_streaming(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "stress":
+        return bench_stress(args)
     log(f"[bench] building workload {args.workload}")
     s = build_workload(args)
     ctx = s["ctx"]

@@ -96,7 +96,9 @@ typedef struct {
   float* sh;
 } dass_grads;
 
-/* Render options.  tile_w x tile_h must be 16x16 in this build. */
+/* Render options.  tile_w, tile_h in {16, 32, 64} pixels (a NULL opts means 16x16): the
+ * tile is the key bin of the binning and sort; the blend splits it into 16x16 sub-tiles.  The
+ * images are the same for every tile size; n_contrib and the keys depend on it. */
 #define DASS_FLAG_COUNT_PAIRS 1u /* render_fwd also counts evaluated / blended (pixel, entry)
                                     pairs (read with dass_debug_pair_counts); slower */
 typedef struct {
@@ -108,8 +110,9 @@ typedef struct {
 typedef struct {
   int32_t max_gaussians; /* capacity of the scenes rendered                     */
   int32_t max_views;     /* views per render call (<= DASS_MAX_VIEWS)            */
-  int64_t max_keys;      /* tile keys per render call, summed over its views     */
-  int64_t max_tiles;     /* tiles per render call, summed over its views         */
+  int64_t max_keys;      /* tile keys per render call, summed over its views;
+                            at most 0xFFFF0000 (keys are indexed with 32 bits)   */
+  int64_t max_tiles;     /* tiles per render call, summed over its views (< 2^31) */
 } dass_limits;
 
 /* ---- context ---------------------------------------------------------------------------- */
@@ -144,7 +147,7 @@ dass_status dass_sync(dass_ctx ctx, dass_stream stream);
  * the transmittance below 1e-4.  out[v] receives view v.  The context keeps the sorted
  * tile lists for the matching render_bwd.
  * Errors: DASS_E_INVALID (null pointers, n > capacity, sh_degree > 3, n_views outside
- * [1, min(max_views, DASS_MAX_VIEWS)], width/height <= 0, tiles other than 16x16);
+ * [1, min(max_views, DASS_MAX_VIEWS)], width/height <= 0, a tile edge not in {16, 32, 64});
  * DASS_E_CAPACITY (n > max_gaussians, total tiles > max_tiles; key overflow via dass_sync). */
 dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
                        int32_t n_views, const float bg[3], dass_image* out,
@@ -157,7 +160,8 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
  * (the historical view-space positional gradient of Sec. 3.4; either may be NULL).  The
  * transmittance of each entry is recovered from T_final walking the list backwards; no
  * per-pixel lists are stored.  Derivatives through an active clamp (alpha = 0.99, colour
- * = 0, Jacobian clamp) are zero.  Float atomics make the sums order-nondeterministic. */
+ * = 0, Jacobian clamp) are zero.  Float atomics make the sums order-nondeterministic.
+ * opts must give the tile size of the matching render_fwd (DASS_E_INVALID otherwise). */
 dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
                        int32_t n_views, const float bg[3], const dass_image* fwd_out,
                        const float* const* dl_drgb, dass_grads* grads, float* gradnorm_sum,
@@ -272,11 +276,26 @@ dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* 
 dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t* vals,
                             int64_t max, int64_t* ranges, int64_t* count);
 
+/* Tile-size autotuner.  For each of the n_candidates options (tile_w, tile_h; flags ignored
+ * except COUNT_PAIRS) runs render_fwd + render_bwd of this workload once to warm up, then
+ * `reps` times between two HIP events on `stream`, and writes the mean milliseconds per
+ * fwd+bwd into ms[c] (host array; -1 for a candidate whose tiles or keys exceed the
+ * context's budgets) and the index of the fastest into *best (host).  out, dl_drgb and grads
+ * are as for render_fwd / render_bwd; grads is accumulated into (scratch for the caller).
+ * Synchronises the stream (not for graph capture) and leaves no state for render_bwd.
+ * DASS_E_CAPACITY if no candidate fits. */
+dass_status dass_autotune_tile(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
+                               int32_t n_views, const float bg[3], dass_image* out,
+                               const float* const* dl_drgb, dass_grads* grads,
+                               const dass_opts* candidates, int32_t n_candidates, int32_t reps,
+                               int32_t* best, float* ms, dass_stream stream);
+
 /* Per-Gaussian projection of g into one camera as render_fwd computes it, [n][16] doubles
  * (device): u, v, A, B, C (conic), opacity, r, g, b, depth, radius, x0, y0, x1, y1 (tile
- * rectangle), visible (integers converted to double). */
+ * rectangle for the tile size of opts, NULL = 16x16), visible (integers converted to
+ * double).  Synchronises the device. */
 dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cam,
-                                  double* out);
+                                  const dass_opts* opts, double* out);
 
 #ifdef __cplusplus
 }

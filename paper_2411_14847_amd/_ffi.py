@@ -16,7 +16,7 @@ MAX_VIEWS = 32
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
            "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
-           "dass_debug_projection", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
+           "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count")
 FLAG_COUNT_PAIRS = 1
 STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
@@ -91,7 +91,9 @@ def lib():
                                      vp]),
             "dass_l1_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), P(vp), P(vp), vp, vp]),
             "dass_debug_keys": (i32, [vp, i32, vp, vp, i64, vp, P(i64)]),
-            "dass_debug_projection": (i32, [vp, P(Gaussians), P(Camera), vp]),
+            "dass_debug_projection": (i32, [vp, P(Gaussians), P(Camera), P(Opts), vp]),
+            "dass_autotune_tile": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(vp), P(Grads), P(Opts),
+                                         i32, i32, P(i32), P(f32), vp]),
             "dass_profile_begin": (i32, [vp, i32]),
             "dass_profile_end": (i32, [vp, P(C.c_double), P(i32)]),
             "dass_debug_pair_counts": (i32, [vp, P(u64), P(u64)]),

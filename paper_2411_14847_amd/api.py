@@ -149,6 +149,7 @@ class Context:
             raise DassError(st, "dass_create failed")
         self.limits = lim
         self.generation = 0  # bumped by every call that replaces the state kept for render_bwd
+        self.tile = (16, 16)  # tile size of render_fwd / render_bwd (16, 32 or 64 per edge)
 
     def close(self):
         if self._h:
@@ -181,7 +182,7 @@ class Context:
         imgs = (F.Image * len(cams))(*[o.struct() for o in out])
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
-        opts = F.Opts(16, 16, F.FLAG_COUNT_PAIRS if count_pairs else 0)
+        opts = F.Opts(self.tile[0], self.tile[1], F.FLAG_COUNT_PAIRS if count_pairs else 0)
         self.generation += 1
         self._check(self._lib.render_fwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs,
                                          C.byref(opts), _stream(stream)))
@@ -194,9 +195,32 @@ class Context:
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
         gr = grads_struct(grads)
-        opts = F.Opts(16, 16, 0)
+        opts = F.Opts(self.tile[0], self.tile[1], 0)
         self._check(self._lib.render_bwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs, dls,
                                          C.byref(gr), _ptr(gradnorm), _ptr(count), C.byref(opts), _stream(stream)))
+
+    TILE_CANDIDATES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64))
+
+    def autotune_tile(self, g: GaussianBuffers, cams: Sequence, bg, out, dl_drgb, grads: GaussianBuffers,
+                      candidates=TILE_CANDIDATES, reps: int = 3, stream=None, apply: bool = True) -> dict:
+        """Times render_fwd + render_bwd of this workload at each candidate tile size (native
+        autotuner; synchronises) and, if `apply`, makes the fastest this context's tile size.
+        Returns {(tw, th): ms or None if it does not fit the budgets}.  `grads` is scratch."""
+        imgs = (F.Image * len(cams))(*[o.struct() for o in out])
+        dls = (C.c_void_p * len(cams))(*[_ptr(d) for d in dl_drgb])
+        bgf = (C.c_float * 3)(*[float(x) for x in bg])
+        gs = g.struct()
+        gr = grads_struct(grads)
+        cand = (F.Opts * len(candidates))(*[F.Opts(int(w), int(h), 0) for w, h in candidates])
+        best = C.c_int32(-1)
+        ms = (C.c_float * len(candidates))()
+        self.generation += 1
+        self._check(self._lib.dass_autotune_tile(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs, dls,
+                                                 C.byref(gr), cand, len(candidates), int(reps), C.byref(best), ms,
+                                                 _stream(stream)))
+        if apply:
+            self.tile = tuple(candidates[best.value])
+        return {tuple(c): (float(ms[i]) if ms[i] >= 0 else None) for i, c in enumerate(candidates)}
 
     def shift_fwd(self, g: GaussianBuffers, out: GaussianBuffers, dyn_idx: torch.Tensor, dpos: torch.Tensor,
                   drot: torch.Tensor, stream=None):
@@ -281,5 +305,7 @@ class Context:
     def debug_projection(self, g: GaussianBuffers, cam):
         out = torch.empty(max(g.n, 1), 16, dtype=torch.float64, device=g.mean.device)
         gs = g.struct()
-        self._check(self._lib.dass_debug_projection(self._h, C.byref(gs), C.byref(camera_struct(cam)), _ptr(out)))
+        opts = F.Opts(self.tile[0], self.tile[1], 0)
+        self._check(self._lib.dass_debug_projection(self._h, C.byref(gs), C.byref(camera_struct(cam)),
+                                                    C.byref(opts), _ptr(out)))
         return out[:g.n].cpu().numpy()

@@ -35,6 +35,7 @@ struct dass_ctx_s {
   bool have_fwd = false;
   int fwd_n = 0, fwd_nv = 0, fwd_stride = 0;
   int64_t fwd_tiles = 0;
+  int fwd_tw = kTile, fwd_th = kTile;
   int fwd_key_buf = 0;
   CamsK fwd_cams{};
 };
@@ -123,8 +124,9 @@ dass_status check_limits(dass_ctx ctx, const dass_limits* l) {
   if (l->max_gaussians < 0 || l->max_views < 1 || l->max_views > DASS_MAX_VIEWS || l->max_keys < 0 ||
       l->max_tiles < 0)
     return fail(ctx, DASS_E_INVALID, "limits out of range");
-  if (l->max_keys > 0xFFFFFFFFll || l->max_tiles > 0x7FFFFFFFll)
-    return fail(ctx, DASS_E_INVALID, "max_keys must be < 2^32 and max_tiles < 2^31");
+  // 32-bit key positions; the margin keeps strided loops over [0, count) from wrapping
+  if (l->max_keys > 0xFFFF0000ll || l->max_tiles > 0x7FFFFFFFll)
+    return fail(ctx, DASS_E_INVALID, "max_keys must be <= 0xFFFF0000 and max_tiles < 2^31");
   if ((int64_t)l->max_views * l->max_gaussians > 0xFFFFFFFFll)
     return fail(ctx, DASS_E_INVALID, "max_views * max_gaussians must be < 2^32");
   return DASS_OK;
@@ -186,7 +188,8 @@ dass_status check_scene(dass_ctx ctx, const dass_gaussians* g) {
   return DASS_OK;
 }
 
-dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, CamsK& out, int64_t& total_tiles) {
+dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, int tw, int th, CamsK& out,
+                      int64_t& total_tiles) {
   if (!cams) return fail(ctx, DASS_E_INVALID, "cams is NULL");
   if (nv < 1 || nv > DASS_MAX_VIEWS || nv > ctx->lim.max_views)
     return fail(ctx, nv > ctx->lim.max_views && nv <= DASS_MAX_VIEWS ? DASS_E_CAPACITY : DASS_E_INVALID,
@@ -208,8 +211,10 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, CamsK& out,
     std::memcpy(k.campos, c.campos, sizeof(k.campos));
     k.W = c.width;
     k.H = c.height;
-    k.TX = (c.width + kTile - 1) / kTile;
-    k.TY = (c.height + kTile - 1) / kTile;
+    k.TX = (c.width + tw - 1) / tw;
+    k.TY = (c.height + th - 1) / th;
+    k.tw = tw;
+    k.th = th;
     k.tile_base = (int)total_tiles;
     total_tiles += (int64_t)k.TX * k.TY;
   }
@@ -219,11 +224,25 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, CamsK& out,
   return DASS_OK;
 }
 
-dass_status check_opts(dass_ctx ctx, const dass_opts* o) {
-  if (o && (o->tile_w != kTile || o->tile_h != kTile))
-    return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (16x16 only)", o->tile_w, o->tile_h);
-  if (o && (o->flags & ~DASS_FLAG_COUNT_PAIRS)) return fail(ctx, DASS_E_INVALID, "unknown option flags");
+bool tile_edge_ok(int e) { return e == 16 || e == 32 || e == 64; }
+
+// Validates the options and returns the tile size (16x16 when o is NULL).
+dass_status check_opts(dass_ctx ctx, const dass_opts* o, int& tw, int& th) {
+  tw = th = kTile;
+  if (!o) return DASS_OK;
+  if (!tile_edge_ok(o->tile_w) || !tile_edge_ok(o->tile_h))
+    return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (edges 16, 32 or 64)", o->tile_w, o->tile_h);
+  if (o->flags & ~DASS_FLAG_COUNT_PAIRS) return fail(ctx, DASS_E_INVALID, "unknown option flags");
+  tw = o->tile_w;
+  th = o->tile_h;
   return DASS_OK;
+}
+
+void set_tiling(ViewsIO& io, int tw, int th) {
+  io.tw = tw;
+  io.th = th;
+  io.sx = tw / kTile;
+  io.sn = (tw / kTile) * (th / kTile);
 }
 
 SceneK scene_of(const dass_gaussians* g) {
@@ -307,12 +326,15 @@ const char* dass_last_error(dass_ctx ctx) { return ctx ? ctx->last_error.c_str()
 dass_status dass_sync(dass_ctx ctx, dass_stream stream) {
   if (!ctx) return DASS_E_INVALID;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  HIP_TRY(ctx, hipStreamSynchronize((hipStream_t)stream));
+  // stream-ordered only: a legacy-stream copy here would also wait for (and, while another
+  // thread captures a graph, conflict with) every other blocking stream of the device
+  hipStream_t st = (hipStream_t)stream;
   uint32_t err = 0;
-  HIP_TRY(ctx, hipMemcpy(&err, ctx->ws.err, sizeof(err), hipMemcpyDeviceToHost));
+  HIP_TRY(ctx, hipMemcpyAsync(&err, ctx->ws.err, sizeof(err), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
   if (err) {
-    HIP_TRY(ctx, hipMemset(ctx->ws.err, 0, sizeof(uint32_t)));
-    HIP_TRY(ctx, hipDeviceSynchronize());
+    launch_fill_u32(ctx->ws.err, 0u, 1, st);
+    HIP_TRY(ctx, hipStreamSynchronize(st));
     if (err & kErrKeyOverflow) return fail(ctx, DASS_E_CAPACITY, "tile-key buffer overflow (raise max_keys)");
   }
   return DASS_OK;
@@ -323,15 +345,17 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  if ((s = check_opts(ctx, opts)) != DASS_OK) return s;
+  int tw, th;
+  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
   if (!bg || !out) return fail(ctx, DASS_E_INVALID, "bg or out is NULL");
   CamsK ck;
   int64_t total_tiles = 0;
-  if ((s = make_cams(ctx, cams, n_views, ck, total_tiles)) != DASS_OK) return s;
+  if ((s = make_cams(ctx, cams, n_views, tw, th, ck, total_tiles)) != DASS_OK) return s;
   if (g->n > ctx->lim.max_gaussians)
     return fail(ctx, DASS_E_CAPACITY, "n=%d exceeds max_gaussians %d", g->n, ctx->lim.max_gaussians);
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
+  set_tiling(io, tw, th);
   for (int v = 0; v < n_views; v++) {
     if (!out[v].rgb || !out[v].t_final || !out[v].n_contrib)
       return fail(ctx, DASS_E_INVALID, "out[%d] has a NULL buffer", v);
@@ -385,6 +409,8 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   ctx->fwd_nv = n_views;
   ctx->fwd_stride = g->capacity;
   ctx->fwd_tiles = total_tiles;
+  ctx->fwd_tw = tw;
+  ctx->fwd_th = th;
   ctx->fwd_key_buf = kcur;
   ctx->fwd_cams = ck;
   return DASS_OK;
@@ -396,16 +422,18 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  if ((s = check_opts(ctx, opts)) != DASS_OK) return s;
+  int tw, th;
+  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
   if (!bg || !fwd_out || !dl_drgb || !grads) return fail(ctx, DASS_E_INVALID, "NULL argument");
   CamsK ck;
   int64_t total_tiles = 0;
-  if ((s = make_cams(ctx, cams, n_views, ck, total_tiles)) != DASS_OK) return s;
+  if ((s = make_cams(ctx, cams, n_views, tw, th, ck, total_tiles)) != DASS_OK) return s;
   if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
-      ctx->fwd_stride != g->capacity)
+      ctx->fwd_stride != g->capacity || ctx->fwd_tw != tw || ctx->fwd_th != th)
     return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
+  set_tiling(io, tw, th);
   for (int v = 0; v < n_views; v++) {
     if (!fwd_out[v].t_final || !fwd_out[v].n_contrib || !dl_drgb[v])
       return fail(ctx, DASS_E_INVALID, "view %d: NULL t_final, n_contrib or dl_drgb", v);
@@ -630,16 +658,19 @@ dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t
   return check_launch(ctx, "dass_debug_keys");
 }
 
-dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cam, double* out) {
+dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cam,
+                                  const dass_opts* opts, double* out) {
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
   if (!out) return fail(ctx, DASS_E_INVALID, "out is NULL");
+  int tw, th;
+  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
   CamsK ck;
   int64_t total = 0;
   const int64_t keep = ctx->ws.cap_tiles;
   ctx->ws.cap_tiles = INT64_MAX;  // the tile budget does not apply to this export
-  s = make_cams(ctx, cam, 1, ck, total);
+  s = make_cams(ctx, cam, 1, tw, th, ck, total);
   ctx->ws.cap_tiles = keep;
   if (s != DASS_OK) return s;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -690,6 +721,66 @@ dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* 
   *evaluated = h[0];
   *blended = h[1];
   return DASS_OK;
+}
+
+dass_status dass_autotune_tile(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                               const float bg[3], dass_image* out, const float* const* dl_drgb, dass_grads* grads,
+                               const dass_opts* candidates, int32_t n_candidates, int32_t reps, int32_t* best,
+                               float* ms, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!candidates || n_candidates < 1 || reps < 1 || !best || !ms)
+    return fail(ctx, DASS_E_INVALID, "autotune: bad candidate list, reps or output pointers");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  dass_status s = DASS_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    s = fail(ctx, DASS_E_HIP, "autotune: hipEventCreate failed");
+  }
+  *best = -1;
+  float best_ms = 0.f;
+  for (int c = 0; c < n_candidates && s == DASS_OK; c++) {
+    ms[c] = -1.f;  // stays negative for a candidate that does not fit the context's budgets
+    const dass_opts* o = &candidates[c];
+    auto one = [&]() -> dass_status {
+      dass_status r = render_fwd(ctx, g, cams, n_views, bg, out, o, stream);
+      if (r == DASS_OK) r = render_bwd(ctx, g, cams, n_views, bg, out, dl_drgb, grads, nullptr, nullptr, o, stream);
+      return r;
+    };
+    dass_status r = one();  // warm-up; also finds a tile or key budget this tile size exceeds
+    if (r == DASS_OK) r = dass_sync(ctx, stream);
+    if (r == DASS_E_CAPACITY) continue;
+    if (r != DASS_OK) {
+      s = r;
+      break;
+    }
+    if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) {
+      s = fail(ctx, DASS_E_HIP, "autotune: hipEventRecord failed");
+      break;
+    }
+    for (int i = 0; i < reps && r == DASS_OK; i++) r = one();
+    if (r == DASS_OK && hipEventRecord(e1, (hipStream_t)stream) != hipSuccess)
+      r = fail(ctx, DASS_E_HIP, "autotune: hipEventRecord failed");
+    if (r == DASS_OK) r = dass_sync(ctx, stream);
+    if (r != DASS_OK) {
+      s = r;
+      break;
+    }
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      s = fail(ctx, DASS_E_HIP, "autotune: hipEventElapsedTime failed");
+      break;
+    }
+    ms[c] = t / (float)reps;
+    if (*best < 0 || ms[c] < best_ms) {
+      *best = c;
+      best_ms = ms[c];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  ctx->have_fwd = false;  // the kept state belongs to the last candidate: render again before render_bwd
+  if (s == DASS_OK && *best < 0) s = fail(ctx, DASS_E_CAPACITY, "autotune: no candidate fits the context's budgets");
+  return s;
 }
 
 }  // extern "C"

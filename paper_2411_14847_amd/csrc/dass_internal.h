@@ -17,8 +17,11 @@ constexpr double kDilation = (double)0.3f;
 constexpr double kNearZ = (double)0.2f;
 constexpr double kClip = (double)1.3f;
 
-constexpr int kTile = 16;          // tile edge in pixels
+constexpr int kTile = 16;          // edge of the pixel block one wave blends (a sub-tile)
 constexpr int kTilePix = kTile * kTile;
+// Tile edges a render call may use (multiples of the sub-tile): a tile of tw x th pixels is one
+// key bin; the blend gives each of its (tw/16)(th/16) sub-tiles its own wave.
+constexpr int kMaxTileEdge = 64;
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dealt round-robin
 
 // Device error bits (ctx->d_err)
@@ -31,6 +34,7 @@ struct CamK {
   float fx, fy, cx, cy;
   float campos[3];
   int W, H, TX, TY;
+  int tw, th;     // tile size in pixels
   int tile_base;  // first global tile index of this view
 };
 struct CamsK {
@@ -56,6 +60,8 @@ struct ViewIO {
 };
 struct ViewsIO {
   ViewIO v[DASS_MAX_VIEWS];
+  int tw, th;  // tile size in pixels
+  int sx, sn;  // 16x16 sub-tiles per tile row, per tile
 };
 
 // The projected record of one (view, Gaussian), as the blend consumes it (48 bytes).

@@ -208,10 +208,11 @@ __device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD
   V.radius = (int)r;
   V.u = ((fx * tx) / tz) + (double)cam.cx;
   V.v = ((fy * ty) / tz) + (double)cam.cy;
-  const double fx0 = floor((V.u - r) / (double)kTile);
-  const double fx1 = floor(((V.u + r) + (double)(kTile - 1)) / (double)kTile);
-  const double fy0 = floor((V.v - r) / (double)kTile);
-  const double fy1 = floor(((V.v + r) + (double)(kTile - 1)) / (double)kTile);
+  const double tw = (double)cam.tw, th = (double)cam.th;
+  const double fx0 = floor((V.u - r) / tw);
+  const double fx1 = floor(((V.u + r) + (tw - 1.0)) / tw);
+  const double fy0 = floor((V.v - r) / th);
+  const double fy1 = floor(((V.v + r) + (th - 1.0)) / th);
   V.x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.TX);
   V.x1 = (int)fmin(fmax(fx1, 0.0), (double)cam.TX);
   V.y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.TY);

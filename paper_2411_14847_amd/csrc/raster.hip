@@ -6,9 +6,10 @@
 // in p order and sorted stably on the tile bits only; the stable order inside a tile is the
 // depth order.  Ranges are the [first, last+1) of each tile id.
 //
-// Blend.  One 256-thread workgroup per 16x16 tile; each wave owns an 8x8 quadrant.  The tile's
-// list is consumed in batches of 256 entries staged in LDS; every lane walks its pixel front
-// to back, and the workgroup stops as soon as every pixel has hit the transmittance stop.
+// Blend.  One wave per 16x16 sub-tile of a tile (a 16x16 tile is its own sub-tile); lane
+// (qx, qy) owns a 2x2 pixel block.  The tile's list is consumed in batches of 128 entries, each
+// culled against the wave's sub-tile and compacted into LDS; every lane walks its pixels front
+// to back, and the wave stops as soon as every pixel has hit the transmittance stop.
 // The backward recomputes each entry's alpha per batch, recovers the transmittance by dividing
 // out (1 - alpha) from T_final while walking backwards, sums each Gaussian's 9 gradient terms
 // over the wave and issues one vector atomic per (Gaussian, wave).
@@ -189,22 +190,25 @@ __device__ __forceinline__ float wave_reduce9(float* v, int lane) {
 __constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, -1, -1};
 
 template <bool COUNT>
-__global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
+__global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
                                                       unsigned long long* __restrict__ pairs) {
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
   __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
-  const int b = xcd_logical(blockIdx.x, per);
-  if (b >= total_tiles) return;
+  const int lb = xcd_logical(blockIdx.x, per);
+  if (lb >= total_blocks) return;
+  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, 16x16 sub-tile of it
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
+  const int ox = tx * io.tw + (sub % io.sx) * kTile, oy = ty * io.th + (sub / io.sx) * kTile;
+  if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
   const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
-  const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
+  const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   float T[4], c0[4], c1[4], c2[4];
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   bool done[4];
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
     T[k] = 1.f;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   }
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   }
 }
 
-__global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_tiles, int per, float bg0,
+__global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
                                                       const uint32_t* __restrict__ gid_s, int n,
@@ -307,15 +311,18 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
   __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
   __shared__ uint32_t s_p[kBatchB];
-  const int b = xcd_logical(blockIdx.x, per);
-  if (b >= total_tiles) return;
+  const int lb = xcd_logical(blockIdx.x, per);
+  if (lb >= total_blocks) return;
+  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, 16x16 sub-tile of it
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
+  const int ox = tx * io.tw + (sub % io.sx) * kTile, oy = ty * io.th + (sub / io.sx) * kTile;
+  if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
   const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
-  const float fx0 = (float)(tx * kTile), fy0 = (float)(ty * kTile);
+  const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const int64_t hw = (int64_t)V.W * V.H;
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   int my_max = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    const int px = tx * kTile + qx + (k & 1), py = ty * kTile + qy + (k >> 1);
+    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
     T[k] = 1.f;
     dC0[k] = dC1[k] = dC2[k] = 0.f;
     last[k] = 0;
@@ -493,23 +500,27 @@ void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hip
 
 static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNumXcd - 1) / kNumXcd); }
 
+// One wave per (tile, 16x16 sub-tile); the sub-tiles of a tile are consecutive logical blocks,
+// so they run on the same XCD and share its L2 for the tile's list and records.
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
                       const uint32_t* vals, bool count_pairs, hipStream_t st) {
-  if (total_tiles == 0) return;
-  const int per = per_xcd(total_tiles);
+  const int64_t total = total_tiles * io.sn;
+  if (total == 0) return;
+  const int per = per_xcd(total);
   if (count_pairs)
-    k_blend_fwd<true><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+    k_blend_fwd<true><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2],
                                                            ws.ranges, vals, ws.rec_s, ws.pairs);
   else
-    k_blend_fwd<false><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2],
+    k_blend_fwd<false><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2],
                                                             ws.ranges, vals, ws.rec_s, nullptr);
 }
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
                       const uint32_t* vals, int n, hipStream_t st) {
-  if (total_tiles == 0) return;
-  const int per = per_xcd(total_tiles);
-  k_blend_bwd<<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total_tiles, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+  const int64_t total = total_tiles * io.sn;
+  if (total == 0) return;
+  const int per = per_xcd(total);
+  k_blend_bwd<<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
                                                    ws.rec_s, ws.gid_s, n, ws.g2d);
 }
 

@@ -21,7 +21,8 @@ from typing import List, Optional
 import numpy as np
 import torch
 
-from .api import Context, GaussianBuffers, RenderOut
+from ._ffi import DASS_E_CAPACITY
+from .api import Context, DassError, GaussianBuffers, RenderOut
 
 
 def tiles_of(cam) -> int:
@@ -162,7 +163,9 @@ class RenderServer:
                         self.latencies.append(t_done - r.arrival)
                     self.completed += len(slot.batch)
                     done += len(slot.batch)
-                except RuntimeError:
+                except DassError as e:
+                    if e.status != DASS_E_CAPACITY:
+                        raise
                     # key budget exceeded: put the batch back at the front and admit smaller batches
                     self.retried += len(slot.batch)
                     for r in reversed(slot.batch):

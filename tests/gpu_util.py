@@ -39,25 +39,26 @@ def tile_pixel_mask(cam, tiles, tile=16):
     return m
 
 
-def radius_flag_pixels(proj, cam, tile=16):
+def radius_flag_pixels(proj, cam, tile=(16, 16)):
     """Pixels of tiles on or next to the rectangle of a Gaussian whose radius sits within rounding
     of an integer (its rectangle may differ by one tile between float64 implementations)."""
-    TX = (cam.width + tile - 1) // tile
-    TY = (cam.height + tile - 1) // tile
+    tw, th = (tile, tile) if np.isscalar(tile) else tile
+    TX = (cam.width + tw - 1) // tw
+    TY = (cam.height + th - 1) // th
     m = np.zeros((cam.height, cam.width), bool)
     for g in np.nonzero(proj.flags & oracle.FLAG_RADIUS)[0]:
         x0, y0, x1, y1 = proj.rect[g]
         if not proj.visible[g]:
             continue
-        xs = slice(max(0, x0 - 1) * tile, min(TX, x1 + 1) * tile)
-        ys = slice(max(0, y0 - 1) * tile, min(TY, y1 + 1) * tile)
+        xs = slice(max(0, x0 - 1) * tw, min(TX, x1 + 1) * tw)
+        ys = slice(max(0, y0 - 1) * th, min(TY, y1 + 1) * th)
         m[ys, xs] = True
     return m
 
 
-def excluded_pixels(vr, cam, grad=False):
+def excluded_pixels(vr, cam, grad=False, tile=(16, 16)):
     flags = oracle.PIXEL_GRAD_FLAGS if grad else oracle.PIXEL_VALUE_FLAGS
-    return ((vr.flags & flags) != 0) | radius_flag_pixels(vr.proj, cam)
+    return ((vr.flags & flags) != 0) | radius_flag_pixels(vr.proj, cam, tile)
 
 
 def assert_grad_close(name, got, want, exclude=None):

@@ -34,11 +34,20 @@ def small_multiview(seed=3, n=3000, views=3, W=200, H=150, deg=3):
     return scene, cams, dls
 
 
+def large_footprint_sub(seed=0):
+    """64 Gaussians from the large-footprint generator (SH3, log-scales N(-2, 0.5)), its four
+    cameras at 32x32, upstream gradients N(0, 1)."""
+    scene, cams = synth.large_footprint_scene(seed, n=64, width=32, height=32)
+    rng = np.random.default_rng(seed + 1)
+    return scene, cams, [rng.normal(size=(3, 32, 32)).astype(np.float32) for _ in cams]
+
+
 CASES = {
     "single_view_2000": lambda: synth.single_view_scene(0),
     "multiview_sh3_ragged": lambda: small_multiview(),
     "multiview_sh1": lambda: small_multiview(seed=5, n=1500, views=2, W=97, H=61, deg=1),
     "tiny_dense": lambda: synth.tiny_scene(2, 300, 40, 36, sh_degree=2, log_scale_mu=-2.0),
+    "large_footprint_64_4x32x32": large_footprint_sub,
 }
 
 

@@ -1,0 +1,138 @@
+"""Tile sizes other than 16x16 (one key bin per tw x th tile, one wave per 16x16 sub-tile) and
+the native tile autotuner, against the CPU oracle run at the same tile size.
+
+Keys, values, ranges and n_contrib depend on the tile size and must match the oracle's
+bit-exactly; images and T_final must be bit-identical to the 16x16 render (same blended
+sequence per pixel, same float32 operations) and within 1e-4 of the oracle; gradients within
+the per-tensor bound of the 16x16 tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import IMG_TOL, assert_grad_close, excluded_pixels, log, make_ctx, to_gpu
+from test_gpu_parity import BG, large_footprint_sub, small_multiview
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(32, 16), (16, 32), (32, 32), (64, 32), (64, 64)]
+CASES = {
+    "multiview_sh3_ragged": lambda: small_multiview(),
+    "tiny_dense": lambda: synth.tiny_scene(2, 300, 40, 36, sh_degree=2, log_scale_mu=-2.0),
+    "large_footprint_64_4x32x32": large_footprint_sub,
+}
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("case", list(CASES))
+def test_tile_keys_images_match_oracle(case, tile):
+    scene, cams, _ = CASES[case]()
+    log(f"[tile {tile[0]}x{tile[1]}] {case}")
+    g = to_gpu(scene)
+    ref_ctx = make_ctx(scene.n, cams)
+    ref = ref_ctx.render_fwd(g, cams, BG)
+    ctx = make_ctx(scene.n, cams)
+    ctx.tile = tile
+    out = ctx.render_fwd(g, cams, BG)
+    ctx.sync()
+    ref_ctx.sync()
+    for v, cam in enumerate(cams):
+        assert torch.equal(out[v].rgb, ref[v].rgb) and torch.equal(out[v].t_final, ref[v].t_final)
+        p = oracle.project(scene, cam, tile)
+        assert not np.any(p.flags & oracle.FLAG_RADIUS)
+        k, val, r = oracle.keys(p, cam, tile)
+        TX, TY = oracle.tiles_of(cam, tile)
+        gk, gv, gr = ctx.debug_keys(v, k.size + 16, TX * TY)
+        np.testing.assert_array_equal(gk, k)
+        np.testing.assert_array_equal(gv, val)
+        np.testing.assert_array_equal(gr, r)
+        vr = oracle.render_view(scene, cam, bg=BG, tile=tile, proj=p, key_data=(k, val, r))
+        ex = excluded_pixels(vr, cam, tile=tile)
+        assert np.abs(out[v].rgb.cpu().numpy() - vr.rgb)[:, ~ex].max() <= IMG_TOL
+        np.testing.assert_array_equal(out[v].n_contrib.cpu().numpy()[~ex], vr.n_contrib[~ex])
+
+
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
+@pytest.mark.parametrize("case", ["multiview_sh3_ragged", "large_footprint_64_4x32x32"])
+def test_tile_gradients_match_oracle(case, tile):
+    scene, cams, dls = CASES[case]()
+    log(f"[tile grad {tile[0]}x{tile[1]}] {case}")
+    renders = [oracle.render_view(scene, c, bg=BG, tile=tile) for c in cams]
+    dls = [d.copy() for d in dls]
+    for d, vr, cam in zip(dls, renders, cams):
+        d[:, excluded_pixels(vr, cam, grad=True, tile=tile)] = 0.0
+    og, _, ogn, ocnt = oracle.render_backward(scene, cams, dls, bg=BG, tile=tile, renders=renders)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    ctx.tile = tile
+    out = ctx.render_fwd(g, cams, BG)
+    grads = g.zeros_like()
+    gn = torch.zeros(g.capacity, device="cuda")
+    cnt = torch.zeros(g.capacity, dtype=torch.int32, device="cuda")
+    ctx.render_bwd(g, cams, BG, out, [torch.as_tensor(d, device="cuda") for d in dls], grads, gn, cnt)
+    ctx.sync()
+    gflag = np.zeros(scene.n, bool)
+    for cam in cams:
+        gflag |= (oracle.project(scene, cam, tile).flags & oracle.GAUSS_GRAD_FLAGS) != 0
+    for name in ("mean", "quat", "log_scale", "logit", "sh"):
+        got = getattr(grads, name)[..., :scene.n].cpu().numpy()
+        rel = assert_grad_close(name, got, getattr(og, name), exclude=gflag)
+        log(f"  {name}: max rel err (significant) {rel:.2e}")
+    np.testing.assert_array_equal(cnt[:scene.n].cpu().numpy(), ocnt)
+    assert_grad_close("gradnorm", gn[:scene.n].cpu().numpy(), ogn, exclude=gflag)
+
+
+def test_backward_rejects_a_tile_size_other_than_the_forwards():
+    from paper_2411_14847_amd import DassError
+    scene, cams, dls = small_multiview(seed=4, n=500, views=2, W=64, H=48)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    ctx.tile = (32, 32)
+    out = ctx.render_fwd(g, cams, BG)
+    ctx.tile = (16, 16)
+    with pytest.raises(DassError):
+        ctx.render_bwd(g, cams, BG, out, [torch.as_tensor(d, device="cuda") for d in dls], g.zeros_like())
+    ctx.tile = (48, 16)
+    with pytest.raises(DassError):
+        ctx.render_fwd(g, cams, BG)
+    ctx.sync()
+
+
+def test_autotuner_picks_a_timed_candidate_and_keeps_parity():
+    scene, cams, dls = small_multiview(seed=6, n=4000, views=3, W=320, H=200)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    out = ctx.render_fwd(g, cams, BG)
+    dl_t = [torch.as_tensor(d, device="cuda") for d in dls]
+    scratch = g.zeros_like()
+    res = ctx.autotune_tile(g, cams, BG, out, dl_t, scratch, reps=2)
+    log(f"  autotune: {res}; chose {ctx.tile}")
+    assert ctx.tile in res and res[ctx.tile] is not None
+    assert res[ctx.tile] == min(v for v in res.values() if v is not None)
+    out = ctx.render_fwd(g, cams, BG)
+    ctx.sync()
+    for v, cam in enumerate(cams):
+        vr = oracle.render_view(scene, cam, bg=BG, tile=ctx.tile)
+        ex = excluded_pixels(vr, cam, tile=ctx.tile)
+        assert np.abs(out[v].rgb.cpu().numpy() - vr.rgb)[:, ~ex].max() <= IMG_TOL
+        np.testing.assert_array_equal(out[v].n_contrib.cpu().numpy()[~ex], vr.n_contrib[~ex])
+
+
+def test_autotuner_marks_candidates_over_budget():
+    scene, cams, dls = small_multiview(seed=7, n=3000, views=2, W=256, H=160)
+    g = to_gpu(scene)
+    keys16 = sum(int(oracle.keys(oracle.project(scene, c), c)[0].size) for c in cams)
+    keys32 = sum(int(oracle.keys(oracle.project(scene, c, (32, 32)), c, (32, 32))[0].size) for c in cams)
+    assert keys32 < keys16
+    from paper_2411_14847_amd import Context
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    ctx = Context(max_gaussians=scene.n, max_views=len(cams), max_keys=keys32, max_tiles=tiles)
+    ctx.tile = (32, 32)
+    out = ctx.render_fwd(g, cams, BG)
+    dl_t = [torch.as_tensor(d, device="cuda") for d in dls]
+    res = ctx.autotune_tile(g, cams, BG, out, dl_t, g.zeros_like(), candidates=((16, 16), (32, 32)), reps=1)
+    log(f"  autotune under a tight key budget: {res}")
+    assert res[(16, 16)] is None and res[(32, 32)] is not None and ctx.tile == (32, 32)
+    ctx.sync()

@@ -371,6 +371,52 @@ def test_gradients_match_finite_differences(seed, deg):
     assert checked > 0.9 * (checked + skipped)
 
 
+def test_large_footprint_subscene_gradients_match_finite_differences():
+    """64 Gaussians of the large-footprint generator (SH3, log-scales N(-2, 0.5)) seen by its four
+    cameras at 32x32: the summed-over-views gradient of L = sum_v <dl_v, render_v> against central
+    differences, on a seeded sample of 240 parameter elements."""
+    sc, cams = synth.large_footprint_scene(0, n=64, width=32, height=32)
+    rng = np.random.default_rng(17)
+    dls = [rng.normal(size=(3, 32, 32)) for _ in cams]
+    bg = (0.1, 0.2, 0.3)
+    g, _, _, _ = oracle.render_backward(sc, cams, dls, bg=bg)
+    sc64 = synth.Scene(sc.mean.astype(np.float64), sc.quat.astype(np.float64), sc.log_scale.astype(np.float64),
+                       sc.logit.astype(np.float64), sc.sh.astype(np.float64), 3)
+
+    def loss_sig():
+        tot, sig = 0.0, []
+        for cam, dl in zip(cams, dls):
+            vr = oracle.render_view(sc64, cam, bg=bg)
+            tot += float(np.sum(vr.rgb * dl))
+            sig.append(vr.keys.tobytes() + vr.signature.tobytes())
+        return tot, sig
+
+    names = ("mean", "quat", "log_scale", "logit", "sh")
+    sizes = [getattr(sc64, nm).size for nm in names]
+    picks = rng.choice(sum(sizes), size=240, replace=False)
+    checked = skipped = 0
+    for flat in picks:
+        k = int(np.searchsorted(np.cumsum(sizes), flat, side="right"))
+        name = names[k]
+        arr = getattr(sc64, name)
+        idx = np.unravel_index(int(flat - (np.cumsum(sizes)[k - 1] if k else 0)), arr.shape)
+        x = arr[idx]
+        h = 1e-6 * max(1.0, abs(x))
+        arr[idx] = x + h
+        lp, sp = loss_sig()
+        arr[idx] = x - h
+        lm, sm = loss_sig()
+        arr[idx] = x
+        if sp != sm:
+            skipped += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        ana = getattr(g, name)[idx]
+        assert abs(ana - fd) <= 2e-5 * max(abs(fd), 1e-3) + 1e-7, f"{name}{idx}: analytic {ana} fd {fd}"
+        checked += 1
+    assert checked > 0.9 * (checked + skipped)
+
+
 # ------------------------------------------------------------------------------------------
 # Shift (Sec. 3.3): p' = p + mu_n, q' = norm(q) x norm(sigma_n)
 # ------------------------------------------------------------------------------------------
