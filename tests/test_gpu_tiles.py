@@ -2,9 +2,10 @@
 the native tile autotuner, against the CPU oracle run at the same tile size.
 
 Keys, values, ranges and n_contrib depend on the tile size and must match the oracle's
-bit-exactly; images and T_final must be bit-identical to the 16x16 render (same blended
-sequence per pixel, same float32 operations) and within 1e-4 of the oracle; gradients within
-the per-tensor bound of the 16x16 tests.
+bit-exactly; images within 1e-4 of the oracle at the same tile size, gradients within the
+per-tensor bound of the 16x16 tests.  (Images themselves depend slightly on the tile size: a
+Gaussian reaches a pixel only if its 3-sigma rectangle, rounded out to whole tiles, covers the
+pixel's tile, and its alpha can stay above 1/255 a little beyond 3 sigma.)
 """
 import numpy as np
 import pytest
@@ -31,15 +32,11 @@ def test_tile_keys_images_match_oracle(case, tile):
     scene, cams, _ = CASES[case]()
     log(f"[tile {tile[0]}x{tile[1]}] {case}")
     g = to_gpu(scene)
-    ref_ctx = make_ctx(scene.n, cams)
-    ref = ref_ctx.render_fwd(g, cams, BG)
     ctx = make_ctx(scene.n, cams)
     ctx.tile = tile
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
-    ref_ctx.sync()
     for v, cam in enumerate(cams):
-        assert torch.equal(out[v].rgb, ref[v].rgb) and torch.equal(out[v].t_final, ref[v].t_final)
         p = oracle.project(scene, cam, tile)
         assert not np.any(p.flags & oracle.FLAG_RADIUS)
         k, val, r = oracle.keys(p, cam, tile)
@@ -51,7 +48,9 @@ def test_tile_keys_images_match_oracle(case, tile):
         vr = oracle.render_view(scene, cam, bg=BG, tile=tile, proj=p, key_data=(k, val, r))
         ex = excluded_pixels(vr, cam, tile=tile)
         assert np.abs(out[v].rgb.cpu().numpy() - vr.rgb)[:, ~ex].max() <= IMG_TOL
+        assert np.abs(out[v].t_final.cpu().numpy() - vr.t_final)[~ex].max() <= IMG_TOL
         np.testing.assert_array_equal(out[v].n_contrib.cpu().numpy()[~ex], vr.n_contrib[~ex])
+        assert ex.mean() <= 0.01
 
 
 @pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
