@@ -292,7 +292,8 @@ def bench_serving(args):
     g = _scene_buffers(scene, cap)
     gt = _scene_buffers(scene, N)
     gt_next = gt.clone()
-    cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, use_graph=True)
+    cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, use_graph=True,
+                       max_inflight=args.max_inflight)
     tr = Trainer(ctx, g, cams, max_dynamic=int(round(0.1 * N)), cfg=cfg)
     snaps = SceneSnapshots(g)
     snaps.publish(g)
@@ -392,12 +393,16 @@ def bench_stress(args):
         ctx.render_fwd(g, cams, args.bg, out=outs)
         ctx.render_bwd(g, cams, args.bg, outs, dls, grads)
 
+    tuned = None
+    if not args.no_autotune:
+        tuned = ctx.autotune_tile(g, cams, args.bg, outs, dls, grads, reps=2)
+        log(f"[bench] stress autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
     step()
     ctx.render_fwd(g, cams, args.bg, out=outs, count_pairs=True)
     ctx.sync()
     evaluated, blended = ctx.pair_counts()
     walked = int(sum(int(o.n_contrib.sum().item()) for o in outs))
-    total_keys = 0
+    total_keys = 0  # at the tile size in use
     for c in cams:
         pr = ctx.debug_projection(g, c)  # [n][16]: ..., x0, y0, x1, y1, visible
         vis = pr[:, 15] > 0.5
@@ -445,7 +450,8 @@ def bench_stress(args):
         "value": round(1000.0 / graph_ms, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(graph_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": "16x16"},
+        "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": f"{ctx.tile[0]}x{ctx.tile[1]}"},
+        "autotune_ms": {f"{w}x{h}": v for (w, h), v in tuned.items()} if tuned else None,
         "eager_ms_per_step": round(eager_ms, 3),
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
         "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
@@ -486,6 +492,11 @@ def main():
     ap.add_argument("--train-alone", type=int, default=2)
     ap.add_argument("--capacity-requests", type=int, default=500)
     ap.add_argument("--stress-n", type=int, default=1_000_000)
+    ap.add_argument("--max-inflight", type=int, default=2,
+                    help="training iterations queued at once while serving (0 = unbounded)")
+    ap.add_argument("--no-autotune", action="store_true", help="stress: keep 16x16 tiles")
+    ap.add_argument("--tile-autotune", action="store_true",
+                    help="multiview/single: pick the tile size with the native autotuner before timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -517,6 +528,12 @@ def main():
     log(f"[bench] building workload {args.workload}")
     s = build_workload(args)
     ctx = s["ctx"]
+    train_step(s, 1, args)
+    tuned = None
+    if args.tile_autotune:
+        # native autotuner over tile sizes on this workload (outside the timed region)
+        tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3)
+        log(f"[bench] autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
     # pair counts of the blend (outside the timed region)
     train_step(s, 1, args)
     ctx.render_fwd(s["gs"], s["cams"], args.bg, out=s["outs"], count_pairs=True)
@@ -561,8 +578,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": s["name"], "n_gaussians": s["N"], "sh_degree": int(s["g"].sh_degree),
-                   "views": len(cams), "width": cams[0].width, "height": cams[0].height, "tile": "16x16",
+                   "views": len(cams), "width": cams[0].width, "height": cams[0].height,
+                   "tile": f"{ctx.tile[0]}x{ctx.tile[1]}",
                    "n_dynamic": s["nd"], "densify_k": args.densify_k, "parallelism": "single GPU"},
+        "tile_autotune_ms": {f"{w}x{h}": v for (w, h), v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},

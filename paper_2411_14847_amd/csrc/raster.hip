@@ -47,43 +47,64 @@ __global__ __launch_bounds__(256) void k_gather_sorted(int n, int64_t vn, const 
   inv[i] = (uint32_t)p;
 }
 
-// Each wave takes 64 consecutive sorted positions and writes their keys one Gaussian at a time
-// with all 64 lanes, so consecutive lanes write consecutive keys.
+// Each wave takes 64 consecutive sorted positions (Gaussian-views) and writes all their keys
+// with the keys spread evenly over the lanes: lane l writes keys l, l + 64, ... of the wave's
+// run, finding the owning Gaussian by a binary search over the run's end offsets in LDS.  The
+// stores of a wave are consecutive, whatever the tile counts.
 __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams, const uint32_t* __restrict__ tt_s,
                                                    const uint2* __restrict__ rect_s, const uint64_t* __restrict__ off,
                                                    int64_t cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ err) {
-  const int lane = threadIdx.x & 63;
+  __shared__ uint32_t s_end[4][64];   // end of each Gaussian's keys, relative to the wave's first key
+  __shared__ uint4 s_g[4][64];        // key of the rectangle's first tile, TX, width, 1/width
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first position of this wave
+  if (p0 >= vn) return;  // uniform over the wave
   const int64_t pm = p0 + lane;
+  const bool valid = pm < vn;
   uint32_t my_tt = 0;
-  uint2 my_r = make_uint2(0, 0);
   uint64_t my_off = 0;
-  if (pm < vn) {
+  if (valid) {
     my_tt = tt_s[pm];
-    my_r = rect_s[pm];
     my_off = off[pm];
     if (my_off + my_tt > (uint64_t)cap) atomicOr(err, kErrKeyOverflow);
+    const uint2 r = rect_s[pm];
+    const int v = (int)(pm / n);
+    const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF;
+    const int w = max(x1 - x0, 1);
+    const int TX = cams.c[v].TX;
+    s_g[wave][lane] = make_uint4((uint32_t)(cams.c[v].tile_base + y0 * TX + x0), (uint32_t)TX, (uint32_t)w,
+                                 __float_as_uint(1.0f / (float)w));
   }
-  uint64_t pending = __ballot(my_tt > 0);
-  while (pending) {
-    const int src = __ffsll((unsigned long long)pending) - 1;
-    pending &= pending - 1;
-    const uint32_t tt = __shfl(my_tt, src, 64);
-    const uint32_t rx = __shfl(my_r.x, src, 64), ry = __shfl(my_r.y, src, 64);
-    const uint64_t base = __shfl(my_off, src, 64);
-    const int64_t p = p0 + src;
-    const int v = (int)(p / n);
-    const int x0 = rx & 0xFFFF, y0 = rx >> 16, x1 = ry & 0xFFFF;
-    const int w = x1 - x0;
-    const int tile0 = cams.c[v].tile_base, TX = cams.c[v].TX;
-    for (uint32_t i = lane; i < tt; i += 64) {
-      const uint64_t k = base + i;
-      if (k < (uint64_t)cap) {
-        const int ty = y0 + (int)(i / (uint32_t)w), tx = x0 + (int)(i % (uint32_t)w);
-        keys[k] = (uint32_t)(tile0 + ty * TX + tx);
-        vals[k] = (uint32_t)p;
-      }
+  const uint64_t first = __shfl(my_off, 0, 64);
+  const uint32_t end = valid ? (uint32_t)(my_off - first) + my_tt : 0xFFFFFFFFu;  // non-decreasing over lanes
+  s_end[wave][lane] = end;
+  const int last = (int)min((int64_t)63, vn - 1 - p0);
+  const uint32_t total = __shfl(end, last, 64);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint32_t k = lane; k < total; k += 64) {
+    int src = 0;  // number of Gaussians whose keys end at or before k
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (s_end[wave][src + step - 1] <= k) src += step;
+    const uint32_t i = k - (src ? s_end[wave][src - 1] : 0u);  // key index within the Gaussian
+    const uint4 gg = s_g[wave][src];
+    // i / width by a float reciprocal, corrected to the exact quotient (i < 2^24)
+    uint32_t q = (uint32_t)((float)i * __uint_as_float(gg.w));
+    int32_t r = (int32_t)(i - q * gg.z);
+    if (r < 0) {
+      q--;
+      r += (int32_t)gg.z;
+    } else if (r >= (int32_t)gg.z) {
+      q++;
+      r -= (int32_t)gg.z;
+    }
+    const uint64_t kk = first + k;
+    if (kk < (uint64_t)cap) {
+      keys[kk] = gg.x + q * gg.y + (uint32_t)r;
+      vals[kk] = (uint32_t)(p0 + src);
     }
   }
 }

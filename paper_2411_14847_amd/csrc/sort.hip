@@ -7,8 +7,9 @@
 //       sub-histograms to spread LDS atomics), written digit-major to global memory;
 //   (2) scan: one workgroup turns the [256][blocks] counts into global write offsets;
 //   (3) scatter: every block re-reads its chunk in batches of 2048 pairs, ranks them stably
-//       with wave ballots (8 ballots give each lane the mask of lanes holding the same
-//       digit), orders the batch by digit in LDS and writes each digit's run contiguously.
+//       with wave ballots (8-9 ballots give each lane the mask of lanes holding the same
+//       digit; each wave ranks its own 512 consecutive pairs), orders the batch by digit in
+//       LDS and writes each digit's run contiguously.
 // A pass never depends on forward progress between workgroups.
 #include "dass_internal.h"
 
@@ -89,7 +90,16 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(const K* __restrict__ 
   __syncthreads();
   uint32_t lo, hi;
   chunk_of(*d_count, blocks, lo, hi);
-  for (uint32_t i = lo + tid; i < hi; i += kSortThreads) atomicAdd(&s_h[wave][digit_of<RB>(keys[i], shift)], 1u);
+  uint32_t i = lo + tid;
+  // eight independent loads in flight per thread, then their LDS increments
+  for (; i + (kSortItems - 1) * kSortThreads < hi; i += kSortItems * kSortThreads) {
+    K k[kSortItems];
+#pragma unroll
+    for (int u = 0; u < kSortItems; u++) k[u] = keys[i + u * kSortThreads];
+#pragma unroll
+    for (int u = 0; u < kSortItems; u++) atomicAdd(&s_h[wave][digit_of<RB>(k[u], shift)], 1u);
+  }
+  for (; i < hi; i += kSortThreads) atomicAdd(&s_h[wave][digit_of<RB>(keys[i], shift)], 1u);
   __syncthreads();
   for (int d = tid; d < R; d += kSortThreads)
     hist[(int64_t)d * blocks + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
@@ -125,6 +135,19 @@ __device__ __forceinline__ uint32_t block_excl_scan_digits(const uint32_t* c, ui
   return block_excl_scan256(sum, s_tmp, total);
 }
 
+// Orders LDS accesses of the lanes of one wave (a wave's LDS instructions complete in order;
+// this only keeps the compiler from moving them across the point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Each batch of 2048 pairs is split into four runs of 512 consecutive pairs, one per wave; a
+// wave ranks its run slot by slot (64 pairs at a time) against its own running digit counts,
+// with no workgroup barrier, so the ranks follow the input order.  Waves are then combined by
+// an exclusive prefix of their counts per digit, the batch is ordered by digit in LDS, and each
+// digit's run is written to its global position.
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                           K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -133,17 +156,18 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
                                                           const uint32_t* __restrict__ totals) {
   constexpr int R = 1 << RB;
   constexpr int D = R / kSortThreads;        // digits owned per thread
+  constexpr int kWaveRun = kSortItems * 64;  // consecutive pairs ranked by one wave per batch
   __shared__ uint32_t s_base[R];             // global write position of the next item of each digit
-  __shared__ uint32_t s_cnt[R];              // items of each digit seen so far in this batch
   __shared__ uint32_t s_boff[R];             // exclusive digit offsets within the batch
-  __shared__ uint32_t s_wcnt[2][4][R];       // per-wave digit counts (double-buffered by sub-round)
+  __shared__ uint32_t s_wc[4][R];            // per-wave digit counts, then their prefix over waves
   __shared__ uint32_t s_tmp[4];
   __shared__ K s_k[kBatch];
   __shared__ uint32_t s_v[kBatch];
 
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const uint32_t count = *d_count;
   uint32_t lo, hi;
-  chunk_of(*d_count, blocks, lo, hi);
+  chunk_of(count, blocks, lo, hi);
   {  // global base of each digit for this block: row prefix + exclusive scan of the digit totals
     uint32_t tv[D];
 #pragma unroll
@@ -160,28 +184,24 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
 
   for (uint32_t batch = lo; batch < hi; batch += kBatch) {
     const uint32_t nb = min((uint32_t)kBatch, hi - batch);
-#pragma unroll
-    for (int i = 0; i < D; i++) s_cnt[tid * D + i] = 0;
+    const uint32_t wbase = batch + (uint32_t)(wave * kWaveRun);
+    for (int d = lane; d < R; d += 64) s_wc[wave][d] = 0;
     K key[kSortItems];
     uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
     for (int s = 0; s < kSortItems; s++) {
-      uint32_t (*wc)[R] = s_wcnt[s & 1];
-#pragma unroll
-      for (int w = 0; w < 4; w++)
-#pragma unroll
-        for (int i = 0; i < D; i++) wc[w][tid * D + i] = 0;
-      const uint32_t idx = batch + s * kSortThreads + tid;
-      const bool valid = idx < hi;
-      uint32_t d = 0;
-      if (valid) {
+      const uint32_t idx = wbase + (uint32_t)(s * 64 + lane);
+      if (idx < hi) {
         key[s] = kin[idx];
         val[s] = vin[idx];
-        d = digit_of<RB>(key[s], shift);
       }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < kSortItems; s++) {
+      const bool valid = wbase + (uint32_t)(s * 64 + lane) < hi;
+      const uint32_t d = valid ? digit_of<RB>(key[s], shift) : 0u;
       dig[s] = d;
-      __syncthreads();
-      // lanes of this wave holding the same digit
       uint64_t peers = __ballot(valid);
 #pragma unroll
       for (int b = 0; b < RB; b++) {
@@ -189,27 +209,26 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
         peers &= ((d >> b) & 1) ? m : ~m;
       }
       const uint32_t rw = __popcll(peers & lt);
-      if (valid && rw == 0) wc[wave][d] = __popcll(peers);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < D; i++) {  // thread owns digits tid*D..: prefix over waves, running count
-        const int dd = tid * D + i;
-        uint32_t run = s_cnt[dd];
-#pragma unroll
-        for (int w = 0; w < 4; w++) {
-          const uint32_t c = wc[w][dd];
-          wc[w][dd] = run;
-          run += c;
-        }
-        s_cnt[dd] = run;
-      }
-      __syncthreads();
-      rank[s] = valid ? wc[wave][d] + rw : 0;
+      const uint32_t base = s_wc[wave][d];  // every lane of the digit reads before the leader adds
+      wave_lds_sync();
+      if (valid && rw == 0) s_wc[wave][d] = base + __popcll(peers);
+      wave_lds_sync();
+      rank[s] = base + rw;
     }
-    // digit offsets within the batch
+    __syncthreads();
     uint32_t c[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) c[i] = s_cnt[tid * D + i];
+    for (int i = 0; i < D; i++) {  // thread owns digits tid*D..: prefix over waves, batch count
+      const int dd = tid * D + i;
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        const uint32_t x = s_wc[w][dd];
+        s_wc[w][dd] = run;
+        run += x;
+      }
+      c[i] = run;
+    }
     {
       uint32_t run = block_excl_scan_digits<D>(c, s_tmp, nullptr);
 #pragma unroll
@@ -221,9 +240,8 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < kSortItems; s++) {
-      const uint32_t idx = batch + s * kSortThreads + tid;
-      if (idx < hi) {
-        const uint32_t pos = s_boff[dig[s]] + rank[s];
+      if (wbase + (uint32_t)(s * 64 + lane) < hi) {
+        const uint32_t pos = s_boff[dig[s]] + s_wc[wave][dig[s]] + rank[s];
         s_k[pos] = key[s];
         s_v[pos] = val[s];
       }
@@ -236,8 +254,10 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
         const K k = s_k[j];
         const uint32_t d = digit_of<RB>(k, shift);
         const uint32_t o = s_base[d] + (j - s_boff[d]);
-        kout[o] = k;
-        vout[o] = s_v[j];
+        if (o < count) {  // always true for a consistent histogram; keeps stores in bounds
+          kout[o] = k;
+          vout[o] = s_v[j];
+        }
       }
     }
     __syncthreads();

@@ -40,6 +40,9 @@ class StreamConfig:
     bg: tuple = (0.0, 0.0, 0.0)
     use_graph: bool = False
     per_view: bool = False        # plain per-view loop (one render_fwd / render_bwd per camera)
+    max_inflight: int = 0         # >0: at most this many iterations queued on the GPU at once, so
+                                  # other streams sharing a hardware queue (serving) are not stuck
+                                  # behind a whole timestep of replayed iterations
     seed: int = 0
 
 
@@ -77,6 +80,7 @@ class Trainer:
         self.nd = 0
         self.graph = None
         self.graph_key = None
+        self._inflight = []
 
     # ---- one iteration --------------------------------------------------------------------
     def _adam_groups(self):
@@ -156,10 +160,19 @@ class Trainer:
         for dst, src in zip(self.targets, images):
             dst.copy_(src)
 
+    def _throttle(self):
+        if self.cfg.max_inflight > 0:
+            ev = torch.cuda.Event()
+            ev.record()
+            self._inflight.append(ev)
+            if len(self._inflight) > self.cfg.max_inflight:
+                self._inflight.pop(0).synchronize()
+
     def run_iterations(self, k: int):
         if not self.cfg.use_graph:
             for _ in range(k):
                 self.iteration()
+                self._throttle()
             return
         key = (self.g.n, self.nd)
         if self.graph is None or self.graph_key != key:
@@ -179,6 +192,7 @@ class Trainer:
             del step0
         for _ in range(k):
             self.graph.replay()
+            self._throttle()
 
     def end_timestep(self, t: int) -> int:
         """Bakes the shift into G and appends Gaussians; returns the number appended."""
@@ -191,6 +205,7 @@ class Trainer:
         k = int(self.n_app.item())
         g.n += k
         self.graph = None
+        self._inflight.clear()  # the item() above waited for everything queued so far
         return k
 
     def timestep(self, t: int, dyn_idx: torch.Tensor, targets: List[torch.Tensor]) -> dict:
