@@ -41,6 +41,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str, workload: str, tile: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None if
+    there is none for this workload and tile size, or the blend source changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    src = os.path.join(ROOT, "paper_2411_14847_amd", "csrc", "raster.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("tile") != tile:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("raster_hip_sha256"):
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def build_workload(args):
     import torch
 
@@ -150,6 +170,44 @@ def render_latency(s, args, reps):
         b.synchronize()
         times.append(a.elapsed_time(b))
     return float(np.percentile(times, 50)), float(np.percentile(times, 99))
+
+
+def fwdbwd_latency(s, args, reps):
+    """Mean latency of zeroing the gradients + render_fwd + render_bwd over all views, issued
+    eagerly and as one replayed HIP graph (launch overhead vs kernel time at small sizes)."""
+    torch = s["torch"]
+    ctx, gs, cams, outs, dls, grads = s["ctx"], s["gs"], s["cams"], s["outs"], s["dls"], s["grads"]
+
+    def step():
+        for t in grads.planes():
+            t.zero_()
+        ctx.render_fwd(gs, cams, args.bg, out=outs)
+        ctx.render_bwd(gs, cams, args.bg, outs, dls, grads)
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    eager = timed(step)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    replay = timed(graph.replay)
+    ctx.sync()
+    return eager, replay
 
 
 def cpu_baseline(s, args):
@@ -398,10 +456,13 @@ def bench_stress(args):
         tuned = ctx.autotune_tile(g, cams, args.bg, outs, dls, grads, reps=2)
         log(f"[bench] stress autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
     step()
+    tile = ctx.tile
+    ctx.tile = (16, 16)  # pair counts at 16x16 tiles (see the multi-view benchmark)
     ctx.render_fwd(g, cams, args.bg, out=outs, count_pairs=True)
     ctx.sync()
     evaluated, blended = ctx.pair_counts()
     walked = int(sum(int(o.n_contrib.sum().item()) for o in outs))
+    ctx.tile = tile
     total_keys = 0  # at the tile size in use
     for c in cams:
         pr = ctx.debug_projection(g, c)  # [n][16]: ..., x0, y0, x1, y1, visible
@@ -495,8 +556,10 @@ def main():
     ap.add_argument("--max-inflight", type=int, default=2,
                     help="training iterations queued at once while serving (0 = unbounded)")
     ap.add_argument("--no-autotune", action="store_true", help="stress: keep 16x16 tiles")
-    ap.add_argument("--tile-autotune", action="store_true",
-                    help="multiview/single: pick the tile size with the native autotuner before timing")
+    ap.add_argument("--no-tile-autotune", action="store_true",
+                    help="multiview/single: keep 16x16 tiles instead of the native autotuner's choice")
+    ap.add_argument("--tile", default="",
+                    help="multiview/single: fixed tile size WxH (edges 16, 32 or 64) instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -530,16 +593,23 @@ def main():
     ctx = s["ctx"]
     train_step(s, 1, args)
     tuned = None
-    if args.tile_autotune:
+    if args.tile:
+        ctx.tile = tuple(int(x) for x in args.tile.lower().split("x"))
+    elif not args.no_tile_autotune:
         # native autotuner over tile sizes on this workload (outside the timed region)
         tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3)
         log(f"[bench] autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
-    # pair counts of the blend (outside the timed region)
+    # pair counts of the blend (outside the timed region), always at 16x16 tiles: with larger
+    # tiles n_contrib counts positions in a longer list whose extra entries are culled per
+    # sub-tile, so only the 16x16 counts measure the work the definition asks for
     train_step(s, 1, args)
+    tile = ctx.tile
+    ctx.tile = (16, 16)
     ctx.render_fwd(s["gs"], s["cams"], args.bg, out=s["outs"], count_pairs=True)
     ctx.sync()
     evaluated, blended = ctx.pair_counts()
     walked = int(sum(int(o.n_contrib.sum().item()) for o in s["outs"]))
+    ctx.tile = tile
     log(f"[bench] pairs evaluated {evaluated:.3e} blended {blended:.3e} walked-bwd {walked:.3e}")
     # timed steps with live stage timers
     log(f"[bench] warmup {args.warmup}, timing {args.steps} steps")
@@ -557,11 +627,20 @@ def main():
     dom = max(cand, key=lambda k: per_stage.get(k, 0.0))
     dom_ms = per_stage[dom]
     achieved = cand[dom] / (dom_ms * 1e-3) / 1e12
+    kname = {"blend_bwd": "k_blend_bwd", "blend_fwd": "k_blend_fwd"}[dom]
+    wl_key = f"multiview_{args.n // 1000}k_{args.views}x{args.width}x{args.height}"
+    tile_s = f"{ctx.tile[0]}x{ctx.tile[1]}"
+    traffic = measured_traffic(kname, wl_key, tile_s) if args.workload == "multiview" else None
     roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_FLOPS / 1e12,
-            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": traffic,
             "flops_per_launch": float(cand[dom]), "avg_launch_ms": round(dom_ms, 4)}
     p50, p99 = render_latency(s, args, args.render_reps)
     log(f"[bench] render p50 {p50:.3f} ms p99 {p99:.3f} ms")
+    lat = None
+    if args.workload == "single":
+        e_ms, g_ms = fwdbwd_latency(s, args, 200)
+        lat = {"eager_us": round(e_ms * 1e3, 2), "graph_us": round(g_ms * 1e3, 2)}
+        log(f"[bench] fwd+bwd latency eager {e_ms * 1e3:.1f} us, graph replay {g_ms * 1e3:.1f} us")
     pv_ms = None
     if args.per_view_steps > 0:
         pv_ms, _ = time_steps(s, args, args.per_view_steps, 1, per_view=True)
@@ -573,7 +652,9 @@ def main():
         log(f"[bench] cpu baseline {cpu['value']:.3e} iters/s")
     cams = s["cams"]
     line = {
-        "metric": "fwd+bwd iters/s @200k Gaussians x 20 views 1352x1014; render p50/p99 ms",
+        "metric": ("fwd+bwd iters/s @200k Gaussians x 20 views 1352x1014; render p50/p99 ms"
+                   if args.workload == "multiview" else
+                   "fwd+bwd iters/s @2k Gaussians x 1 view 128x128 (single-view scene); fwd+bwd latency us"),
         "value": round(1000.0 / ms, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -583,6 +664,7 @@ def main():
                    "n_dynamic": s["nd"], "densify_k": args.densify_k, "parallelism": "single GPU"},
         "tile_autotune_ms": {f"{w}x{h}": v for (w, h), v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
+        "fwd_bwd_latency": lat,
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
         "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},

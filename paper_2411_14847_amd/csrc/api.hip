@@ -778,6 +778,15 @@ dass_status dass_autotune_tile(dass_ctx ctx, const dass_gaussians* g, const dass
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  // the first candidate (in the caller's order of preference) within 2% of the fastest, so that
+  // timing noise between near-equal sizes does not flip the choice from run to run
+  if (s == DASS_OK && *best >= 0) {
+    for (int c = 0; c < n_candidates; c++)
+      if (ms[c] >= 0.f && ms[c] <= 1.02f * best_ms) {
+        *best = c;
+        break;
+      }
+  }
   ctx->have_fwd = false;  // the kept state belongs to the last candidate: render again before render_bwd
   if (s == DASS_OK && *best < 0) s = fail(ctx, DASS_E_CAPACITY, "autotune: no candidate fits the context's budgets");
   return s;

@@ -91,7 +91,8 @@ struct Workspace {
   uint64_t* off_s = nullptr;       // exclusive prefix of tiles touched, [cap_vn + 1]
   uint32_t* inv = nullptr;         // inv[v*n + g] = p
   uint32_t* gid_s = nullptr;       // gid of sorted position p
-  float* g2d = nullptr;            // [cap_vn][9], row v * n + g
+  float* g2d = nullptr;            // [cap_vn][9], row v * n + g: blend-backward sums (moments of
+                                   // dL/d(exponent) over the offsets, d opacity, d rgb)
   // keys
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};

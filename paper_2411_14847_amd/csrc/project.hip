@@ -327,13 +327,19 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
     ViewD V;
     project_view(L, cam, V);
     if (!V.visible) continue;
+    // blend sums of this (view, Gaussian): M = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
+    // sum dP dy^2, d opacity, d rgb) with dP = dL/d(exponent), exponent = -(A dx^2 + 2B dx dy +
+    // C dy^2)/2 and (dx, dy) = mean - pixel, so dL/du = -(A M0 + B M1), dL/dv = -(B M0 + C M1),
+    // dL/dA = -M2/2, dL/dB = -M3, dL/dC = -M4/2
     const float* gd = g2d + ((int64_t)v * sc.n + g) * 9;
-    const double du = gd[0], dv = gd[1], dA = gd[2], dB = gd[3], dC = gd[4];
+    const double A = V.A, B = V.B, C = V.C;
+    const double M0 = gd[0], M1 = gd[1];
+    const double du = -(A * M0 + B * M1), dv = -(B * M0 + C * M1);
+    const double dA = -0.5 * (double)gd[2], dB = -(double)gd[3], dC = -0.5 * (double)gd[4];
     dop += (double)gd[5];
     gnorm += sqrt(du * du + dv * dv);
     cnt++;
     // conic (A, B, C) = inverse of [[a, b], [b, c]]: dSigma2D = -Q G Q with G = [[dA, dB/2], [dB/2, dC]]
-    const double A = V.A, B = V.B, C = V.C;
     const double hB = 0.5 * dB;
     const double qg00 = A * dA + B * hB, qg01 = A * hB + B * dC;
     const double qg10 = B * dA + C * hB, qg11 = B * hB + C * dC;

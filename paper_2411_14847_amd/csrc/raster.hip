@@ -190,7 +190,9 @@ __device__ __forceinline__ void tstep(float* v, bool upper) {
 }
 
 // Sums 9 per-lane values over the wave.  Afterwards lane l (l < 16) holds the total of value
-// kRedSlot[l] (-1: none); lanes l + 16, l + 32, l + 48 hold the same total.
+// kRedSlot[l] (-1: none); lanes l + 16, l + 32, l + 48 hold the same total.  DPP moves within
+// rows, two shuffles across rows (measured faster here than gfx950's permlane16/32 swaps, which
+// need more registers and cost an occupancy step).
 __device__ __forceinline__ float wave_reduce9(float* v, int lane) {
   tstep<9, 5, 0xB1>(v, lane & 1);         // xor 1 (quad_perm 1,0,3,2)
   tstep<5, 3, 0x4E>(v, (lane >> 1) & 1);  // xor 2 (quad_perm 2,3,0,1)
@@ -234,14 +236,15 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   const uint2 r = ranges[b];
   float T[4], c0[4], c1[4], c2[4];
   int last[4];
-  bool done[4];
+  float live[4];  // 1 while the pixel is walking its list, 0 once stopped (or outside the image):
+                  // alpha is scaled by it, so a stopped pixel neither blends nor stops again
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
     T[k] = 1.f;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
-    done[k] = !(px < V.W && py < V.H);
+    live[k] = (px < V.W && py < V.H) ? 1.f : 0.f;
   }
   uint32_t n_eval = 0, n_blend = 0;
   for (uint32_t start = r.x; start < r.y; start += kBatchB) {
@@ -282,25 +285,25 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       for (int k = 0; k < 4; k++) {
         const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
-        const bool ok = !done[k] && (pw <= 0.f) && (a >= kAlphaMin);
+        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw)) * live[k];
+        const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
         const float Tn = T[k] - T[k] * a;
-        const bool stop = ok && (Tn < kTStop);
-        const bool blend = ok && !stop;
-        done[k] = done[k] || stop;
+        const bool go = Tn >= kTStop;
+        const bool blend = ok && go;
+        if (COUNT) {
+          n_eval += live[k] != 0.f ? 1u : 0u;
+          n_blend += blend ? 1u : 0u;
+        }
+        live[k] = (ok && !go) ? 0.f : live[k];
         const float w = blend ? a * T[k] : 0.f;
         c0[k] += c.x * w;
         c1[k] += c.y * w;
         c2[k] += c.z * w;
         T[k] = blend ? Tn : T[k];
         last[k] = blend ? pos1 : last[k];
-        if (COUNT) {
-          n_eval += (!done[k] || stop) ? 1u : 0u;
-          n_blend += blend ? 1u : 0u;
-        }
       }
     }
-    const bool alive = !(done[0] && done[1] && done[2] && done[3]);
+    const bool alive = (live[0] + live[1] + live[2] + live[3]) != 0.f;
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
@@ -374,6 +377,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   const int max_last = min(my_max, (int)(r.y - r.x));  // n_contrib never exceeds the list length
   if (max_last <= 0) return;
   const int slot = kRedSlot[lane & 15];
+  const bool writes = lane < 16 && slot >= 0;
   const int nbatch = (max_last + kBatchB - 1) / kBatchB;
   for (int bi = nbatch - 1; bi >= 0; bi--) {
     const uint32_t start = r.x + (uint32_t)bi * kBatchB;
@@ -414,7 +418,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
       const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
       // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
-      // sum dP dy^2, d opacity, d rgb); the conic is applied after the wave reduction
+      // sum dP dy^2, d opacity, d rgb), dP = dL/d(exponent), (dx, dy) = mean - pixel
       float m[9];
 #pragma unroll
       for (int q = 0; q < 9; q++) m[q] = 0.f;
@@ -450,18 +454,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         }
       }
       if (__ballot(any) != 0) {
+        // the sums are linear in the entry's conic, so the conic is applied once per
+        // (view, Gaussian) by the projection adjoint, not here
         const float tot = wave_reduce9(m, lane);
-        // lanes 0..15 hold the totals; lane 4 (slot 1) needs slot 0's partner values, so the
-        // mean / conic terms are formed by the lane holding each output from the moments.
-        const float s0 = __shfl(tot, 0, 64), s1 = __shfl(tot, 4, 64);  // sum dP dx, sum dP dy
-        const float cnx = co.x * (-2.f / kLog2e), cny = co.y * (-1.f / kLog2e), cnz = co.z * (-2.f / kLog2e);
-        float out = tot;
-        if (slot == 0) out = -cnx * s0 - cny * s1;           // d u
-        else if (slot == 1) out = -cnz * s1 - cny * s0;      // d v
-        else if (slot == 2) out = -0.5f * tot;               // d A
-        else if (slot == 3) out = -tot;                      // d B
-        else if (slot == 4) out = -0.5f * tot;               // d C
-        if (lane < 16 && slot >= 0) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], out);
+        if (writes) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], tot);
       }
     }
   }

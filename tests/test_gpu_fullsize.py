@@ -2,7 +2,8 @@
 all views in one render call as the benchmark runs them), on outputs the oracle computes one
 by one: complete sorted keys / ranges of two views, sampled tiles of the images, and complete
 gradients of sampled Gaussians (the oracle blends only the tiles those Gaussians touch, which
-is all their gradients depend on)."""
+is all their gradients depend on).  Run at 16x16 tiles and at 32x64, the size the tile
+autotuner picks for this workload on MI355X."""
 import numpy as np
 import pytest
 import torch
@@ -16,19 +17,21 @@ pytestmark = pytest.mark.gpu
 BG = (0.0, 0.0, 0.0)
 
 
-@pytest.fixture(scope="module")
-def full():
-    log("[fullsize] generating 200k-Gaussian, 20-view scene")
+@pytest.fixture(scope="module", params=[(16, 16), (32, 64)], ids=["tile16x16", "tile32x64"])
+def full(request):
+    tile = request.param
+    log(f"[fullsize] generating 200k-Gaussian, 20-view scene (tile {tile[0]}x{tile[1]})")
     scene, cams, dls = synth.multiview_scene(0, n=200_000, n_views=20)
     g = to_gpu(scene)
     ctx = make_ctx(scene.n, cams, keys_per_gaussian=24)
+    ctx.tile = tile
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
     log("[fullsize] GPU forward done")
-    projs = [oracle.project(scene, c) for c in cams]
-    keys = [oracle.keys(p, c) for p, c in zip(projs, cams)]
+    projs = [oracle.project(scene, c, tile) for c in cams]
+    keys = [oracle.keys(p, c, tile) for p, c in zip(projs, cams)]
     log("[fullsize] oracle projections and keys done")
-    return dict(scene=scene, cams=cams, dls=dls, g=g, ctx=ctx, out=out, projs=projs, keys=keys)
+    return dict(scene=scene, cams=cams, dls=dls, g=g, ctx=ctx, out=out, projs=projs, keys=keys, tile=tile)
 
 
 @pytest.mark.parametrize("view", [0, 19])
@@ -36,7 +39,7 @@ def test_fullsize_keys_bit_exact(full, view):
     cam, p = full["cams"][view], full["projs"][view]
     k, v, r = full["keys"][view]
     flagged = np.nonzero(p.flags & oracle.FLAG_RADIUS)[0]
-    TX, TY = oracle.tiles_of(cam, (16, 16))
+    TX, TY = oracle.tiles_of(cam, full["tile"])
     gk, gv, gr = full["ctx"].debug_keys(view, k.size + 4096, TX * TY)
     log(f"  view {view}: {k.size} keys, radius-flagged Gaussians {flagged.size}")
     if flagged.size == 0:
@@ -56,13 +59,14 @@ def test_fullsize_keys_bit_exact(full, view):
 
 @pytest.mark.parametrize("view", [0, 7, 19])
 def test_fullsize_sampled_tiles_match(full, view):
-    cam = full["cams"][view]
-    TX, TY = oracle.tiles_of(cam, (16, 16))
+    cam, tile = full["cams"][view], full["tile"]
+    TX, TY = oracle.tiles_of(cam, tile)
     rng = np.random.default_rng(100 + view)
-    tiles = np.concatenate([rng.choice(TX * TY, 20, replace=False), [TX * TY - 1, TX - 1]])  # + ragged corner tiles
-    vr = oracle.render_view(full["scene"], cam, bg=BG, tiles=tiles, proj=full["projs"][view],
+    n_pick = max(4, 20 * 256 // (tile[0] * tile[1]))
+    tiles = np.concatenate([rng.choice(TX * TY, n_pick, replace=False), [TX * TY - 1, TX - 1]])  # + ragged corners
+    vr = oracle.render_view(full["scene"], cam, bg=BG, tile=tile, tiles=tiles, proj=full["projs"][view],
                             key_data=full["keys"][view])
-    m = vr.computed & ~excluded_pixels(vr, cam)
+    m = vr.computed & ~excluded_pixels(vr, cam, tile=tile)
     o = full["out"][view]
     err = np.abs(o.rgb.cpu().numpy() - vr.rgb)[:, m].max()
     log(f"  view {view}: {m.sum()} pixels compared, max |rgb| err {err:.2e}")
@@ -72,7 +76,7 @@ def test_fullsize_sampled_tiles_match(full, view):
 
 
 def test_fullsize_sampled_gaussian_gradients(full):
-    scene, cams, projs = full["scene"], full["cams"], full["projs"]
+    scene, cams, projs, tile = full["scene"], full["cams"], full["projs"], full["tile"]
     n = scene.n
     rng = np.random.default_rng(7)
     nvis = np.sum([p.visible for p in projs], axis=0)
@@ -87,7 +91,7 @@ def test_fullsize_sampled_gaussian_gradients(full):
     dls = [d.copy() for d in full["dls"]]
     renders, tile_lists = [], []
     for v, (cam, p) in enumerate(zip(cams, projs)):
-        TX, _ = oracle.tiles_of(cam, (16, 16))
+        TX, _ = oracle.tiles_of(cam, tile)
         ts = set()
         for gidx in sample:
             if p.visible[gidx]:
@@ -95,11 +99,12 @@ def test_fullsize_sampled_gaussian_gradients(full):
                 ts.update(ty * TX + tx for ty in range(y0, y1) for tx in range(x0, x1))
         tl = np.array(sorted(ts), np.int32)
         tile_lists.append(tl)
-        vr = oracle.render_view(scene, cam, bg=BG, tiles=tl, proj=p, key_data=full["keys"][v])
-        dls[v][:, vr.computed & excluded_pixels(vr, cam, grad=True)] = 0.0
+        vr = oracle.render_view(scene, cam, bg=BG, tile=tile, tiles=tl, proj=p, key_data=full["keys"][v])
+        dls[v][:, vr.computed & excluded_pixels(vr, cam, grad=True, tile=tile)] = 0.0
         renders.append(vr)
     log(f"  oracle backward over {sum(t.size for t in tile_lists)} tiles")
-    og, _, ogn, ocnt = oracle.render_backward(scene, cams, dls, bg=BG, renders=renders, tiles=tile_lists, only=only)
+    og, _, ogn, ocnt = oracle.render_backward(scene, cams, dls, bg=BG, tile=tile, renders=renders, tiles=tile_lists,
+                                              only=only)
     ctx, g = full["ctx"], full["g"]
     grads = g.zeros_like()
     gn = torch.zeros(g.capacity, device="cuda")

@@ -109,7 +109,9 @@ def test_autotuner_picks_a_timed_candidate_and_keeps_parity():
     res = ctx.autotune_tile(g, cams, BG, out, dl_t, scratch, reps=2)
     log(f"  autotune: {res}; chose {ctx.tile}")
     assert ctx.tile in res and res[ctx.tile] is not None
-    assert res[ctx.tile] == min(v for v in res.values() if v is not None)
+    fastest = min(v for v in res.values() if v is not None)
+    first_close = next(c for c, v in res.items() if v is not None and v <= 1.02 * fastest)
+    assert ctx.tile == first_close
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
     for v, cam in enumerate(cams):
