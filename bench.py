@@ -41,6 +41,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def tile_name(t) -> str:
+    """'WxH' for 16x16 sub-tiles, 'WxHs8' for 8x8 sub-tiles (one pixel per lane)."""
+    return f"{t[0]}x{t[1]}" + ("s8" if len(t) > 2 and int(t[2]) == 8 else "")
+
+
+def parse_tile(name: str):
+    name = name.lower()
+    sub = 8 if name.endswith("s8") else 16
+    w, h = (int(x) for x in (name[:-2] if sub == 8 else name).split("x"))
+    return (w, h, sub) if sub == 8 else (w, h)
+
+
 def measured_traffic(kernel: str, workload: str, tile: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None if
     there is none for this workload and tile size, or the blend source changed since the
@@ -291,6 +303,16 @@ def bench_streaming(args):
                       max_tiles=tiles)
         cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, **kw)
         tr = Trainer(ctx, g, cams, max_dynamic=int(dyns[0].numel()), cfg=cfg)
+        tuned = None
+        if args.tile:
+            ctx.tile = parse_tile(args.tile)
+        elif not args.no_tile_autotune and name != "per_view_eager":
+            # tile size from the autotuner on the first timestep's render (one iteration first)
+            tr.begin_timestep(1, dyns[0])
+            tr.set_targets(targets[0])
+            tr.iteration()
+            tuned = tr.autotune_tile()
+            log(f"[bench] streaming {name}: autotune {tuned}; using {ctx.tile}")
         T = args.timesteps if name != "per_view_eager" else min(args.timesteps, args.per_view_timesteps)
         rows = []
         prof_from = T - 2 if name == "batched_eager" and T >= 3 else None
@@ -309,7 +331,8 @@ def bench_streaming(args):
                      "loss_first_last_final_t": [rows[-1]["loss_first"], rows[-1]["loss_last"]],
                      "psnr_final_t": round(rows[-1]["psnr"], 2),
                      "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows])),
-                     "ms_series": [round(r["ms"], 1) for r in rows], "n_series": [r["n"] for r in rows]}
+                     "ms_series": [round(r["ms"], 1) for r in rows], "n_series": [r["n"] for r in rows],
+                     "tile": tile_name(ctx.tile)}
         if stages is not None:
             res[name]["stage_ms_per_timestep_last3"] = {k: round(v[0] / 3.0, 3) for k, v in stages.items()}
         log(f"[bench] streaming {name}: {res[name]}")
@@ -511,8 +534,8 @@ def bench_stress(args):
         "value": round(1000.0 / graph_ms, 3), "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(graph_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": f"{ctx.tile[0]}x{ctx.tile[1]}"},
-        "autotune_ms": {f"{w}x{h}": v for (w, h), v in tuned.items()} if tuned else None,
+        "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": tile_name(ctx.tile)},
+        "autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
         "eager_ms_per_step": round(eager_ms, 3),
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
         "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
@@ -559,7 +582,8 @@ def main():
     ap.add_argument("--no-tile-autotune", action="store_true",
                     help="multiview/single: keep 16x16 tiles instead of the native autotuner's choice")
     ap.add_argument("--tile", default="",
-                    help="multiview/single: fixed tile size WxH (edges 16, 32 or 64) instead of autotuning")
+                    help="multiview/single: fixed tile size WxH (edges 16, 32 or 64; suffix s8 for 8x8 "
+                         "sub-tiles) instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -594,7 +618,7 @@ def main():
     train_step(s, 1, args)
     tuned = None
     if args.tile:
-        ctx.tile = tuple(int(x) for x in args.tile.lower().split("x"))
+        ctx.tile = parse_tile(args.tile)
     elif not args.no_tile_autotune:
         # native autotuner over tile sizes on this workload (outside the timed region)
         tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3)
@@ -629,7 +653,7 @@ def main():
     achieved = cand[dom] / (dom_ms * 1e-3) / 1e12
     kname = {"blend_bwd": "k_blend_bwd", "blend_fwd": "k_blend_fwd"}[dom]
     wl_key = f"multiview_{args.n // 1000}k_{args.views}x{args.width}x{args.height}"
-    tile_s = f"{ctx.tile[0]}x{ctx.tile[1]}"
+    tile_s = tile_name(ctx.tile)
     traffic = measured_traffic(kname, wl_key, tile_s) if args.workload == "multiview" else None
     roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_FLOPS / 1e12,
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": traffic,
@@ -660,9 +684,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": s["name"], "n_gaussians": s["N"], "sh_degree": int(s["g"].sh_degree),
                    "views": len(cams), "width": cams[0].width, "height": cams[0].height,
-                   "tile": f"{ctx.tile[0]}x{ctx.tile[1]}",
+                   "tile": tile_name(ctx.tile),
                    "n_dynamic": s["nd"], "densify_k": args.densify_k, "parallelism": "single GPU"},
-        "tile_autotune_ms": {f"{w}x{h}": v for (w, h), v in tuned.items()} if tuned else None,
+        "tile_autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
         "fwd_bwd_latency": lat,
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,

@@ -101,6 +101,10 @@ typedef struct {
  * images are the same for every tile size; n_contrib and the keys depend on it. */
 #define DASS_FLAG_COUNT_PAIRS 1u /* render_fwd also counts evaluated / blended (pixel, entry)
                                     pairs (read with dass_debug_pair_counts); slower */
+#define DASS_FLAG_SUBTILE8 2u    /* blend each tile as 8x8 sub-tiles, one pixel per lane (four
+                                    times the waves: for small images with long lists); same
+                                    lists and order as 16x16 sub-tiles, pixel offsets rounded
+                                    relative to the smaller sub-tile's origin */
 typedef struct {
   int32_t tile_w, tile_h;
   uint32_t flags; /* DASS_FLAG_* bits */
@@ -276,8 +280,8 @@ dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* 
 dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t* vals,
                             int64_t max, int64_t* ranges, int64_t* count);
 
-/* Tile-size autotuner.  For each of the n_candidates options (tile_w, tile_h; flags ignored
- * except COUNT_PAIRS) runs render_fwd + render_bwd of this workload once to warm up, then
+/* Tile-size autotuner.  For each of the n_candidates options (tile_w, tile_h and flags, e.g.
+ * DASS_FLAG_SUBTILE8) runs render_fwd + render_bwd of this workload once to warm up, then
  * `reps` times between two HIP events on `stream`, and writes the mean milliseconds per
  * fwd+bwd into ms[c] (host array; -1 for a candidate whose tiles or keys exceed the
  * context's budgets) and into *best (host) the index of the first candidate, in the given

@@ -19,6 +19,7 @@ EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "da
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count")
 FLAG_COUNT_PAIRS = 1
+FLAG_SUBTILE8 = 2
 STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
           "shift", "adam", "l1", "densify")
 

@@ -149,7 +149,9 @@ class Context:
             raise DassError(st, "dass_create failed")
         self.limits = lim
         self.generation = 0  # bumped by every call that replaces the state kept for render_bwd
-        self.tile = (16, 16)  # tile size of render_fwd / render_bwd (16, 32 or 64 per edge)
+        # tile size of render_fwd / render_bwd: (tw, th) with edges 16, 32 or 64, optionally with
+        # a third entry, the sub-tile edge of the blend (16, or 8 for one pixel per lane)
+        self.tile = (16, 16)
 
     def close(self):
         if self._h:
@@ -161,6 +163,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    @staticmethod
+    def _opts_for(tile, flags: int = 0) -> F.Opts:
+        if len(tile) > 2 and int(tile[2]) == 8:
+            flags |= F.FLAG_SUBTILE8
+        return F.Opts(int(tile[0]), int(tile[1]), flags)
+
+    def _opts(self, flags: int = 0) -> F.Opts:
+        return self._opts_for(self.tile, flags)
 
     def _check(self, st: int):
         if st != F.DASS_OK:
@@ -182,7 +193,7 @@ class Context:
         imgs = (F.Image * len(cams))(*[o.struct() for o in out])
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
-        opts = F.Opts(self.tile[0], self.tile[1], F.FLAG_COUNT_PAIRS if count_pairs else 0)
+        opts = self._opts(F.FLAG_COUNT_PAIRS if count_pairs else 0)
         self.generation += 1
         self._check(self._lib.render_fwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs,
                                          C.byref(opts), _stream(stream)))
@@ -195,12 +206,14 @@ class Context:
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
         gr = grads_struct(grads)
-        opts = F.Opts(self.tile[0], self.tile[1], 0)
+        opts = self._opts()
         self._check(self._lib.render_bwd(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs, dls,
                                          C.byref(gr), _ptr(gradnorm), _ptr(count), C.byref(opts), _stream(stream)))
 
-    # order of preference: smaller key bins first (less work per list when times are close)
-    TILE_CANDIDATES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64))
+    # order of preference: 16x16 sub-tiles first, smaller key bins first (less work per list when
+    # times are close); then 8x8 sub-tiles (one pixel per lane), which pay off on small images
+    TILE_CANDIDATES = ((16, 16), (32, 16), (16, 32), (32, 32), (64, 32), (32, 64), (64, 64),
+                       (16, 16, 8), (32, 16, 8), (32, 32, 8), (64, 64, 8))
 
     def autotune_tile(self, g: GaussianBuffers, cams: Sequence, bg, out, dl_drgb, grads: GaussianBuffers,
                       candidates=TILE_CANDIDATES, reps: int = 3, stream=None, apply: bool = True) -> dict:
@@ -213,7 +226,7 @@ class Context:
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
         gr = grads_struct(grads)
-        cand = (F.Opts * len(candidates))(*[F.Opts(int(w), int(h), 0) for w, h in candidates])
+        cand = (F.Opts * len(candidates))(*[self._opts_for(c) for c in candidates])
         best = C.c_int32(-1)
         ms = (C.c_float * len(candidates))()
         self.generation += 1
@@ -221,7 +234,7 @@ class Context:
                                                  C.byref(gr), cand, len(candidates), int(reps), C.byref(best), ms,
                                                  _stream(stream)))
         if apply:
-            self.tile = tuple(candidates[best.value])
+            self.tile = tuple(int(x) for x in candidates[best.value])
         return {tuple(c): (float(ms[i]) if ms[i] >= 0 else None) for i, c in enumerate(candidates)}
 
     def shift_fwd(self, g: GaussianBuffers, out: GaussianBuffers, dyn_idx: torch.Tensor, dpos: torch.Tensor,
@@ -307,7 +320,7 @@ class Context:
     def debug_projection(self, g: GaussianBuffers, cam):
         out = torch.empty(max(g.n, 1), 16, dtype=torch.float64, device=g.mean.device)
         gs = g.struct()
-        opts = F.Opts(self.tile[0], self.tile[1], 0)
+        opts = self._opts()
         self._check(self._lib.dass_debug_projection(self._h, C.byref(gs), C.byref(camera_struct(cam)),
                                                     C.byref(opts), _ptr(out)))
         return out[:g.n].cpu().numpy()

@@ -226,23 +226,27 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, int tw, int
 
 bool tile_edge_ok(int e) { return e == 16 || e == 32 || e == 64; }
 
-// Validates the options and returns the tile size (16x16 when o is NULL).
-dass_status check_opts(dass_ctx ctx, const dass_opts* o, int& tw, int& th) {
+// Validates the options and returns the tile size (16x16 when o is NULL) and sub-tile edge.
+dass_status check_opts(dass_ctx ctx, const dass_opts* o, int& tw, int& th, int& sub) {
   tw = th = kTile;
+  sub = kTile;
   if (!o) return DASS_OK;
   if (!tile_edge_ok(o->tile_w) || !tile_edge_ok(o->tile_h))
     return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (edges 16, 32 or 64)", o->tile_w, o->tile_h);
-  if (o->flags & ~DASS_FLAG_COUNT_PAIRS) return fail(ctx, DASS_E_INVALID, "unknown option flags");
+  if (o->flags & ~(DASS_FLAG_COUNT_PAIRS | DASS_FLAG_SUBTILE8))
+    return fail(ctx, DASS_E_INVALID, "unknown option flags");
   tw = o->tile_w;
   th = o->tile_h;
+  sub = (o->flags & DASS_FLAG_SUBTILE8) ? 8 : kTile;
   return DASS_OK;
 }
 
-void set_tiling(ViewsIO& io, int tw, int th) {
+void set_tiling(ViewsIO& io, int tw, int th, int sub) {
   io.tw = tw;
   io.th = th;
-  io.sx = tw / kTile;
-  io.sn = (tw / kTile) * (th / kTile);
+  io.sub = sub;
+  io.sx = tw / sub;
+  io.sn = (tw / sub) * (th / sub);
 }
 
 SceneK scene_of(const dass_gaussians* g) {
@@ -345,8 +349,8 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  int tw, th;
-  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
+  int tw, th, sub;
+  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
   if (!bg || !out) return fail(ctx, DASS_E_INVALID, "bg or out is NULL");
   CamsK ck;
   int64_t total_tiles = 0;
@@ -355,7 +359,7 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
     return fail(ctx, DASS_E_CAPACITY, "n=%d exceeds max_gaussians %d", g->n, ctx->lim.max_gaussians);
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
-  set_tiling(io, tw, th);
+  set_tiling(io, tw, th, sub);
   for (int v = 0; v < n_views; v++) {
     if (!out[v].rgb || !out[v].t_final || !out[v].n_contrib)
       return fail(ctx, DASS_E_INVALID, "out[%d] has a NULL buffer", v);
@@ -422,8 +426,8 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  int tw, th;
-  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
+  int tw, th, sub;
+  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
   if (!bg || !fwd_out || !dl_drgb || !grads) return fail(ctx, DASS_E_INVALID, "NULL argument");
   CamsK ck;
   int64_t total_tiles = 0;
@@ -433,7 +437,7 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
     return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
-  set_tiling(io, tw, th);
+  set_tiling(io, tw, th, sub);
   for (int v = 0; v < n_views; v++) {
     if (!fwd_out[v].t_final || !fwd_out[v].n_contrib || !dl_drgb[v])
       return fail(ctx, DASS_E_INVALID, "view %d: NULL t_final, n_contrib or dl_drgb", v);
@@ -664,8 +668,9 @@ dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const d
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
   if (!out) return fail(ctx, DASS_E_INVALID, "out is NULL");
-  int tw, th;
-  if ((s = check_opts(ctx, opts, tw, th)) != DASS_OK) return s;
+  int tw, th, sub;
+  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  (void)sub;
   CamsK ck;
   int64_t total = 0;
   const int64_t keep = ctx->ws.cap_tiles;

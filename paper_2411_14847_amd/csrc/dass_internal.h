@@ -61,7 +61,8 @@ struct ViewIO {
 struct ViewsIO {
   ViewIO v[DASS_MAX_VIEWS];
   int tw, th;  // tile size in pixels
-  int sx, sn;  // 16x16 sub-tiles per tile row, per tile
+  int sub;     // sub-tile edge (16: 2x2 pixels per lane, 8: one pixel per lane)
+  int sx, sn;  // sub-tiles per tile row, per tile
 };
 
 // The projected record of one (view, Gaussian), as the blend consumes it (48 bytes).

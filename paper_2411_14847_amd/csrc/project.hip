@@ -25,81 +25,79 @@ constexpr double kY3c = 0.4570457994644658;   // sqrt(21/(2 pi))/4
 constexpr double kY3d = 0.3731763325901154;   // sqrt(7/pi)/4
 constexpr double kY3e = 1.445305721320277;    // sqrt(105/pi)/4
 
-template <int DEG, bool GRAD>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y, double* gx, double* gy,
-                                         double* gz) {
-  Y[0] = kY0;
-  if (GRAD) { gx[0] = gy[0] = gz[0] = 0.0; }
+template <int DEG, bool GRAD, typename F = double>
+__device__ __forceinline__ void sh_basis(F x, F y, F z, F* Y, F* gx, F* gy, F* gz) {
+  Y[0] = F(kY0);
+  if (GRAD) { gx[0] = gy[0] = gz[0] = F(0.0); }
   if (DEG >= 1) {
-    Y[1] = kY1 * y; Y[2] = kY1 * z; Y[3] = kY1 * x;
+    Y[1] = F(kY1) * y; Y[2] = F(kY1) * z; Y[3] = F(kY1) * x;
     if (GRAD) {
-      gx[1] = 0.0; gy[1] = kY1; gz[1] = 0.0;
-      gx[2] = 0.0; gy[2] = 0.0; gz[2] = kY1;
-      gx[3] = kY1; gy[3] = 0.0; gz[3] = 0.0;
+      gx[1] = F(0.0); gy[1] = F(kY1); gz[1] = F(0.0);
+      gx[2] = F(0.0); gy[2] = F(0.0); gz[2] = F(kY1);
+      gx[3] = F(kY1); gy[3] = F(0.0); gz[3] = F(0.0);
     }
   }
   if (DEG >= 2) {
-    double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kY2a * x * y;
-    Y[5] = kY2a * y * z;
-    Y[6] = kY2b * (2.0 * zz - xx - yy);
-    Y[7] = kY2a * x * z;
-    Y[8] = kY2c * (xx - yy);
+    F xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = F(kY2a) * x * y;
+    Y[5] = F(kY2a) * y * z;
+    Y[6] = F(kY2b) * (F(2.0) * zz - xx - yy);
+    Y[7] = F(kY2a) * x * z;
+    Y[8] = F(kY2c) * (xx - yy);
     if (GRAD) {
-      gx[4] = kY2a * y; gy[4] = kY2a * x; gz[4] = 0.0;
-      gx[5] = 0.0; gy[5] = kY2a * z; gz[5] = kY2a * y;
-      gx[6] = -2.0 * kY2b * x; gy[6] = -2.0 * kY2b * y; gz[6] = 4.0 * kY2b * z;
-      gx[7] = kY2a * z; gy[7] = 0.0; gz[7] = kY2a * x;
-      gx[8] = 2.0 * kY2c * x; gy[8] = -2.0 * kY2c * y; gz[8] = 0.0;
+      gx[4] = F(kY2a) * y; gy[4] = F(kY2a) * x; gz[4] = F(0.0);
+      gx[5] = F(0.0); gy[5] = F(kY2a) * z; gz[5] = F(kY2a) * y;
+      gx[6] = -F(2.0) * F(kY2b) * x; gy[6] = -F(2.0) * F(kY2b) * y; gz[6] = F(4.0) * F(kY2b) * z;
+      gx[7] = F(kY2a) * z; gy[7] = F(0.0); gz[7] = F(kY2a) * x;
+      gx[8] = F(2.0) * F(kY2c) * x; gy[8] = -F(2.0) * F(kY2c) * y; gz[8] = F(0.0);
     }
   }
   if (DEG >= 3) {
-    double xx = x * x, yy = y * y, zz = z * z;
-    Y[9] = kY3a * y * (3.0 * xx - yy);
-    Y[10] = kY3b * x * y * z;
-    Y[11] = kY3c * y * (4.0 * zz - xx - yy);
-    Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-    Y[13] = kY3c * x * (4.0 * zz - xx - yy);
-    Y[14] = kY3e * z * (xx - yy);
-    Y[15] = kY3a * x * (xx - 3.0 * yy);
+    F xx = x * x, yy = y * y, zz = z * z;
+    Y[9] = F(kY3a) * y * (F(3.0) * xx - yy);
+    Y[10] = F(kY3b) * x * y * z;
+    Y[11] = F(kY3c) * y * (F(4.0) * zz - xx - yy);
+    Y[12] = F(kY3d) * z * (F(2.0) * zz - F(3.0) * xx - F(3.0) * yy);
+    Y[13] = F(kY3c) * x * (F(4.0) * zz - xx - yy);
+    Y[14] = F(kY3e) * z * (xx - yy);
+    Y[15] = F(kY3a) * x * (xx - F(3.0) * yy);
     if (GRAD) {
-      gx[9] = kY3a * 6.0 * x * y; gy[9] = kY3a * 3.0 * (xx - yy); gz[9] = 0.0;
-      gx[10] = kY3b * y * z; gy[10] = kY3b * x * z; gz[10] = kY3b * x * y;
-      gx[11] = -2.0 * kY3c * x * y; gy[11] = kY3c * (4.0 * zz - xx - 3.0 * yy); gz[11] = 8.0 * kY3c * y * z;
-      gx[12] = -6.0 * kY3d * x * z; gy[12] = -6.0 * kY3d * y * z; gz[12] = kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-      gx[13] = kY3c * (4.0 * zz - 3.0 * xx - yy); gy[13] = -2.0 * kY3c * x * y; gz[13] = 8.0 * kY3c * x * z;
-      gx[14] = 2.0 * kY3e * x * z; gy[14] = -2.0 * kY3e * y * z; gz[14] = kY3e * (xx - yy);
-      gx[15] = kY3a * 3.0 * (xx - yy); gy[15] = -6.0 * kY3a * x * y; gz[15] = 0.0;
+      gx[9] = F(kY3a) * F(6.0) * x * y; gy[9] = F(kY3a) * F(3.0) * (xx - yy); gz[9] = F(0.0);
+      gx[10] = F(kY3b) * y * z; gy[10] = F(kY3b) * x * z; gz[10] = F(kY3b) * x * y;
+      gx[11] = -F(2.0) * F(kY3c) * x * y; gy[11] = F(kY3c) * (F(4.0) * zz - xx - F(3.0) * yy); gz[11] = F(8.0) * F(kY3c) * y * z;
+      gx[12] = -F(6.0) * F(kY3d) * x * z; gy[12] = -F(6.0) * F(kY3d) * y * z; gz[12] = F(kY3d) * (F(6.0) * zz - F(3.0) * xx - F(3.0) * yy);
+      gx[13] = F(kY3c) * (F(4.0) * zz - F(3.0) * xx - yy); gy[13] = -F(2.0) * F(kY3c) * x * y; gz[13] = F(8.0) * F(kY3c) * x * z;
+      gx[14] = F(2.0) * F(kY3e) * x * z; gy[14] = -F(2.0) * F(kY3e) * y * z; gz[14] = F(kY3e) * (xx - yy);
+      gx[15] = F(kY3a) * F(3.0) * (xx - yy); gy[15] = -F(6.0) * F(kY3a) * x * y; gz[15] = F(0.0);
     }
   }
 }
 
 // d/d(x,y,z) of sum_k w_k Y_k(x,y,z) (the polynomial forms above), without materialising the
 // per-basis gradient arrays.
-template <int DEG>
-__device__ __forceinline__ void sh_weighted_grad(double x, double y, double z, const double* w, double& gx,
-                                                 double& gy, double& gz) {
-  gx = gy = gz = 0.0;
+template <int DEG, typename F = double>
+__device__ __forceinline__ void sh_weighted_grad(F x, F y, F z, const F* w, F& gx, F& gy, F& gz) {
+  gx = gy = gz = F(0.0);
   if (DEG >= 1) {
-    gy += w[1] * kY1;
-    gz += w[2] * kY1;
-    gx += w[3] * kY1;
+    gy += w[1] * F(kY1);
+    gz += w[2] * F(kY1);
+    gx += w[3] * F(kY1);
   }
   if (DEG >= 2) {
-    gx += w[4] * kY2a * y + w[6] * (-2.0 * kY2b * x) + w[7] * kY2a * z + w[8] * (2.0 * kY2c * x);
-    gy += w[4] * kY2a * x + w[5] * kY2a * z + w[6] * (-2.0 * kY2b * y) + w[8] * (-2.0 * kY2c * y);
-    gz += w[5] * kY2a * y + w[6] * (4.0 * kY2b * z) + w[7] * kY2a * x;
+    gx += w[4] * F(kY2a) * y + w[6] * (-F(2.0) * F(kY2b) * x) + w[7] * F(kY2a) * z + w[8] * (F(2.0) * F(kY2c) * x);
+    gy += w[4] * F(kY2a) * x + w[5] * F(kY2a) * z + w[6] * (-F(2.0) * F(kY2b) * y) + w[8] * (-F(2.0) * F(kY2c) * y);
+    gz += w[5] * F(kY2a) * y + w[6] * (F(4.0) * F(kY2b) * z) + w[7] * F(kY2a) * x;
   }
   if (DEG >= 3) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    gx += w[9] * (6.0 * kY3a * x * y) + w[10] * (kY3b * y * z) + w[11] * (-2.0 * kY3c * x * y) +
-          w[12] * (-6.0 * kY3d * x * z) + w[13] * (kY3c * (4.0 * zz - 3.0 * xx - yy)) +
-          w[14] * (2.0 * kY3e * x * z) + w[15] * (3.0 * kY3a * (xx - yy));
-    gy += w[9] * (3.0 * kY3a * (xx - yy)) + w[10] * (kY3b * x * z) + w[11] * (kY3c * (4.0 * zz - xx - 3.0 * yy)) +
-          w[12] * (-6.0 * kY3d * y * z) + w[13] * (-2.0 * kY3c * x * y) + w[14] * (-2.0 * kY3e * y * z) +
-          w[15] * (-6.0 * kY3a * x * y);
-    gz += w[10] * (kY3b * x * y) + w[11] * (8.0 * kY3c * y * z) + w[12] * (kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy)) +
-          w[13] * (8.0 * kY3c * x * z) + w[14] * (kY3e * (xx - yy));
+    const F xx = x * x, yy = y * y, zz = z * z;
+    gx += w[9] * (F(6.0) * F(kY3a) * x * y) + w[10] * (F(kY3b) * y * z) + w[11] * (-F(2.0) * F(kY3c) * x * y) +
+          w[12] * (-F(6.0) * F(kY3d) * x * z) + w[13] * (F(kY3c) * (F(4.0) * zz - F(3.0) * xx - yy)) +
+          w[14] * (F(2.0) * F(kY3e) * x * z) + w[15] * (F(3.0) * F(kY3a) * (xx - yy));
+    gy += w[9] * (F(3.0) * F(kY3a) * (xx - yy)) + w[10] * (F(kY3b) * x * z) + w[11] * (F(kY3c) * (F(4.0) * zz - xx - F(3.0) * yy)) +
+          w[12] * (-F(6.0) * F(kY3d) * y * z) + w[13] * (-F(2.0) * F(kY3c) * x * y) + w[14] * (-F(2.0) * F(kY3e) * y * z) +
+          w[15] * (-F(6.0) * F(kY3a) * x * y);
+    gz += w[10] * (F(kY3b) * x * y) + w[11] * (F(8.0) * F(kY3c) * y * z) + w[12] * (F(kY3d) * (F(6.0) * zz - F(3.0) * xx - F(3.0) * yy)) +
+          w[13] * (F(8.0) * F(kY3c) * x * z) + w[14] * (F(kY3e) * (xx - yy));
   }
 }
 
@@ -231,7 +229,7 @@ __device__ __forceinline__ void colour(const GT& G, const CamK& cam, const float
   const double inv = dn > 0.0 ? 1.0 / dn : 0.0;
   for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv;
   double Y[16];
-  sh_basis<DEG, false>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
+  sh_basis<DEG, false, double>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
 #pragma unroll
   for (int ch = 0; ch < 3; ch++) {
     double acc = 0.0;
@@ -441,10 +439,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
 // Four lanes per Gaussian: lane c < 3 owns channel c (its K coefficients and their gradients,
 // over all views); the direction gradients of the three channels are summed at the end.
 // Visibility in a view is read from the forward's per-(view, Gaussian) tile counts (a visible
-// Gaussian touches >= 1 tile), so no projection is recomputed here.
+// Gaussian touches >= 1 tile) and the clamp from the forward's stored colour (0 where the
+// clamp was active), so neither is recomputed; the gradient arithmetic itself is float32.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK cams, int nv,
                                                                const uint32_t* __restrict__ tt_u,
+                                                               const Rec* __restrict__ rec_u,
                                                                const float* __restrict__ g2d, dass_grads gr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,46 +452,44 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
   const bool live = g_raw < sc.n && ch < 3;
   const int g = g_raw < sc.n ? g_raw : sc.n - 1;
   const int c = ch < 3 ? ch : 2;
-  double mu[3];
-  for (int i = 0; i < 3; i++) mu[i] = (double)sc.mean[(int64_t)i * sc.stride + g];
+  float mu[3];
+  for (int i = 0; i < 3; i++) mu[i] = sc.mean[(int64_t)i * sc.stride + g];
   float shc[K], dsh[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
     shc[k] = sc.sh[(int64_t)(k * 3 + c) * sc.stride + g];
     dsh[k] = 0.f;
   }
-  double dmu[3] = {0.0, 0.0, 0.0};
+  float dmu[3] = {0.f, 0.f, 0.f};
   for (int v = 0; v < nv && live; v++) {
     const int64_t row = (int64_t)v * sc.n + g;
     if (tt_u[row] == 0) continue;  // not visible in this view
+    const float rgb = c == 0 ? rec_u[row].r2.x : (c == 1 ? rec_u[row].r2.y : rec_u[row].r2.z);
+    if (!(rgb > 0.f)) continue;  // clamped channel: no derivative
     const CamK& cam = cams.c[v];
-    double dir[3];
-    for (int i = 0; i < 3; i++) dir[i] = mu[i] - (double)cam.campos[i];
-    const double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-    const double inv_dn = dn > 0.0 ? 1.0 / dn : 0.0;
-    double dhat[3];
+    float dir[3];
+    for (int i = 0; i < 3; i++) dir[i] = mu[i] - cam.campos[i];
+    const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    const float inv_dn = dn > 0.f ? 1.f / dn : 0.f;
+    float dhat[3];
     for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv_dn;
-    double Y[16];
-    sh_basis<DEG, false>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; k++) acc += (double)shc[k] * Y[k];
-    if (acc + 0.5 < 0.0) continue;  // clamped channel: no derivative
-    const double d = (double)g2d[row * 9 + 6 + c];
-    double w[16];
+    float Y[16];
+    sh_basis<DEG, false, float>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
+    const float d = g2d[row * 9 + 6 + c];
+    float w[16];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-      dsh[k] += (float)(d * Y[k]);
-      w[k] = d * (double)shc[k];
+      dsh[k] += d * Y[k];
+      w[k] = d * shc[k];
     }
-    double dd[3];
-    sh_weighted_grad<DEG>(dhat[0], dhat[1], dhat[2], w, dd[0], dd[1], dd[2]);
-    if (dn > 0.0) {
-      const double dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
+    float dd[3];
+    sh_weighted_grad<DEG, float>(dhat[0], dhat[1], dhat[2], w, dd[0], dd[1], dd[2]);
+    if (dn > 0.f) {
+      const float dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
       for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) * inv_dn;
     }
   }
-  for (int i = 0; i < 3; i++) dmu[i] = quad_sum(dmu[i]);
+  for (int i = 0; i < 3; i++) dmu[i] = quad_sumf(dmu[i]);
   if (g_raw >= sc.n) return;
   const int64_t st = sc.stride;
   if (live && gr.sh) {
@@ -499,7 +497,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
     for (int k = 0; k < K; k++) gr.sh[(int64_t)(k * 3 + c) * st + g] += dsh[k];
   }
   if (ch == 0 && gr.mean)
-    for (int i = 0; i < 3; i++) gr.mean[i * st + g] += (float)dmu[i];
+    for (int i = 0; i < 3; i++) gr.mean[i * st + g] += dmu[i];
 }
 
 __global__ void k_debug_projection(SceneK sc, CamK cam, double* out) {
@@ -542,10 +540,10 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   k_preprocess_bwd_geom<<<grid, block, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
   if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
-    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
-    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
-    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
-    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.g2d, grads); break;
+    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
+    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
+    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
+    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
   }
 }
 

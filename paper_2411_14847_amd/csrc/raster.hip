@@ -6,8 +6,9 @@
 // in p order and sorted stably on the tile bits only; the stable order inside a tile is the
 // depth order.  Ranges are the [first, last+1) of each tile id.
 //
-// Blend.  One wave per 16x16 sub-tile of a tile (a 16x16 tile is its own sub-tile); lane
-// (qx, qy) owns a 2x2 pixel block.  The tile's list is consumed in batches of 128 entries, each
+// Blend.  One wave per sub-tile of a tile (16x16 with a 2x2 pixel block per lane, or 8x8 with
+// one pixel per lane, for small images where the lists are walked by few waves); lane
+// (qx, qy) owns its pixels.  The tile's list is consumed in batches of 128 entries, each
 // culled against the wave's sub-tile and compacted into LDS; every lane walks its pixels front
 // to back, and the wave stops as soon as every pixel has hit the transmittance stop.
 // The backward recomputes each entry's alpha per batch, recovers the transmittance by dividing
@@ -143,11 +144,13 @@ constexpr int kCullPad = 0;
 
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
-// true if the entry cannot reach alpha >= 1/255 at any pixel centre of [0,15]^2 (tile-relative)
+// true if the entry cannot reach alpha >= 1/255 at any pixel centre of [0,SUB-1]^2 (relative to
+// the sub-tile)
+template <int SUB>
 __device__ __forceinline__ bool cull_entry(float mx, float my, float A, float B, float C, float o) {
   if (!(o * 255.0f > 0.999f)) return true;  // alpha <= o < 1/255 everywhere (with margin)
   const float thr = 2.0f * __logf(255.0f * o);  // q <= thr  <=>  o exp(-q/2) >= 1/255
-  const float lo = 0.0f, hi = (float)(kTile - 1);
+  const float lo = 0.0f, hi = (float)(SUB - 1);
   if (mx >= lo && mx <= hi && my >= lo && my <= hi) return false;
   float qmin = 3.0e38f;
   // vertical edges x = lo, hi
@@ -212,35 +215,36 @@ __device__ __forceinline__ float wave_reduce9(float* v, int lane) {
 // value index held by lanes 0..15 after wave_reduce9 (bits 0,1,3,2 halve 9 -> 5 -> 3 -> 2 -> 1)
 __constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, -1, -1};
 
-template <bool COUNT>
+template <bool COUNT, int SUB>
 __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
                                                       unsigned long long* __restrict__ pairs) {
+  constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
   __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
-  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, 16x16 sub-tile of it
+  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
-  const int ox = tx * io.tw + (sub % io.sx) * kTile, oy = ty * io.th + (sub / io.sx) * kTile;
+  const int ox = tx * io.tw + (sub % io.sx) * SUB, oy = ty * io.th + (sub / io.sx) * SUB;
   if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
-  const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
+  const int qx = PW * (lane & 7), qy = PW * (lane >> 3);
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
-  float T[4], c0[4], c1[4], c2[4];
-  int last[4];
-  float live[4];  // 1 while the pixel is walking its list, 0 once stopped (or outside the image):
+  float T[NP], c0[NP], c1[NP], c2[NP];
+  int last[NP];
+  float live[NP];  // 1 while the pixel is walking its list, 0 once stopped (or outside the image):
                   // alpha is scaled by it, so a stopped pixel neither blends nor stops again
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
+  for (int k = 0; k < NP; k++) {
+    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
     T[k] = 1.f;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       if (e < n_in) {
         const Rec R = rec_s[vals[start + e]];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
-        keep = !cull_entry(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
+        keep = !cull_entry<SUB>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
         co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
         rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((int)(start - r.x) + e));
       }
@@ -278,12 +282,11 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
       const int pos1 = __float_as_int(c.w) + 1;
-      const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
-      const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
+      const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
       // branch-free: every pixel evaluates the entry; selects keep skipped / stopped pixels unchanged
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
+      for (int k = 0; k < NP; k++) {
+        const float dx = dxb - (float)(k % PW), dy = dyb - (float)(k / PW);
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
         const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw)) * live[k];
         const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
@@ -303,13 +306,16 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         last[k] = blend ? pos1 : last[k];
       }
     }
-    const bool alive = (live[0] + live[1] + live[2] + live[3]) != 0.f;
+    float lsum = 0.f;
+#pragma unroll
+    for (int k = 0; k < NP; k++) lsum += live[k];
+    const bool alive = lsum != 0.f;
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
+  for (int k = 0; k < NP; k++) {
+    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
@@ -326,36 +332,38 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   }
 }
 
+template <int SUB>
 __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
                                                       const uint32_t* __restrict__ gid_s, int n,
                                                       float* __restrict__ g2d) {
+  constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
   __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
   __shared__ uint32_t s_p[kBatchB];
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
-  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, 16x16 sub-tile of it
+  const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
   const int v = view_of(io, nv, b);
   const ViewIO& V = io.v[v];
   const int t = b - V.tile_base;
   const int tx = t % V.TX, ty = t / V.TX;
-  const int ox = tx * io.tw + (sub % io.sx) * kTile, oy = ty * io.th + (sub / io.sx) * kTile;
+  const int ox = tx * io.tw + (sub % io.sx) * SUB, oy = ty * io.th + (sub / io.sx) * SUB;
   if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
-  const int qx = 2 * (lane & 7), qy = 2 * (lane >> 3);
+  const int qx = PW * (lane & 7), qy = PW * (lane >> 3);
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const int64_t hw = (int64_t)V.W * V.H;
-  float T[4], dC0[4], dC1[4], dC2[4], B0[4], B1[4], B2[4];
-  int last[4];
+  float T[NP], dC0[NP], dC1[NP], dC2[NP], B0[NP], B1[NP], B2[NP];
+  int last[NP];
   int my_max = 0;
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int px = ox + qx + (k & 1), py = oy + qy + (k >> 1);
+  for (int k = 0; k < NP; k++) {
+    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
     T[k] = 1.f;
     dC0[k] = dC1[k] = dC2[k] = 0.f;
     last[k] = 0;
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
         rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(bi * kBatchB + e));
-        keep = !cull_entry(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
+        keep = !cull_entry<SUB>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
       }
       const uint64_t m = __ballot(keep);
       if (keep) {
@@ -415,8 +423,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
       const int idx = __float_as_int(c.w);
-      const float dx0 = xy.x - (float)qx, dx1 = dx0 - 1.f;
-      const float dy0 = xy.y - (float)qy, dy1 = dy0 - 1.f;
+      const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
       // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
       // sum dP dy^2, d opacity, d rgb), dP = dL/d(exponent), (dx, dy) = mean - pixel
       float m[9];
@@ -424,8 +431,8 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       for (int q = 0; q < 9; q++) m[q] = 0.f;
       bool any = false;
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const float dx = (k & 1) ? dx1 : dx0, dy = (k >> 1) ? dy1 : dy0;
+      for (int k = 0; k < NP; k++) {
+        const float dx = dxb - (float)(k % PW), dy = dyb - (float)(k / PW);
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
         const float G = __builtin_amdgcn_exp2f(pw);
         const float araw = co.w * G;
@@ -517,19 +524,30 @@ void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hip
 
 static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNumXcd - 1) / kNumXcd); }
 
-// One wave per (tile, 16x16 sub-tile); the sub-tiles of a tile are consecutive logical blocks,
-// so they run on the same XCD and share its L2 for the tile's list and records.
+// One wave per (tile, sub-tile); the sub-tiles of a tile are consecutive logical blocks, so they
+// run on the same XCD and share its L2 for the tile's list and records.
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
                       const uint32_t* vals, bool count_pairs, hipStream_t st) {
   const int64_t total = total_tiles * io.sn;
   if (total == 0) return;
   const int per = per_xcd(total);
-  if (count_pairs)
-    k_blend_fwd<true><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2],
-                                                           ws.ranges, vals, ws.rec_s, ws.pairs);
-  else
-    k_blend_fwd<false><<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2],
-                                                            ws.ranges, vals, ws.rec_s, nullptr);
+  const dim3 grid(per * kNumXcd), block(kLanes);
+  unsigned long long* pairs = count_pairs ? ws.pairs : nullptr;
+  if (io.sub == 8) {
+    if (count_pairs)
+      k_blend_fwd<true, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                  ws.rec_s, pairs);
+    else
+      k_blend_fwd<false, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                   ws.rec_s, pairs);
+  } else {
+    if (count_pairs)
+      k_blend_fwd<true, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                   ws.rec_s, pairs);
+    else
+      k_blend_fwd<false, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                    ws.rec_s, pairs);
+  }
 }
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
@@ -537,8 +555,13 @@ void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   const int64_t total = total_tiles * io.sn;
   if (total == 0) return;
   const int per = per_xcd(total);
-  k_blend_bwd<<<per * kNumXcd, kLanes, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_s, ws.gid_s, n, ws.g2d);
+  const dim3 grid(per * kNumXcd), block(kLanes);
+  if (io.sub == 8)
+    k_blend_bwd<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_s,
+                                           ws.gid_s, n, ws.g2d);
+  else
+    k_blend_bwd<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_s,
+                                            ws.gid_s, n, ws.g2d);
 }
 
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,

@@ -132,6 +132,15 @@ class Trainer:
         if groups:
             ctx.adam_step(groups, cfg.beta1, cfg.beta2, cfg.eps, stream=stream, d_step=self.d_step)
 
+    def autotune_tile(self, reps: int = 3) -> dict:
+        """Picks the context's tile size with the native autotuner on the current timestep's
+        render (call after at least one iteration of the timestep, so the upstream gradients
+        are real).  The graph of the timestep is re-captured at the next replay."""
+        scratch = self.g.zeros_like()
+        res = self.ctx.autotune_tile(self.gs, self.cams, self.cfg.bg, self.outs, self.dls, scratch, reps=reps)
+        self.graph = None
+        return res
+
     # ---- one timestep -----------------------------------------------------------------------
     def begin_timestep(self, t: int, dyn_idx: torch.Tensor):
         cfg, g = self.cfg, self.g

@@ -18,7 +18,7 @@ from test_gpu_parity import BG, large_footprint_sub, small_multiview
 
 pytestmark = pytest.mark.gpu
 
-TILES = [(32, 16), (16, 32), (32, 32), (64, 32), (64, 64)]
+TILES = [(32, 16), (16, 32), (32, 32), (64, 32), (64, 64), (16, 16, 8), (32, 32, 8)]
 CASES = {
     "multiview_sh3_ragged": lambda: small_multiview(),
     "tiny_dense": lambda: synth.tiny_scene(2, 300, 40, 36, sh_degree=2, log_scale_mu=-2.0),
@@ -30,12 +30,13 @@ CASES = {
 @pytest.mark.parametrize("case", list(CASES))
 def test_tile_keys_images_match_oracle(case, tile):
     scene, cams, _ = CASES[case]()
-    log(f"[tile {tile[0]}x{tile[1]}] {case}")
+    log(f"[tile {tile}] {case}")
     g = to_gpu(scene)
     ctx = make_ctx(scene.n, cams)
     ctx.tile = tile
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
+    tile = tile[:2]  # the sub-tile split is internal to the blend; the definition has the tile size
     for v, cam in enumerate(cams):
         p = oracle.project(scene, cam, tile)
         assert not np.any(p.flags & oracle.FLAG_RADIUS)
@@ -53,11 +54,12 @@ def test_tile_keys_images_match_oracle(case, tile):
         assert ex.mean() <= 0.01
 
 
-@pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32), (16, 16, 8)])
 @pytest.mark.parametrize("case", ["multiview_sh3_ragged", "large_footprint_64_4x32x32"])
 def test_tile_gradients_match_oracle(case, tile):
     scene, cams, dls = CASES[case]()
-    log(f"[tile grad {tile[0]}x{tile[1]}] {case}")
+    log(f"[tile grad {tile}] {case}")
+    gtile, tile = tile, tile[:2]
     renders = [oracle.render_view(scene, c, bg=BG, tile=tile) for c in cams]
     dls = [d.copy() for d in dls]
     for d, vr, cam in zip(dls, renders, cams):
@@ -65,7 +67,7 @@ def test_tile_gradients_match_oracle(case, tile):
     og, _, ogn, ocnt = oracle.render_backward(scene, cams, dls, bg=BG, tile=tile, renders=renders)
     g = to_gpu(scene)
     ctx = make_ctx(scene.n, cams)
-    ctx.tile = tile
+    ctx.tile = gtile
     out = ctx.render_fwd(g, cams, BG)
     grads = g.zeros_like()
     gn = torch.zeros(g.capacity, device="cuda")
@@ -81,6 +83,26 @@ def test_tile_gradients_match_oracle(case, tile):
         log(f"  {name}: max rel err (significant) {rel:.2e}")
     np.testing.assert_array_equal(cnt[:scene.n].cpu().numpy(), ocnt)
     assert_grad_close("gradnorm", gn[:scene.n].cpu().numpy(), ogn, exclude=gflag)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32)])
+def test_subtile8_forward_matches_subtile16(tile):
+    """8x8 sub-tiles (one pixel per lane) walk the same lists in the same order as 16x16
+    sub-tiles; only the float32 rounding of the pixel offsets differs (they are formed relative
+    to the sub-tile's origin), so images agree to float32 rounding and n_contrib everywhere but
+    at decisions within rounding of a threshold."""
+    scene, cams, dls = small_multiview(seed=9, n=2500, views=2, W=150, H=110)
+    g = to_gpu(scene)
+    outs = []
+    for sub in (16, 8):
+        ctx = make_ctx(scene.n, cams)
+        ctx.tile = (*tile, sub)
+        outs.append(ctx.render_fwd(g, cams, BG))
+        ctx.sync()
+    for a, b in zip(*outs):
+        assert (a.rgb - b.rgb).abs().max().item() <= 1e-5
+        assert (a.t_final - b.t_final).abs().max().item() <= 1e-5
+        assert (a.n_contrib != b.n_contrib).float().mean().item() <= 1e-3
 
 
 def test_backward_rejects_a_tile_size_other_than_the_forwards():
@@ -114,9 +136,10 @@ def test_autotuner_picks_a_timed_candidate_and_keeps_parity():
     assert ctx.tile == first_close
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
+    tile = ctx.tile[:2]  # a third entry is the blend's sub-tile size, internal to the kernels
     for v, cam in enumerate(cams):
-        vr = oracle.render_view(scene, cam, bg=BG, tile=ctx.tile)
-        ex = excluded_pixels(vr, cam, tile=ctx.tile)
+        vr = oracle.render_view(scene, cam, bg=BG, tile=tile)
+        ex = excluded_pixels(vr, cam, tile=tile)
         assert np.abs(out[v].rgb.cpu().numpy() - vr.rgb)[:, ~ex].max() <= IMG_TOL
         np.testing.assert_array_equal(out[v].n_contrib.cpu().numpy()[~ex], vr.n_contrib[~ex])
 
