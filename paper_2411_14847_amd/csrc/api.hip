@@ -160,7 +160,7 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.vals[0], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.vals[1], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.ranges, w.cap_tiles > 0 ? w.cap_tiles : 1);
-  ALLOC(w.hist, 512 * 1024 + 512);  // [radix][max sort blocks] counts + radix digit totals
+  ALLOC(w.hist, 1024 * 1024 + 1024);  // [radix][max sort blocks] counts + radix digit totals
   ALLOC(w.scan_tmp, scan_tmp_elems(vn));
   ALLOC(w.counters, 16);
   ALLOC(w.pairs, 2);
@@ -603,6 +603,7 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
   a.gamma_err = gamma_err;
   a.tau_pos = tau_pos;
   a.tau_err = tau_err;
+  a.gbits = std::max(1, bit_width((uint64_t)(g->n_base > 0 ? g->n_base - 1 : 0)));
   for (int v = 0; v < n_views; v++) {
     if (!err_maps[v]) return fail(ctx, DASS_E_INVALID, "err_maps[%d] is NULL", v);
     const dass_camera& c = cams[v];
@@ -625,11 +626,12 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
   stage_begin(ctx, DASS_STAGE_DENSIFY, st);
   launch_fill_u32(ws.counters + 1, 0u, 1, st);
   launch_densify_select(sc, a, gradnorm_sum, grad_count, g->n_base, ws.dkey[0], ws.dval[0], ws.counters + 1, st);
-  const int cur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 1, g->n_base, 0, 64, ws.hist,
+  // rank by score (descending) then index: sort only the 32 + gbits bits the key occupies
+  const int cur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 1, g->n_base, 0, 32 + a.gbits, ws.hist,
                                  sort_blocks_for(g->n_base), st);
   const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
   launch_densify_spawn(g->mean, g->quat, g->log_scale, g->opacity_logit, g->sh, 3 * K, g->capacity, g->n,
-                       g->capacity, ws.dkey[cur], ws.counters + 1, k_max, seed, n_appended, st);
+                       g->capacity, ws.dval[cur], ws.counters + 1, k_max, seed, n_appended, st);
   stage_end(ctx, DASS_STAGE_DENSIFY, st);
   ctx->have_fwd = false;  // the depth-order buffers were reused
   return check_launch(ctx, "densify_append");

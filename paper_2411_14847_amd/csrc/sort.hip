@@ -2,12 +2,12 @@
 //
 // Radix sort: reduce-then-scan with a fixed grid, so that the element count can stay on the
 // device (no host round trip inside a render; the launch sequence is graph-capturable).
-// Each pass over an 8-bit digit is
+// Each pass over a digit of 8 to 10 bits is
 //   (1) upsweep: every block histograms its contiguous chunk into LDS (per-wave
 //       sub-histograms to spread LDS atomics), written digit-major to global memory;
-//   (2) scan: one workgroup turns the [256][blocks] counts into global write offsets;
+//   (2) scan: one workgroup per digit turns the [radix][blocks] counts into global offsets;
 //   (3) scatter: every block re-reads its chunk in batches of 2048 pairs, ranks them stably
-//       with wave ballots (8-9 ballots give each lane the mask of lanes holding the same
+//       with wave ballots (8-10 ballots give each lane the mask of lanes holding the same
 //       digit; each wave ranks its own 512 consecutive pairs), orders the batch by digit in
 //       LDS and writes each digit's run contiguously.
 // A pass never depends on forward progress between workgroups.
@@ -19,7 +19,7 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;                      // items per thread per batch
 constexpr int kBatch = kSortThreads * kSortItems;  // 2048
-constexpr int kMaxRadixBits = 9;
+constexpr int kMaxRadixBits = 10;
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kMaxSortBlocks = 1024;
 
@@ -344,10 +344,11 @@ int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int6
                     int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
   int cur = 0;
   if (max_count == 0 || end_bit <= begin_bit) return cur;
-  // fewest passes of at most kMaxRadixBits; 8-bit digits when that costs no extra pass
+  // fewest passes of at most kMaxRadixBits, with the narrowest digit (>= 8 bits) that keeps
+  // that pass count: wider digits cost LDS and ballots per item
   const int bits = end_bit - begin_bit;
   const int passes = (bits + kMaxRadixBits - 1) / kMaxRadixBits;
-  const int rb = ((bits + 7) / 8 == passes) ? 8 : kMaxRadixBits;
+  const int rb = max(8, (bits + passes - 1) / passes);
   uint32_t* totals = hist + (int64_t)kMaxRadix * kMaxSortBlocks;
   for (int shift = begin_bit; shift < end_bit; shift += rb) {
     if (rb == 8) {
@@ -355,11 +356,16 @@ int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int6
       k_scan_rows<<<256, kSortThreads, 0, st>>>(hist, blocks, totals);
       k_scatter<K, 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
                                                        shift, blocks, hist, totals);
-    } else {
+    } else if (rb == 9) {
       k_upsweep<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
       k_scan_rows<<<512, kSortThreads, 0, st>>>(hist, blocks, totals);
       k_scatter<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
                                                        shift, blocks, hist, totals);
+    } else {
+      k_upsweep<K, 10><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
+      k_scan_rows<<<1024, kSortThreads, 0, st>>>(hist, blocks, totals);
+      k_scatter<K, 10><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
+                                                        shift, blocks, hist, totals);
     }
     cur ^= 1;
   }

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_densify_select(SceneK s, DensifyArgs a,
   const bool in_s = (gbar > a.tau_pos) || (in_err && gbar > a.tau_err);
   if (!in_s) return;
   const uint32_t pos = atomicAdd(d_count, 1u);
-  sel_keys[pos] = ((uint64_t)(~__float_as_uint(score)) << 32) | (uint64_t)(uint32_t)g;
+  sel_keys[pos] = ((uint64_t)(~__float_as_uint(score)) << a.gbits) | (uint64_t)(uint32_t)g;
   sel_vals[pos] = (uint32_t)g;
 }
 
@@ -206,7 +206,7 @@ __device__ __forceinline__ double u01(uint64_t x) { return (double)(x >> 11) * 0
 __global__ __launch_bounds__(256) void k_densify_spawn(float* __restrict__ mean, float* __restrict__ quat,
                                                        float* __restrict__ log_scale, float* __restrict__ logit,
                                                        float* __restrict__ sh, int n_sh, int stride, int n, int capacity,
-                                                       const uint64_t* __restrict__ sel_keys,
+                                                       const uint32_t* __restrict__ sel_idx,
                                                        const uint32_t* __restrict__ d_count, int k_max, uint64_t seed,
                                                        int32_t* __restrict__ n_appended) {
   const uint32_t ns = *d_count;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_densify_spawn(float* __restrict__ mean,
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0 && n_appended) *n_appended = n_app < 0 ? 0 : n_app;
   if (j >= n_app) return;
-  const int64_t p = (int64_t)(uint32_t)(sel_keys[j % ns] & 0xFFFFFFFFull);
+  const int64_t p = (int64_t)sel_idx[j % ns];  // parents in rank order
   const int64_t c = (int64_t)n + j;
   const int64_t st = stride;
   double q[4], qn = 0.0;
@@ -286,10 +286,10 @@ void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* g
 }
 
 void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
-                          int stride, int n, int capacity, const uint64_t* sel_keys, const uint32_t* d_count, int k_max,
+                          int stride, int n, int capacity, const uint32_t* sel_idx, const uint32_t* d_count, int k_max,
                           uint64_t seed, int32_t* n_appended, hipStream_t st) {
   const int blocks = k_max > 0 ? (k_max + 255) / 256 : 1;
-  k_densify_spawn<<<blocks, 256, 0, st>>>(mean, quat, log_scale, logit, sh, n_planes_sh, stride, n, capacity, sel_keys,
+  k_densify_spawn<<<blocks, 256, 0, st>>>(mean, quat, log_scale, logit, sh, n_planes_sh, stride, n, capacity, sel_idx,
                                            d_count, k_max, seed, n_appended);
 }
 
