@@ -160,7 +160,7 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.vals[0], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.vals[1], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.ranges, w.cap_tiles > 0 ? w.cap_tiles : 1);
-  ALLOC(w.hist, 1024 * 1024 + 1024);  // [radix][max sort blocks] counts + radix digit totals
+  ALLOC(w.hist, 2048 * 1024 + 2048);  // [radix][max sort blocks] counts + radix digit totals
   ALLOC(w.scan_tmp, scan_tmp_elems(vn));
   ALLOC(w.counters, 16);
   ALLOC(w.pairs, 2);

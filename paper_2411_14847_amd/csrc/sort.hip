@@ -2,12 +2,12 @@
 //
 // Radix sort: reduce-then-scan with a fixed grid, so that the element count can stay on the
 // device (no host round trip inside a render; the launch sequence is graph-capturable).
-// Each pass over a digit of 8 to 10 bits is
+// Each pass over a digit of 8 to 11 bits is
 //   (1) upsweep: every block histograms its contiguous chunk into LDS (per-wave
 //       sub-histograms to spread LDS atomics), written digit-major to global memory;
 //   (2) scan: one workgroup per digit turns the [radix][blocks] counts into global offsets;
 //   (3) scatter: every block re-reads its chunk in batches of 2048 pairs, ranks them stably
-//       with wave ballots (8-10 ballots give each lane the mask of lanes holding the same
+//       with wave ballots (8-11 ballots give each lane the mask of lanes holding the same
 //       digit; each wave ranks its own 512 consecutive pairs), orders the batch by digit in
 //       LDS and writes each digit's run contiguously.
 // A pass never depends on forward progress between workgroups.
@@ -19,7 +19,7 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;                      // items per thread per batch
 constexpr int kBatch = kSortThreads * kSortItems;  // 2048
-constexpr int kMaxRadixBits = 10;
+constexpr int kMaxRadixBits = 11;  // 32-bit keys; 64-bit keys use at most 10 (LDS per block)
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kMaxSortBlocks = 1024;
 
@@ -339,33 +339,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_final(const uint32_t* __r
 
 __global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
 
+template <typename K, int RB>
+void radix_pass(K* keys[2], uint32_t* vals[2], int cur, const uint32_t* d_count, int shift, int blocks,
+                uint32_t* hist, uint32_t* totals, hipStream_t st) {
+  k_upsweep<K, RB><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
+  k_scan_rows<<<1 << RB, kSortThreads, 0, st>>>(hist, blocks, totals);
+  k_scatter<K, RB><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count, shift,
+                                                   blocks, hist, totals);
+}
+
 template <typename K>
 int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
                     int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
   int cur = 0;
   if (max_count == 0 || end_bit <= begin_bit) return cur;
-  // fewest passes of at most kMaxRadixBits, with the narrowest digit (>= 8 bits) that keeps
-  // that pass count: wider digits cost LDS and ballots per item
+  // fewest passes of at most max_bits, with the narrowest digit (>= 8 bits) that keeps that pass
+  // count: wider digits cost LDS and ballots per item
+  constexpr int max_bits = sizeof(K) == 4 ? kMaxRadixBits : kMaxRadixBits - 1;
   const int bits = end_bit - begin_bit;
-  const int passes = (bits + kMaxRadixBits - 1) / kMaxRadixBits;
+  const int passes = (bits + max_bits - 1) / max_bits;
   const int rb = max(8, (bits + passes - 1) / passes);
   uint32_t* totals = hist + (int64_t)kMaxRadix * kMaxSortBlocks;
   for (int shift = begin_bit; shift < end_bit; shift += rb) {
-    if (rb == 8) {
-      k_upsweep<K, 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
-      k_scan_rows<<<256, kSortThreads, 0, st>>>(hist, blocks, totals);
-      k_scatter<K, 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
-                                                       shift, blocks, hist, totals);
-    } else if (rb == 9) {
-      k_upsweep<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
-      k_scan_rows<<<512, kSortThreads, 0, st>>>(hist, blocks, totals);
-      k_scatter<K, 9><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
-                                                       shift, blocks, hist, totals);
-    } else {
-      k_upsweep<K, 10><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
-      k_scan_rows<<<1024, kSortThreads, 0, st>>>(hist, blocks, totals);
-      k_scatter<K, 10><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count,
-                                                        shift, blocks, hist, totals);
+    switch (rb) {
+      case 8: radix_pass<K, 8>(keys, vals, cur, d_count, shift, blocks, hist, totals, st); break;
+      case 9: radix_pass<K, 9>(keys, vals, cur, d_count, shift, blocks, hist, totals, st); break;
+      case 10: radix_pass<K, 10>(keys, vals, cur, d_count, shift, blocks, hist, totals, st); break;
+      default: radix_pass<K, sizeof(K) == 4 ? 11 : 10>(keys, vals, cur, d_count, shift, blocks, hist, totals, st);
     }
     cur ^= 1;
   }
