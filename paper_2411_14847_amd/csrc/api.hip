@@ -149,11 +149,9 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.dkey[1], vn);
   ALLOC(w.dval[0], vn);
   ALLOC(w.dval[1], vn);
-  ALLOC(w.rec_s, vn);
   ALLOC(w.rect_s, vn);
   ALLOC(w.tt_s, vn);
   ALLOC(w.off_s, vn + 1);
-  ALLOC(w.inv, vn);
   ALLOC(w.g2d, vn * 9);
   ALLOC(w.keys[0], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.keys[1], w.cap_keys > 0 ? w.cap_keys : 1);

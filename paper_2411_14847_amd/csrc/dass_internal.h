@@ -86,12 +86,11 @@ struct Workspace {
   uint64_t* dkey[2] = {nullptr, nullptr};
   uint32_t* dval[2] = {nullptr, nullptr};
   // per sorted position p (view-major, depth order)
-  Rec* rec_s = nullptr;
   uint2* rect_s = nullptr;
   uint32_t* tt_s = nullptr;        // tiles touched, sorted order
   uint64_t* off_s = nullptr;       // exclusive prefix of tiles touched, [cap_vn + 1]
-  uint32_t* inv = nullptr;         // inv[v*n + g] = p
   uint32_t* gid_s = nullptr;       // gid of sorted position p
+  // tile keys carry the record index v * n + g as their value
   float* g2d = nullptr;            // [cap_vn][9], row v * n + g: blend-backward sums (moments of
                                    // dL/d(exponent) over the offsets, d opacity, d rgb)
   // keys

@@ -1,10 +1,10 @@
 // Tile binning and the front-to-back blend with its adjoint (App. A.1).
 //
-// Binning.  After the per-view depth sort of (view, depth bits, index), the projected records
-// are permuted into that order, so a Gaussian's sorted position p already encodes its view
-// and depth rank.  Keys are then just global tile ids (view tile base + ty*TX + tx), emitted
-// in p order and sorted stably on the tile bits only; the stable order inside a tile is the
-// depth order.  Ranges are the [first, last+1) of each tile id.
+// Binning.  After the per-view depth sort of (view, depth bits, index), the tile counts and
+// rectangles are gathered into that order.  Keys are then just global tile ids (view tile base
+// + ty*TX + tx), emitted in (view, depth) order with the record index (view * n + Gaussian) as
+// value and sorted stably on the tile bits only; the stable order inside a tile is the depth
+// order.  Ranges are the [first, last+1) of each tile id.
 //
 // Blend.  One wave per sub-tile of a tile (16x16 with a 2x2 pixel block per lane, or 8x8 with
 // one pixel per lane, for small images where the lists are walked by few waves); lane
@@ -33,31 +33,31 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   for (int64_t j = i; j < n; j += stride) p[j] = v;
 }
 
+// Tiles touched and tile rectangle of each (view, Gaussian) in (view, depth) order, for the scan
+// and the key emission; the records themselves stay where the projection wrote them.
 __global__ __launch_bounds__(256) void k_gather_sorted(int n, int64_t vn, const uint32_t* __restrict__ sorted_gid,
-                                                       const Rec* __restrict__ rec_u, const uint32_t* __restrict__ tt_u,
-                                                       const uint2* __restrict__ rect_u, Rec* __restrict__ rec_s,
-                                                       uint32_t* __restrict__ tt_s, uint2* __restrict__ rect_s,
-                                                       uint32_t* __restrict__ inv) {
+                                                       const uint32_t* __restrict__ tt_u, const uint2* __restrict__ rect_u,
+                                                       uint32_t* __restrict__ tt_s, uint2* __restrict__ rect_s) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= vn) return;
   const int64_t v = p / n;
   const int64_t i = v * n + sorted_gid[p];
-  rec_s[p] = rec_u[i];
   tt_s[p] = tt_u[i];
   rect_s[p] = rect_u[i];
-  inv[i] = (uint32_t)p;
 }
 
 // Each wave takes 64 consecutive sorted positions (Gaussian-views) and writes all their keys
-// with the keys spread evenly over the lanes: lane l writes keys l, l + 64, ... of the wave's
+// (value: the record index of the Gaussian-view) with the keys spread evenly over the lanes: lane l writes keys l, l + 64, ... of the wave's
 // run, finding the owning Gaussian by a binary search over the run's end offsets in LDS.  The
 // stores of a wave are consecutive, whatever the tile counts.
 __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams, const uint32_t* __restrict__ tt_s,
-                                                   const uint2* __restrict__ rect_s, const uint64_t* __restrict__ off,
-                                                   int64_t cap, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                   const uint2* __restrict__ rect_s, const uint32_t* __restrict__ sorted_gid,
+                                                   const uint64_t* __restrict__ off, int64_t cap,
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ err) {
   __shared__ uint32_t s_end[4][64];   // end of each Gaussian's keys, relative to the wave's first key
   __shared__ uint4 s_g[4][64];        // key of the rectangle's first tile, TX, width, 1/width
+  __shared__ uint32_t s_rec[4][64];   // record index (view * n + Gaussian) = the keys' value
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane;  // first position of this wave
   if (p0 >= vn) return;  // uniform over the wave
@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams
     const int TX = cams.c[v].TX;
     s_g[wave][lane] = make_uint4((uint32_t)(cams.c[v].tile_base + y0 * TX + x0), (uint32_t)TX, (uint32_t)w,
                                  __float_as_uint(1.0f / (float)w));
+    s_rec[wave][lane] = (uint32_t)((int64_t)v * n + sorted_gid[pm]);
   }
   const uint64_t first = __shfl(my_off, 0, 64);
   const uint32_t end = valid ? (uint32_t)(my_off - first) + my_tt : 0xFFFFFFFFu;  // non-decreasing over lanes
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams
     const uint64_t kk = first + k;
     if (kk < (uint64_t)cap) {
       keys[kk] = gg.x + q * gg.y + (uint32_t)r;
-      vals[kk] = (uint32_t)(p0 + src);
+      vals[kk] = s_rec[wave][src];
     }
   }
 }
@@ -218,7 +219,7 @@ __constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, 
 template <bool COUNT, int SUB>
 __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
+                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       unsigned long long* __restrict__ pairs) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
   __shared__ float2 s_xy[kBatchB];
@@ -261,7 +262,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       float2 xy;
       float4 co, rgb;
       if (e < n_in) {
-        const Rec R = rec_s[vals[start + e]];
+        const Rec R = rec[vals[start + e]];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         keep = !cull_entry<SUB>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
         co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
@@ -335,8 +336,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
 template <int SUB>
 __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
-                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec_s,
-                                                      const uint32_t* __restrict__ gid_s, int n,
+                                                      const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       float* __restrict__ g2d) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
   __shared__ float2 s_xy[kBatchB];
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       uint32_t p = 0;
       if (e < n_in) {
         p = vals[start + e];
-        const Rec R = rec_s[p];
+        const Rec R = rec[p];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
         rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(bi * kBatchB + e));
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         s_xy[pos] = xy;
         s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, cn.w);
         s_rgb[pos] = rgb;
-        s_p[pos] = (uint32_t)v * (uint32_t)n + gid_s[p];  // gradient row: (view, Gaussian)
+        s_p[pos] = p;  // record index = gradient row (view * n + Gaussian)
       }
       n_kept += __popcll(m);
     }
@@ -470,15 +470,15 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   }
 }
 
-__global__ void k_debug_keys(int view_tile_base, const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                             const Rec* __restrict__ rec_s, const uint32_t* __restrict__ gid_s, uint32_t lo,
+__global__ void k_debug_keys(int view_tile_base, uint32_t row0, const uint32_t* __restrict__ keys,
+                             const uint32_t* __restrict__ vals, const Rec* __restrict__ rec, uint32_t lo,
                              uint32_t cnt, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   const uint32_t k = keys[lo + i];
-  const uint32_t p = vals[lo + i];
-  kout[i] = ((uint64_t)(k - (uint32_t)view_tile_base) << 32) | (uint64_t)__float_as_uint(rec_s[p].r2.w);
-  vout[i] = gid_s[p];
+  const uint32_t p = vals[lo + i];  // record index of the view's Gaussian
+  kout[i] = ((uint64_t)(k - (uint32_t)view_tile_base) << 32) | (uint64_t)__float_as_uint(rec[p].r2.w);
+  vout[i] = p - row0;
 }
 
 __global__ void k_debug_ranges(const uint2* __restrict__ ranges, int tile_base, int n_tiles, uint32_t lo,
@@ -502,15 +502,15 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
 
 void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspace& ws, hipStream_t st) {
   if (vn == 0) return;
-  k_gather_sorted<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, sorted_gid, ws.rec_u, ws.tt_u, ws.rect_u,
-                                                                 ws.rec_s, ws.tt_s, ws.rect_s, ws.inv);
+  k_gather_sorted<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, sorted_gid, ws.tt_u, ws.rect_u, ws.tt_s,
+                                                                 ws.rect_s);
 }
 
 void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipStream_t st) {
   scan_u32_to_u64(ws.tt_s, ws.off_s, vn, ws.scan_tmp, st);
   if (vn > 0)
-    k_emit_keys<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, cams, ws.tt_s, ws.rect_s, ws.off_s, ws.cap_keys,
-                                                               ws.keys[0], ws.vals[0], ws.err);
+    k_emit_keys<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, cams, ws.tt_s, ws.rect_s, ws.gid_s, ws.off_s,
+                                                               ws.cap_keys, ws.keys[0], ws.vals[0], ws.err);
   k_clamp_count<<<1, 1, 0, st>>>(ws.off_s + vn, ws.cap_keys, ws.counters);
 }
 
@@ -536,17 +536,17 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   if (io.sub == 8) {
     if (count_pairs)
       k_blend_fwd<true, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                  ws.rec_s, pairs);
+                                                  ws.rec_u, pairs);
     else
       k_blend_fwd<false, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_s, pairs);
+                                                   ws.rec_u, pairs);
   } else {
     if (count_pairs)
       k_blend_fwd<true, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_s, pairs);
+                                                   ws.rec_u, pairs);
     else
       k_blend_fwd<false, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                    ws.rec_s, pairs);
+                                                    ws.rec_u, pairs);
   }
 }
 
@@ -557,21 +557,19 @@ void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   const int per = per_xcd(total);
   const dim3 grid(per * kNumXcd), block(kLanes);
   if (io.sub == 8)
-    k_blend_bwd<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_s,
-                                           ws.gid_s, n, ws.g2d);
+    k_blend_bwd<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_u,
+                                           ws.g2d);
   else
-    k_blend_bwd<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_s,
-                                            ws.gid_s, n, ws.g2d);
+    k_blend_bwd<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_u,
+                                            ws.g2d);
 }
 
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,
                        uint32_t lo, uint32_t cnt, const CamK& cam, uint64_t* kout, uint32_t* vout, int64_t* rout,
                        hipStream_t st) {
-  (void)view;
-  (void)n;
   if (cnt > 0)
-    k_debug_keys<<<(cnt + 255) / 256, 256, 0, st>>>(cam.tile_base, keys_sorted, vals_sorted, ws.rec_s, ws.gid_s, lo,
-                                                     cnt, kout, vout);
+    k_debug_keys<<<(cnt + 255) / 256, 256, 0, st>>>(cam.tile_base, (uint32_t)((int64_t)view * n), keys_sorted,
+                                                     vals_sorted, ws.rec_u, lo, cnt, kout, vout);
   const int nt = cam.TX * cam.TY;
   k_debug_ranges<<<(nt + 255) / 256, 256, 0, st>>>(ws.ranges, cam.tile_base, nt, lo, rout);
 }
