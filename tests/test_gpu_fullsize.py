@@ -2,8 +2,8 @@
 all views in one render call as the benchmark runs them), on outputs the oracle computes one
 by one: complete sorted keys / ranges of two views, sampled tiles of the images, and complete
 gradients of sampled Gaussians (the oracle blends only the tiles those Gaussians touch, which
-is all their gradients depend on).  Run at 16x16 tiles and at 32x64, the size the tile
-autotuner picks for this workload on MI355X."""
+is all their gradients depend on).  Run at 16x16 tiles and at 32x64 and 64x32, the sizes the
+tile autotuner picks for this workload on MI355X."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 BG = (0.0, 0.0, 0.0)
 
 
-@pytest.fixture(scope="module", params=[(16, 16), (32, 64)], ids=["tile16x16", "tile32x64"])
+@pytest.fixture(scope="module", params=[(16, 16), (32, 64), (64, 32)], ids=["tile16x16", "tile32x64", "tile64x32"])
 def full(request):
     tile = request.param
     log(f"[fullsize] generating 200k-Gaussian, 20-view scene (tile {tile[0]}x{tile[1]})")
@@ -119,3 +119,39 @@ def test_fullsize_sampled_gaussian_gradients(full):
         log(f"  {name}: max rel err (significant) {rel:.2e}")
     np.testing.assert_array_equal(cnt.cpu().numpy()[sample], ocnt[sample])
     assert_grad_close("gradnorm", gn.cpu().numpy()[sample], ogn[sample])
+
+
+def test_large_footprint_fullsize_sampled_tiles():
+    """The large-footprint workload at full size (1,000,000 Gaussians, SH3, log-scales N(-2, 0.5),
+    four 1920x1080 views) at the 64x64 tiles the autotuner picks for it: sampled tiles of two
+    views against the oracle (keys of those views computed by the oracle at the same tile size)."""
+    tile = (64, 64)
+    log("[stress fullsize] generating the 1M-Gaussian scene")
+    scene, cams = synth.large_footprint_scene(0)
+    g = to_gpu(scene)
+    from paper_2411_14847_amd import Context
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    ctx = Context(max_gaussians=scene.n, max_views=len(cams), max_keys=400_000_000, max_tiles=tiles)
+    ctx.tile = tile
+    out = ctx.render_fwd(g, cams, BG)
+    ctx.sync()
+    log("[stress fullsize] GPU forward done")
+    for view in (0, 3):
+        cam = cams[view]
+        p = oracle.project(scene, cam, tile)
+        k, v, r = oracle.keys(p, cam, tile)
+        TX, TY = oracle.tiles_of(cam, tile)
+        rng = np.random.default_rng(300 + view)
+        picks = np.concatenate([rng.choice(TX * TY, 3, replace=False), [TX * TY - 1]])  # + ragged corner
+        vr = oracle.render_view(scene, cam, bg=BG, tile=tile, tiles=picks, proj=p, key_data=(k, v, r))
+        m = vr.computed & ~excluded_pixels(vr, cam, tile=tile)
+        o = out[view]
+        err = np.abs(o.rgb.cpu().numpy() - vr.rgb)[:, m].max()
+        log(f"  view {view}: {k.size} keys, {m.sum()} pixels compared, max |rgb| err {err:.2e}")
+        assert err <= IMG_TOL
+        assert np.abs(o.t_final.cpu().numpy() - vr.t_final)[m].max() <= IMG_TOL
+        np.testing.assert_array_equal(o.n_contrib.cpu().numpy()[m], vr.n_contrib[m])
+        gk, gv, gr = ctx.debug_keys(view, k.size + 4096, TX * TY)
+        for t in picks:  # the sampled tiles' sorted key lists, bit-exact
+            np.testing.assert_array_equal(gk[gr[t, 0]:gr[t, 1]], k[r[t, 0]:r[t, 1]])
+            np.testing.assert_array_equal(gv[gr[t, 0]:gr[t, 1]], v[r[t, 0]:r[t, 1]])
