@@ -66,11 +66,11 @@ def measured_traffic(kernel: str, workload: str, tile: str):
     if "```json" not in text:
         return None
     rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("tile") != tile:
+    if rec.get("kernel") != kernel or rec.get("workload") != workload or tile not in rec.get("by_tile", {}):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("raster_hip_sha256"):
         return None
-    return float(rec["traffic_bytes"])
+    return float(rec["by_tile"][tile]["traffic_bytes"])
 
 
 def build_workload(args):
