@@ -112,7 +112,7 @@ typedef struct {
 
 /* Sizes the context reserves device memory for. */
 typedef struct {
-  int32_t max_gaussians; /* capacity of the scenes rendered                     */
+  int32_t max_gaussians; /* capacity of the scenes rendered (< 2^28)            */
   int32_t max_views;     /* views per render call (<= DASS_MAX_VIEWS)            */
   int64_t max_keys;      /* tile keys per render call, summed over its views;
                             at most 0xFFFF0000 (keys are indexed with 32 bits)   */

@@ -129,6 +129,8 @@ dass_status check_limits(dass_ctx ctx, const dass_limits* l) {
     return fail(ctx, DASS_E_INVALID, "max_keys must be <= 0xFFFF0000 and max_tiles < 2^31");
   if ((int64_t)l->max_views * l->max_gaussians > 0xFFFFFFFFll)
     return fail(ctx, DASS_E_INVALID, "max_views * max_gaussians must be < 2^32");
+  // the blend carries list positions (< max_gaussians) in 28 bits
+  if (l->max_gaussians >= (1 << 28)) return fail(ctx, DASS_E_INVALID, "max_gaussians must be < 2^28");
   return DASS_OK;
 }
 

@@ -6,11 +6,12 @@
 // value and sorted stably on the tile bits only; the stable order inside a tile is the depth
 // order.  Ranges are the [first, last+1) of each tile id.
 //
-// Blend.  One wave per sub-tile of a tile (16x16 with a 2x2 pixel block per lane, or 8x8 with
-// one pixel per lane, for small images where the lists are walked by few waves); lane
-// (qx, qy) owns its pixels.  The tile's list is consumed in batches of 128 entries, each
-// culled against the wave's sub-tile and compacted into LDS; every lane walks its pixels front
-// to back, and the wave stops as soon as every pixel has hit the transmittance stop.
+// Blend.  One wave per sub-tile of a tile (16x16 with four pixels per lane, one in each 8x8
+// quadrant, or 8x8 with one pixel per lane, for small images where the lists are walked by few
+// waves).  The tile's list is consumed in batches of 128 entries, each culled against the
+// quadrants of the wave's sub-tile and compacted into LDS; every lane walks its pixels front
+// to back, skipping the quadrants an entry misses, and the wave stops as soon as every pixel
+// has hit the transmittance stop.
 // The backward recomputes each entry's alpha per batch, recovers the transmittance by dividing
 // out (1 - alpha) from T_final while walking backwards, sums each Gaussian's 9 gradient terms
 // over the wave and issues one vector atomic per (Gaussian, wave).
@@ -134,42 +135,58 @@ __device__ __forceinline__ int view_of(const ViewsIO& io, int nv, int b) {
 }
 
 // ---- blend ------------------------------------------------------------------------------------
-// One wave per 16x16 tile; lane (qx, qy) of the 8x8 lane grid owns the 2x2 pixel block at
-// (2qx, 2qy).  Batches of up to 256 list entries are loaded by the wave, culled against the
-// tile and compacted into LDS in list order.  The cull drops an entry only if the minimum of its
-// quadratic form over the tile's pixel rectangle exceeds the alpha >= 1/255 level by a margin,
-// i.e. when every pixel of the tile would skip it anyway; the list position of every kept entry
-// is carried along, so n_contrib still counts positions in the full list.
+// One wave per sub-tile (16x16 or 8x8 pixels).  The sub-tile is cut into 8x8 quadrants and
+// lane (qx, qy) of the 8x8 lane grid owns pixel (qx, qy) of every quadrant.  Batches of up to
+// 128 list entries are loaded by the wave, culled per quadrant and compacted into LDS in list
+// order; an entry leaves a quadrant only if the minimum of its quadratic form over the
+// quadrant's pixel rectangle exceeds the alpha >= 1/255 level by a margin, i.e. when every pixel
+// of that quadrant would skip it anyway, and leaves the list when no quadrant keeps it.  The list
+// position of every kept entry is carried along (low 28 bits, the quadrant mask above them), so
+// n_contrib still counts positions in the full list; the walk skips a quadrant an entry misses
+// with a uniform branch.
 constexpr int kLanes = 64;
-constexpr int kCullPad = 0;
+constexpr int kPosBits = 28;  // list positions carried with the quadrant mask
+constexpr int kPosMask = (1 << kPosBits) - 1;
 
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
-// true if the entry cannot reach alpha >= 1/255 at any pixel centre of [0,SUB-1]^2 (relative to
-// the sub-tile)
-template <int SUB>
-__device__ __forceinline__ bool cull_entry(float mx, float my, float A, float B, float C, float o) {
-  if (!(o * 255.0f > 0.999f)) return true;  // alpha <= o < 1/255 everywhere (with margin)
-  const float thr = 2.0f * __logf(255.0f * o);  // q <= thr  <=>  o exp(-q/2) >= 1/255
-  const float lo = 0.0f, hi = (float)(SUB - 1);
-  if (mx >= lo && mx <= hi && my >= lo && my <= hi) return false;
+// Minimum of q(d) = A dx^2 + 2B dx dy + C dy^2, d = pixel - mean, over the pixel-centre
+// rectangle [x0, x1] x [y0, y1] (mean at (mx, my)); ia, ic = 1/A, 1/C (0 if not positive).  Off
+// the rectangle the minimum is on an edge, where the line minimiser is clamped to the segment.
+__device__ __forceinline__ float rect_min_q(float mx, float my, float A, float B, float C, float ia, float ic,
+                                            float x0, float x1, float y0, float y1) {
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
   float qmin = 3.0e38f;
-  // vertical edges x = lo, hi
 #pragma unroll
-  for (int e = 0; e < 2; e++) {
-    const float dx = (e ? hi : lo) - mx;
-    float dy = C > 0.f ? -B * dx / C : 0.f;
-    dy = fminf(fmaxf(dy, lo - my), hi - my);
+  for (int e = 0; e < 2; e++) {  // vertical edges
+    const float dx = (e ? x1 : x0) - mx;
+    const float dy = fminf(fmaxf(-B * dx * ic, y0 - my), y1 - my);
     qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
   }
 #pragma unroll
-  for (int e = 0; e < 2; e++) {
-    const float dy = (e ? hi : lo) - my;
-    float dx = A > 0.f ? -B * dy / A : 0.f;
-    dx = fminf(fmaxf(dx, lo - mx), hi - mx);
+  for (int e = 0; e < 2; e++) {  // horizontal edges
+    const float dy = (e ? y1 : y0) - my;
+    const float dx = fminf(fmaxf(-B * dy * ia, x0 - mx), x1 - mx);
     qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
   }
-  return qmin > thr * 1.001f + 1e-3f;
+  return qmin;
+}
+
+// Bit k set if the entry (mean (mx, my) relative to the sub-tile origin, conic A B C, opacity o)
+// may reach alpha >= 1/255 at a pixel centre of 8x8 quadrant k = (k % PW, k / PW).
+template <int PW>
+__device__ __forceinline__ uint32_t quad_mask(float mx, float my, float A, float B, float C, float o) {
+  if (!(o * 255.0f > 0.999f)) return 0u;  // alpha <= o < 1/255 everywhere (with margin)
+  // q <= 2 ln(255 o)  <=>  o exp(-q/2) >= 1/255; the margin keeps every kept decision
+  const float thr = 2.0f * __logf(255.0f * o) * 1.001f + 1e-3f;
+  const float ia = A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f, ic = C > 0.f ? __builtin_amdgcn_rcpf(C) : 0.f;
+  uint32_t m = 0;
+#pragma unroll 1  // rolled: unrolled, the four rectangles cost the forward an occupancy step
+  for (int k = 0; k < PW * PW; k++) {
+    const float x0 = (float)(8 * (k % PW)), y0 = (float)(8 * (k / PW));
+    if (rect_min_q(mx, my, A, B, C, ia, ic, x0, x0 + 7.f, y0, y0 + 7.f) <= thr) m |= 1u << k;
+  }
+  return m;
 }
 
 template <int CTRL>
@@ -221,10 +238,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       unsigned long long* __restrict__ pairs) {
-  constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
+  constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
-  __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
+  __shared__ float4 s_rgb[kBatchB];  // colour, list position | quadrant mask << 28 (int bits)
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
@@ -235,7 +252,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   const int ox = tx * io.tw + (sub % io.sx) * SUB, oy = ty * io.th + (sub / io.sx) * SUB;
   if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
-  const int qx = PW * (lane & 7), qy = PW * (lane >> 3);
+  const int qx = lane & 7, qy = lane >> 3;
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
@@ -245,7 +262,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
                   // alpha is scaled by it, so a stopped pixel neither blends nor stops again
 #pragma unroll
   for (int k = 0; k < NP; k++) {
-    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
+    const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
     T[k] = 1.f;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
@@ -258,16 +275,17 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
 #pragma unroll
     for (int k = 0; k < kBatchB / kLanes; k++) {
       const int e = k * kLanes + lane;
-      bool keep = false;
+      uint32_t qm = 0;
       float2 xy;
       float4 co, rgb;
       if (e < n_in) {
         const Rec R = rec[vals[start + e]];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
-        keep = !cull_entry<SUB>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
+        qm = quad_mask<PW>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
         co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
-        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((int)(start - r.x) + e));
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(((int)(start - r.x) + e) | (int)(qm << kPosBits)));
       }
+      const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
       if (keep) {
         const int pos = n_kept + __popcll(m & lt);
@@ -277,17 +295,25 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       }
       n_kept += __popcll(m);
     }
+    // quadrants with a pixel still walking (a stopped pixel stays stopped)
+    uint32_t qalive = 0;
+#pragma unroll
+    for (int k = 0; k < NP; k++) qalive |= __ballot(live[k] != 0.f) != 0 ? 1u << k : 0u;
     __syncthreads();
     for (int j = 0; j < n_kept; j++) {
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
-      const int pos1 = __float_as_int(c.w) + 1;
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(c.w));  // same for all lanes
+      const int pos1 = (int)(w & kPosMask) + 1;
+      const uint32_t qm = (w >> kPosBits) & qalive;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
-      // branch-free: every pixel evaluates the entry; selects keep skipped / stopped pixels unchanged
+      // branch-free within a quadrant: every pixel evaluates the entry; selects keep skipped /
+      // stopped pixels unchanged
 #pragma unroll
       for (int k = 0; k < NP; k++) {
-        const float dx = dxb - (float)(k % PW), dy = dyb - (float)(k / PW);
+        if (NP > 1 && !((qm >> k) & 1u)) continue;  // uniform: no pixel of quadrant k can take it
+        const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
         const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw)) * live[k];
         const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
@@ -299,10 +325,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
           n_blend += blend ? 1u : 0u;
         }
         live[k] = (ok && !go) ? 0.f : live[k];
-        const float w = blend ? a * T[k] : 0.f;
-        c0[k] += c.x * w;
-        c1[k] += c.y * w;
-        c2[k] += c.z * w;
+        const float wgt = blend ? a * T[k] : 0.f;
+        c0[k] += c.x * wgt;
+        c1[k] += c.y * wgt;
+        c2[k] += c.z * wgt;
         T[k] = blend ? Tn : T[k];
         last[k] = blend ? pos1 : last[k];
       }
@@ -316,7 +342,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   }
 #pragma unroll
   for (int k = 0; k < NP; k++) {
-    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
+    const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
@@ -338,10 +364,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       float* __restrict__ g2d) {
-  constexpr int PW = SUB / 8, NP = PW * PW;  // pixels per lane along x and y, in all
+  constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
-  __shared__ float4 s_rgb[kBatchB];  // colour, list position (int bits)
+  __shared__ float4 s_rgb[kBatchB];  // colour, list position | quadrant mask << 28 (int bits)
   __shared__ uint32_t s_p[kBatchB];
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
@@ -353,17 +379,18 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   const int ox = tx * io.tw + (sub % io.sx) * SUB, oy = ty * io.th + (sub / io.sx) * SUB;
   if (ox >= V.W || oy >= V.H) return;  // sub-tile entirely outside the image
   const int lane = threadIdx.x;
-  const int qx = PW * (lane & 7), qy = PW * (lane >> 3);
+  const int qx = lane & 7, qy = lane >> 3;
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const int64_t hw = (int64_t)V.W * V.H;
   float T[NP], dC0[NP], dC1[NP], dC2[NP], B0[NP], B1[NP], B2[NP];
   int last[NP];
-  int my_max = 0;
+  int qlast[NP];  // per quadrant: the largest n_contrib of its pixels (uniform)
+  int max_all = 0;
 #pragma unroll
   for (int k = 0; k < NP; k++) {
-    const int px = ox + qx + (k % PW), py = oy + qy + (k / PW);
+    const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
     T[k] = 1.f;
     dC0[k] = dC1[k] = dC2[k] = 0.f;
     last[k] = 0;
@@ -378,11 +405,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       dC1[k] = V.dl[hw + pix];
       dC2[k] = V.dl[2 * hw + pix];
     }
-    my_max = max(my_max, last[k]);
-  }
+    int mx = last[k];
 #pragma unroll
-  for (int d = 32; d > 0; d >>= 1) my_max = max(my_max, __shfl_xor(my_max, d, 64));
-  const int max_last = min(my_max, (int)(r.y - r.x));  // n_contrib never exceeds the list length
+    for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
+    qlast[k] = __builtin_amdgcn_readfirstlane(mx);
+    max_all = max(max_all, qlast[k]);
+  }
+  const int max_last = min(max_all, (int)(r.y - r.x));  // n_contrib never exceeds the list length
   if (max_last <= 0) return;
   const int slot = kRedSlot[lane & 15];
   const bool writes = lane < 16 && slot >= 0;
@@ -395,7 +424,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
 #pragma unroll
     for (int k = 0; k < kBatchB / kLanes; k++) {
       const int e = k * kLanes + lane;
-      bool keep = false;
+      uint32_t qm = 0;
       float2 xy;
       float4 cn, rgb;
       uint32_t p = 0;
@@ -404,9 +433,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         const Rec R = rec[p];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
-        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(bi * kBatchB + e));
-        keep = !cull_entry<SUB>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
+        qm = quad_mask<PW>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((bi * kBatchB + e) | (int)(qm << kPosBits)));
       }
+      const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
       if (keep) {
         const int pos = n_kept + __popcll(m & lt);
@@ -422,7 +452,9 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
-      const int idx = __float_as_int(c.w);
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(c.w));  // same for all lanes
+      const int idx = (int)(w & kPosMask);
+      const uint32_t qm = w >> kPosBits;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
       // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
       // sum dP dy^2, d opacity, d rgb), dP = dL/d(exponent), (dx, dy) = mean - pixel
@@ -432,7 +464,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       bool any = false;
 #pragma unroll
       for (int k = 0; k < NP; k++) {
-        const float dx = dxb - (float)(k % PW), dy = dyb - (float)(k / PW);
+        // uniform: the entry misses quadrant k, or lies behind the last contribution of every
+        // pixel there
+        if (NP > 1 && !(((qm >> k) & 1u) && idx < qlast[k])) continue;
+        const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
         const float G = __builtin_amdgcn_exp2f(pw);
         const float araw = co.w * G;
@@ -440,10 +475,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         if (!((idx < last[k]) && (pw <= 0.f) && (a >= kAlphaMin))) continue;
         any = true;
         T[k] = T[k] * __builtin_amdgcn_rcpf(1.f - a);  // transmittance before this entry
-        const float w = a * T[k];
-        m[6] += w * dC0[k];
-        m[7] += w * dC1[k];
-        m[8] += w * dC2[k];
+        const float wgt = a * T[k];
+        m[6] += wgt * dC0[k];
+        m[7] += wgt * dC1[k];
+        m[8] += wgt * dC2[k];
         const float e0 = c.x - B0[k], e1 = c.y - B1[k], e2 = c.z - B2[k];
         const float da = T[k] * (e0 * dC0[k] + e1 * dC1[k] + e2 * dC2[k]);
         B0[k] += a * e0;
