@@ -384,7 +384,9 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const int64_t hw = (int64_t)V.W * V.H;
-  float T[NP], dC0[NP], dC1[NP], dC2[NP], B0[NP], B1[NP], B2[NP];
+  // per pixel: transmittance, dL/d(pixel colour), S = dL/dC . (colour blended behind the
+  // current entry, background included)
+  float T[NP], dC0[NP], dC1[NP], dC2[NP], S[NP];
   int last[NP];
   int qlast[NP];  // per quadrant: the largest n_contrib of its pixels (uniform)
   int max_all = 0;
@@ -394,9 +396,6 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
     T[k] = 1.f;
     dC0[k] = dC1[k] = dC2[k] = 0.f;
     last[k] = 0;
-    B0[k] = bg0;
-    B1[k] = bg1;
-    B2[k] = bg2;
     if (px < V.W && py < V.H) {
       const int64_t pix = (int64_t)py * V.W + px;
       T[k] = V.t_final[pix];
@@ -405,6 +404,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       dC1[k] = V.dl[hw + pix];
       dC2[k] = V.dl[2 * hw + pix];
     }
+    S[k] = bg0 * dC0[k] + bg1 * dC1[k] + bg2 * dC2[k];
     int mx = last[k];
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
@@ -479,11 +479,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         m[6] += wgt * dC0[k];
         m[7] += wgt * dC1[k];
         m[8] += wgt * dC2[k];
-        const float e0 = c.x - B0[k], e1 = c.y - B1[k], e2 = c.z - B2[k];
-        const float da = T[k] * (e0 * dC0[k] + e1 * dC1[k] + e2 * dC2[k]);
-        B0[k] += a * e0;
-        B1[k] += a * e1;
-        B2[k] += a * e2;
+        // dL/d alpha = T (dL/dC . (colour - colour behind)); the colour behind moves by alpha of that
+        const float ed = (c.x * dC0[k] + c.y * dC1[k] + c.z * dC2[k]) - S[k];
+        const float da = T[k] * ed;
+        S[k] += a * ed;
         if (araw < kAlphaMax) {  // no derivative through an active clamp
           const float dP = da * a;
           m[5] += da * G;
