@@ -73,6 +73,18 @@ def measured_traffic(kernel: str, workload: str, tile: str):
     return float(rec["by_tile"][tile]["traffic_bytes"])
 
 
+def count_tile_keys(ctx, g, cams) -> int:
+    """Tile keys of one render of g into cams at the context's tile size (sum of the visible
+    Gaussians' tile-rectangle areas)."""
+    total = 0
+    for c in cams:
+        pr = ctx.debug_projection(g, c)  # [n][16]: ..., x0, y0, x1, y1, visible
+        vis = pr[:, 15] > 0.5
+        total += int(((pr[vis, 13] - pr[vis, 11]) * (pr[vis, 14] - pr[vis, 12])).sum().item())
+        del pr
+    return total
+
+
 def build_workload(args):
     import torch
 
@@ -486,12 +498,7 @@ def bench_stress(args):
     evaluated, blended = ctx.pair_counts()
     walked = int(sum(int(o.n_contrib.sum().item()) for o in outs))
     ctx.tile = tile
-    total_keys = 0  # at the tile size in use
-    for c in cams:
-        pr = ctx.debug_projection(g, c)  # [n][16]: ..., x0, y0, x1, y1, visible
-        vis = pr[:, 15] > 0.5
-        total_keys += int(((pr[vis, 13] - pr[vis, 11]) * (pr[vis, 14] - pr[vis, 12])).sum().item())
-        del pr
+    total_keys = count_tile_keys(ctx, g, cams)
     log(f"[bench] stress pairs evaluated {evaluated:.3e} blended {blended:.3e} walked {walked:.3e} keys {total_keys}")
     # eager, with stage timers
     for _ in range(args.warmup):
@@ -634,7 +641,9 @@ def main():
     evaluated, blended = ctx.pair_counts()
     walked = int(sum(int(o.n_contrib.sum().item()) for o in s["outs"]))
     ctx.tile = tile
-    log(f"[bench] pairs evaluated {evaluated:.3e} blended {blended:.3e} walked-bwd {walked:.3e}")
+    tile_keys = count_tile_keys(ctx, s["gs"], s["cams"])
+    log(f"[bench] pairs evaluated {evaluated:.3e} blended {blended:.3e} walked-bwd {walked:.3e}; "
+        f"{tile_keys} tile keys at {tile_name(ctx.tile)}")
     # timed steps with live stage timers
     log(f"[bench] warmup {args.warmup}, timing {args.steps} steps")
     for i in range(args.warmup):
@@ -692,6 +701,7 @@ def main():
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
         "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
+        "tile_keys": tile_keys,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

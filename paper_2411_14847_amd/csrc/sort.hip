@@ -376,6 +376,8 @@ int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int6
 
 int sort_blocks_for(int64_t max_count) {
   int64_t b = (max_count + 4 * kBatch - 1) / (4 * kBatch);
+  const int64_t one = (max_count + kBatch - 1) / kBatch;
+  if (b < 256) b = one < 256 ? one : 256;
   if (b < 1) b = 1;
   if (b > kMaxSortBlocks) b = kMaxSortBlocks;
   return (int)b;

@@ -140,24 +140,29 @@ __global__ __launch_bounds__(256) void k_l1(L1Args a, float* __restrict__ loss) 
 // ---- densification ----------------------------------------------------------------------------
 // Alg. 1: [P, 1] T with T the full (row-vector) projection built from the intrinsics; pixel
 // x = Round(0.5((x_norm + 1) W - 1)), y likewise with y_norm and H, Round(z) = floor(z + 0.5).
-__device__ bool alg1_pixel(const CamK& c, double X, double Y, double Z, int& xn, int& yn) {
+// Columns 0 (x), 1 (y) and 3 (homogeneous) of T, rows P0, P1, P2, 1, for one camera:
+__device__ void alg1_columns(const CamK& c, double* T /* [3][4] */) {
 #pragma clang fp contract(off)
   const double W = (double)c.W, H = (double)c.H;
   const double sx = (2.0 * (double)c.fx) / W, sy = (2.0 * (double)c.fy) / H;
   const double kx = (2.0 * (double)c.cx + 1.0) / W - 1.0;
   const double ky = (2.0 * (double)c.cy + 1.0) / H - 1.0;
-  double T0[4], T1[4], T3[4];  // columns 0 (x), 1 (y), 3 (homogeneous) of T, rows P0, P1, P2, 1
   for (int i = 0; i < 3; i++) {
-    T0[i] = sx * (double)c.R[i] + kx * (double)c.R[6 + i];
-    T1[i] = sy * (double)c.R[3 + i] + ky * (double)c.R[6 + i];
-    T3[i] = (double)c.R[6 + i];
+    T[i] = sx * (double)c.R[i] + kx * (double)c.R[6 + i];
+    T[4 + i] = sy * (double)c.R[3 + i] + ky * (double)c.R[6 + i];
+    T[8 + i] = (double)c.R[6 + i];
   }
-  T0[3] = sx * (double)c.t[0] + kx * (double)c.t[2];
-  T1[3] = sy * (double)c.t[1] + ky * (double)c.t[2];
-  T3[3] = (double)c.t[2];
-  const double hx = ((X * T0[0] + Y * T0[1]) + Z * T0[2]) + T0[3];
-  const double hy = ((X * T1[0] + Y * T1[1]) + Z * T1[2]) + T1[3];
-  const double hw = ((X * T3[0] + Y * T3[1]) + Z * T3[2]) + T3[3];
+  T[3] = sx * (double)c.t[0] + kx * (double)c.t[2];
+  T[7] = sy * (double)c.t[1] + ky * (double)c.t[2];
+  T[11] = (double)c.t[2];
+}
+
+__device__ bool alg1_pixel(const double* T, int Wi, int Hi, double X, double Y, double Z, int& xn, int& yn) {
+#pragma clang fp contract(off)
+  const double W = (double)Wi, H = (double)Hi;
+  const double hx = ((X * T[0] + Y * T[1]) + Z * T[2]) + T[3];
+  const double hy = ((X * T[4] + Y * T[5]) + Z * T[6]) + T[7];
+  const double hw = ((X * T[8] + Y * T[9]) + Z * T[10]) + T[11];
   if (!(hw > 0.0)) return false;
   const double xnorm = hx / hw, ynorm = hy / hw;
   const double xf = floor(0.5 * ((xnorm + 1.0) * W - 1.0) + 0.5);
@@ -168,28 +173,60 @@ __device__ bool alg1_pixel(const CamK& c, double X, double Y, double Z, int& xn,
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_densify_select(SceneK s, DensifyArgs a, const float* __restrict__ gsum,
-                                                        const int32_t* __restrict__ gcnt, int n_base,
-                                                        uint64_t* __restrict__ sel_keys, uint32_t* __restrict__ sel_vals,
-                                                        uint32_t* __restrict__ d_count) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_base) return;
-  const double X = s.mean[g], Y = s.mean[(int64_t)s.stride + g], Z = s.mean[2 * (int64_t)s.stride + g];
+// Selection (Alg. 1): a workgroup takes 64 base Gaussians, its wave w the views w, w + 4, ...
+// (the view index stays uniform over a wave); the score is the largest error at the Gaussian's
+// pixel over the views that see it.  Wave 0 combines the four waves and appends the selected
+// Gaussians with one atomic.
+constexpr int kSelWaves = 4;
+__global__ __launch_bounds__(64 * kSelWaves) void k_densify_select(SceneK s, DensifyArgs a,
+                                                                   const float* __restrict__ gsum,
+                                                                   const int32_t* __restrict__ gcnt, int n_base,
+                                                                   uint64_t* __restrict__ sel_keys,
+                                                                   uint32_t* __restrict__ sel_vals,
+                                                                   uint32_t* __restrict__ d_count) {
+  __shared__ double s_T[DASS_MAX_VIEWS][12];
+  __shared__ float s_score[kSelWaves][64];
+  __shared__ int s_ie[kSelWaves][64];
+  for (int v = threadIdx.x; v < a.nv; v += blockDim.x) alg1_columns(a.cams[v], s_T[v]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = blockIdx.x * 64 + lane;
   bool in_err = false;
   float score = 0.f;
-  for (int v = 0; v < a.nv; v++) {
-    int x, y;
-    if (alg1_pixel(a.cams[v], X, Y, Z, x, y)) {
-      const float e = a.err[v][(int64_t)y * a.cams[v].W + x];
-      in_err |= e > a.gamma_err;
-      score = fmaxf(score, e);
+  if (g < n_base) {
+    const double X = s.mean[g], Y = s.mean[(int64_t)s.stride + g], Z = s.mean[2 * (int64_t)s.stride + g];
+    for (int v = wave; v < a.nv; v += kSelWaves) {
+      int x, y;
+      if (alg1_pixel(s_T[v], a.cams[v].W, a.cams[v].H, X, Y, Z, x, y)) {
+        const float e = a.err[v][(int64_t)y * a.cams[v].W + x];
+        in_err |= e > a.gamma_err;
+        score = fmaxf(score, e);
+      }
     }
   }
-  const int32_t c = gcnt[g];
-  const float gbar = c > 0 ? gsum[g] / (float)c : 0.f;
-  const bool in_s = (gbar > a.tau_pos) || (in_err && gbar > a.tau_err);
+  s_score[wave][lane] = score;
+  s_ie[wave][lane] = in_err ? 1 : 0;
+  __syncthreads();
+  if (wave != 0) return;
+  int ie = 0;
+#pragma unroll
+  for (int w = 0; w < kSelWaves; w++) {
+    score = fmaxf(score, s_score[w][lane]);
+    ie |= s_ie[w][lane];
+  }
+  bool in_s = false;
+  if (g < n_base) {
+    const int32_t c = gcnt[g];
+    const float gbar = c > 0 ? gsum[g] / (float)c : 0.f;
+    in_s = (gbar > a.tau_pos) || (ie != 0 && gbar > a.tau_err);
+  }
+  const uint64_t m = __ballot(in_s);
+  if (m == 0) return;
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(d_count, (uint32_t)__popcll(m));
+  base = __shfl(base, 0, 64);
   if (!in_s) return;
-  const uint32_t pos = atomicAdd(d_count, 1u);
+  const uint32_t pos = base + (uint32_t)__popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
   sel_keys[pos] = ((uint64_t)(~__float_as_uint(score)) << a.gbits) | (uint64_t)(uint32_t)g;
   sel_vals[pos] = (uint32_t)g;
 }
@@ -246,7 +283,14 @@ __global__ __launch_bounds__(256) void k_densify_spawn(float* __restrict__ mean,
   const double ln16 = 0.47000362924573558;  // ln 1.6
   for (int i = 0; i < 3; i++) log_scale[i * st + c] = (float)((double)log_scale[i * st + p] - ln16);
   logit[c] = logit[p];
-  for (int k = 0; k < n_sh; k++) sh[k * st + c] = sh[k * st + p];
+  // the child row c >= n never overlaps a parent row p < n: load every coefficient first so the
+  // loads are in flight together, then store
+  float shv[48];
+#pragma unroll
+  for (int k = 0; k < 48; k++) shv[k] = k < n_sh ? sh[k * st + p] : 0.f;
+#pragma unroll
+  for (int k = 0; k < 48; k++)
+    if (k < n_sh) sh[k * st + c] = shv[k];
 }
 
 }  // namespace
@@ -282,7 +326,8 @@ void launch_l1(const L1Args& a, int64_t total_blocks, float* loss, hipStream_t s
 void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* gsum, const int32_t* gcnt, int n_base,
                            uint64_t* sel_keys, uint32_t* sel_vals, uint32_t* d_count, hipStream_t st) {
   if (n_base > 0)
-    k_densify_select<<<(n_base + 255) / 256, 256, 0, st>>>(s, a, gsum, gcnt, n_base, sel_keys, sel_vals, d_count);
+    k_densify_select<<<(n_base + 63) / 64, 64 * kSelWaves, 0, st>>>(s, a, gsum, gcnt, n_base, sel_keys, sel_vals,
+                                                                    d_count);
 }
 
 void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
