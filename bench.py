@@ -2,10 +2,11 @@
 """Benchmark of the streaming Gaussian-splatting hot path on one MI355X.
 
 One step = one optimisation iteration of the shift stage over every view of a timestep:
-  shift_apply (forward) -> render_fwd (all views, one launch sequence) -> L1 loss gradient and
-  error maps -> render_bwd (full parameter gradients + historical positional gradient) ->
-  shift_apply (adjoint) -> adam_step -> densify_append (children written into spare rows;
-  the live count is not advanced, so every step sees the same scene size).
+  shift_apply (forward) -> render_fwd with the L1 term fused into its blend (all views, one
+  launch sequence: loss gradient and error maps) -> render_bwd (full parameter gradients +
+  historical positional gradient) -> shift_apply (adjoint) -> adam_step -> densify_append
+  (children written into spare rows; the live count is not advanced, so every step sees the
+  same scene size).
 Inputs are synthetic and resident in device memory before timing starts.
 
 Prints one JSON line (rank 0).  `python bench.py` defaults to one GPU.
@@ -139,8 +140,10 @@ def train_step(s, it, args, per_view=False):
     for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
         t.zero_()
     if not per_view:
-        ctx.render_fwd(gs, cams, args.bg, out=s["outs"])
-        ctx.l1_loss_grad(cams, [o.rgb for o in s["outs"]], s["targets"], s["dls"], s["errs"], s["loss"])
+        # render fused with the L1 term (the step reads only the loss gradient, error maps and the
+        # forward's transmittance / contributor counts, so the images are not written)
+        ctx.render_fwd_l1(gs, cams, args.bg, s["targets"], s["dls"], s["errs"], s["loss"], out=s["outs"],
+                          keep_rgb=False)
         ctx.render_bwd(gs, cams, args.bg, s["outs"], s["dls"], s["grads"], s["gn"], s["cnt"])
     else:
         # plain per-view path: one render_fwd / loss / render_bwd per camera

@@ -239,6 +239,17 @@ dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_v
                               float* const* dl_drgb, float* const* err, float* loss,
                               dass_stream stream);
 
+/* render_fwd fused with dass_l1_loss_grad: the same render (out[v].t_final, n_contrib, and
+ * out[v].rgb unless it is NULL) with the blend's epilogue forming the L1 term against
+ * target[v]: dl_drgb[v] and err[v] (err may be NULL) bit-identical to dass_l1_loss_grad on
+ * the rendered image, and *loss (device float, may be NULL) += L summed in a different order
+ * (equal up to float rounding).  Saves writing and re-reading the image in a training step.
+ * Errors as render_fwd, plus DASS_E_INVALID for a NULL target or dl_drgb array or entry. */
+dass_status dass_render_fwd_l1(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
+                               int32_t n_views, const float bg[3], dass_image* out,
+                               const float* const* target, float* const* dl_drgb, float* const* err,
+                               float* loss, const dass_opts* opts, dass_stream stream);
+
 /* ---- stage timers --------------------------------------------------------------------- */
 
 /* Stages timed with HIP events on the stream of each call while profiling is on. */

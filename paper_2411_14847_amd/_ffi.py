@@ -15,7 +15,7 @@ MAX_VIEWS = 32
 
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
-           "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
+           "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count")
 FLAG_COUNT_PAIRS = 1
@@ -83,6 +83,8 @@ def lib():
             "dass_last_error": (C.c_char_p, [vp]),
             "dass_sync": (i32, [vp, vp]),
             "render_fwd": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(Opts), vp]),
+            "dass_render_fwd_l1": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(vp), P(vp), P(vp), vp,
+                                         P(Opts), vp]),
             "render_bwd": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(vp), P(Grads), vp, vp,
                                  P(Opts), vp]),
             "shift_apply": (i32, [vp, i32, vp, i32, vp, vp, P(Gaussians), P(Gaussians), P(Grads), vp, vp, vp]),

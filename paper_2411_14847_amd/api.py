@@ -269,6 +269,26 @@ class Context:
             self._check(self._lib.adam_step(self._h, arr, len(groups), beta1, beta2, eps, int(step),
                                             _stream(stream)))
 
+    def render_fwd_l1(self, g: GaussianBuffers, cams: Sequence, bg, targets, dl_out, err_out=None,
+                      loss: Optional[torch.Tensor] = None, out=None, keep_rgb: bool = True, stream=None):
+        """render_fwd fused with l1_loss_grad: the blend's epilogue writes dl_out (and err_out,
+        and adds the loss into `loss`) as l1_loss_grad would on the rendered images.  With
+        keep_rgb False the images themselves are not written (out[v].rgb is left as it was)."""
+        out = out if out is not None else [RenderOut.allocate(c, g.mean.device) for c in cams]
+        V = len(cams)
+        imgs = (F.Image * V)(*[F.Image(_ptr(o.rgb) if keep_rgb else None, _ptr(o.t_final), _ptr(o.n_contrib))
+                               for o in out])
+        bgf = (C.c_float * 3)(*[float(x) for x in bg])
+        T = (C.c_void_p * V)(*[_ptr(t) for t in targets])
+        D = (C.c_void_p * V)(*[_ptr(d) for d in dl_out])
+        E = (C.c_void_p * V)(*[_ptr(e) for e in err_out]) if err_out is not None else None
+        gs = g.struct()
+        opts = self._opts()
+        self.generation += 1
+        self._check(self._lib.dass_render_fwd_l1(self._h, C.byref(gs), cameras_array(cams), V, bgf, imgs, T, D, E,
+                                                 _ptr(loss), C.byref(opts), _stream(stream)))
+        return out
+
     def l1_loss_grad(self, cams, renders, targets, dl_out, err_out=None, loss: Optional[torch.Tensor] = None,
                      stream=None):
         V = len(cams)

@@ -164,12 +164,14 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.scan_tmp, scan_tmp_elems(vn));
   ALLOC(w.counters, 16);
   ALLOC(w.pairs, 2);
+  ALLOC(w.loss_slots, kLossSlots);
   ALLOC(w.err, 1);
 #undef ALLOC
   w.gid_s = w.dval[0];
   HIP_TRY(ctx, hipMemset(w.counters, 0, 16 * sizeof(uint32_t)));
   HIP_TRY(ctx, hipMemset(w.err, 0, sizeof(uint32_t)));
   HIP_TRY(ctx, hipMemset(w.pairs, 0, 2 * sizeof(unsigned long long)));
+  HIP_TRY(ctx, hipMemset(w.loss_slots, 0, kLossSlots * sizeof(float)));  // kept at zero by the loss finish
   HIP_TRY(ctx, hipDeviceSynchronize());
   ctx->lim = l;
   ctx->have_fwd = false;
@@ -344,8 +346,17 @@ dass_status dass_sync(dass_ctx ctx, dass_stream stream) {
   return DASS_OK;
 }
 
-dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
-                       const float bg[3], dass_image* out, const dass_opts* opts, dass_stream stream) {
+// The fused L1 term of render_fwd_l1 (NULL for a plain render_fwd).
+struct L1Out {
+  const float* const* target;
+  float* const* dl_drgb;
+  float* const* err;
+  float* loss;
+};
+
+dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                            const float bg[3], dass_image* out, const L1Out* l1, const dass_opts* opts,
+                            dass_stream stream) {
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
@@ -360,13 +371,22 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
   set_tiling(io, tw, th, sub);
+  if (l1 && (!l1->target || !l1->dl_drgb)) return fail(ctx, DASS_E_INVALID, "targets or dl_drgb is NULL");
   for (int v = 0; v < n_views; v++) {
-    if (!out[v].rgb || !out[v].t_final || !out[v].n_contrib)
+    if ((!out[v].rgb && !l1) || !out[v].t_final || !out[v].n_contrib)
       return fail(ctx, DASS_E_INVALID, "out[%d] has a NULL buffer", v);
     io.v[v].rgb = out[v].rgb;
     io.v[v].t_final = out[v].t_final;
     io.v[v].n_contrib = out[v].n_contrib;
     io.v[v].dl = nullptr;
+    if (l1) {
+      if (!l1->target[v] || !l1->dl_drgb[v]) return fail(ctx, DASS_E_INVALID, "view %d: NULL target or dl_drgb", v);
+      io.v[v].target = l1->target[v];
+      io.v[v].dl_out = l1->dl_drgb[v];
+      io.v[v].err = l1->err ? l1->err[v] : nullptr;
+      // as dass_l1_loss_grad: (1/V) / (3 H W)
+      io.v[v].l1_scale = (1.0f / (float)n_views) / (3.0f * (float)((int64_t)ck.c[v].W * ck.c[v].H));
+    }
     io.v[v].W = ck.c[v].W;
     io.v[v].H = ck.c[v].H;
     io.v[v].TX = ck.c[v].TX;
@@ -405,8 +425,13 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   // 4. blend
   if (count_pairs) launch_fill_u32(reinterpret_cast<uint32_t*>(ws.pairs), 0u, 4, st);
   stage_begin(ctx, DASS_STAGE_BLEND_FWD, st);
-  launch_blend_fwd(io, n_views, total_tiles, bg, ws, ws.vals[kcur], count_pairs, st);
+  launch_blend_fwd(io, n_views, total_tiles, bg, ws, ws.vals[kcur], count_pairs, l1 != nullptr, st);
   stage_end(ctx, DASS_STAGE_BLEND_FWD, st);
+  if (l1) {
+    stage_begin(ctx, DASS_STAGE_L1, st);
+    launch_loss_finish(ws.loss_slots, l1->loss, st);
+    stage_end(ctx, DASS_STAGE_L1, st);
+  }
   if ((s = check_launch(ctx, "render_fwd")) != DASS_OK) return s;
   ctx->have_fwd = true;
   ctx->fwd_n = g->n;
@@ -418,6 +443,19 @@ dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   ctx->fwd_key_buf = kcur;
   ctx->fwd_cams = ck;
   return DASS_OK;
+}
+
+dass_status render_fwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                       const float bg[3], dass_image* out, const dass_opts* opts, dass_stream stream) {
+  return render_fwd_impl(ctx, g, cams, n_views, bg, out, nullptr, opts, stream);
+}
+
+dass_status dass_render_fwd_l1(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                               const float bg[3], dass_image* out, const float* const* target,
+                               float* const* dl_drgb, float* const* err, float* loss, const dass_opts* opts,
+                               dass_stream stream) {
+  const L1Out l1{target, dl_drgb, err, loss};
+  return render_fwd_impl(ctx, g, cams, n_views, bg, out, &l1, opts, stream);
 }
 
 dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,

@@ -52,18 +52,23 @@ struct SceneK {
 
 // Per-view output pointers for the blend kernels.
 struct ViewIO {
-  float* rgb;
+  float* rgb;         // may be NULL in the forward with the fused L1 term (image not kept)
   float* t_final;
   int32_t* n_contrib;
-  const float* dl;  // upstream gradient (backward only)
+  const float* dl;    // upstream gradient (backward only)
+  const float* target;  // fused L1 term (forward only): target image, dL/drgb out, error map out
+  float* dl_out;
+  float* err;           // may be NULL
+  float l1_scale;       // 1 / (3 H W n_views)
   int W, H, TX, tile_base;
 };
 struct ViewsIO {
   ViewIO v[DASS_MAX_VIEWS];
   int tw, th;  // tile size in pixels
-  int sub;     // sub-tile edge (16: 2x2 pixels per lane, 8: one pixel per lane)
+  int sub;     // sub-tile edge (16: four pixels per lane, one per 8x8 quadrant; 8: one pixel)
   int sx, sn;  // sub-tiles per tile row, per tile
 };
+constexpr int kLossSlots = 4096;  // partial sums of the fused L1 loss (spread to avoid contention)
 
 // The projected record of one (view, Gaussian), as the blend consumes it (48 bytes).
 //   r0 = (u_hi, v_hi, u_lo, v_lo)   pixel-space mean as float hi + lo (fp64-accurate)
@@ -102,6 +107,7 @@ struct Workspace {
   uint64_t* scan_tmp = nullptr;    // scan block sums
   uint32_t* counters = nullptr;    // [0] = key count (clamped), [1] = densify |S|, [2] = depth-sort count
   unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
+  float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
   uint32_t* err = nullptr;         // device error bits
 };
 
@@ -131,7 +137,9 @@ void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspa
 void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipStream_t st);
 void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
-                      const Workspace& ws, const uint32_t* vals, bool count_pairs, hipStream_t st);
+                      const Workspace& ws, const uint32_t* vals, bool count_pairs, bool l1, hipStream_t st);
+// Adds the fused L1 partial sums to *loss (fixed order) and clears them.
+void launch_loss_finish(float* slots, float* loss, hipStream_t st);
 // accumulates the per-(view, Gaussian) 2D gradients into ws.g2d[(v * n + g) * 9 + k]
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, int n, hipStream_t st);

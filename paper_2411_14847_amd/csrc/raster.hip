@@ -233,11 +233,14 @@ __device__ __forceinline__ float wave_reduce9(float* v, int lane) {
 // value index held by lanes 0..15 after wave_reduce9 (bits 0,1,3,2 halve 9 -> 5 -> 3 -> 2 -> 1)
 __constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, -1, -1};
 
-template <bool COUNT, int SUB>
+// L1: the epilogue also forms the L1 term against the view's target (dL/drgb, error map and
+// this sub-tile's share of the loss, added into one of kLossSlots partial sums).
+template <bool COUNT, bool L1, int SUB>
 __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
-                                                      unsigned long long* __restrict__ pairs) {
+                                                      unsigned long long* __restrict__ pairs,
+                                                      float* __restrict__ loss_slots) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
   __shared__ float2 s_xy[kBatchB];
   __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
@@ -340,18 +343,38 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
+  float l1sum = 0.f;
 #pragma unroll
   for (int k = 0; k < NP; k++) {
     const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
-      V.rgb[pix] = c0[k] + T[k] * bg0;
-      V.rgb[hw + pix] = c1[k] + T[k] * bg1;
-      V.rgb[2 * hw + pix] = c2[k] + T[k] * bg2;
+      const float col[3] = {c0[k] + T[k] * bg0, c1[k] + T[k] * bg1, c2[k] + T[k] * bg2};
+      if (!L1 || V.rgb) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) V.rgb[c * hw + pix] = col[c];
+      }
       V.t_final[pix] = T[k];
       V.n_contrib[pix] = last[k];
+      if (L1) {
+        const float sc = V.l1_scale;
+        float e = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          const float d = col[c] - V.target[c * hw + pix];
+          V.dl_out[c * hw + pix] = d > 0.f ? sc : (d < 0.f ? -sc : 0.f);
+          e += fabsf(d);
+        }
+        if (V.err) V.err[pix] = e * (1.0f / 3.0f);
+        l1sum += e;
+      }
     }
+  }
+  if (L1) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) l1sum += __shfl_xor(l1sum, d, 64);
+    if (lane == 0) atomicAdd(&loss_slots[lb % kLossSlots], l1sum * V.l1_scale);
   }
   if (COUNT) {
     atomicAdd(&pairs[0], (unsigned long long)n_eval);
@@ -560,29 +583,51 @@ static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNu
 
 // One wave per (tile, sub-tile); the sub-tiles of a tile are consecutive logical blocks, so they
 // run on the same XCD and share its L2 for the tile's list and records.
+template <bool COUNT, bool L1>
+void blend_fwd_variant(const ViewsIO& io, int nv, int total, int per, const float bg[3], const Workspace& ws,
+                       const uint32_t* vals, hipStream_t st) {
+  const dim3 grid(per * kNumXcd), block(kLanes);
+  if (io.sub == 8)
+    k_blend_fwd<COUNT, L1, 8><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                     ws.rec_u, ws.pairs, ws.loss_slots);
+  else
+    k_blend_fwd<COUNT, L1, 16><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                      ws.rec_u, ws.pairs, ws.loss_slots);
+}
+
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
-                      const uint32_t* vals, bool count_pairs, hipStream_t st) {
+                      const uint32_t* vals, bool count_pairs, bool l1, hipStream_t st) {
   const int64_t total = total_tiles * io.sn;
   if (total == 0) return;
   const int per = per_xcd(total);
-  const dim3 grid(per * kNumXcd), block(kLanes);
-  unsigned long long* pairs = count_pairs ? ws.pairs : nullptr;
-  if (io.sub == 8) {
-    if (count_pairs)
-      k_blend_fwd<true, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                  ws.rec_u, pairs);
+  if (count_pairs) {
+    if (l1)
+      blend_fwd_variant<true, true>(io, nv, (int)total, per, bg, ws, vals, st);
     else
-      k_blend_fwd<false, 8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_u, pairs);
+      blend_fwd_variant<true, false>(io, nv, (int)total, per, bg, ws, vals, st);
   } else {
-    if (count_pairs)
-      k_blend_fwd<true, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                   ws.rec_u, pairs);
+    if (l1)
+      blend_fwd_variant<false, true>(io, nv, (int)total, per, bg, ws, vals, st);
     else
-      k_blend_fwd<false, 16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                    ws.rec_u, pairs);
+      blend_fwd_variant<false, false>(io, nv, (int)total, per, bg, ws, vals, st);
   }
 }
+
+__global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, float* __restrict__ loss) {
+  __shared__ float s_w[4];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < kLossSlots; i += 256) {
+    acc += slots[i];
+    slots[i] = 0.f;
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) *loss += (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+}
+
+void launch_loss_finish(float* slots, float* loss, hipStream_t st) { k_loss_finish<<<1, 256, 0, st>>>(slots, loss); }
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
                       const uint32_t* vals, int n, hipStream_t st) {

@@ -111,9 +111,8 @@ class Trainer:
         for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
             t.zero_()
         if not cfg.per_view:
-            ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
-            ctx.l1_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, self.dls, self.errs, self.loss,
-                             stream=stream)
+            ctx.render_fwd_l1(gs, self.cams, cfg.bg, self.targets, self.dls, self.errs, self.loss, out=self.outs,
+                              stream=stream)
             ctx.render_bwd(gs, self.cams, cfg.bg, self.outs, self.dls, self.grads, self.gn, self.cnt, stream=stream)
         else:
             V = len(self.cams)

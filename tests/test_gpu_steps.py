@@ -106,6 +106,53 @@ def test_l1_loss_gradient_and_error_maps():
     assert float(loss.item()) == pytest.approx(want_loss, rel=1e-5)
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32), (16, 16, 8)])
+def test_fused_forward_l1_matches_render_then_l1(tile):
+    """render_fwd_l1 against render_fwd followed by l1_loss_grad (which the oracle pins above):
+    images, dL/drgb and error maps bit-identical, loss equal up to float summation order; with
+    keep_rgb False the image buffers are left untouched."""
+    from test_gpu_parity import small_multiview
+    scene, cams, _ = small_multiview(seed=11, n=2500, views=3, W=150, H=110)
+    rng = np.random.default_rng(12)
+    targets = [dev(rng.uniform(size=(3, c.height, c.width)).astype(np.float32)) for c in cams]
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    ctx.tile = tile
+    out = ctx.render_fwd(g, cams, BG)
+    dl = [torch.zeros(3, c.height, c.width, device="cuda") for c in cams]
+    err = [torch.zeros(c.height, c.width, device="cuda") for c in cams]
+    loss = torch.zeros(1, device="cuda")
+    ctx.l1_loss_grad(cams, [o.rgb for o in out], targets, dl, err, loss)
+    for keep in (True, False):
+        out2 = [type(o).allocate(c) for o, c in zip(out, cams)]
+        for o in out2:
+            o.rgb.fill_(-7.0)
+        dl2 = [torch.full_like(d, 5.0) for d in dl]
+        err2 = [torch.full_like(e, 5.0) for e in err]
+        loss2 = torch.full((1,), 0.25, device="cuda")
+        ctx.render_fwd_l1(g, cams, BG, targets, dl2, err2, loss2, out=out2, keep_rgb=keep)
+        ctx.sync()
+        for v in range(len(cams)):
+            if keep:
+                assert torch.equal(out2[v].rgb, out[v].rgb)
+            else:
+                assert bool((out2[v].rgb == -7.0).all())
+            assert torch.equal(out2[v].t_final, out[v].t_final)
+            assert torch.equal(out2[v].n_contrib, out[v].n_contrib)
+            assert torch.equal(dl2[v], dl[v])
+            assert torch.equal(err2[v], err[v])
+        assert float(loss2.item()) - 0.25 == pytest.approx(float(loss.item()), rel=1e-5)
+    # the fused forward also feeds render_bwd like render_fwd does
+    grads_a, grads_b = g.zeros_like(), g.zeros_like()
+    ctx.render_fwd(g, cams, BG, out=out)
+    ctx.render_bwd(g, cams, BG, out, dl, grads_a)
+    ctx.render_fwd_l1(g, cams, BG, targets, dl2, None, None, out=out2, keep_rgb=False)
+    ctx.render_bwd(g, cams, BG, out2, dl2, grads_b)
+    ctx.sync()
+    for a, b in zip(grads_a.planes(), grads_b.planes()):
+        torch.testing.assert_close(a, b, rtol=1e-5, atol=1e-7)
+
+
 def _densify_case(seed, n, views, k_max, extra_cap, tau_pos, tau_err, gamma):
     rng = np.random.default_rng(seed)
     scene, cams, _ = synth.multiview_scene(seed, n=n, n_views=views, width=96, height=72, with_grads=False)
