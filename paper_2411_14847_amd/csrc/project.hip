@@ -286,24 +286,25 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
 // ---------------------------------------------------------------------------------------------
 constexpr int kBwdSplit = 4;  // lanes per Gaussian in the adjoint (views split round-robin)
 
-__device__ __forceinline__ double quad_sum(double x) {
-  x += __shfl_xor(x, 1, 64);
-  x += __shfl_xor(x, 2, 64);
-  return x;
-}
 __device__ __forceinline__ float quad_sumf(float x) {
   x += __shfl_xor(x, 1, 64);
   x += __shfl_xor(x, 2, 64);
   return x;
 }
 
-// Geometry part: pixel mean and conic back to mean, quaternion and log-scale; opacity.
-__global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK cams, int nv,
-                                                             const float* __restrict__ g2d, dass_grads gr,
-                                                             float* __restrict__ gradnorm, int32_t* __restrict__ gcount) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int g_raw = tid / kBwdSplit, r = tid % kBwdSplit;
-  // every lane of a quad stays to the end (the quad shuffles need all four)
+// Geometry part: pixel mean and conic back to mean, quaternion and log-scale; opacity.  A
+// workgroup takes 64 Gaussians; its wave w takes the views w, w + 4, ... (the view index stays
+// uniform over a wave, so camera data are scalar loads); wave 0 adds the other waves' sums
+// and chains them back to the parameters with every lane busy.
+constexpr int kAdjWaves = 4;
+__global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK sc, CamsK cams, int nv,
+                                                                        const float* __restrict__ g2d, dass_grads gr,
+                                                                        float* __restrict__ gradnorm,
+                                                                        int32_t* __restrict__ gcount) {
+  __shared__ double s_part[kAdjWaves - 1][11][64];  // dmu[3], dSig[6], dop, gnorm of waves 1..3
+  __shared__ int s_cnt[kAdjWaves - 1][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g_raw = blockIdx.x * 64 + lane;
   const bool live = g_raw < sc.n;
   const int g = live ? g_raw : sc.n - 1;
   GaussLite L;
@@ -320,8 +321,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
   double dSig[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   double dop = 0.0, gnorm = 0.0;
   int cnt = 0;
-  for (int v = r; v < nv && live; v += kBwdSplit) {
+  for (int v = wave; v < nv && live; v += kAdjWaves) {
     const CamK& cam = cams.c[v];
+    const float* gd = g2d + ((int64_t)v * sc.n + g) * 9;
+    float gv[6];  // issued before the projection so that the loads overlap it
+#pragma unroll
+    for (int i = 0; i < 6; i++) gv[i] = gd[i];
     ViewD V;
     project_view(L, cam, V);
     if (!V.visible) continue;
@@ -329,12 +334,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
     // sum dP dy^2, d opacity, d rgb) with dP = dL/d(exponent), exponent = -(A dx^2 + 2B dx dy +
     // C dy^2)/2 and (dx, dy) = mean - pixel, so dL/du = -(A M0 + B M1), dL/dv = -(B M0 + C M1),
     // dL/dA = -M2/2, dL/dB = -M3, dL/dC = -M4/2
-    const float* gd = g2d + ((int64_t)v * sc.n + g) * 9;
     const double A = V.A, B = V.B, C = V.C;
-    const double M0 = gd[0], M1 = gd[1];
+    const double M0 = gv[0], M1 = gv[1];
     const double du = -(A * M0 + B * M1), dv = -(B * M0 + C * M1);
-    const double dA = -0.5 * (double)gd[2], dB = -(double)gd[3], dC = -0.5 * (double)gd[4];
-    dop += (double)gd[5];
+    const double dA = -0.5 * (double)gv[2], dB = -(double)gv[3], dC = -0.5 * (double)gv[4];
+    dop += (double)gv[5];
     gnorm += sqrt(du * du + dv * dv);
     cnt++;
     // conic (A, B, C) = inverse of [[a, b], [b, c]]: dSigma2D = -Q G Q with G = [[dA, dB/2], [dB/2, dC]]
@@ -387,14 +391,26 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_geom(SceneK sc, CamsK ca
     dt[2] -= (du * fx * tx + dv * fy * ty) / tz2;
     for (int i = 0; i < 3; i++) dmu[i] += W[i] * dt[0] + W[3 + i] * dt[1] + W[6 + i] * dt[2];
   }
-  // combine the four lanes of this Gaussian
-  for (int i = 0; i < 3; i++) dmu[i] = quad_sum(dmu[i]);
-  for (int i = 0; i < 6; i++) dSig[i] = quad_sum(dSig[i]);
-  dop = quad_sum(dop);
-  gnorm = quad_sum(gnorm);
-  cnt += __shfl_xor(cnt, 1, 64);
-  cnt += __shfl_xor(cnt, 2, 64);
-  if (!live || r != 0 || cnt == 0) return;
+  // combine the waves of this Gaussian (fixed order)
+  if (wave > 0) {
+    double* p = &s_part[wave - 1][0][lane];
+    for (int i = 0; i < 3; i++) p[i * 64] = dmu[i];
+    for (int i = 0; i < 6; i++) p[(3 + i) * 64] = dSig[i];
+    p[9 * 64] = dop;
+    p[10 * 64] = gnorm;
+    s_cnt[wave - 1][lane] = cnt;
+  }
+  __syncthreads();
+  if (wave > 0) return;
+  for (int w = 0; w < kAdjWaves - 1; w++) {
+    const double* p = &s_part[w][0][lane];
+    for (int i = 0; i < 3; i++) dmu[i] += p[i * 64];
+    for (int i = 0; i < 6; i++) dSig[i] += p[(3 + i) * 64];
+    dop += p[9 * 64];
+    gnorm += p[10 * 64];
+    cnt += s_cnt[w][lane];
+  }
+  if (!live || cnt == 0) return;
   GaussD G;
   load_gaussian(sc, g, G);
   // Sigma = M M^T -> dM = 2 dSigma M (dSigma symmetric)
@@ -461,32 +477,47 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
     dsh[k] = 0.f;
   }
   float dmu[3] = {0.f, 0.f, 0.f};
-  for (int v = 0; v < nv && live; v++) {
-    const int64_t row = (int64_t)v * sc.n + g;
-    if (tt_u[row] == 0) continue;  // not visible in this view
-    const float rgb = c == 0 ? rec_u[row].r2.x : (c == 1 ? rec_u[row].r2.y : rec_u[row].r2.z);
-    if (!(rgb > 0.f)) continue;  // clamped channel: no derivative
-    const CamK& cam = cams.c[v];
-    float dir[3];
-    for (int i = 0; i < 3; i++) dir[i] = mu[i] - cam.campos[i];
-    const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-    const float inv_dn = dn > 0.f ? 1.f / dn : 0.f;
-    float dhat[3];
-    for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv_dn;
-    float Y[16];
-    sh_basis<DEG, false, float>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
-    const float d = g2d[row * 9 + 6 + c];
-    float w[16];
+  constexpr int kAhead = 4;  // views whose inputs are loaded together
+  for (int v0 = 0; v0 < nv && live; v0 += kAhead) {
+    uint32_t tt4[kAhead];
+    float rgb4[kAhead], d4[kAhead];
 #pragma unroll
-    for (int k = 0; k < K; k++) {
-      dsh[k] += d * Y[k];
-      w[k] = d * shc[k];
+    for (int u = 0; u < kAhead; u++) {
+      tt4[u] = 0;
+      if (v0 + u < nv) {
+        const int64_t row = (int64_t)(v0 + u) * sc.n + g;
+        tt4[u] = tt_u[row];
+        rgb4[u] = reinterpret_cast<const float*>(&rec_u[row].r2)[c];
+        d4[u] = g2d[row * 9 + 6 + c];
+      }
     }
-    float dd[3];
-    sh_weighted_grad<DEG, float>(dhat[0], dhat[1], dhat[2], w, dd[0], dd[1], dd[2]);
-    if (dn > 0.f) {
-      const float dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
-      for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) * inv_dn;
+#pragma unroll
+    for (int u = 0; u < kAhead; u++) {
+      const int v = v0 + u;
+      if (tt4[u] == 0) continue;  // not visible in this view (or past the last view)
+      if (!(rgb4[u] > 0.f)) continue;  // clamped channel: no derivative
+      const CamK& cam = cams.c[v];
+      float dir[3];
+      for (int i = 0; i < 3; i++) dir[i] = mu[i] - cam.campos[i];
+      const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+      const float inv_dn = dn > 0.f ? 1.f / dn : 0.f;
+      float dhat[3];
+      for (int i = 0; i < 3; i++) dhat[i] = dir[i] * inv_dn;
+      float Y[16];
+      sh_basis<DEG, false, float>(dhat[0], dhat[1], dhat[2], Y, nullptr, nullptr, nullptr);
+      const float d = d4[u];
+      float w[16];
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        dsh[k] += d * Y[k];
+        w[k] = d * shc[k];
+      }
+      float dd[3];
+      sh_weighted_grad<DEG, float>(dhat[0], dhat[1], dhat[2], w, dd[0], dd[1], dd[2]);
+      if (dn > 0.f) {
+        const float dot = dhat[0] * dd[0] + dhat[1] * dd[1] + dhat[2] * dd[2];
+        for (int i = 0; i < 3; i++) dmu[i] += (dd[i] - dhat[i] * dot) * inv_dn;
+      }
     }
   }
   for (int i = 0; i < 3; i++) dmu[i] = quad_sumf(dmu[i]);
@@ -537,7 +568,7 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   if (s.n == 0) return;
   const int64_t threads = (int64_t)s.n * kBwdSplit;
   dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  k_preprocess_bwd_geom<<<grid, block, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
+  k_preprocess_bwd_geom<<<(s.n + 63) / 64, 64 * kAdjWaves, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
   if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
     case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
