@@ -259,17 +259,16 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
+  // T[k] > 0 while the pixel walks its list; a stopped pixel (or one outside the image) keeps
+  // -T: its updates T - T a stay negative, below the stop level, so it never blends again
   float T[NP], c0[NP], c1[NP], c2[NP];
   int last[NP];
-  float live[NP];  // 1 while the pixel is walking its list, 0 once stopped (or outside the image):
-                  // alpha is scaled by it, so a stopped pixel neither blends nor stops again
 #pragma unroll
   for (int k = 0; k < NP; k++) {
     const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
-    T[k] = 1.f;
+    T[k] = (px < V.W && py < V.H) ? 1.f : -1.f;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
-    live[k] = (px < V.W && py < V.H) ? 1.f : 0.f;
   }
   uint32_t n_eval = 0, n_blend = 0;
   for (uint32_t start = r.x; start < r.y; start += kBatchB) {
@@ -301,7 +300,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     // quadrants with a pixel still walking (a stopped pixel stays stopped)
     uint32_t qalive = 0;
 #pragma unroll
-    for (int k = 0; k < NP; k++) qalive |= __ballot(live[k] != 0.f) != 0 ? 1u << k : 0u;
+    for (int k = 0; k < NP; k++) qalive |= __ballot(T[k] > 0.f) != 0 ? 1u << k : 0u;
     __syncthreads();
     for (int j = 0; j < n_kept; j++) {
       const float2 xy = s_xy[j];
@@ -318,28 +317,27 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         if (NP > 1 && !((qm >> k) & 1u)) continue;  // uniform: no pixel of quadrant k can take it
         const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
         const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw)) * live[k];
+        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
         const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
         const float Tn = T[k] - T[k] * a;
-        const bool go = Tn >= kTStop;
+        const bool go = Tn >= kTStop;  // false for a stopped pixel (T < 0)
         const bool blend = ok && go;
         if (COUNT) {
-          n_eval += live[k] != 0.f ? 1u : 0u;
+          n_eval += T[k] > 0.f ? 1u : 0u;
           n_blend += blend ? 1u : 0u;
         }
-        live[k] = (ok && !go) ? 0.f : live[k];
         const float wgt = blend ? a * T[k] : 0.f;
         c0[k] += c.x * wgt;
         c1[k] += c.y * wgt;
         c2[k] += c.z * wgt;
-        T[k] = blend ? Tn : T[k];
+        // blended: T - T a; the pixel stops here: -|T| (a stopped pixel stays as it is)
+        T[k] = blend ? Tn : (ok ? -fabsf(T[k]) : T[k]);
         last[k] = blend ? pos1 : last[k];
       }
     }
-    float lsum = 0.f;
+    bool alive = false;
 #pragma unroll
-    for (int k = 0; k < NP; k++) lsum += live[k];
-    const bool alive = lsum != 0.f;
+    for (int k = 0; k < NP; k++) alive = alive || T[k] > 0.f;
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
@@ -350,6 +348,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
+      T[k] = fabsf(T[k]);
       const float col[3] = {c0[k] + T[k] * bg0, c1[k] + T[k] * bg1, c2[k] + T[k] * bg2};
       if (!L1 || V.rgb) {
 #pragma unroll
