@@ -287,6 +287,74 @@ def l1_loss_grad(renders, targets):
     return loss, dl, err
 
 
+# ---- D-SSIM term of the fidelity loss (Eq. 3) ----------------------------------------------
+# Readings (the paper names "the fidelity loss in the vanilla 3DGS": L1 plus D-SSIM): single-scale
+# SSIM with an 11x11 Gaussian window (sigma 1.5, weights normalised to sum 1), images in [0, 1]
+# so C1 = 0.01^2 and C2 = 0.03^2, window sums with zero padding ("same" size), the SSIM map
+# averaged over the three channels and all pixels, D-SSIM = 1 - SSIM.
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window() -> np.ndarray:
+    """The 11x11 window: outer product of the normalised 1-D Gaussian (sigma 1.5)."""
+    k = np.arange(11, dtype=np.float64) - 5.0
+    g = np.exp(-(k * k) / (2.0 * 1.5 * 1.5))
+    g /= g.sum()
+    return np.outer(g, g)
+
+
+def ssim_window_sum(img) -> np.ndarray:
+    """sum_q w(q - p) img(q) at every pixel p of an (H, W) image, zero outside it."""
+    from scipy.ndimage import correlate
+    return correlate(np.asarray(img, np.float64), ssim_window(), mode="constant", cval=0.0)
+
+
+def ssim_terms(x, y):
+    """SSIM map of two (H, W) images and its partial derivatives with respect to the window
+    moments mu_x = w*x, E_xx = w*(x^2), E_xy = w*(x y) (the others held fixed)."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    mx, my = ssim_window_sum(x), ssim_window_sum(y)
+    exx, eyy, exy = ssim_window_sum(x * x), ssim_window_sum(y * y), ssim_window_sum(x * y)
+    A = 2.0 * mx * my + SSIM_C1               # luminance numerator
+    B = 2.0 * (exy - mx * my) + SSIM_C2       # 2 sigma_xy + C2
+    Cc = mx * mx + my * my + SSIM_C1          # luminance denominator
+    D = (exx - mx * mx) + (eyy - my * my) + SSIM_C2  # sigma_x^2 + sigma_y^2 + C2
+    S = (A * B) / (Cc * D)
+    dS_dmx = (2.0 * my * B - 2.0 * my * A) / (Cc * D) - S * (2.0 * mx / Cc - 2.0 * mx / D)
+    dS_dexx = -S / D
+    dS_dexy = 2.0 * A / (Cc * D)
+    return S, dS_dmx, dS_dexx, dS_dexy
+
+
+def fidelity_loss_grad(renders, targets, lam: float):
+    """Eq. (3) fidelity term over V views: L = (1/V) sum_v [(1 - lam) mean|r - t| + lam (1 -
+    mean SSIM(r, t))], means over channels and pixels.  renders/targets (V,3,H,W).  Returns
+    (L, dL/drender (V,3,H,W), error map (V,H,W) = mean over channels of |r - t|)."""
+    r = np.asarray(renders, np.float64)
+    t = np.asarray(targets, np.float64)
+    V, _, H, W = r.shape
+    n = 3.0 * H * W
+    loss = 0.0
+    dl = np.zeros(r.shape)
+    err = np.zeros((V, H, W))
+    for v in range(V):
+        loss += lam / V  # the 1 of 1 - SSIM
+        for c in range(3):
+            x, y = r[v, c], t[v, c]
+            d = x - y
+            S, dmx, dexx, dexy = ssim_terms(x, y)
+            loss += ((1.0 - lam) * np.abs(d).sum() / n - lam * S.sum() / n) / V
+            # adjoint of the window sums: the window is symmetric, so it is the same sum
+            gS = -lam / (n * V)
+            dssim = ssim_window_sum(gS * dmx) + 2.0 * x * ssim_window_sum(gS * dexx) + \
+                y * ssim_window_sum(gS * dexy)
+            dl[v, c] = (1.0 - lam) * np.sign(d) / (n * V) + dssim
+            err[v] += np.abs(d) / 3.0
+    return loss, dl, err
+
+
 def _cams_array(cams):
     arr = (Cam * len(cams))()
     for i, c in enumerate(cams):

@@ -610,3 +610,78 @@ def test_child_normals_distribution():
     for k in range(3):
         assert stats.kstest(z[:, k], "norm").pvalue > 1e-3
     assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 0.06
+
+
+# ---- D-SSIM term of the fidelity loss (Eq. 3) ----------------------------------------------
+def test_ssim_window_and_window_sum_brute_force():
+    """The window is the normalised 11-tap Gaussian (sigma 1.5) outer product, and the window
+    sum is the zero-padded 'same' correlation, checked by explicit loops on a tiny image."""
+    w = oracle.ssim_window()
+    assert w.shape == (11, 11)
+    assert abs(w.sum() - 1.0) < 1e-15
+    np.testing.assert_allclose(w, w.T, rtol=0, atol=0)
+    g = np.exp(-((np.arange(11) - 5.0) ** 2) / 4.5)
+    np.testing.assert_allclose(w, np.outer(g, g) / g.sum() ** 2, rtol=1e-14)
+    rng = np.random.default_rng(21)
+    img = rng.uniform(size=(9, 7))
+    want = np.zeros_like(img)
+    H, W = img.shape
+    for py in range(H):
+        for px in range(W):
+            for dy in range(-5, 6):
+                for dx in range(-5, 6):
+                    qy, qx = py + dy, px + dx
+                    if 0 <= qy < H and 0 <= qx < W:
+                        want[py, px] += w[dy + 5, dx + 5] * img[qy, qx]
+    np.testing.assert_allclose(oracle.ssim_window_sum(img), want, rtol=1e-13, atol=1e-15)
+
+
+def test_ssim_constant_images_closed_form():
+    """Constant images a, b: away from the border the window sees no variance, so the SSIM
+    map is the luminance term (2ab + C1) / (a^2 + b^2 + C1)."""
+    a, b = 0.3, 0.7
+    S = oracle.ssim_terms(np.full((31, 31), a), np.full((31, 31), b))[0]
+    want = (2 * a * b + oracle.SSIM_C1) / (a * a + b * b + oracle.SSIM_C1)
+    np.testing.assert_allclose(S[5:-5, 5:-5], want, rtol=1e-12)
+    assert not np.allclose(S[0, 0], want)  # the zero padding changes the border, as defined
+
+
+def test_fidelity_loss_identity_symmetry_and_lambda_zero():
+    rng = np.random.default_rng(22)
+    r = rng.uniform(size=(2, 3, 13, 11))
+    t = rng.uniform(size=(2, 3, 13, 11))
+    # SSIM(x, x) = 1: no loss, no gradient (a maximum of SSIM, and the L1 kink at 0 has sign 0)
+    S = oracle.ssim_terms(r[0, 0], r[0, 0])[0]
+    np.testing.assert_allclose(S, 1.0, rtol=1e-13)
+    L, dl, err = oracle.fidelity_loss_grad(r, r, 0.4)
+    assert abs(L) < 1e-13
+    assert np.abs(dl).max() < 1e-13 and np.abs(err).max() == 0.0
+    # symmetric in its two images
+    assert oracle.fidelity_loss_grad(r, t, 0.4)[0] == pytest.approx(oracle.fidelity_loss_grad(t, r, 0.4)[0], rel=1e-13)
+    # lambda = 0 is the L1 term of the C oracle
+    L0, dl0, err0 = oracle.fidelity_loss_grad(r.astype(np.float32), t.astype(np.float32), 0.0)
+    L1, dl1, err1 = oracle.l1_loss_grad(r.astype(np.float32), t.astype(np.float32))
+    assert L0 == pytest.approx(L1, rel=1e-12)
+    np.testing.assert_allclose(dl0, dl1, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(err0, err1, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("lam", [0.2, 1.0])
+def test_fidelity_gradient_matches_finite_differences(lam):
+    rng = np.random.default_rng(23)
+    r = rng.uniform(size=(2, 3, 10, 12))
+    t = rng.uniform(size=(2, 3, 10, 12))
+    _, dl, _ = oracle.fidelity_loss_grad(r, t, lam)
+    idx = [tuple(rng.integers(0, s) for s in r.shape) for _ in range(40)]
+    checked = 0
+    for i in idx:
+        if abs(r[i] - t[i]) < 1e-3:  # the L1 kink
+            continue
+        h = 1e-6
+        rp, rm = r.copy(), r.copy()
+        rp[i] += h
+        rm[i] -= h
+        fd = (oracle.fidelity_loss_grad(rp, t, lam)[0] - oracle.fidelity_loss_grad(rm, t, lam)[0]) / (2 * h)
+        assert dl[i] == pytest.approx(fd, rel=1e-6, abs=1e-12)
+        checked += 1
+    assert checked >= 30
