@@ -250,6 +250,21 @@ dass_status dass_render_fwd_l1(dass_ctx ctx, const dass_gaussians* g, const dass
                                const float* const* target, float* const* dl_drgb, float* const* err,
                                float* loss, const dass_opts* opts, dass_stream stream);
 
+/* The fidelity loss of Eq. (3): L = (1/V) sum_v [(1 - lambda) L1_v + lambda D-SSIM_v] with
+ * L1_v = mean over channels and pixels of |render - target| and D-SSIM_v = 1 - SSIM_v, SSIM_v
+ * the mean over channels and pixels of the single-scale SSIM map (11x11 Gaussian window,
+ * sigma 1.5, normalised; window sums with zero padding; C1 = 0.01^2, C2 = 0.03^2 for images in
+ * [0, 1]).  Writes dl_drgb[v] = dL/drender (not accumulated) and err[v] [H][W] = mean over
+ * channels of |render - target| (Sec. 3.4; err may be NULL); *loss (device float, may be
+ * NULL) += L.  lambda in [0, 1]; lambda = 0 is dass_l1_loss_grad (scratch may then be NULL).
+ * scratch: host array of n_views device pointers to 9 H W floats each, caller-owned and
+ * overwritten.  Host arrays of n_views device pointers otherwise as dass_l1_loss_grad.
+ * Errors: DASS_E_INVALID (lambda outside [0, 1], NULL arrays or entries, bad sizes). */
+dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views,
+                                    const float* const* render, const float* const* target,
+                                    float lambda, float* const* dl_drgb, float* const* err,
+                                    float* loss, float* const* scratch, dass_stream stream);
+
 /* ---- stage timers --------------------------------------------------------------------- */
 
 /* Stages timed with HIP events on the stream of each call while profiling is on. */
@@ -264,7 +279,7 @@ typedef enum {
   DASS_STAGE_PROJECT_BWD = 7, /* adjoint of the projection                           */
   DASS_STAGE_SHIFT = 8,       /* shift_apply (either mode)                           */
   DASS_STAGE_ADAM = 9,        /* adam_step                                           */
-  DASS_STAGE_L1 = 10,         /* dass_l1_loss_grad                                   */
+  DASS_STAGE_L1 = 10,         /* dass_l1_loss_grad, dass_fidelity_loss_grad          */
   DASS_STAGE_DENSIFY = 11,    /* densify_append                                      */
   DASS_NUM_STAGES = 12
 } dass_stage;

@@ -15,7 +15,7 @@ MAX_VIEWS = 32
 
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
-           "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_debug_keys",
+           "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_fidelity_loss_grad", "dass_debug_keys",
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count")
 FLAG_COUNT_PAIRS = 1
@@ -93,6 +93,7 @@ def lib():
             "densify_append": (i32, [vp, P(Gaussians), P(vp), P(Camera), i32, vp, vp, f32, f32, f32, i32, u64, vp,
                                      vp]),
             "dass_l1_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), P(vp), P(vp), vp, vp]),
+            "dass_fidelity_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), f32, P(vp), P(vp), vp, P(vp), vp]),
             "dass_debug_keys": (i32, [vp, i32, vp, vp, i64, vp, P(i64)]),
             "dass_debug_projection": (i32, [vp, P(Gaussians), P(Camera), P(Opts), vp]),
             "dass_autotune_tile": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(vp), P(Grads), P(Opts),

@@ -299,6 +299,25 @@ class Context:
         self._check(self._lib.dass_l1_loss_grad(self._h, cameras_array(cams), V, R, T, D, E, _ptr(loss),
                                                 _stream(stream)))
 
+    def fidelity_loss_grad(self, cams, renders, targets, lam: float, dl_out, err_out=None,
+                           loss: Optional[torch.Tensor] = None, scratch=None, stream=None):
+        """Eq. (3) fidelity loss (1 - lam) L1 + lam D-SSIM: writes dl_out (and err_out, adds the
+        loss into `loss`).  scratch: per view a float32 tensor of at least 9 H W elements (made
+        here if None; pass preallocated ones in a captured or allocation-free loop)."""
+        V = len(cams)
+        if scratch is None and lam > 0.0:
+            scratch = [torch.empty(9 * c.height * c.width, device=dl_out[i].device) for i, c in enumerate(cams)]
+        for i, c in enumerate(cams):
+            if scratch is not None and scratch[i].numel() < 9 * c.height * c.width:
+                raise ValueError(f"scratch[{i}] holds {scratch[i].numel()} floats, needs {9 * c.height * c.width}")
+        R = (C.c_void_p * V)(*[_ptr(r) for r in renders])
+        T = (C.c_void_p * V)(*[_ptr(t) for t in targets])
+        D = (C.c_void_p * V)(*[_ptr(d) for d in dl_out])
+        E = (C.c_void_p * V)(*[_ptr(e) for e in err_out]) if err_out is not None else None
+        S = (C.c_void_p * V)(*[_ptr(x) for x in scratch]) if scratch is not None else None
+        self._check(self._lib.dass_fidelity_loss_grad(self._h, cameras_array(cams), V, R, T, float(lam), D, E,
+                                                      _ptr(loss), S, _stream(stream)))
+
     def densify_append(self, g: GaussianBuffers, err_maps, cams, gradnorm, count, gamma_err, tau_pos, tau_err,
                        k_max, seed, n_appended: torch.Tensor, stream=None):
         """Appends children in rows [g.n, g.n + K); K lands in n_appended (device int32); the caller

@@ -429,7 +429,7 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   stage_end(ctx, DASS_STAGE_BLEND_FWD, st);
   if (l1) {
     stage_begin(ctx, DASS_STAGE_L1, st);
-    launch_loss_finish(ws.loss_slots, l1->loss, st);
+    launch_loss_finish(ws.loss_slots, l1->loss, 0.f, st);
     stage_end(ctx, DASS_STAGE_L1, st);
   }
   if ((s = check_launch(ctx, "render_fwd")) != DASS_OK) return s;
@@ -621,6 +621,52 @@ dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_v
   launch_l1(a, blocks, loss, (hipStream_t)stream);
   stage_end(ctx, DASS_STAGE_L1, (hipStream_t)stream);
   return check_launch(ctx, "dass_l1_loss_grad");
+}
+
+dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* render,
+                                   const float* const* target, float lambda, float* const* dl_drgb,
+                                   float* const* err, float* loss, float* const* scratch, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(ctx, DASS_E_INVALID, "lambda %g outside [0, 1]", lambda);
+  if (lambda == 0.f)  // the L1 term alone
+    return dass_l1_loss_grad(ctx, cams, n_views, render, target, dl_drgb, err, loss, stream);
+  if (!cams || !render || !target || !dl_drgb || !scratch || n_views < 1 || n_views > DASS_MAX_VIEWS)
+    return fail(ctx, DASS_E_INVALID, "bad arguments");
+  SsimArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nv = n_views;
+  {
+    double g[11], sum = 0.0;
+    for (int k = 0; k < 11; k++) sum += (g[k] = std::exp(-((k - 5.0) * (k - 5.0)) / (2.0 * 1.5 * 1.5)));
+    for (int k = 0; k < 11; k++) a.w[k] = (float)(g[k] / sum);
+  }
+  int64_t blocks = 0;
+  for (int v = 0; v < n_views; v++) {
+    if (!render[v] || !target[v] || !dl_drgb[v] || !scratch[v])
+      return fail(ctx, DASS_E_INVALID, "view %d: NULL buffer", v);
+    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    SsimView& V = a.v[v];
+    V.render = render[v];
+    V.target = target[v];
+    V.dl = dl_drgb[v];
+    V.err = err ? err[v] : nullptr;
+    V.scratch = scratch[v];
+    V.W = cams[v].width;
+    V.H = cams[v].height;
+    V.TX = (V.W + 15) / 16;
+    V.block_begin = blocks;
+    blocks += ssim_tiles(V.W, V.H);
+    const double n = 3.0 * (double)V.W * (double)V.H * (double)n_views;
+    a.gS[v] = (float)(-(double)lambda / n);
+    a.l1_scale[v] = (float)((1.0 - (double)lambda) / n);
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  stage_begin(ctx, DASS_STAGE_L1, st);
+  launch_ssim(a, blocks, ctx->ws.loss_slots, st);
+  launch_loss_finish(ctx->ws.loss_slots, loss, lambda, st);  // + lambda: the 1 of 1 - SSIM, over views
+  stage_end(ctx, DASS_STAGE_L1, st);
+  return check_launch(ctx, "dass_fidelity_loss_grad");
 }
 
 dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* err_maps, const dass_camera* cams,

@@ -138,8 +138,8 @@ void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipSt
 void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, bool count_pairs, bool l1, hipStream_t st);
-// Adds the fused L1 partial sums to *loss (fixed order) and clears them.
-void launch_loss_finish(float* slots, float* loss, hipStream_t st);
+// Adds the loss partial sums and `add` to *loss (fixed order) and clears the sums.
+void launch_loss_finish(float* slots, float* loss, float add, hipStream_t st);
 // accumulates the per-(view, Gaussian) 2D gradients into ws.g2d[(v * n + g) * 9 + k]
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, int n, hipStream_t st);
@@ -187,6 +187,28 @@ struct L1Args {
   float scale;  // 1 / (3 H W V) per view is computed per view; scale = 1/V
 };
 void launch_l1(const L1Args& a, int64_t total_blocks, float* loss, hipStream_t st);
+
+// D-SSIM term of the fidelity loss (loss.hip): one workgroup per 16x16 pixel tile of a view.
+struct SsimView {
+  const float* render;  // [3][H][W]
+  const float* target;  // [3][H][W]
+  float* dl;            // [3][H][W] written
+  float* err;           // [H][W] or NULL
+  float* scratch;       // [3 channels][3 maps][H][W]
+  int W, H, TX;         // TX = 16x16 tiles per row
+  int64_t block_begin;
+};
+struct SsimArgs {
+  SsimView v[DASS_MAX_VIEWS];
+  float gS[DASS_MAX_VIEWS];        // dL/dSSIM(pixel, channel) = -lambda / (3 H W V)
+  float l1_scale[DASS_MAX_VIEWS];  // (1 - lambda) / (3 H W V)
+  float w[11];                     // normalised Gaussian window, sigma 1.5
+  int nv;
+};
+int64_t ssim_tiles(int W, int H);
+// Forward (SSIM map, its derivatives into scratch, loss partials) then backward (dL/drgb, error
+// map, L1 partials); the partials go to loss_slots.
+void launch_ssim(const SsimArgs& a, int64_t total_blocks, float* loss_slots, hipStream_t st);
 
 struct DensifyArgs {
   const float* err[DASS_MAX_VIEWS];

@@ -612,7 +612,7 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   }
 }
 
-__global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, float* __restrict__ loss) {
+__global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, float* __restrict__ loss, float add) {
   __shared__ float s_w[4];
   float acc = 0.f;
   for (int i = threadIdx.x; i < kLossSlots; i += 256) {
@@ -623,10 +623,12 @@ __global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, 
   for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0 && loss) *loss += (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
+  if (threadIdx.x == 0 && loss) *loss += ((s_w[0] + s_w[1]) + (s_w[2] + s_w[3])) + add;
 }
 
-void launch_loss_finish(float* slots, float* loss, hipStream_t st) { k_loss_finish<<<1, 256, 0, st>>>(slots, loss); }
+void launch_loss_finish(float* slots, float* loss, float add, hipStream_t st) {
+  k_loss_finish<<<1, 256, 0, st>>>(slots, loss, add);
+}
 
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
                       const uint32_t* vals, int n, hipStream_t st) {

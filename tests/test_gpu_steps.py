@@ -153,6 +153,52 @@ def test_fused_forward_l1_matches_render_then_l1(tile):
         torch.testing.assert_close(a, b, rtol=1e-5, atol=1e-7)
 
 
+@pytest.mark.parametrize("lam", [0.2, 1.0])
+def test_fidelity_loss_with_dssim_matches_oracle(lam):
+    """Eq. (3) fidelity term with D-SSIM against the oracle: several views of ragged sizes
+    (tiles of 16 with a remainder, images smaller than the window), renders and targets of
+    random and smooth content (small local variance, where SSIM's moments cancel most)."""
+    rng = np.random.default_rng(31)
+    sizes = ((64, 48), (37, 29), (150, 110), (9, 7))
+    cams = [synth.make_camera(np.eye(3), (0, 0, 0), w, h) for w, h in sizes]
+    R, T = [], []
+    for k, c in enumerate(cams):
+        if k % 2 == 0:
+            r = rng.uniform(size=(3, c.height, c.width))
+            t = np.clip(r + rng.normal(0, 0.1, size=r.shape), 0, 1)
+        else:
+            yy, xx = np.mgrid[0:c.height, 0:c.width]
+            r = 0.5 + 0.4 * np.sin(xx / 7.0 + np.arange(3)[:, None, None]) * np.cos(yy / 5.0)
+            t = r + 0.02 * rng.normal(size=r.shape)
+        R.append(r.astype(np.float32))
+        T.append(t.astype(np.float32))
+    ctx = make_ctx(10, cams)
+    dl = [torch.full((3, c.height, c.width), 7.0, device="cuda") for c in cams]
+    err = [torch.zeros(c.height, c.width, device="cuda") for c in cams]
+    loss = torch.full((1,), 0.5, device="cuda")
+    ctx.fidelity_loss_grad(cams, [dev(r) for r in R], [dev(t) for t in T], lam, dl, err, loss)
+    ctx.sync()
+    want = [oracle.fidelity_loss_grad(R[v][None], T[v][None], lam) for v in range(len(cams))]
+    V = len(cams)
+    want_loss = sum(w[0] for w in want) / V
+    assert float(loss.item()) - 0.5 == pytest.approx(want_loss, rel=1e-5)
+    for v in range(V):
+        got = dl[v].cpu().numpy()
+        o = want[v][1][0] / V
+        # per-tensor bound of the gradient tests: |g - o| <= 1e-3 |o| + 1e-4 max|o|
+        bad = np.abs(got - o) > 1e-3 * np.abs(o) + 1e-4 * np.abs(o).max()
+        assert not bad.any(), (v, np.abs(got - o).max(), np.abs(o).max())
+        np.testing.assert_allclose(err[v].cpu().numpy(), want[v][2][0], rtol=1e-6, atol=1e-7)
+    # lambda = 0 is the L1 call, bit for bit
+    dl0 = [torch.zeros_like(d) for d in dl]
+    dl1 = [torch.zeros_like(d) for d in dl]
+    ctx.fidelity_loss_grad(cams, [dev(r) for r in R], [dev(t) for t in T], 0.0, dl0)
+    ctx.l1_loss_grad(cams, [dev(r) for r in R], [dev(t) for t in T], dl1)
+    ctx.sync()
+    for a, b in zip(dl0, dl1):
+        assert torch.equal(a, b)
+
+
 def _densify_case(seed, n, views, k_max, extra_cap, tau_pos, tau_err, gamma):
     rng = np.random.default_rng(seed)
     scene, cams, _ = synth.multiview_scene(seed, n=n, n_views=views, width=96, height=72, with_grads=False)
