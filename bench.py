@@ -96,6 +96,8 @@ def build_workload(args):
         scene, cams, _ = synth.multiview_scene(args.seed, n=args.n, n_views=args.views, width=args.width,
                                                height=args.height, with_grads=False)
         name = f"multiview_{args.n // 1000}k_sh3_{args.views}x{args.width}x{args.height}"
+        if getattr(args, "ssim_lambda", 0.0) > 0.0:
+            name += f"_dssim{args.ssim_lambda:g}"
     else:
         scene, cams, _ = synth.single_view_scene(args.seed)
         name = "single_view_2k_sh0_128x128"
@@ -123,6 +125,8 @@ def build_workload(args):
         outs=[RenderOut.allocate(c) for c in cams],
         dls=[torch.zeros(3, c.height, c.width, device=dev) for c in cams],
         errs=[torch.zeros(c.height, c.width, device=dev) for c in cams],
+        ssim_scratch=([torch.empty(9 * c.height * c.width, device=dev) for c in cams]
+                      if getattr(args, "ssim_lambda", 0.0) > 0.0 else None),
         grads=g.zeros_like(), loss=torch.zeros(1, device=dev),
         gn=torch.zeros(cap, device=dev), cnt=torch.zeros(cap, dtype=torch.int32, device=dev),
         dpos=torch.zeros(3, nd, device=dev), drot=torch.cat([torch.ones(1, nd), torch.zeros(3, nd)]).to(dev),
@@ -139,7 +143,14 @@ def train_step(s, it, args, per_view=False):
     ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
     for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
         t.zero_()
-    if not per_view:
+    lam = getattr(args, "ssim_lambda", 0.0)
+    if not per_view and lam > 0.0:
+        # Eq. (3) with its D-SSIM term: the render, then the fidelity loss over the images
+        ctx.render_fwd(gs, cams, args.bg, out=s["outs"])
+        ctx.fidelity_loss_grad(cams, [o.rgb for o in s["outs"]], s["targets"], lam, s["dls"], s["errs"], s["loss"],
+                               scratch=s["ssim_scratch"])
+        ctx.render_bwd(gs, cams, args.bg, s["outs"], s["dls"], s["grads"], s["gn"], s["cnt"])
+    elif not per_view:
         # render fused with the L1 term (the step reads only the loss gradient, error maps and the
         # forward's transmittance / contributor counts, so the images are not written)
         ctx.render_fwd_l1(gs, cams, args.bg, s["targets"], s["dls"], s["errs"], s["loss"], out=s["outs"],
@@ -150,8 +161,12 @@ def train_step(s, it, args, per_view=False):
         V = len(cams)
         for v in range(V):
             ctx.render_fwd(gs, cams[v:v + 1], args.bg, out=s["outs"][v:v + 1])
-            ctx.l1_loss_grad(cams[v:v + 1], [s["outs"][v].rgb], s["targets"][v:v + 1], s["dls"][v:v + 1],
-                             s["errs"][v:v + 1], s["loss"])
+            if lam > 0.0:
+                ctx.fidelity_loss_grad(cams[v:v + 1], [s["outs"][v].rgb], s["targets"][v:v + 1], lam,
+                                       s["dls"][v:v + 1], s["errs"][v:v + 1], s["loss"], scratch=[s["ssim_scratch"][v]])
+            else:
+                ctx.l1_loss_grad(cams[v:v + 1], [s["outs"][v].rgb], s["targets"][v:v + 1], s["dls"][v:v + 1],
+                                 s["errs"][v:v + 1], s["loss"])
             s["dls"][v].mul_(1.0 / V)
             ctx.render_bwd(gs, cams[v:v + 1], args.bg, s["outs"][v:v + 1], s["dls"][v:v + 1], s["grads"], s["gn"],
                            s["cnt"])
@@ -568,6 +583,8 @@ def main():
     ap.add_argument("--height", type=int, default=1014)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--densify-k", type=int, default=5000)
+    ap.add_argument("--ssim-lambda", type=float, default=0.0,
+                    help="weight of the D-SSIM term of the fidelity loss (Eq. 3); 0 = L1 only")
     ap.add_argument("--max-keys", type=int, default=0)
     ap.add_argument("--lr-pos", type=float, default=1e-3)
     ap.add_argument("--lr-rot", type=float, default=1e-3)
@@ -697,7 +714,9 @@ def main():
         "config": {"workload": s["name"], "n_gaussians": s["N"], "sh_degree": int(s["g"].sh_degree),
                    "views": len(cams), "width": cams[0].width, "height": cams[0].height,
                    "tile": tile_name(ctx.tile),
-                   "n_dynamic": s["nd"], "densify_k": args.densify_k, "parallelism": "single GPU"},
+                   "n_dynamic": s["nd"], "densify_k": args.densify_k,
+                   "loss": "l1" if args.ssim_lambda == 0.0 else f"(1-l) L1 + l D-SSIM, l = {args.ssim_lambda}",
+                   "parallelism": "single GPU"},
         "tile_autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
         "fwd_bwd_latency": lat,

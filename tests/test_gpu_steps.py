@@ -199,6 +199,29 @@ def test_fidelity_loss_with_dssim_matches_oracle(lam):
         assert torch.equal(a, b)
 
 
+def test_fidelity_loss_with_dssim_fullsize():
+    """Two views at the benchmark's 1352x1014, lambda 0.2: every element against the oracle."""
+    rng = np.random.default_rng(32)
+    cams = [synth.make_camera(np.eye(3), (0, 0, 0), 1352, 1014) for _ in range(2)]
+    R = [rng.uniform(size=(3, 1014, 1352)).astype(np.float32) for _ in cams]
+    T = [np.clip(r + rng.normal(0, 0.05, size=r.shape), 0, 1).astype(np.float32) for r in R]
+    ctx = make_ctx(10, cams)
+    dl = [torch.zeros(3, 1014, 1352, device="cuda") for _ in cams]
+    err = [torch.zeros(1014, 1352, device="cuda") for _ in cams]
+    loss = torch.zeros(1, device="cuda")
+    ctx.fidelity_loss_grad(cams, [dev(r) for r in R], [dev(t) for t in T], 0.2, dl, err, loss)
+    ctx.sync()
+    total = 0.0
+    for v in range(2):
+        lv, dv, ev = oracle.fidelity_loss_grad(R[v][None], T[v][None], 0.2)
+        total += lv / 2
+        o = dv[0] / 2
+        got = dl[v].cpu().numpy()
+        assert not (np.abs(got - o) > 1e-3 * np.abs(o) + 1e-4 * np.abs(o).max()).any()
+        np.testing.assert_allclose(err[v].cpu().numpy(), ev[0], rtol=1e-6, atol=1e-7)
+    assert float(loss.item()) == pytest.approx(total, rel=1e-5)
+
+
 def _densify_case(seed, n, views, k_max, extra_cap, tau_pos, tau_err, gamma):
     rng = np.random.default_rng(seed)
     scene, cams, _ = synth.multiview_scene(seed, n=n, n_views=views, width=96, height=72, with_grads=False)
