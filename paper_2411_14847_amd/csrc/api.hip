@@ -653,7 +653,7 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
     V.scratch = scratch[v];
     V.W = cams[v].width;
     V.H = cams[v].height;
-    V.TX = (V.W + 15) / 16;
+    V.TX = (V.W + ssim_tile_edge() - 1) / ssim_tile_edge();
     V.block_begin = blocks;
     blocks += ssim_tiles(V.W, V.H);
     const double n = 3.0 * (double)V.W * (double)V.H * (double)n_views;

@@ -188,14 +188,14 @@ struct L1Args {
 };
 void launch_l1(const L1Args& a, int64_t total_blocks, float* loss, hipStream_t st);
 
-// D-SSIM term of the fidelity loss (loss.hip): one workgroup per 16x16 pixel tile of a view.
+// D-SSIM term of the fidelity loss (loss.hip): one workgroup per ssim_tile_edge()^2 pixel tile.
 struct SsimView {
   const float* render;  // [3][H][W]
   const float* target;  // [3][H][W]
   float* dl;            // [3][H][W] written
   float* err;           // [H][W] or NULL
   float* scratch;       // [3 channels][3 maps][H][W]
-  int W, H, TX;         // TX = 16x16 tiles per row
+  int W, H, TX;         // TX = tiles per row
   int64_t block_begin;
 };
 struct SsimArgs {
@@ -206,6 +206,7 @@ struct SsimArgs {
   int nv;
 };
 int64_t ssim_tiles(int W, int H);
+int ssim_tile_edge();
 // Forward (SSIM map, its derivatives into scratch, loss partials) then backward (dL/drgb, error
 // map, L1 partials); the partials go to loss_slots.
 void launch_ssim(const SsimArgs& a, int64_t total_blocks, float* loss_slots, hipStream_t st);
