@@ -38,6 +38,7 @@ class StreamConfig:
     beta2: float = 0.999
     eps: float = 1e-15
     bg: tuple = (0.0, 0.0, 0.0)
+    ssim_lambda: float = 0.0      # weight of the D-SSIM term of Eq. (3); 0 = L1 only
     use_graph: bool = False
     per_view: bool = False        # plain per-view loop (one render_fwd / render_bwd per camera)
     max_inflight: int = 0         # >0: at most this many iterations queued on the GPU at once, so
@@ -60,6 +61,8 @@ class Trainer:
         self.outs = [RenderOut.allocate(c, dev) for c in self.cams]
         self.dls = [torch.zeros(3, c.height, c.width, device=dev) for c in self.cams]
         self.errs = [torch.zeros(c.height, c.width, device=dev) for c in self.cams]
+        self.ssim_scratch = ([torch.empty(9 * c.height * c.width, device=dev) for c in self.cams]
+                             if cfg.ssim_lambda > 0.0 else None)
         self.targets = [torch.zeros(3, c.height, c.width, device=dev) for c in self.cams]
         self.grads = g.zeros_like()
         self.loss = torch.zeros(1, device=dev)
@@ -111,16 +114,26 @@ class Trainer:
         for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
             t.zero_()
         if not cfg.per_view:
-            ctx.render_fwd_l1(gs, self.cams, cfg.bg, self.targets, self.dls, self.errs, self.loss, out=self.outs,
-                              stream=stream)
+            if cfg.ssim_lambda > 0.0:
+                ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
+                ctx.fidelity_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, cfg.ssim_lambda, self.dls,
+                                       self.errs, self.loss, scratch=self.ssim_scratch, stream=stream)
+            else:
+                ctx.render_fwd_l1(gs, self.cams, cfg.bg, self.targets, self.dls, self.errs, self.loss,
+                                  out=self.outs, stream=stream)
             ctx.render_bwd(gs, self.cams, cfg.bg, self.outs, self.dls, self.grads, self.gn, self.cnt, stream=stream)
         else:
             V = len(self.cams)
             for v in range(V):
                 sl = slice(v, v + 1)
                 ctx.render_fwd(gs, self.cams[sl], cfg.bg, out=self.outs[sl], stream=stream)
-                ctx.l1_loss_grad(self.cams[sl], [self.outs[v].rgb], self.targets[sl], self.dls[sl], self.errs[sl],
-                                 self.loss, stream=stream)
+                if cfg.ssim_lambda > 0.0:
+                    ctx.fidelity_loss_grad(self.cams[sl], [self.outs[v].rgb], self.targets[sl], cfg.ssim_lambda,
+                                           self.dls[sl], self.errs[sl], self.loss, scratch=self.ssim_scratch[sl],
+                                           stream=stream)
+                else:
+                    ctx.l1_loss_grad(self.cams[sl], [self.outs[v].rgb], self.targets[sl], self.dls[sl], self.errs[sl],
+                                     self.loss, stream=stream)
                 with torch.cuda.stream(stream or torch.cuda.current_stream()):
                     self.dls[v].mul_(1.0 / V)
                 ctx.render_bwd(gs, self.cams[sl], cfg.bg, self.outs[sl], self.dls[sl], self.grads, self.gn, self.cnt,

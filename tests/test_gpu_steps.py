@@ -332,12 +332,13 @@ def test_autograd_function_matches_render_bwd():
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_streaming_driver(use_graph):
+@pytest.mark.parametrize("lam", [0.0, 0.2], ids=["l1", "l1_dssim"])
+def test_streaming_driver(use_graph, lam):
     from paper_2411_14847_amd import Context, GaussianBuffers
     from paper_2411_14847_amd.streaming import StreamConfig, Trainer
     scene, _, _ = synth.single_view_scene(0, n=600)
     cams = synth.streaming_rig(64, 64)[:4]
-    cfg = StreamConfig(iters=25, k_append=80, erase_every=2, use_graph=use_graph)
+    cfg = StreamConfig(iters=25, k_append=80, erase_every=2, use_graph=use_graph, ssim_lambda=lam)
     cap = scene.n + 2 * cfg.k_append
     g = GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh, 0, capacity=cap)
     gt = g.clone()
