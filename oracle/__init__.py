@@ -416,3 +416,7 @@ def sh_eval(deg, dirs):
     out = np.zeros((d.shape[0], K))
     lib().orc_sh_eval(C.c_int32(deg), C.c_int32(d.shape[0]), _p(d), _p(out))
     return out
+
+
+# hash-encoded deformation fields (Sec. 3.3, App. B)
+from .hashfield import Field as HashField, field_bwd as hash_field_bwd, field_fwd as hash_field_fwd  # noqa: E402

@@ -275,3 +275,56 @@ def tiny_scene(seed: int, n: int, width: int, height: int, sh_degree: int = 0, l
     cam = make_camera(np.diag([1.0, -1.0, -1.0]), (0.0, 0.0, 4.0), width, height)
     dl = rng.normal(0.0, 1.0, size=(3, height, width)).astype(np.float32)
     return Scene(mean, quat, log_scale, logit, sh, sh_degree), [cam], [dl]
+
+
+@dataclass
+class HashFieldParams:
+    """Parameters of one hash-encoded deformation field (float32): per-level grid resolutions,
+    F features per table row, 2^log2_table rows per level, an MLP of one hidden layer."""
+    res: list
+    features: int
+    log2_table: int
+    hidden: int
+    aabb_min: np.ndarray
+    aabb_max: np.ndarray
+    table: np.ndarray  # (L, T, F)
+    w1: np.ndarray     # (hidden, L*F)
+    b1: np.ndarray     # (hidden,)
+    w2: np.ndarray     # (7, hidden)
+    b2: np.ndarray     # (7,)
+
+
+def geometric_res(n_min: int, n_max: int, levels: int) -> list:
+    """Level resolutions N_min..N_max in a geometric progression, floored (top level exact)."""
+    if levels == 1:
+        return [int(n_min)]
+    return [int(math.floor(n_min * (n_max / n_min) ** (l / (levels - 1)) + 1e-9)) for l in range(levels)]
+
+
+def hash_field_params(seed: int, levels: int = 16, features: int = 4, log2_table: int = 16,
+                      hidden: int = 64, n_min: int = 16, n_max: int = 2048, aabb=(-1.5, 1.5),
+                      table_scale: float = 0.5, w2_scale: float = 0.1) -> HashFieldParams:
+    """Random field parameters; draws table, w1, b1, w2, b2 in that order.  Defaults: the dynamic
+    group's field of the N3DV setting (T = 2^16, F = 4; App. B)."""
+    rng = np.random.default_rng(seed)
+    lf = levels * features
+    table = rng.uniform(-table_scale, table_scale, size=(levels, 1 << log2_table, features)).astype(np.float32)
+    w1 = (rng.normal(0.0, 1.0, size=(hidden, lf)) * math.sqrt(2.0 / lf)).astype(np.float32)
+    b1 = rng.normal(0.0, 0.1, size=hidden).astype(np.float32)
+    w2 = (rng.normal(0.0, 1.0, size=(7, hidden)) * w2_scale).astype(np.float32)
+    b2 = rng.normal(0.0, 0.01, size=7).astype(np.float32)
+    lo = np.full(3, aabb[0], np.float32)
+    hi = np.full(3, aabb[1], np.float32)
+    return HashFieldParams(geometric_res(n_min, n_max, levels), features, log2_table, hidden, lo, hi,
+                           table, w1, b1, w2, b2)
+
+
+def field_queries(seed: int, n: int, m: int, spread: float = 1.2):
+    """Positions (3, n) in a box of half-width `spread`, m distinct query indices (sorted), and
+    upstream gradients d_dpos (3, m), d_drot (4, m)."""
+    rng = np.random.default_rng(seed)
+    mean = rng.uniform(-spread, spread, size=(3, n)).astype(np.float32)
+    idx = np.sort(rng.choice(n, size=m, replace=False)).astype(np.int32)
+    d_dpos = rng.normal(0.0, 1.0, size=(3, m)).astype(np.float32)
+    d_drot = rng.normal(0.0, 1.0, size=(4, m)).astype(np.float32)
+    return mean, idx, d_dpos, d_drot

@@ -685,3 +685,132 @@ def test_fidelity_gradient_matches_finite_differences(lam):
         assert dl[i] == pytest.approx(fd, rel=1e-6, abs=1e-12)
         checked += 1
     assert checked >= 30
+
+
+# ------------------------------------------------------------------------------------------
+# Hash-encoded deformation fields (Sec. 3.3, App. B)
+# ------------------------------------------------------------------------------------------
+from oracle import hashfield as HF  # noqa: E402
+
+
+def _field(res, features, log2_table, hidden, seed=0, **kw):
+    p = synth.hash_field_params(seed, levels=len(res), features=features, log2_table=log2_table,
+                                hidden=hidden, **kw)
+    p.res = list(res)
+    return HF.from_params(p)
+
+
+def test_hash_encoding_reproduces_linear_functions_on_dense_levels():
+    """Trilinear interpolation is exact for functions linear in the grid coordinates: with
+    every dense level's rows set to a.c + b at corner c, the encoding at p is a.(p N_l) + b."""
+    f = _field([3, 5, 7], 2, 10, 8)  # (N+1)^3 = 64, 216, 512 <= 1024: all dense
+    a = np.array([[0.7, -1.3, 2.1], [-0.4, 0.9, 0.25]])
+    b = np.array([0.3, -0.8])
+    for l, n in enumerate(f.res):
+        g = np.arange(n + 1)
+        cz, cy, cx = np.meshgrid(g, g, g, indexing="ij")
+        c = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], -1)
+        f.table[l][:] = 0.0
+        f.table[l][HF.corner_index(f, l, c)] = c @ a.T + b
+    rng = np.random.default_rng(3)
+    p = rng.uniform(0, 1, size=(50, 3))
+    p[0] = 1.0                                   # top corner of the box (the clamped cell)
+    p[1] = [0.0, 1.0, 0.5]
+    enc = HF.encode(f, p)
+    for l, n in enumerate(f.res):
+        np.testing.assert_allclose(enc[:, 2 * l:2 * l + 2], (p * n) @ a.T + b, rtol=0, atol=1e-12)
+
+
+def test_hash_dense_index_is_x_fastest():
+    f = _field([3], 1, 8, 4)
+    assert HF.corner_index(f, 0, [[1, 0, 0]])[0] == 1
+    assert HF.corner_index(f, 0, [[0, 1, 0]])[0] == 4
+    assert HF.corner_index(f, 0, [[0, 0, 1]])[0] == 16
+    assert HF.corner_index(f, 0, [[3, 3, 3]])[0] == 63
+
+
+def test_spatial_hash_on_grid_vertices():
+    """On a hashed level, a query exactly on a grid vertex reads that vertex's row alone; with
+    row r holding the feature r, the encoding returns the hash (x*1 xor y*2654435761 xor
+    z*805459861) mod T, whose primes are the published ones of the multi-resolution encoding."""
+    T = 1 << 12
+    f = _field([100], 1, 12, 4)  # 101^3 > 4096: hashed
+    f.table[0][:, 0] = np.arange(T)
+    coords = [(37, 0, 0), (0, 1, 0), (0, 0, 1), (0, 2, 0), (5, 7, 11)]
+    p = np.array(coords, np.float64) / 100.0
+    enc = np.rint(HF.encode(f, p)[:, 0])        # vertex weight 1 up to the rounding of p N
+    assert enc[0] == 37                        # prime 1 on x: identity along the x axis
+    assert enc[1] == 2654435761 % T           # = 0x9E3779B1 mod 2^12 = 0x9B1
+    assert enc[1] == 0x9B1
+    assert enc[2] == 805459861 % T            # = 0x30025795 mod 2^12 = 0x795
+    assert enc[2] == 0x795
+    assert enc[3] == (2 * 2654435761) % T
+    assert enc[4] == (5 ^ (7 * 2654435761 % 2**32) ^ (11 * 805459861 % 2**32)) % T
+
+
+def test_hash_field_identity_and_mlp_closed_form():
+    """A zero output layer is the identity shift (dpos 0, drot (1,0,0,0)); with one level, an
+    identity first layer and non-negative features, the MLP is the affine map W2 enc + b2."""
+    f = _field([4], 4, 10, 4)
+    rng = np.random.default_rng(5)
+    mean = rng.uniform(-1.4, 1.4, size=(3, 20))
+    f.w2[:] = 0.0
+    f.b2[:] = 0.0
+    dp, dr = HF.field_fwd(f, mean)
+    assert np.all(dp == 0.0) and np.all(dr[0] == 1.0) and np.all(dr[1:] == 0.0)
+    f.table[:] = np.abs(f.table)
+    f.w1[:] = np.eye(4)
+    f.b1[:] = 0.0
+    f.w2[:] = rng.normal(size=(7, 4))
+    f.b2[:] = rng.normal(size=7)
+    enc = HF.encode(f, HF.normalised(f, mean))
+    dp, dr = HF.field_fwd(f, mean)
+    out = enc @ f.w2.T + f.b2
+    np.testing.assert_allclose(dp, out[:, :3].T, atol=1e-14)
+    np.testing.assert_allclose(dr, out[:, 3:].T + np.array([[1.0], [0], [0], [0]]), atol=1e-14)
+    # ReLU: a negative bias beyond every pre-activation leaves only b2
+    f.b1[:] = -10.0
+    dp, dr = HF.field_fwd(f, mean)
+    np.testing.assert_allclose(dp, np.repeat(f.b2[:3, None], 20, 1), atol=0)
+
+
+def test_hash_field_clamps_to_the_box():
+    f = _field([4, 9], 2, 8, 8)
+    inside = np.array([[1.5, -0.3, 0.2], [-1.5, 1.5, 0.9]]).T        # on the box faces
+    outside = np.array([[4.0, -0.3, 0.2], [-9.0, 7.5, 0.9]]).T
+    for a, b in zip(HF.field_fwd(f, inside), HF.field_fwd(f, outside)):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("res,features,log2_table", [([2, 5, 11], 2, 7), ([3, 40], 4, 9)])
+def test_hash_field_gradients_match_finite_differences(res, features, log2_table):
+    """Every parameter group, dense and hashed levels: central differences of
+    <d_dpos, dpos> + <d_drot, drot>."""
+    f = _field(res, features, log2_table, 16, seed=2)
+    mean, idx, ddp, ddr = synth.field_queries(7, 40, 40)
+    mean = mean.astype(np.float64)
+    g = HF.field_bwd(f, mean, ddp, ddr)
+
+    def obj():
+        a, b = HF.field_fwd(f, mean)
+        return float((a * ddp).sum() + (b * ddr).sum())
+
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for name in ("table", "w1", "b1", "w2", "b2"):
+        arr = getattr(f, name)
+        if name == "table":
+            used = np.argwhere(np.abs(g["table"]) > 0)
+            picks = [tuple(used[i]) for i in rng.choice(len(used), 6, replace=False)]
+            picks.append(tuple(np.argwhere(g["table"] == 0)[0]))       # an unused row: zero
+        else:
+            picks = [tuple(rng.integers(0, s) for s in arr.shape) for _ in range(6)]
+        for ix in picks:
+            old = arr[ix]
+            arr[ix] = old + h
+            fp = obj()
+            arr[ix] = old - h
+            fm = obj()
+            arr[ix] = old
+            fd = (fp - fm) / (2 * h)
+            assert abs(g[name][ix] - fd) <= 1e-6 * max(1.0, abs(fd)), (name, ix, g[name][ix], fd)
