@@ -265,6 +265,62 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
                                     float lambda, float* const* dl_drgb, float* const* err,
                                     float* loss, float* const* scratch, dass_stream stream);
 
+/* ---- hash-encoded deformation fields (Sec. 3.3; sizes in App. B) ------------------------ */
+
+/* A deformation field H_dyn or H_st: the multi-resolution hash encoding of a position followed
+ * by an MLP with one ReLU hidden layer, giving the shift offsets of Sec. 3.3.  For a query at
+ * mu: p = clamp((mu - aabb_min) / (aabb_max - aabb_min), 0, 1) per axis; at level l, with
+ * x = p N_l, the cell c0 = min(floor(x), N_l - 1) and frac = x - c0, the encoding's F features
+ * are the trilinear blend of the rows of the 8 corners c0 + d (d in {0,1}^3, weight
+ * prod(d ? frac : 1 - frac)); a corner's row is c_x + (N_l+1)(c_y + (N_l+1) c_z) when
+ * (N_l+1)^3 <= T, else (c_x xor c_y 2654435761 xor c_z 805459861) mod T (32-bit unsigned).
+ * The L levels' features, level-major, form enc (L*F); h = relu(w1 enc + b1);
+ * out = w2 h + b2; dpos = out[0:3], drot = (1, 0, 0, 0) + out[3:7] (a zero output layer is the
+ * identity shift; shift_apply normalises drot). */
+#define DASS_HASH_MAX_LEVELS 16
+typedef struct {
+  int32_t levels;      /* L in [1, 16]                                              */
+  int32_t features;    /* F in {1, 2, 4, 8}, L * F <= 64                             */
+  int32_t log2_table;  /* T = 2^log2_table rows per level, log2_table in [4, 24]     */
+  int32_t hidden;      /* hidden units: 32 or 64                                     */
+  int32_t res[DASS_HASH_MAX_LEVELS]; /* N_l in [1, 2^20] for l < L (others unread)  */
+  float aabb_min[3], aabb_max[3];    /* the box mapped onto [0, 1]^3 (max > min)    */
+  float* table;        /* [L][T][F] device                                           */
+  float* w1;           /* [hidden][L*F] device                                       */
+  float* b1;           /* [hidden] device                                            */
+  float* w2;           /* [7][hidden] device                                         */
+  float* b2;           /* [7] device                                                 */
+} dass_hash_field;
+
+/* Gradients with the shapes of a dass_hash_field's arrays (device; NULL skips one).
+ * Accumulated (+=). */
+typedef struct {
+  float* table;
+  float* w1;
+  float* b1;
+  float* w2;
+  float* b2;
+} dass_hash_field_grads;
+
+/* Queries the field at m Gaussians: query j reads row idx[j] of mean [3][stride] (idx NULL:
+ * row j) and writes dpos [3][ld] and drot [4][ld] column j (ld >= m).  A row outside [0, n)
+ * gets the identity shift (dpos 0, drot (1, 0, 0, 0)).  The outputs feed shift_apply.
+ * Errors: DASS_E_INVALID for a field outside the limits above, NULL pointers, m < 0, n < 0,
+ * stride < n, ld < m, or idx NULL with m > n. */
+dass_status dass_hash_field_fwd(dass_ctx ctx, const dass_hash_field* field, const float* mean,
+                                int64_t stride, int32_t n, const int32_t* idx, int32_t m,
+                                float* dpos, float* drot, int64_t ld, dass_stream stream);
+
+/* Reverse-mode adjoint of dass_hash_field_fwd with the same arguments: given d_dpos [3][ld] and
+ * d_drot [4][ld] (dL/d of the outputs), accumulates dL/d(table, w1, b1, w2, b2) into `grads`.
+ * Queries outside [0, n) add nothing.  The weight gradients are summed per workgroup and then
+ * over workgroups in a fixed order; table gradients use float atomics (order-nondeterministic).
+ * Errors as dass_hash_field_fwd, plus DASS_E_INVALID for a NULL grads. */
+dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, const float* mean,
+                                int64_t stride, int32_t n, const int32_t* idx, int32_t m,
+                                const float* d_dpos, const float* d_drot, int64_t ld,
+                                const dass_hash_field_grads* grads, dass_stream stream);
+
 /* ---- stage timers --------------------------------------------------------------------- */
 
 /* Stages timed with HIP events on the stream of each call while profiling is on. */
@@ -281,7 +337,8 @@ typedef enum {
   DASS_STAGE_ADAM = 9,        /* adam_step                                           */
   DASS_STAGE_L1 = 10,         /* dass_l1_loss_grad, dass_fidelity_loss_grad          */
   DASS_STAGE_DENSIFY = 11,    /* densify_append                                      */
-  DASS_NUM_STAGES = 12
+  DASS_STAGE_FIELD = 12,      /* dass_hash_field_fwd / dass_hash_field_bwd             */
+  DASS_NUM_STAGES = 13
 } dass_stage;
 
 /* Starts recording: up to max_records intervals per stage (allocates the events). */

@@ -17,11 +17,11 @@ MAX_VIEWS = 32
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
            "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_fidelity_loss_grad", "dass_debug_keys",
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
-           "adam_step_device_count")
+           "adam_step_device_count", "dass_hash_field_fwd", "dass_hash_field_bwd")
 FLAG_COUNT_PAIRS = 1
 FLAG_SUBTILE8 = 2
 STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
-          "shift", "adam", "l1", "densify")
+          "shift", "adam", "l1", "densify", "field")
 
 
 class Gaussians(C.Structure):
@@ -57,6 +57,21 @@ class Limits(C.Structure):
 class AdamGroup(C.Structure):
     _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
                 ("n", C.c_int64), ("lr", C.c_float)]
+
+
+HASH_MAX_LEVELS = 16
+
+
+class HashField(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("features", C.c_int32), ("log2_table", C.c_int32), ("hidden", C.c_int32),
+                ("res", C.c_int32 * HASH_MAX_LEVELS), ("aabb_min", C.c_float * 3), ("aabb_max", C.c_float * 3),
+                ("table", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p),
+                ("b2", C.c_void_p)]
+
+
+class HashFieldGrads(C.Structure):
+    _fields_ = [("table", C.c_void_p), ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p),
+                ("b2", C.c_void_p)]
 
 
 _lib = None
@@ -101,6 +116,9 @@ def lib():
             "dass_profile_begin": (i32, [vp, i32]),
             "dass_profile_end": (i32, [vp, P(C.c_double), P(i32)]),
             "dass_debug_pair_counts": (i32, [vp, P(u64), P(u64)]),
+            "dass_hash_field_fwd": (i32, [vp, P(HashField), vp, i64, i32, vp, i32, vp, vp, i64, vp]),
+            "dass_hash_field_bwd": (i32, [vp, P(HashField), vp, i64, i32, vp, i32, vp, vp, i64, P(HashFieldGrads),
+                                          vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

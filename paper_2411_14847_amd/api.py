@@ -136,6 +136,70 @@ def keys_needed_estimate(n_gaussians: int, n_views: int, tiles_per_gaussian: flo
     return int(n_gaussians * n_views * tiles_per_gaussian)
 
 
+def geometric_res(n_min: int, n_max: int, levels: int) -> list:
+    """Level resolutions from n_min to n_max in a geometric progression, floored (top level exact)."""
+    if levels == 1:
+        return [int(n_min)]
+    return [int(np.floor(n_min * (n_max / n_min) ** (l / (levels - 1)) + 1e-9)) for l in range(levels)]
+
+
+@dataclass
+class HashField:
+    """Device parameters of one hash-encoded deformation field (dass_hash_field)."""
+    res: list
+    features: int
+    log2_table: int
+    hidden: int
+    aabb_min: tuple
+    aabb_max: tuple
+    table: torch.Tensor  # (L, T, F)
+    w1: torch.Tensor     # (hidden, L*F)
+    b1: torch.Tensor     # (hidden,)
+    w2: torch.Tensor     # (7, hidden)
+    b2: torch.Tensor     # (7,)
+
+    @property
+    def levels(self) -> int:
+        return len(self.res)
+
+    def arrays(self):
+        return (self.table, self.w1, self.b1, self.w2, self.b2)
+
+    def zeros_like(self) -> "HashField":
+        return HashField(list(self.res), self.features, self.log2_table, self.hidden, self.aabb_min, self.aabb_max,
+                         *[torch.zeros_like(t) for t in self.arrays()])
+
+    def struct(self) -> F.HashField:
+        L = self.levels
+        r = (list(self.res) + [0] * F.HASH_MAX_LEVELS)[:F.HASH_MAX_LEVELS]  # levels > 16: refused by the library
+        res = (C.c_int32 * F.HASH_MAX_LEVELS)(*r)
+        return F.HashField(L, int(self.features), int(self.log2_table), int(self.hidden), res,
+                           (C.c_float * 3)(*self.aabb_min), (C.c_float * 3)(*self.aabb_max),
+                           *[_ptr(t) for t in self.arrays()])
+
+    @staticmethod
+    def from_numpy(p, device) -> "HashField":
+        """From host arrays (an object with res, features, log2_table, hidden, aabb_min, aabb_max,
+        table, w1, b1, w2, b2)."""
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(device)
+        return HashField(list(p.res), int(p.features), int(p.log2_table), int(p.hidden),
+                         tuple(float(x) for x in p.aabb_min), tuple(float(x) for x in p.aabb_max),
+                         t(p.table), t(p.w1), t(p.b1), t(p.w2), t(p.b2))
+
+    @staticmethod
+    def init(res, features, log2_table, hidden, aabb_min, aabb_max, device, seed=0, table_scale=1e-4):
+        """A fresh field: table entries uniform in +-table_scale, a He-normal first layer, zero
+        biases and a zero output layer (the identity shift)."""
+        g = torch.Generator(device="cpu").manual_seed(int(seed))
+        L, lf = len(res), len(res) * features
+        table = (torch.rand(L, 1 << log2_table, features, generator=g) * 2 - 1) * table_scale
+        w1 = torch.randn(hidden, lf, generator=g) * float(np.sqrt(2.0 / lf))
+        return HashField(list(res), int(features), int(log2_table), int(hidden), tuple(map(float, aabb_min)),
+                         tuple(map(float, aabb_max)), table.to(device), w1.to(device),
+                         torch.zeros(hidden, device=device), torch.zeros(7, hidden, device=device),
+                         torch.zeros(7, device=device))
+
+
 class Context:
     """One libdass context (device workspace + state of the last render_fwd)."""
 
@@ -250,6 +314,25 @@ class Context:
         self._check(self._lib.shift_apply(self._h, F.DASS_ADJOINT, _ptr(dyn_idx), int(dyn_idx.numel()), None,
                                           _ptr(drot), C.byref(gs), None, C.byref(gr), _ptr(d_dpos), _ptr(d_drot),
                                           _stream(stream)))
+
+    def hash_field_fwd(self, field: "HashField", mean: torch.Tensor, n: int, idx: Optional[torch.Tensor],
+                       m: int, dpos: torch.Tensor, drot: torch.Tensor, stream=None):
+        """Offsets of the field at rows idx (or rows [0, m)) of mean (3, stride): columns [0, m)
+        of dpos (3, ld) and drot (4, ld)."""
+        fs = field.struct()
+        self._check(self._lib.dass_hash_field_fwd(self._h, C.byref(fs), _ptr(mean), int(mean.shape[1]), int(n),
+                                                  _ptr(idx), int(m), _ptr(dpos), _ptr(drot), int(dpos.shape[1]),
+                                                  _stream(stream)))
+
+    def hash_field_bwd(self, field: "HashField", mean: torch.Tensor, n: int, idx: Optional[torch.Tensor], m: int,
+                       d_dpos: torch.Tensor, d_drot: torch.Tensor, grads: "HashField", stream=None):
+        """Accumulates the field's parameter gradients into the arrays of `grads` (a HashField of
+        the same shapes) from d_dpos (3, ld), d_drot (4, ld)."""
+        fs = field.struct()
+        gs = F.HashFieldGrads(*[_ptr(t) for t in grads.arrays()])
+        self._check(self._lib.dass_hash_field_bwd(self._h, C.byref(fs), _ptr(mean), int(mean.shape[1]), int(n),
+                                                  _ptr(idx), int(m), _ptr(d_dpos), _ptr(d_drot),
+                                                  int(d_dpos.shape[1]), C.byref(gs), _stream(stream)))
 
     @staticmethod
     def _adam_groups(groups):

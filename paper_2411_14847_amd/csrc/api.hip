@@ -165,6 +165,7 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.counters, 16);
   ALLOC(w.pairs, 2);
   ALLOC(w.loss_slots, kLossSlots);
+  ALLOC(w.field_part, (size_t)kFieldMaxBlocks * field_part_stride(64, 64));
   ALLOC(w.err, 1);
 #undef ALLOC
   w.gid_s = w.dval[0];
@@ -532,6 +533,84 @@ dass_status shift_apply(dass_ctx ctx, int32_t mode, const int32_t* dyn_idx, int3
     return fail(ctx, DASS_E_INVALID, "mode must be DASS_FWD or DASS_ADJOINT");
   }
   return check_launch(ctx, "shift_apply");
+}
+
+static dass_status field_args(dass_ctx ctx, const dass_hash_field* f, const float* mean, int64_t stride, int32_t n,
+                              const int32_t* idx, int32_t m, int64_t ld, FieldK& fk, QueryK& qk) {
+  if (!f) return fail(ctx, DASS_E_INVALID, "field is NULL");
+  const int L = f->levels, F = f->features;
+  if (L < 1 || L > DASS_HASH_MAX_LEVELS) return fail(ctx, DASS_E_INVALID, "levels %d outside [1, 16]", L);
+  if (F != 1 && F != 2 && F != 4 && F != 8) return fail(ctx, DASS_E_INVALID, "features %d not 1, 2, 4 or 8", F);
+  if (L * F > 64) return fail(ctx, DASS_E_INVALID, "levels * features = %d > 64", L * F);
+  if (f->log2_table < 4 || f->log2_table > 24)
+    return fail(ctx, DASS_E_INVALID, "log2_table %d outside [4, 24]", f->log2_table);
+  if (f->hidden != 32 && f->hidden != 64) return fail(ctx, DASS_E_INVALID, "hidden %d not 32 or 64", f->hidden);
+  if (!f->table || !f->w1 || !f->b1 || !f->w2 || !f->b2) return fail(ctx, DASS_E_INVALID, "a field array is NULL");
+  fk = FieldK{};
+  fk.table = f->table;
+  fk.w1 = f->w1;
+  fk.b1 = f->b1;
+  fk.w2 = f->w2;
+  fk.b2 = f->b2;
+  fk.L = L;
+  fk.log2T = f->log2_table;
+  const int64_t T = int64_t(1) << f->log2_table;
+  for (int l = 0; l < L; l++) {
+    const int64_t N = f->res[l];
+    if (N < 1 || N > (1 << 20)) return fail(ctx, DASS_E_INVALID, "res[%d] = %lld outside [1, 2^20]", l, (long long)N);
+    fk.res[l] = (int)N;
+    if ((N + 1) * (N + 1) * (N + 1) <= T) fk.dense |= 1u << l;
+  }
+  for (int d = 0; d < 3; d++) {
+    const float lo = f->aabb_min[d], hi = f->aabb_max[d];
+    if (!(std::isfinite(lo) && std::isfinite(hi) && hi > lo))
+      return fail(ctx, DASS_E_INVALID, "aabb axis %d: need finite min < max", d);
+    fk.lo[d] = lo;
+    fk.ext[d] = hi - lo;
+  }
+  if (m < 0 || n < 0) return fail(ctx, DASS_E_INVALID, "m %d or n %d negative", m, n);
+  if (stride < n) return fail(ctx, DASS_E_INVALID, "stride < n");
+  if (ld < m) return fail(ctx, DASS_E_INVALID, "ld < m");
+  if (!idx && m > n) return fail(ctx, DASS_E_INVALID, "idx NULL needs m <= n");
+  if (m > 0 && !mean) return fail(ctx, DASS_E_INVALID, "mean is NULL");
+  qk = QueryK{mean, stride, n, idx, m, ld};
+  return DASS_OK;
+}
+
+dass_status dass_hash_field_fwd(dass_ctx ctx, const dass_hash_field* field, const float* mean, int64_t stride,
+                                int32_t n, const int32_t* idx, int32_t m, float* dpos, float* drot, int64_t ld,
+                                dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  FieldK fk;
+  QueryK qk;
+  dass_status s;
+  if ((s = field_args(ctx, field, mean, stride, n, idx, m, ld, fk, qk)) != DASS_OK) return s;
+  if (m > 0 && (!dpos || !drot)) return fail(ctx, DASS_E_INVALID, "dpos or drot is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  stage_begin(ctx, DASS_STAGE_FIELD, st);
+  launch_field_fwd(fk, field->features, field->hidden, qk, dpos, drot, st);
+  stage_end(ctx, DASS_STAGE_FIELD, st);
+  return check_launch(ctx, "dass_hash_field_fwd");
+}
+
+dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, const float* mean, int64_t stride,
+                                int32_t n, const int32_t* idx, int32_t m, const float* d_dpos, const float* d_drot,
+                                int64_t ld, const dass_hash_field_grads* grads, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  FieldK fk;
+  QueryK qk;
+  dass_status s;
+  if ((s = field_args(ctx, field, mean, stride, n, idx, m, ld, fk, qk)) != DASS_OK) return s;
+  if (!grads) return fail(ctx, DASS_E_INVALID, "grads is NULL");
+  if (m > 0 && (!d_dpos || !d_drot)) return fail(ctx, DASS_E_INVALID, "d_dpos or d_drot is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const FieldGradsK gk{grads->table, grads->w1, grads->b1, grads->w2, grads->b2};
+  stage_begin(ctx, DASS_STAGE_FIELD, st);
+  launch_field_bwd(fk, field->features, field->hidden, qk, d_dpos, d_drot, gk, ctx->ws.field_part, st);
+  stage_end(ctx, DASS_STAGE_FIELD, st);
+  return check_launch(ctx, "dass_hash_field_bwd");
 }
 
 static dass_status adam_impl(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,

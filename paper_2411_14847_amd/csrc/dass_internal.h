@@ -79,6 +79,41 @@ struct Rec {
 };
 
 // ---- workspace -------------------------------------------------------------------------
+// ---- hash-encoded deformation fields (field.hip) ----------------------------------------
+constexpr int kFieldMaxLevels = 16;
+constexpr int kFieldMaxBlocks = 768;  // workgroups of the field backward (one partial row each)
+struct FieldK {
+  const float* table;  // [L][2^log2T][F]
+  const float* w1;     // [hidden][L*F]
+  const float* b1;     // [hidden]
+  const float* w2;     // [7][hidden]
+  const float* b2;     // [7]
+  int res[kFieldMaxLevels];
+  uint32_t dense;      // bit l: level l indexed densely ((N_l + 1)^3 <= T), else hashed
+  int L, log2T;
+  float lo[3], ext[3];
+};
+struct QueryK {
+  const float* mean;  // [3][stride]
+  int64_t stride;
+  int n;              // rows [0, n) are valid queries
+  const int32_t* idx; // [m] rows, or NULL for rows [0, m)
+  int m;
+  int64_t ld;         // column stride of the offsets / their gradients
+};
+struct FieldGradsK {
+  float* table;
+  float* w1;
+  float* b1;
+  float* w2;
+  float* b2;
+};
+__host__ __device__ constexpr int field_part_stride(int hidden, int lf) { return hidden * lf + 8 * hidden + 7; }
+void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float* dpos, float* drot,
+                      hipStream_t st);
+void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
+                      const float* d_drot, const FieldGradsK& g, float* part, hipStream_t st);
+
 struct Workspace {
   int64_t cap_vn = 0;     // max views * max gaussians
   int64_t cap_keys = 0;
@@ -108,6 +143,7 @@ struct Workspace {
   uint32_t* counters = nullptr;    // [0] = key count (clamped), [1] = densify |S|, [2] = depth-sort count
   unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
   float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
+  float* field_part = nullptr;          // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
   uint32_t* err = nullptr;         // device error bits
 };
 

@@ -1,0 +1,323 @@
+// Hash-encoded deformation fields H_dyn / H_st (Sec. 3.3; table sizes in App. B): a
+// multi-resolution hash encoding of a Gaussian's normalised position followed by an MLP with
+// one ReLU hidden layer and seven outputs, the position offset (3) and the rotation offset (4,
+// added to the identity quaternion).
+//
+// Forward: one query per lane; the encoding (L levels x 8 corners, one F-float row each) sits in
+// registers and the weights are read with wave-uniform addresses.
+// Backward: one wave per workgroup, looping over chunks of 64 queries.  Lanes are queries while
+// the encoding and the MLP adjoint are recomputed (table gradients leave as float atomics, one
+// per corner and feature); then lanes are hidden units and sum the chunk's weight gradients
+// from LDS into registers that live across chunks.  Each workgroup writes its sums once and a
+// second kernel adds the workgroups' partials in a fixed order.
+#include "dass_internal.h"
+
+namespace dass {
+namespace {
+
+constexpr uint32_t kPrimeY = 2654435761u;  // the encoding's spatial-hash primes (x: 1)
+constexpr uint32_t kPrimeZ = 805459861u;
+constexpr int kFwdThreads = 256;
+
+template <int F>
+constexpr int max_levels() { return (64 / F) < kFieldMaxLevels ? 64 / F : kFieldMaxLevels; }
+
+template <int F>
+__device__ __forceinline__ void load_row(const float* __restrict__ p, float* v) {
+  if constexpr (F == 1) {
+    v[0] = p[0];
+  } else if constexpr (F == 2) {
+    const float2 a = *reinterpret_cast<const float2*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < F; i += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(p + i);
+      v[i] = a.x;
+      v[i + 1] = a.y;
+      v[i + 2] = a.z;
+      v[i + 3] = a.w;
+    }
+  }
+}
+
+__device__ __forceinline__ void normalised(const FieldK& f, const QueryK& q, int g, float p[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float x = (q.mean[d * q.stride + g] - f.lo[d]) / f.ext[d];
+    p[d] = fminf(fmaxf(x, 0.f), 1.f);  // NaN -> 0
+  }
+}
+
+// Calls fn(level, float offset of the corner's row in the table, trilinear weight) for the 8
+// corners of each level's cell around p.
+template <int F, class Fn>
+__device__ __forceinline__ void for_corners(const FieldK& f, const float p[3], Fn&& fn) {
+  constexpr int KL = max_levels<F>();
+  const uint32_t mask = (1u << f.log2T) - 1u;
+#pragma unroll
+  for (int l = 0; l < KL; ++l) {
+    if (l < f.L) {
+      const int N = f.res[l];
+      int c[3];
+      float fr[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float x = p[d] * (float)N;
+        c[d] = min((int)floorf(x), N - 1);
+        fr[d] = x - (float)c[d];
+      }
+      const bool dense = (f.dense >> l) & 1u;
+      const size_t base = (size_t)l << f.log2T;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t x = (uint32_t)(c[0] + (k & 1)), y = (uint32_t)(c[1] + ((k >> 1) & 1)),
+                       z = (uint32_t)(c[2] + ((k >> 2) & 1));
+        const uint32_t row = dense ? x + (uint32_t)(N + 1) * (y + (uint32_t)(N + 1) * z)
+                                   : (x ^ (y * kPrimeY) ^ (z * kPrimeZ)) & mask;
+        const float w = ((k & 1) ? fr[0] : 1.f - fr[0]) * ((k & 2) ? fr[1] : 1.f - fr[1]) *
+                        ((k & 4) ? fr[2] : 1.f - fr[2]);
+        fn(l, (base + row) * F, w);
+      }
+    }
+  }
+}
+
+template <int F>
+__device__ __forceinline__ void encode(const FieldK& f, const float p[3], float* enc) {
+  constexpr int KL = max_levels<F>();
+#pragma unroll
+  for (int i = 0; i < KL * F; ++i) enc[i] = 0.f;
+  for_corners<F>(f, p, [&](int l, size_t off, float w) {
+    float v[F];
+    load_row<F>(f.table + off, v);
+#pragma unroll
+    for (int i = 0; i < F; ++i) enc[l * F + i] = fmaf(w, v[i], enc[l * F + i]);
+  });
+}
+
+// pre-activation of hidden unit h: b1[h] + W1[h] . enc (levels beyond L hold zeros)
+template <int F>
+__device__ __forceinline__ float hidden_pre(const FieldK& f, int h, int LF, const float* enc) {
+  constexpr int KL = max_levels<F>();
+  const float* __restrict__ w = f.w1 + h * LF;
+  float a = f.b1[h];
+#pragma unroll
+  for (int l = 0; l < KL; ++l)
+    if (l < f.L) {
+#pragma unroll
+      for (int i = 0; i < F; ++i) a = fmaf(w[l * F + i], enc[l * F + i], a);
+    }
+  return a;
+}
+
+template <int F, int HID>
+__global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const QueryK q,
+                                                           float* __restrict__ dpos, float* __restrict__ drot) {
+  constexpr int KL = max_levels<F>();
+  const int j = blockIdx.x * kFwdThreads + threadIdx.x;
+  if (j >= q.m) return;
+  const int g = q.idx ? q.idx[j] : j;
+  float out[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (g >= 0 && g < q.n) {
+    float p[3];
+    normalised(f, q, g, p);
+    float enc[KL * F];
+    encode<F>(f, p, enc);
+    const int LF = f.L * F;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) out[o] = f.b2[o];
+    for (int h = 0; h < HID; ++h) {
+      const float a = fmaxf(hidden_pre<F>(f, h, LF, enc), 0.f);
+#pragma unroll
+      for (int o = 0; o < 7; ++o) out[o] = fmaf(f.w2[o * HID + h], a, out[o]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) dpos[d * q.ld + j] = out[d];
+  drot[j] = 1.f + out[3];
+#pragma unroll
+  for (int d = 1; d < 4; ++d) drot[d * q.ld + j] = out[3 + d];
+}
+
+template <int F, int HID>
+__global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q, const float* __restrict__ d_dpos,
+                                                  const float* __restrict__ d_drot, float* __restrict__ gtable,
+                                                  float* __restrict__ part, int chunks) {
+  constexpr int KL = max_levels<F>();
+  constexpr int LFM = KL * F;
+  __shared__ float s_enc[64][LFM + 1];
+  __shared__ float s_dp[64][HID + 1];
+  __shared__ float s_h[64][HID + 1];
+  __shared__ float s_do[64][8];
+  const int lane = threadIdx.x;
+  const int LF = f.L * F;
+  float aw1[LFM], aw2[7], ab1 = 0.f, ab2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < LFM; ++i) aw1[i] = 0.f;
+#pragma unroll
+  for (int o = 0; o < 7; ++o) aw2[o] = 0.f;
+
+  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
+    // ---- lanes = queries: encoding, MLP adjoint, table scatter
+    const int j = c * 64 + lane;
+    int g = -1;
+    if (j < q.m) {
+      g = q.idx ? q.idx[j] : j;
+      if (g < 0 || g >= q.n) g = -1;
+    }
+    float p[3] = {0.f, 0.f, 0.f}, dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float enc[LFM];
+#pragma unroll
+    for (int i = 0; i < LFM; ++i) enc[i] = 0.f;
+    if (g >= 0) {
+      normalised(f, q, g, p);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dout[d] = d_dpos[d * q.ld + j];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) dout[3 + d] = d_drot[d * q.ld + j];
+      encode<F>(f, p, enc);
+    }
+#pragma unroll
+    for (int i = 0; i < LFM; ++i) s_enc[lane][i] = enc[i];
+#pragma unroll
+    for (int o = 0; o < 7; ++o) s_do[lane][o] = dout[o];
+    float denc[LFM];
+#pragma unroll
+    for (int i = 0; i < LFM; ++i) denc[i] = 0.f;
+    for (int h = 0; h < HID; ++h) {
+      const float a = hidden_pre<F>(f, h, LF, enc);
+      float dh = 0.f;
+#pragma unroll
+      for (int o = 0; o < 7; ++o) dh = fmaf(f.w2[o * HID + h], dout[o], dh);
+      const float dp = a > 0.f ? dh : 0.f;
+      s_dp[lane][h] = dp;
+      s_h[lane][h] = fmaxf(a, 0.f);
+      const float* __restrict__ w = f.w1 + h * LF;
+#pragma unroll
+      for (int l = 0; l < KL; ++l)
+        if (l < f.L) {
+#pragma unroll
+          for (int i = 0; i < F; ++i) denc[l * F + i] = fmaf(w[l * F + i], dp, denc[l * F + i]);
+        }
+    }
+    if (g >= 0 && gtable) {
+      for_corners<F>(f, p, [&](int l, size_t off, float w) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) atomicAdd(gtable + off + i, w * denc[l * F + i]);
+      });
+    }
+    __syncthreads();
+    // ---- lanes = hidden units: weight-gradient sums over the chunk's queries
+    if (lane < HID) {
+      for (int s = 0; s < 64; ++s) {
+        const float dp = s_dp[s][lane], hv = s_h[s][lane];
+        ab1 += dp;
+#pragma unroll
+        for (int l = 0; l < KL; ++l)
+          if (l < f.L) {
+#pragma unroll
+            for (int i = 0; i < F; ++i) aw1[l * F + i] = fmaf(dp, s_enc[s][l * F + i], aw1[l * F + i]);
+          }
+#pragma unroll
+        for (int o = 0; o < 7; ++o) aw2[o] = fmaf(s_do[s][o], hv, aw2[o]);
+      }
+    }
+    if (lane < 7)
+      for (int s = 0; s < 64; ++s) ab2 += s_do[s][lane];
+    __syncthreads();
+  }
+
+  // partial sums of this workgroup: [w1: HID][LF] [b1: HID] [w2: 7][HID] [b2: 7]
+  float* P = part + (size_t)blockIdx.x * field_part_stride(HID, LF);
+  if (lane < HID) {
+#pragma unroll
+    for (int l = 0; l < KL; ++l)
+      if (l < f.L) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) P[lane * LF + l * F + i] = aw1[l * F + i];
+      }
+    P[HID * LF + lane] = ab1;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) P[HID * LF + HID + o * HID + lane] = aw2[o];
+  }
+  if (lane < 7) P[HID * LF + HID + 7 * HID + lane] = ab2;
+}
+
+// grad += sum over the workgroups' partials (fixed order); column c of the partial rows
+__global__ __launch_bounds__(256) void k_field_reduce(const float* __restrict__ part, int rows, int stride,
+                                                      int n_w1, int hid, float* __restrict__ gw1,
+                                                      float* __restrict__ gb1, float* __restrict__ gw2,
+                                                      float* __restrict__ gb2) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= stride) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += part[(size_t)r * stride + c];
+  float* dst;
+  int i;
+  if (c < n_w1) {
+    dst = gw1;
+    i = c;
+  } else if (c < n_w1 + hid) {
+    dst = gb1;
+    i = c - n_w1;
+  } else if (c < n_w1 + hid + 7 * hid) {
+    dst = gw2;
+    i = c - n_w1 - hid;
+  } else {
+    dst = gb2;
+    i = c - n_w1 - 8 * hid;
+  }
+  if (dst) dst[i] += s;
+}
+
+template <int HID>
+void fwd_f(int F, const FieldK& f, const QueryK& q, float* dpos, float* drot, hipStream_t st) {
+  const int blocks = (q.m + kFwdThreads - 1) / kFwdThreads;
+  switch (F) {
+    case 1: k_field_fwd<1, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
+    case 2: k_field_fwd<2, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
+    case 4: k_field_fwd<4, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
+    default: k_field_fwd<8, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
+  }
+}
+
+template <int HID>
+void bwd_f(int F, int blocks, int chunks, const FieldK& f, const QueryK& q, const float* d_dpos,
+           const float* d_drot, float* gtable, float* part, hipStream_t st) {
+  switch (F) {
+    case 1: k_field_bwd<1, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
+    case 2: k_field_bwd<2, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
+    case 4: k_field_bwd<4, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
+    default: k_field_bwd<8, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
+  }
+}
+
+}  // namespace
+
+void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float* dpos, float* drot,
+                      hipStream_t st) {
+  if (q.m <= 0) return;
+  if (hidden == 32)
+    fwd_f<32>(F, f, q, dpos, drot, st);
+  else
+    fwd_f<64>(F, f, q, dpos, drot, st);
+}
+
+void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
+                      const float* d_drot, const FieldGradsK& g, float* part, hipStream_t st) {
+  if (q.m <= 0) return;
+  const int chunks = (q.m + 63) / 64;
+  const int blocks = chunks < kFieldMaxBlocks ? chunks : kFieldMaxBlocks;
+  if (hidden == 32)
+    bwd_f<32>(F, blocks, chunks, f, q, d_dpos, d_drot, g.table, part, st);
+  else
+    bwd_f<64>(F, blocks, chunks, f, q, d_dpos, d_drot, g.table, part, st);
+  const int LF = f.L * F;
+  const int stride = field_part_stride(hidden, LF);
+  k_field_reduce<<<(stride + 255) / 256, 256, 0, st>>>(part, blocks, stride, hidden * LF, hidden, g.w1, g.b1,
+                                                        g.w2, g.b2);
+}
+
+}  // namespace dass
