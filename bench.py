@@ -98,6 +98,8 @@ def build_workload(args):
         name = f"multiview_{args.n // 1000}k_sh3_{args.views}x{args.width}x{args.height}"
         if getattr(args, "ssim_lambda", 0.0) > 0.0:
             name += f"_dssim{args.ssim_lambda:g}"
+        if getattr(args, "shift", "direct") == "hash":
+            name += "_hashfields"
     else:
         scene, cams, _ = synth.single_view_scene(args.seed)
         name = "single_view_2k_sh0_128x128"
@@ -135,12 +137,40 @@ def build_workload(args):
         v=[torch.zeros(3, nd, device=dev), torch.zeros(4, nd, device=dev)],
         n_app=torch.zeros(1, dtype=torch.int32, device=dev), nd=nd, N=N, cap=cap,
     )
+    if getattr(args, "shift", "direct") == "hash":
+        # H_dyn over the dynamic rows, H_st over the static ones (N3DV table sizes, App. B); offsets
+        # laid out [dynamic | static] over all N base rows
+        from paper_2411_14847_amd import HashField, geometric_res
+        import numpy as np
+        st_rows = np.setdiff1d(np.arange(N, dtype=np.int32), motion.dynamic).astype(np.int32)
+        rows = torch.as_tensor(np.concatenate([motion.dynamic, st_rows]).astype(np.int32), device=dev)
+        lo = (scene.mean.min(axis=1) - 0.1).tolist()
+        hi = (scene.mean.max(axis=1) + 0.1).tolist()
+        fields = {"dyn": HashField.init(geometric_res(16, 2048, 16), 4, 16, 64, lo, hi, dev, seed=1),
+                  "st": HashField.init(geometric_res(16, 2048, 16), 2, 14, 64, lo, hi, dev, seed=2)}
+        for f in fields.values():  # a field part-way through its optimisation: a non-zero output layer
+            f.w2.normal_(0.0, 1e-3)
+        st.update(rows=rows, dyn_rows=rows[:nd], st_rows=rows[nd:], ns=N - nd, fields=fields,
+                  field_grads={k: f.zeros_like() for k, f in fields.items()},
+                  field_mv={k: (f.zeros_like(), f.zeros_like()) for k, f in fields.items()},
+                  dpos=torch.zeros(3, N, device=dev), drot=torch.cat([torch.ones(1, N), torch.zeros(3, N)]).to(dev),
+                  d_dpos=torch.zeros(3, N, device=dev), d_drot=torch.zeros(4, N, device=dev))
     return st
 
 
 def train_step(s, it, args, per_view=False):
     ctx, g, gs, cams = s["ctx"], s["g"], s["gs"], s["cams"]
-    ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
+    fields = s.get("fields")
+    if fields:
+        nd, ns = s["nd"], s["ns"]
+        ctx.hash_field_fwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["dpos"], s["drot"], col=0)
+        ctx.hash_field_fwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["dpos"], s["drot"], col=nd)
+        ctx.shift_fwd(g, gs, s["rows"], s["dpos"], s["drot"])
+        for f in s["field_grads"].values():
+            for t in f.arrays():
+                t.zero_()
+    else:
+        ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
     for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
         t.zero_()
     lam = getattr(args, "ssim_lambda", 0.0)
@@ -170,9 +200,22 @@ def train_step(s, it, args, per_view=False):
             s["dls"][v].mul_(1.0 / V)
             ctx.render_bwd(gs, cams[v:v + 1], args.bg, s["outs"][v:v + 1], s["dls"][v:v + 1], s["grads"], s["gn"],
                            s["cnt"])
-    ctx.shift_adjoint(g, s["dyn"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
-    ctx.adam_step([(s["dpos"], s["d_dpos"], s["m"][0], s["v"][0], args.lr_pos),
-                   (s["drot"], s["d_drot"], s["m"][1], s["v"][1], args.lr_rot)], step=it)
+    if fields:
+        ctx.shift_adjoint(g, s["rows"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
+        ctx.hash_field_bwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["d_dpos"], s["d_drot"],
+                           s["field_grads"]["dyn"], col=0)
+        ctx.hash_field_bwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["d_dpos"], s["d_drot"],
+                           s["field_grads"]["st"], col=nd)
+        groups = []
+        for k, f in fields.items():
+            m, v = s["field_mv"][k]
+            groups += [(p, gr, mm, vv, args.lr_field) for p, gr, mm, vv in
+                       zip(f.arrays(), s["field_grads"][k].arrays(), m.arrays(), v.arrays())]
+        ctx.adam_step(groups, step=it)
+    else:
+        ctx.shift_adjoint(g, s["dyn"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
+        ctx.adam_step([(s["dpos"], s["d_dpos"], s["m"][0], s["v"][0], args.lr_pos),
+                       (s["drot"], s["d_drot"], s["m"][1], s["v"][1], args.lr_rot)], step=it)
     ctx.densify_append(g, s["errs"], cams, s["gn"], s["cnt"], 0.0, 0.0, 0.0, args.densify_k, it, s["n_app"])
 
 
@@ -585,6 +628,10 @@ def main():
     ap.add_argument("--densify-k", type=int, default=5000)
     ap.add_argument("--ssim-lambda", type=float, default=0.0,
                     help="weight of the D-SSIM term of the fidelity loss (Eq. 3); 0 = L1 only")
+    ap.add_argument("--shift", choices=["direct", "hash"], default="direct",
+                    help="shift offsets: per-Gaussian for the dynamic group (direct), or produced by the "
+                         "H_dyn / H_st hash-encoded deformation fields over every base Gaussian (Sec. 3.3)")
+    ap.add_argument("--lr-field", type=float, default=2e-3)
     ap.add_argument("--max-keys", type=int, default=0)
     ap.add_argument("--lr-pos", type=float, default=1e-3)
     ap.add_argument("--lr-rot", type=float, default=1e-3)
@@ -716,6 +763,8 @@ def main():
                    "tile": tile_name(ctx.tile),
                    "n_dynamic": s["nd"], "densify_k": args.densify_k,
                    "loss": "l1" if args.ssim_lambda == 0.0 else f"(1-l) L1 + l D-SSIM, l = {args.ssim_lambda}",
+                   "shift": ("direct offsets of the dynamic group" if args.shift == "direct" else
+                             "H_dyn (T 2^16, F 4) / H_st (T 2^14, F 2) hash fields, 16 levels, 64 hidden"),
                    "parallelism": "single GPU"},
         "tile_autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),

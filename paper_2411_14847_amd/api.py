@@ -315,24 +315,35 @@ class Context:
                                           _ptr(drot), C.byref(gs), None, C.byref(gr), _ptr(d_dpos), _ptr(d_drot),
                                           _stream(stream)))
 
+    @staticmethod
+    def _cols(t: torch.Tensor, col: int, m: int):
+        """Pointer to column `col` of a contiguous (rows, ld) float32 tensor holding m columns from there."""
+        if t.dtype != torch.float32 or t.dim() != 2:
+            raise ValueError("offset buffers are (rows, ld) float32 tensors")
+        if col < 0 or col + m > t.shape[1]:
+            raise ValueError(f"columns [{col}, {col + m}) outside a buffer of {t.shape[1]}")
+        p = _ptr(t)
+        return C.c_void_p(p.value + 4 * col) if p is not None else None
+
     def hash_field_fwd(self, field: "HashField", mean: torch.Tensor, n: int, idx: Optional[torch.Tensor],
-                       m: int, dpos: torch.Tensor, drot: torch.Tensor, stream=None):
-        """Offsets of the field at rows idx (or rows [0, m)) of mean (3, stride): columns [0, m)
-        of dpos (3, ld) and drot (4, ld)."""
+                       m: int, dpos: torch.Tensor, drot: torch.Tensor, col: int = 0, stream=None):
+        """Offsets of the field at rows idx (or rows [0, m)) of mean (3, stride): columns
+        [col, col + m) of dpos (3, ld) and drot (4, ld)."""
         fs = field.struct()
         self._check(self._lib.dass_hash_field_fwd(self._h, C.byref(fs), _ptr(mean), int(mean.shape[1]), int(n),
-                                                  _ptr(idx), int(m), _ptr(dpos), _ptr(drot), int(dpos.shape[1]),
-                                                  _stream(stream)))
+                                                  _ptr(idx), int(m), self._cols(dpos, col, m),
+                                                  self._cols(drot, col, m), int(dpos.shape[1]), _stream(stream)))
 
     def hash_field_bwd(self, field: "HashField", mean: torch.Tensor, n: int, idx: Optional[torch.Tensor], m: int,
-                       d_dpos: torch.Tensor, d_drot: torch.Tensor, grads: "HashField", stream=None):
+                       d_dpos: torch.Tensor, d_drot: torch.Tensor, grads: "HashField", col: int = 0, stream=None):
         """Accumulates the field's parameter gradients into the arrays of `grads` (a HashField of
-        the same shapes) from d_dpos (3, ld), d_drot (4, ld)."""
+        the same shapes) from columns [col, col + m) of d_dpos (3, ld), d_drot (4, ld)."""
         fs = field.struct()
         gs = F.HashFieldGrads(*[_ptr(t) for t in grads.arrays()])
         self._check(self._lib.dass_hash_field_bwd(self._h, C.byref(fs), _ptr(mean), int(mean.shape[1]), int(n),
-                                                  _ptr(idx), int(m), _ptr(d_dpos), _ptr(d_drot),
-                                                  int(d_dpos.shape[1]), C.byref(gs), _stream(stream)))
+                                                  _ptr(idx), int(m), self._cols(d_dpos, col, m),
+                                                  self._cols(d_drot, col, m), int(d_dpos.shape[1]), C.byref(gs),
+                                                  _stream(stream)))
 
     @staticmethod
     def _adam_groups(groups):

@@ -166,6 +166,10 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.pairs, 2);
   ALLOC(w.loss_slots, kLossSlots);
   ALLOC(w.field_part, (size_t)kFieldMaxBlocks * field_part_stride(64, 64));
+  w.cap_g = l.max_gaussians > 0 ? l.max_gaussians : 1;
+  ALLOC(w.field_denc, (size_t)64 * w.cap_g);
+  ALLOC(w.field_pn, (size_t)3 * w.cap_g);
+  ALLOC(w.field_tpart, (size_t)kFieldPartialFloats);
   ALLOC(w.err, 1);
 #undef ALLOC
   w.gid_s = w.dval[0];
@@ -566,7 +570,7 @@ static dass_status field_args(dass_ctx ctx, const dass_hash_field* f, const floa
     if (!(std::isfinite(lo) && std::isfinite(hi) && hi > lo))
       return fail(ctx, DASS_E_INVALID, "aabb axis %d: need finite min < max", d);
     fk.lo[d] = lo;
-    fk.ext[d] = hi - lo;
+    fk.ext[d] = (double)hi - (double)lo;
   }
   if (m < 0 || n < 0) return fail(ctx, DASS_E_INVALID, "m %d or n %d negative", m, n);
   if (stride < n) return fail(ctx, DASS_E_INVALID, "stride < n");
@@ -608,7 +612,11 @@ dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, cons
   hipStream_t st = (hipStream_t)stream;
   const FieldGradsK gk{grads->table, grads->w1, grads->b1, grads->w2, grads->b2};
   stage_begin(ctx, DASS_STAGE_FIELD, st);
-  launch_field_bwd(fk, field->features, field->hidden, qk, d_dpos, d_drot, gk, ctx->ws.field_part, st);
+  if (m > ctx->ws.cap_g)
+    return fail(ctx, DASS_E_CAPACITY, "m %d > max_gaussians %lld (the backward's per-query workspace)", m,
+                (long long)ctx->ws.cap_g);
+  const FieldScratch fs{ctx->ws.field_denc, ctx->ws.field_pn, ctx->ws.field_part, ctx->ws.field_tpart};
+  launch_field_bwd(fk, field->features, field->hidden, qk, d_dpos, d_drot, gk, fs, st);
   stage_end(ctx, DASS_STAGE_FIELD, st);
   return check_launch(ctx, "dass_hash_field_bwd");
 }

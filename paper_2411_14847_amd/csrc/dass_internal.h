@@ -91,7 +91,7 @@ struct FieldK {
   int res[kFieldMaxLevels];
   uint32_t dense;      // bit l: level l indexed densely ((N_l + 1)^3 <= T), else hashed
   int L, log2T;
-  float lo[3], ext[3];
+  double lo[3], ext[3];  // box minimum and extent (max - min, exact in float64)
 };
 struct QueryK {
   const float* mean;  // [3][stride]
@@ -108,11 +108,23 @@ struct FieldGradsK {
   float* w2;
   float* b2;
 };
+constexpr int64_t kFieldPartialFloats = int64_t(1) << 24;  // per-query-part table-gradient slices (64 MB)
+struct SliceMap {
+  int begin[kFieldMaxLevels];              // first slice of each level
+  int64_t level_floats[kFieldMaxLevels];   // floats of the level's table that can be touched
+  int n_slices, n_qparts, features;
+};
+struct FieldScratch {
+  float* denc;   // [64][max_gaussians] dL/d(encoding) per query, feature-major
+  double* pn;    // [3][max_gaussians] normalised query positions
+  float* part;   // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
+  float* tpart;  // [kFieldPartialFloats] table-gradient slices of the query parts
+};
 __host__ __device__ constexpr int field_part_stride(int hidden, int lf) { return hidden * lf + 8 * hidden + 7; }
 void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float* dpos, float* drot,
                       hipStream_t st);
 void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
-                      const float* d_drot, const FieldGradsK& g, float* part, hipStream_t st);
+                      const float* d_drot, const FieldGradsK& g, const FieldScratch& ws, hipStream_t st);
 
 struct Workspace {
   int64_t cap_vn = 0;     // max views * max gaussians
@@ -144,6 +156,10 @@ struct Workspace {
   unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
   float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
   float* field_part = nullptr;          // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
+  float* field_denc = nullptr;          // [64][cap_g] per-query dL/d(encoding) of the field backward
+  double* field_pn = nullptr;           // [3][cap_g] normalised query positions
+  float* field_tpart = nullptr;         // [kFieldPartialFloats] table-gradient slices of query parts
+  int64_t cap_g = 0;                    // queries per field call (max_gaussians)
   uint32_t* err = nullptr;         // device error bits
 };
 

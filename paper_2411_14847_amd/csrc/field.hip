@@ -5,11 +5,20 @@
 //
 // Forward: one query per lane; the encoding (L levels x 8 corners, one F-float row each) sits in
 // registers and the weights are read with wave-uniform addresses.
-// Backward: one wave per workgroup, looping over chunks of 64 queries.  Lanes are queries while
-// the encoding and the MLP adjoint are recomputed (table gradients leave as float atomics, one
-// per corner and feature); then lanes are hidden units and sum the chunk's weight gradients
-// from LDS into registers that live across chunks.  Each workgroup writes its sums once and a
-// second kernel adds the workgroups' partials in a fixed order.
+// Backward, three kernels:
+//  1. one wave per workgroup, looping over chunks of 64 queries.  Lanes are queries while the
+//     encoding and the MLP adjoint are recomputed; each query's dL/d(encoding) and normalised
+//     position go to a workspace.  Then lanes are hidden units and sum the chunk's weight
+//     gradients from LDS into registers that live across chunks; each workgroup writes its
+//     sums once.
+//  2. the workgroups' weight-gradient partials added in a fixed order.
+//  3. table gradients without global atomics: each workgroup owns one slice (up to 128 KB) of
+//     one level's table, accumulates every query's corner contributions that fall in it with
+//     LDS atomics, then adds the slice to the gradient.  (Float atomics to global memory from
+//     every query -- L x 8 x F per query -- ran at ~1.5e10 per second here, and many queries hit
+//     the same rows of the coarse levels.)
+#include <algorithm>
+
 #include "dass_internal.h"
 
 namespace dass {
@@ -17,7 +26,10 @@ namespace {
 
 constexpr uint32_t kPrimeY = 2654435761u;  // the encoding's spatial-hash primes (x: 1)
 constexpr uint32_t kPrimeZ = 805459861u;
-constexpr int kFwdThreads = 256;
+constexpr int kFwdThreads = 64;     // one wave: small query counts still spread over every CU
+constexpr int kSliceFloats = 32768;  // table-gradient slice held in LDS (128 KB)
+constexpr int kSliceThreads = 1024;
+constexpr int kSliceTargetBlocks = 512;
 
 template <int F>
 constexpr int max_levels() { return (64 / F) < kFieldMaxLevels ? 64 / F : kFieldMaxLevels; }
@@ -42,50 +54,59 @@ __device__ __forceinline__ void load_row(const float* __restrict__ p, float* v) 
   }
 }
 
-__device__ __forceinline__ void normalised(const FieldK& f, const QueryK& q, int g, float p[3]) {
+// The position in the box in float64: at the finest levels (N ~ 2^11) float32 rounding of the
+// normalisation would move a query by ~1e-4 cells and decide some cells differently.
+__device__ __forceinline__ void normalised(const FieldK& f, const QueryK& q, int g, double p[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float x = (q.mean[d * q.stride + g] - f.lo[d]) / f.ext[d];
-    p[d] = fminf(fmaxf(x, 0.f), 1.f);  // NaN -> 0
+    const double x = ((double)q.mean[d * q.stride + g] - f.lo[d]) / f.ext[d];
+    p[d] = fmin(fmax(x, 0.0), 1.0);  // NaN -> 0
+  }
+}
+
+// Calls fn(corner, row of the level's table, trilinear weight) for the 8 corners of level l's
+// cell around p.
+template <class Fn>
+__device__ __forceinline__ void level_corners(const FieldK& f, int l, const double p[3], Fn&& fn) {
+  const int N = f.res[l];
+  int c[3];
+  float fr[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double x = p[d] * (double)N;
+    c[d] = min((int)floor(x), N - 1);
+    fr[d] = (float)(x - (double)c[d]);
+  }
+  const bool dense = (f.dense >> l) & 1u;
+  const uint32_t mask = (1u << f.log2T) - 1u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t x = (uint32_t)(c[0] + (k & 1)), y = (uint32_t)(c[1] + ((k >> 1) & 1)),
+                   z = (uint32_t)(c[2] + ((k >> 2) & 1));
+    const uint32_t row = dense ? x + (uint32_t)(N + 1) * (y + (uint32_t)(N + 1) * z)
+                               : (x ^ (y * kPrimeY) ^ (z * kPrimeZ)) & mask;
+    const float w = ((k & 1) ? fr[0] : 1.f - fr[0]) * ((k & 2) ? fr[1] : 1.f - fr[1]) *
+                    ((k & 4) ? fr[2] : 1.f - fr[2]);
+    fn(k, row, w);
   }
 }
 
 // Calls fn(level, float offset of the corner's row in the table, trilinear weight) for the 8
 // corners of each level's cell around p.
 template <int F, class Fn>
-__device__ __forceinline__ void for_corners(const FieldK& f, const float p[3], Fn&& fn) {
+__device__ __forceinline__ void for_corners(const FieldK& f, const double p[3], Fn&& fn) {
   constexpr int KL = max_levels<F>();
-  const uint32_t mask = (1u << f.log2T) - 1u;
 #pragma unroll
   for (int l = 0; l < KL; ++l) {
     if (l < f.L) {
-      const int N = f.res[l];
-      int c[3];
-      float fr[3];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float x = p[d] * (float)N;
-        c[d] = min((int)floorf(x), N - 1);
-        fr[d] = x - (float)c[d];
-      }
-      const bool dense = (f.dense >> l) & 1u;
       const size_t base = (size_t)l << f.log2T;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint32_t x = (uint32_t)(c[0] + (k & 1)), y = (uint32_t)(c[1] + ((k >> 1) & 1)),
-                       z = (uint32_t)(c[2] + ((k >> 2) & 1));
-        const uint32_t row = dense ? x + (uint32_t)(N + 1) * (y + (uint32_t)(N + 1) * z)
-                                   : (x ^ (y * kPrimeY) ^ (z * kPrimeZ)) & mask;
-        const float w = ((k & 1) ? fr[0] : 1.f - fr[0]) * ((k & 2) ? fr[1] : 1.f - fr[1]) *
-                        ((k & 4) ? fr[2] : 1.f - fr[2]);
-        fn(l, (base + row) * F, w);
-      }
+      level_corners(f, l, p, [&](int, uint32_t row, float w) { fn(l, (base + row) * F, w); });
     }
   }
 }
 
 template <int F>
-__device__ __forceinline__ void encode(const FieldK& f, const float p[3], float* enc) {
+__device__ __forceinline__ void encode(const FieldK& f, const double p[3], float* enc) {
   constexpr int KL = max_levels<F>();
 #pragma unroll
   for (int i = 0; i < KL * F; ++i) enc[i] = 0.f;
@@ -121,7 +142,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const
   const int g = q.idx ? q.idx[j] : j;
   float out[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (g >= 0 && g < q.n) {
-    float p[3];
+    double p[3];
     normalised(f, q, g, p);
     float enc[KL * F];
     encode<F>(f, p, enc);
@@ -143,8 +164,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const
 
 template <int F, int HID>
 __global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q, const float* __restrict__ d_dpos,
-                                                  const float* __restrict__ d_drot, float* __restrict__ gtable,
-                                                  float* __restrict__ part, int chunks) {
+                                                  const float* __restrict__ d_drot, float* __restrict__ denc_out,
+                                                  double* __restrict__ p_out, float* __restrict__ part, int chunks) {
   constexpr int KL = max_levels<F>();
   constexpr int LFM = KL * F;
   __shared__ float s_enc[64][LFM + 1];
@@ -167,7 +188,8 @@ __global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q
       g = q.idx ? q.idx[j] : j;
       if (g < 0 || g >= q.n) g = -1;
     }
-    float p[3] = {0.f, 0.f, 0.f}, dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double p[3] = {0.0, 0.0, 0.0};
+    float dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float enc[LFM];
 #pragma unroll
     for (int i = 0; i < LFM; ++i) enc[i] = 0.f;
@@ -202,11 +224,15 @@ __global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q
           for (int i = 0; i < F; ++i) denc[l * F + i] = fmaf(w[l * F + i], dp, denc[l * F + i]);
         }
     }
-    if (g >= 0 && gtable) {
-      for_corners<F>(f, p, [&](int l, size_t off, float w) {
+    if (j < q.m) {  // feature-major [LF][m]; zeros for rows outside [0, n)
 #pragma unroll
-        for (int i = 0; i < F; ++i) atomicAdd(gtable + off + i, w * denc[l * F + i]);
-      });
+      for (int l = 0; l < KL; ++l)
+        if (l < f.L) {
+#pragma unroll
+          for (int i = 0; i < F; ++i) denc_out[(size_t)(l * F + i) * q.m + j] = denc[l * F + i];
+        }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p_out[(size_t)d * q.m + j] = p[d];
     }
     __syncthreads();
     // ---- lanes = hidden units: weight-gradient sums over the chunk's queries
@@ -245,15 +271,90 @@ __global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q
   if (lane < 7) P[HID * LF + HID + 7 * HID + lane] = ab2;
 }
 
-// grad += sum over the workgroups' partials (fixed order); column c of the partial rows
+// Level, first float and end of slice b of the table (slice_begin: prefix over levels).
+__device__ __forceinline__ void slice_of(const FieldK& f, const SliceMap& sm, int b, int& l, int64_t& lo,
+                                         int64_t& hi) {
+  l = 0;
+  while (l + 1 < f.L && sm.begin[l + 1] <= b) ++l;
+  lo = (int64_t)(b - sm.begin[l]) * kSliceFloats;
+  hi = min(lo + kSliceFloats, sm.level_floats[l]);
+}
+
+// Table gradient of one slice [lo, hi) (float offsets) of level l's table over the queries
+// [m q_part / n_qparts, m (q_part + 1) / n_qparts), with (slice, q_part) from the workgroup
+// index.  One query part: added to the gradient; several: written to partial[q_part][slice].
+template <int F>
+__global__ __launch_bounds__(kSliceThreads) void k_field_table_grad(const FieldK f, int m,
+                                                                   const double* __restrict__ pn,
+                                                                   const float* __restrict__ denc,
+                                                                   SliceMap sm, float* __restrict__ gtable,
+                                                                   float* __restrict__ partial) {
+  __shared__ float s_g[kSliceFloats];
+  const int b = blockIdx.x % sm.n_slices, qp = blockIdx.x / sm.n_slices;
+  int l;
+  int64_t lo, hi;
+  slice_of(f, sm, b, l, lo, hi);
+  const int q0 = (int)((int64_t)m * qp / sm.n_qparts), q1 = (int)((int64_t)m * (qp + 1) / sm.n_qparts);
+  for (int i = threadIdx.x; i < kSliceFloats; i += kSliceThreads) s_g[i] = 0.f;
+  __syncthreads();
+  for (int q = q0 + threadIdx.x; q < q1; q += kSliceThreads) {
+    double p[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p[d] = pn[(size_t)d * m + q];
+    float dv[F];
+#pragma unroll
+    for (int i = 0; i < F; ++i) dv[i] = denc[(size_t)(l * F + i) * m + q];
+    level_corners(f, l, p, [&](int, uint32_t row, float w) {
+      const int64_t off = (int64_t)row * F;
+      if (off >= lo && off < hi) {
+#pragma unroll
+        for (int i = 0; i < F; ++i) atomicAdd(&s_g[off - lo + i], w * dv[i]);
+      }
+    });
+  }
+  __syncthreads();
+  if (sm.n_qparts == 1) {
+    float* __restrict__ dst = gtable + ((size_t)l << f.log2T) * F + lo;
+    for (int i = threadIdx.x; i < hi - lo; i += kSliceThreads) dst[i] += s_g[i];
+  } else {
+    float* __restrict__ dst = partial + ((size_t)qp * sm.n_slices + b) * kSliceFloats;
+    for (int i = threadIdx.x; i < hi - lo; i += kSliceThreads) dst[i] = s_g[i];
+  }
+}
+
+// gradient += the query parts' partial slices, added in part order
+__global__ __launch_bounds__(256) void k_field_table_sum(const FieldK f, SliceMap sm, const float* __restrict__ partial,
+                                                         float* __restrict__ gtable) {
+  constexpr int kBlocksPerSlice = kSliceFloats / 256;
+  const int b = blockIdx.x / kBlocksPerSlice;
+  const int i = (blockIdx.x % kBlocksPerSlice) * 256 + threadIdx.x;
+  int l;
+  int64_t lo, hi;
+  slice_of(f, sm, b, l, lo, hi);
+  if (i >= hi - lo) return;
+  float s = 0.f;
+  for (int qp = 0; qp < sm.n_qparts; ++qp) s += partial[((size_t)qp * sm.n_slices + b) * kSliceFloats + i];
+  gtable[((size_t)l << f.log2T) * sm.features + lo + i] += s;
+}
+
+// grad += sum over the workgroups' partials (fixed order): a workgroup takes kRedCols columns,
+// its 8 row groups each sum every 8th partial row, then the groups are added in order.
+constexpr int kRedCols = 32;
 __global__ __launch_bounds__(256) void k_field_reduce(const float* __restrict__ part, int rows, int stride,
                                                       int n_w1, int hid, float* __restrict__ gw1,
                                                       float* __restrict__ gb1, float* __restrict__ gw2,
                                                       float* __restrict__ gb2) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= stride) return;
+  __shared__ float s_sum[8][kRedCols];
+  const int col = threadIdx.x % kRedCols, rg = threadIdx.x / kRedCols;
+  const int c = blockIdx.x * kRedCols + col;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += part[(size_t)r * stride + c];
+  if (c < stride)
+    for (int r = rg; r < rows; r += 8) s += part[(size_t)r * stride + c];
+  s_sum[rg][col] = s;
+  __syncthreads();
+  if (rg != 0 || c >= stride) return;
+  s = s_sum[0][col];
+  for (int k = 1; k < 8; ++k) s += s_sum[k][col];
   float* dst;
   int i;
   if (c < n_w1) {
@@ -285,12 +386,12 @@ void fwd_f(int F, const FieldK& f, const QueryK& q, float* dpos, float* drot, hi
 
 template <int HID>
 void bwd_f(int F, int blocks, int chunks, const FieldK& f, const QueryK& q, const float* d_dpos,
-           const float* d_drot, float* gtable, float* part, hipStream_t st) {
+           const float* d_drot, float* denc, double* pn, float* part, hipStream_t st) {
   switch (F) {
-    case 1: k_field_bwd<1, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
-    case 2: k_field_bwd<2, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
-    case 4: k_field_bwd<4, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
-    default: k_field_bwd<8, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, gtable, part, chunks); break;
+    case 1: k_field_bwd<1, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
+    case 2: k_field_bwd<2, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
+    case 4: k_field_bwd<4, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
+    default: k_field_bwd<8, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
   }
 }
 
@@ -306,18 +407,47 @@ void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float
 }
 
 void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
-                      const float* d_drot, const FieldGradsK& g, float* part, hipStream_t st) {
+                      const float* d_drot, const FieldGradsK& g, const FieldScratch& ws, hipStream_t st) {
   if (q.m <= 0) return;
   const int chunks = (q.m + 63) / 64;
   const int blocks = chunks < kFieldMaxBlocks ? chunks : kFieldMaxBlocks;
   if (hidden == 32)
-    bwd_f<32>(F, blocks, chunks, f, q, d_dpos, d_drot, g.table, part, st);
+    bwd_f<32>(F, blocks, chunks, f, q, d_dpos, d_drot, ws.denc, ws.pn, ws.part, st);
   else
-    bwd_f<64>(F, blocks, chunks, f, q, d_dpos, d_drot, g.table, part, st);
+    bwd_f<64>(F, blocks, chunks, f, q, d_dpos, d_drot, ws.denc, ws.pn, ws.part, st);
   const int LF = f.L * F;
   const int stride = field_part_stride(hidden, LF);
-  k_field_reduce<<<(stride + 255) / 256, 256, 0, st>>>(part, blocks, stride, hidden * LF, hidden, g.w1, g.b1,
-                                                        g.w2, g.b2);
+  k_field_reduce<<<(stride + kRedCols - 1) / kRedCols, 256, 0, st>>>(ws.part, blocks, stride, hidden * LF, hidden,
+                                                                    g.w1, g.b1, g.w2, g.b2);
+  if (g.table) {
+    SliceMap sm{};
+    int total = 0;
+    for (int l = 0; l < f.L; l++) {
+      const int64_t N1 = (int64_t)f.res[l] + 1;
+      const int64_t rows = ((f.dense >> l) & 1u) ? N1 * N1 * N1 : (int64_t(1) << f.log2T);
+      sm.begin[l] = total;
+      sm.level_floats[l] = rows * F;
+      total += (int)((rows * F + kSliceFloats - 1) / kSliceFloats);
+    }
+    // split the queries so that about kSliceTargetBlocks workgroups run, within the partial buffer
+    // and with at least kSliceThreads queries per workgroup
+    int64_t parts = (kSliceTargetBlocks + total - 1) / total;
+    parts = std::min<int64_t>(parts, kFieldPartialFloats / ((int64_t)total * kSliceFloats));
+    parts = std::min<int64_t>(parts, (q.m + kSliceThreads - 1) / kSliceThreads);
+    if (parts < 1) parts = 1;
+    sm.n_slices = total;
+    sm.n_qparts = (int)parts;
+    sm.features = F;
+    const unsigned grid = (unsigned)(total * parts);
+    switch (F) {
+      case 1: k_field_table_grad<1><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
+      case 2: k_field_table_grad<2><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
+      case 4: k_field_table_grad<4><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
+      default: k_field_table_grad<8><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
+    }
+    if (parts > 1)
+      k_field_table_sum<<<(unsigned)total * (kSliceFloats / 256), 256, 0, st>>>(f, sm, ws.tpart, g.table);
+  }
 }
 
 }  // namespace dass

@@ -6,6 +6,10 @@ mask (the dynamic Gaussians' indices) it runs `iters` iterations of
     shift_apply(FWD) -> render_fwd (all views) -> L1 gradient + error maps -> render_bwd
     -> shift_apply(ADJOINT) -> adam_step over {dpos, drot} and every parameter of G^var,
 
+where the offsets (dpos, drot) are either learnt directly for the dynamic Gaussians, or (shift =
+"hash") produced by two hash-encoded deformation fields, H_dyn for the dynamic and H_st for the
+static base Gaussians (Sec. 3.3), whose parameters Adam then updates instead;
+
 bakes the shift into G, and appends Gaussians where the error is large (densify_append).  The
 densified set G^var is kept between timesteps and erased every `erase_every` timesteps (App. B).
 The iteration can be captured once per timestep in a HIP graph and replayed (device-side Adam
@@ -45,6 +49,13 @@ class StreamConfig:
                                   # other streams sharing a hardware queue (serving) are not stuck
                                   # behind a whole timestep of replayed iterations
     seed: int = 0
+    shift: str = "direct"         # "direct": per-Gaussian offsets of the dynamic group;
+                                  # "hash": H_dyn / H_st deformation fields over every base Gaussian
+    # (levels, features, log2 table rows, hidden units, N_min, N_max) of H_dyn and H_st; table
+    # sizes of the N3DV setting (App. B)
+    field_dyn: tuple = (16, 4, 16, 64, 16, 2048)
+    field_st: tuple = (16, 2, 14, 64, 16, 2048)
+    lr_field: float = 2e-3
 
 
 class Trainer:
@@ -81,16 +92,50 @@ class Trainer:
         self.m_var = g.zeros_like()
         self.v_var = g.zeros_like()
         self.nd = 0
+        self.fields = None
+        if cfg.shift == "hash":
+            self._init_fields()
+        elif cfg.shift != "direct":
+            raise ValueError(f"shift must be 'direct' or 'hash', not {cfg.shift!r}")
         self.graph = None
         self.graph_key = None
         self._inflight = []
+
+    def _init_fields(self):
+        """Two fields over the base Gaussians' bounding box (10% margin); reset to their initial
+        (identity) parameters at every timestep.  Offsets are laid out [dynamic | static]."""
+        from .api import HashField, geometric_res
+        g, cfg, dev = self.g, self.cfg, self.dev
+        nb = max(1, g.n_base)
+        lo = g.mean[:, :nb].amin(dim=1).cpu()
+        hi = g.mean[:, :nb].amax(dim=1).cpu()
+        ext = (hi - lo).clamp_min(1e-3)
+        lo, hi = (lo - 0.1 * ext).tolist(), (hi + 0.1 * ext).tolist()
+        self.fields, self.field0, self.field_grads, self.field_mv = {}, {}, {}, {}
+        for k, (L, F, lt, hid, nmin, nmax) in (("dyn", cfg.field_dyn), ("st", cfg.field_st)):
+            f = HashField.init(geometric_res(nmin, nmax, L), F, lt, hid, lo, hi, dev, seed=cfg.seed + (k == "st"))
+            self.fields[k] = f
+            self.field0[k] = [t.clone() for t in f.arrays()]
+            self.field_grads[k] = f.zeros_like()
+            self.field_mv[k] = (f.zeros_like(), f.zeros_like())
+        cap = g.capacity
+        self.shift_buf = torch.zeros(cap, dtype=torch.int32, device=dev)
+        self.dpos_buf = torch.zeros(3, cap, device=dev)
+        self.drot_buf = torch.zeros(4, cap, device=dev)
+        self.d_dpos_buf = torch.zeros(3, cap, device=dev)
+        self.d_drot_buf = torch.zeros(4, cap, device=dev)
 
     # ---- one iteration --------------------------------------------------------------------
     def _adam_groups(self):
         cfg, g = self.cfg, self.g
         nd = self.nd
         groups = []
-        if nd > 0:
+        if self.fields is not None:
+            for k, f in self.fields.items():
+                m, v = self.field_mv[k]
+                for p, gr, mm, vv in zip(f.arrays(), self.field_grads[k].arrays(), m.arrays(), v.arrays()):
+                    groups.append((p, gr, mm, vv, cfg.lr_field))
+        elif nd > 0:
             groups.append((self._dpos, self._d_dpos, self._m_dpos, self._v_dpos, cfg.lr_dpos))
             groups.append((self._drot, self._d_drot, self._m_drot, self._v_drot, cfg.lr_drot))
         lo, hi = g.n_base, g.n
@@ -110,9 +155,17 @@ class Trainer:
     def iteration(self, stream=None):
         ctx, g, gs, cfg = self.ctx, self.g, self.gs, self.cfg
         gs.n, gs.n_base = g.n, g.n_base
-        ctx.shift_fwd(g, gs, self._dyn, self._dpos, self._drot, stream=stream)
+        if self.fields is not None:
+            nd, ns, F = self.nd, self.ns, self.fields
+            ctx.hash_field_fwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._dpos, self._drot, col=0, stream=stream)
+            ctx.hash_field_fwd(F["st"], g.mean, g.n_base, self._st, ns, self._dpos, self._drot, col=nd, stream=stream)
+        ctx.shift_fwd(g, gs, self._shift_idx, self._dpos, self._drot, stream=stream)
         for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
             t.zero_()
+        if self.fields is not None:
+            for k in ("dyn", "st"):
+                for t in self.field_grads[k].arrays():
+                    t.zero_()
         if not cfg.per_view:
             if cfg.ssim_lambda > 0.0:
                 ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
@@ -138,8 +191,14 @@ class Trainer:
                     self.dls[v].mul_(1.0 / V)
                 ctx.render_bwd(gs, self.cams[sl], cfg.bg, self.outs[sl], self.dls[sl], self.grads, self.gn, self.cnt,
                                stream=stream)
-        if self.nd > 0:
-            ctx.shift_adjoint(g, self._dyn, self._drot, self.grads, self._d_dpos, self._d_drot, stream=stream)
+        if int(self._shift_idx.numel()) > 0:
+            ctx.shift_adjoint(g, self._shift_idx, self._drot, self.grads, self._d_dpos, self._d_drot, stream=stream)
+        if self.fields is not None:
+            nd, ns, F = self.nd, self.ns, self.fields
+            ctx.hash_field_bwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._d_dpos, self._d_drot,
+                               self.field_grads["dyn"], col=0, stream=stream)
+            ctx.hash_field_bwd(F["st"], g.mean, g.n_base, self._st, ns, self._d_dpos, self._d_drot,
+                               self.field_grads["st"], col=nd, stream=stream)
         groups = self._adam_groups()
         if groups:
             ctx.adam_step(groups, cfg.beta1, cfg.beta2, cfg.eps, stream=stream, d_step=self.d_step)
@@ -160,15 +219,18 @@ class Trainer:
             g.n = g.n_base  # erase G^var
         nd = int(dyn_idx.numel())
         self.nd = nd
-        self.dyn_buf[:nd] = dyn_idx
-        for t_ in self.mv_dyn:
-            t_.zero_()
         for t_ in (*self.m_var.planes(), *self.v_var.planes()):
             t_.zero_()
         self.d_step.zero_()
+        if self.fields is not None:
+            return self._begin_fields(dyn_idx)
+        self.dyn_buf[:nd] = dyn_idx
+        for t_ in self.mv_dyn:
+            t_.zero_()
         # contiguous views of the preallocated buffers used by the kernels for this timestep
         flat = lambda buf, rows: buf.view(-1)[:rows * nd].view(rows, nd)
         self._dyn = self.dyn_buf[:nd]
+        self._shift_idx = self._dyn
         self._dpos, self._drot = flat(self.dpos_buf, 3), flat(self.drot_buf, 4)
         self._dpos.zero_()
         self._drot.zero_()
@@ -176,6 +238,29 @@ class Trainer:
         self._d_dpos, self._d_drot = flat(self.d_dpos_buf, 3), flat(self.d_drot_buf, 4)
         self._m_dpos, self._v_dpos = flat(self.mv_dyn[0], 3), flat(self.mv_dyn[1], 3)
         self._m_drot, self._v_drot = flat(self.mv_dyn[2], 4), flat(self.mv_dyn[3], 4)
+
+    def _begin_fields(self, dyn_idx: torch.Tensor):
+        """Shift rows [dynamic | static] of the base set; fields back to their initial parameters."""
+        g, nd = self.g, self.nd
+        nb = g.n_base
+        static = torch.ones(nb, dtype=torch.bool, device=self.dev)
+        static[dyn_idx.long()] = False
+        st = static.nonzero().view(-1).to(torch.int32)
+        self.ns = int(st.numel())
+        if self.ns + nd != nb:
+            raise ValueError("dynamic indices must be distinct rows of the base set")
+        self.shift_buf[:nd] = dyn_idx
+        self.shift_buf[nd:nb] = st
+        self._shift_idx = self.shift_buf[:nb]
+        self._dyn, self._st = self.shift_buf[:nd], self.shift_buf[nd:nb]
+        flat = lambda buf, rows: buf.view(-1)[:rows * nb].view(rows, nb)
+        self._dpos, self._drot = flat(self.dpos_buf, 3), flat(self.drot_buf, 4)
+        self._d_dpos, self._d_drot = flat(self.d_dpos_buf, 3), flat(self.d_drot_buf, 4)
+        for k, f in self.fields.items():
+            for dst, src in zip(f.arrays(), self.field0[k]):
+                dst.copy_(src)
+            for t_ in (*self.field_mv[k][0].arrays(), *self.field_mv[k][1].arrays()):
+                t_.zero_()
 
     def set_targets(self, images: List[torch.Tensor]):
         for dst, src in zip(self.targets, images):

@@ -176,3 +176,96 @@ def test_field_fullsize_dynamic_and_static_groups():
         og = HF.field_bwd(f, mq, ddp, ddr)
         for k, t in zip(("table", "w1", "b1", "w2", "b2"), grads.arrays()):
             assert_grad_close(k, t.cpu().numpy(), og[k])
+
+
+def test_fields_through_shift_match_oracle():
+    """The shift of Sec. 3.3 driven by the two fields: offsets of the dynamic rows from H_dyn and
+    of the static rows from H_st, laid out [dynamic | static] in one offset buffer, applied by
+    shift_apply; then the adjoint of an upstream gradient back through shift_apply into both
+    fields' parameters -- all against the oracle's composition of the same steps."""
+    import oracle
+    from paper_2411_14847_amd import Context
+    scene, cams, _ = synth.single_view_scene(5, n=3000)
+    n = scene.n
+    rng = np.random.default_rng(21)
+    dyn = np.sort(rng.choice(n, 300, replace=False)).astype(np.int32)
+    st = np.setdiff1d(np.arange(n, dtype=np.int32), dyn).astype(np.int32)
+    mean64 = scene.mean.astype(np.float64)
+    parts = []
+    from paper_2411_14847_amd import HashField
+    box = (float(scene.mean.min()) - 0.05, float(scene.mean.max()) + 0.05)
+    for name, idx, seed in (("n3dv_dyn", dyn, 6), ("n3dv_st", st, 7)):
+        L, F, lt, hid, nmax = CONFIGS[name]
+        p = synth.hash_field_params(seed, levels=L, features=F, log2_table=lt, hidden=hid, n_max=nmax, aabb=box)
+        f = HF.from_params(p)
+        parts.append((f, HashField.from_numpy(p, "cuda"), clean_queries(f, mean64, idx)))
+    (fdy, fdy_d, dyn), (fst, fst_d, st) = parts
+    nd, ns = dyn.size, st.size
+    rows = np.concatenate([dyn, st]).astype(np.int32)
+    from gpu_util import to_gpu
+    g = to_gpu(scene)
+    out = g.zeros_like()
+    ctx = Context(max_gaussians=n, max_views=1, max_keys=1 << 12, max_tiles=64)
+    dpos = torch.zeros(3, nd + ns, device="cuda")
+    drot = torch.zeros(4, nd + ns, device="cuda")
+    ctx.hash_field_fwd(fdy_d, g.mean, n, dev(dyn), nd, dpos, drot, col=0)
+    ctx.hash_field_fwd(fst_d, g.mean, n, dev(st), ns, dpos, drot, col=nd)
+    ctx.shift_fwd(g, out, dev(rows), dpos, drot)
+    dmean = rng.normal(size=(3, n)).astype(np.float32)
+    dquat = rng.normal(size=(4, n)).astype(np.float32)
+    d_out = g.zeros_like()
+    d_out.mean.copy_(dev(dmean))
+    d_out.quat.copy_(dev(dquat))
+    d_dpos = torch.zeros(3, nd + ns, device="cuda")
+    d_drot = torch.zeros(4, nd + ns, device="cuda")
+    ctx.shift_adjoint(g, dev(rows), drot, d_out, d_dpos, d_drot)
+    gdy, gst = fdy_d.zeros_like(), fst_d.zeros_like()
+    ctx.hash_field_bwd(fdy_d, g.mean, n, dev(dyn), nd, d_dpos, d_drot, gdy, col=0)
+    ctx.hash_field_bwd(fst_d, g.mean, n, dev(st), ns, d_dpos, d_drot, gst, col=nd)
+    ctx.sync()
+    # oracle composition
+    a_dp, a_dr = HF.field_fwd(fdy, mean64[:, dyn])
+    b_dp, b_dr = HF.field_fwd(fst, mean64[:, st])
+    o_dp, o_dr = np.concatenate([a_dp, b_dp], 1), np.concatenate([a_dr, b_dr], 1)
+    om, oq = oracle.shift_fwd(scene, rows, o_dp, o_dr)
+    assert_grad_close("mean", out.mean.cpu().numpy(), om)
+    assert_grad_close("quat", out.quat.cpu().numpy(), oq)
+    oddp, oddr = oracle.shift_adj(scene, rows, o_dr, dmean, dquat)
+    assert_grad_close("d_dpos", d_dpos.cpu().numpy(), oddp)
+    assert_grad_close("d_drot", d_drot.cpu().numpy(), oddr)
+    for f, gd, sl in ((fdy, gdy, slice(0, nd)), (fst, gst, slice(nd, nd + ns))):
+        idx = dyn if sl.start == 0 else st
+        og = HF.field_bwd(f, mean64[:, idx], oddp[:, sl], oddr[:, sl])
+        for k, t in zip(("table", "w1", "b1", "w2", "b2"), gd.arrays()):
+            assert_grad_close(k, t.cpu().numpy(), og[k])
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_streaming_with_hash_fields(use_graph):
+    """The streaming driver with the H_dyn / H_st shift: the loss falls within each timestep and
+    densification and erasure behave as with direct offsets."""
+    from paper_2411_14847_amd import Context, GaussianBuffers
+    from paper_2411_14847_amd.streaming import StreamConfig, Trainer
+    scene, _, _ = synth.single_view_scene(0, n=600)
+    cams = synth.streaming_rig(64, 64)[:4]
+    cfg = StreamConfig(iters=25, k_append=80, erase_every=2, use_graph=use_graph, shift="hash",
+                       field_dyn=(8, 4, 12, 64, 4, 64), field_st=(8, 2, 10, 32, 4, 32))
+    cap = scene.n + 2 * cfg.k_append
+    g = GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh, 0, capacity=cap)
+    gt = g.clone()
+    ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 32, max_tiles=4 * 16)
+    tr = Trainer(ctx, g, cams, max_dynamic=scene.n // 10, cfg=cfg)
+    gt_ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 32, max_tiles=4 * 16)
+    ns = []
+    for t in range(1, 4):
+        m = synth.timestep_motion(0, t, scene.n)
+        gt_out = gt.zeros_like()
+        gt_ctx.shift_fwd(gt, gt_out, dev(m.dynamic), dev(m.dpos), dev(m.dquat))
+        gt.mean.copy_(gt_out.mean); gt.quat.copy_(gt_out.quat)
+        targets = [o.rgb.clone() for o in gt_ctx.render_fwd(gt, cams, cfg.bg)]
+        st = tr.timestep(t, dev(m.dynamic), targets)
+        log(f"  t={t} loss {st['loss_first']:.5f} -> {st['loss_last']:.5f}, appended {st['appended']}, n {st['n']}")
+        assert st["loss_last"] < st["loss_first"]
+        ns.append(st["n"])
+    ctx.sync()
+    assert ns[0] == scene.n + 80 and ns[1] == scene.n + 80 and ns[2] == scene.n + 160
