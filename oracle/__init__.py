@@ -420,3 +420,6 @@ def sh_eval(deg, dirs):
 
 # hash-encoded deformation fields (Sec. 3.3, App. B)
 from .hashfield import Field as HashField, field_bwd as hash_field_bwd, field_fwd as hash_field_fwd  # noqa: E402
+
+# selective inheritance and pruning of G^var (Sec. 3.2, App. B, Sec. 3.4)
+from . import inherit  # noqa: E402,F401

@@ -328,3 +328,14 @@ def field_queries(seed: int, n: int, m: int, spread: float = 1.2):
     d_dpos = rng.normal(0.0, 1.0, size=(3, m)).astype(np.float32)
     d_drot = rng.normal(0.0, 1.0, size=(4, m)).astype(np.float32)
     return mean, idx, d_dpos, d_drot
+
+
+def inheritance_logits(seed: int, n_var: int, frac_masked: float = 0.3):
+    """Learnable inheritance values m of G^var: about frac_masked of them negative (masked out),
+    a few exactly zero (the rounding tie of Quant(sigmoid(m)) at 1/2)."""
+    rng = np.random.default_rng(seed)
+    m = np.abs(rng.normal(0.0, 1.5, size=n_var)) + 1e-3
+    neg = rng.random(n_var) < frac_masked
+    m[neg] = -m[neg]
+    m[rng.random(n_var) < 0.02] = 0.0
+    return m.astype(np.float32)

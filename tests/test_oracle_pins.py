@@ -814,3 +814,104 @@ def test_hash_field_gradients_match_finite_differences(res, features, log2_table
             arr[ix] = old
             fd = (fp - fm) / (2 * h)
             assert abs(g[name][ix] - fd) <= 1e-6 * max(1.0, abs(fd)), (name, ix, g[name][ix], fd)
+
+
+# ------------------------------------------------------------------------------------------
+# Selective inheritance (Sec. 3.2, STE of App. B) and pruning of G^var (Sec. 3.4)
+# ------------------------------------------------------------------------------------------
+from oracle import inherit as INH  # noqa: E402
+from scipy.special import expit  # noqa: E402
+
+
+def test_quant_mask_is_rounding_of_the_sigmoid():
+    """Quant(sigmoid(m)) with 1/2 rounding up equals m >= 0 (values where float64 sigmoid is not
+    itself rounded to 1/2, |m| > 1e-16, or m = 0)."""
+    m = np.concatenate([synth.inheritance_logits(3, 400), [0.0, -0.0, 1e-12, -1e-12, 40.0, -40.0]])
+    np.testing.assert_array_equal(INH.quant_mask(m), expit(m.astype(np.float64)) >= 0.5)
+
+
+def _var_scene(seed, n_base=30, n_var=30, W=40, H=32):
+    scene, cams, dls = synth.tiny_scene(seed, n_base + n_var, W, H, log_scale_mu=-2.2)
+    scene.n_base = n_base
+    return scene, cams, dls
+
+
+def _eff_scene(scene, lg, ls):
+    return synth.Scene(scene.mean.astype(np.float64), scene.quat.astype(np.float64), ls, lg,
+                       scene.sh.astype(np.float64), scene.sh_degree, scene.n_base)
+
+
+def test_masked_gaussians_are_not_drawn():
+    """Rendering with the inheritance mask equals rendering without the masked rows."""
+    scene, cams, _ = _var_scene(4)
+    m = synth.inheritance_logits(5, scene.n - scene.n_base, frac_masked=0.5)
+    lg, ls = INH.inherit_planes(scene.logit, scene.log_scale, scene.n_base, m)
+    img = oracle.render(_eff_scene(scene, lg, ls), cams)[0].rgb
+    keep = INH.keep_rows(scene.logit, scene.n_base, m)
+    sub = scene.subset(np.concatenate([np.arange(scene.n_base), scene.n_base + np.nonzero(keep)[0]]))
+    ref = oracle.render(sub, cams)[0].rgb
+    assert keep.sum() < keep.size
+    np.testing.assert_allclose(img, ref, rtol=0, atol=1e-12)
+    # unmasked rows keep their parameters exactly
+    on = scene.n_base + np.nonzero(INH.quant_mask(m))[0]
+    np.testing.assert_array_equal(lg[on], scene.logit[on].astype(np.float64))
+
+
+def test_inheritance_gradient_matches_finite_differences_of_the_mask():
+    """The straight-through gradient: for an unmasked Gaussian, dL/dM at M = 1 by central
+    differences of the rendered loss with o_r = M o and s_r = M s; masked ones get the mask
+    loss only; the mask loss's own value and gradient in closed form."""
+    scene, cams, dls = _var_scene(6)
+    nv = scene.n - scene.n_base
+    m = synth.inheritance_logits(7, nv, frac_masked=0.3)
+    lam = 0.05
+    lg, ls = INH.inherit_planes(scene.logit, scene.log_scale, scene.n_base, m)
+    eff = _eff_scene(scene, lg, ls)
+    grads, _, _, _ = oracle.render_backward(eff, cams, dls)
+    dm, loss = INH.inherit_grad(scene.logit, scene.n_base, m, grads.logit, grads.log_scale, lam)
+    sp = expit(m.astype(np.float64)) * (1 - expit(m.astype(np.float64)))
+    assert loss == pytest.approx(lam * expit(m.astype(np.float64)).sum(), rel=1e-14)
+    M = INH.quant_mask(m)
+    np.testing.assert_allclose(dm[~M], lam * sp[~M], rtol=1e-14)
+
+    def L(i, Mi):
+        o = expit(float(scene.logit[i]))
+        lg2, ls2 = lg.copy(), ls.copy()
+        lg2[i] = np.log(Mi * o / (1.0 - Mi * o))
+        ls2[:, i] = scene.log_scale[:, i].astype(np.float64) + np.log(Mi)
+        return float((oracle.render(_eff_scene(scene, lg2, ls2), cams)[0].rgb * dls[0]).sum())
+
+    checked = 0
+    for j in np.nonzero(M)[0]:
+        i = scene.n_base + j
+        dM = (dm[j] - lam * sp[j]) / sp[j]
+        if abs(dM) < 1e-3:
+            continue
+        h = 1e-6
+        fd = (L(i, 1 + h) - L(i, 1 - h)) / (2 * h)
+        assert abs(dM - fd) <= 1e-4 * max(1.0, abs(fd)), (i, dM, fd)
+        checked += 1
+    assert checked >= 5
+
+
+def test_compaction_and_pruning_brute_force():
+    rng = np.random.default_rng(8)
+    n_base, nv = 7, 50
+    n = n_base + nv
+    planes = {"mean": rng.normal(size=(3, n)), "logit": rng.normal(0, 3, size=n), "sh": rng.normal(size=(12, n))}
+    m = synth.inheritance_logits(9, nv)
+    for mm, floor in ((m, 0.0), (None, 0.05), (m, 0.05)):
+        keep = INH.keep_rows(planes["logit"], n_base, mm, floor)
+        want = []
+        for j in range(nv):
+            ok = True
+            if mm is not None:
+                ok &= expit(float(mm[j])) >= 0.5
+            if floor > 0:
+                ok &= expit(planes["logit"][n_base + j]) >= floor
+            want.append(ok)
+        np.testing.assert_array_equal(keep, want)
+        out = INH.compact(planes, n_base, keep)
+        rows = list(range(n_base)) + [n_base + j for j in range(nv) if want[j]]
+        for k in planes:
+            np.testing.assert_array_equal(out[k], planes[k][..., rows])
