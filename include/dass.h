@@ -321,6 +321,43 @@ dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, cons
                                 const float* d_dpos, const float* d_drot, int64_t ld,
                                 const dass_hash_field_grads* grads, dass_stream stream);
 
+/* ---- selective inheritance and pruning of G^var (Sec. 3.2, App. B, Sec. 3.4) ------------- */
+
+/* Selective inheritance: each G^var Gaussian (row n_base + j, j < n - n_base) has a learnable
+ * m[j]; the mask M_j = Quant(sigmoid(m_j)) (1 exactly when m_j >= 0) multiplies the rendered
+ * opacity and scale, o_r = M o and s_r = M s.  Writes the planes to render with, in the scene's
+ * parametrisation and capacity stride: logit_eff [capacity] and log_scale_eff [3][capacity] get
+ * rows [0, n) of the scene's opacity logits and log-scales, with -inf (opacity and scale 0) for
+ * masked G^var rows.  Render a dass_gaussians whose opacity_logit / log_scale point at them.
+ * Errors: DASS_E_INVALID (scene checks as render_fwd, NULL outputs, outputs aliasing the
+ * scene's planes, m NULL with G^var non-empty). */
+dass_status dass_inherit_apply(dass_ctx ctx, const dass_gaussians* g, const float* m,
+                               float* logit_eff, float* log_scale_eff, dass_stream stream);
+
+/* Gradient of the inheritance values with the straight-through estimator (App. B): the forward
+ * used M, the backward treats it as sigmoid(m).  Given the render's gradients with respect to
+ * the effective planes (d_logit_eff [capacity], d_log_scale_eff [3][capacity], e.g. render_bwd
+ * into a dass_grads), accumulates into dm [n - n_base]
+ *   dm_j += (dL/dM_j + lambda_inher) sigmoid'(m_j),
+ * dL/dM_j = d_logit_eff / (1 - o) + sum_d d_log_scale_eff,d for unmasked rows (o = sigmoid of the
+ * scene's logit), 0 for masked ones (they are not drawn); *loss (device float, may be NULL)
+ * += lambda_inher sum_j sigmoid(m_j), the mask loss of Eq. (2).
+ * Errors: DASS_E_INVALID (NULL arrays with G^var non-empty, lambda_inher negative or not
+ * finite). */
+dass_status dass_inherit_adjoint(dass_ctx ctx, const dass_gaussians* g, const float* m,
+                                 const float* d_logit_eff, const float* d_log_scale_eff,
+                                 float lambda_inher, float* dm, float* loss, dass_stream stream);
+
+/* Removes G^var rows in place, keeping the order of the rest: row n_base + j stays when
+ * (m == NULL or m[j] >= 0, the inheritance mask) and (min_opacity <= 0 or its opacity
+ * sigmoid(logit) >= min_opacity, the low-opacity pruning of Sec. 3.4).  Every parameter plane is
+ * moved; rows [0, n_base) are untouched.  The kept count is written to the device int *n_kept;
+ * the caller reads it and sets g->n = n_base + *n_kept (rows beyond are left unspecified).
+ * Errors: DASS_E_INVALID (scene checks, NULL n_kept, min_opacity >= 1), DASS_E_CAPACITY (more
+ * G^var rows than max_gaussians). */
+dass_status dass_compact_var(dass_ctx ctx, dass_gaussians* g, const float* m, float min_opacity,
+                             int32_t* n_kept, dass_stream stream);
+
 /* ---- stage timers --------------------------------------------------------------------- */
 
 /* Stages timed with HIP events on the stream of each call while profiling is on. */
@@ -338,7 +375,8 @@ typedef enum {
   DASS_STAGE_L1 = 10,         /* dass_l1_loss_grad, dass_fidelity_loss_grad          */
   DASS_STAGE_DENSIFY = 11,    /* densify_append                                      */
   DASS_STAGE_FIELD = 12,      /* dass_hash_field_fwd / dass_hash_field_bwd             */
-  DASS_NUM_STAGES = 13
+  DASS_STAGE_INHERIT = 13,    /* dass_inherit_apply / _adjoint, dass_compact_var       */
+  DASS_NUM_STAGES = 14
 } dass_stage;
 
 /* Starts recording: up to max_records intervals per stage (allocates the events). */

@@ -345,6 +345,30 @@ class Context:
                                                   self._cols(d_drot, col, m), int(d_dpos.shape[1]), C.byref(gs),
                                                   _stream(stream)))
 
+    # ---- selective inheritance and pruning of G^var ----------------------------------------
+    def inherit_apply(self, g: GaussianBuffers, m: torch.Tensor, logit_eff: torch.Tensor,
+                      log_scale_eff: torch.Tensor, stream=None):
+        """Planes to render with under the inheritance mask of m (one value per G^var row)."""
+        gs = g.struct()
+        self._check(self._lib.dass_inherit_apply(self._h, C.byref(gs), _ptr(m), _ptr(logit_eff), _ptr(log_scale_eff),
+                                                 _stream(stream)))
+
+    def inherit_adjoint(self, g: GaussianBuffers, m: torch.Tensor, d_logit_eff: torch.Tensor,
+                        d_log_scale_eff: torch.Tensor, lam: float, dm: torch.Tensor,
+                        loss: Optional[torch.Tensor] = None, stream=None):
+        gs = g.struct()
+        self._check(self._lib.dass_inherit_adjoint(self._h, C.byref(gs), _ptr(m), _ptr(d_logit_eff),
+                                                   _ptr(d_log_scale_eff), float(lam), _ptr(dm), _ptr(loss),
+                                                   _stream(stream)))
+
+    def compact_var(self, g: GaussianBuffers, m: Optional[torch.Tensor], min_opacity: float, n_kept: torch.Tensor,
+                    stream=None):
+        """Removes G^var rows in place (masked by m and/or below min_opacity); the kept count lands in
+        n_kept (device int32): the caller reads it and sets g.n = g.n_base + kept."""
+        gs = g.struct()
+        self._check(self._lib.dass_compact_var(self._h, C.byref(gs), _ptr(m), float(min_opacity), _ptr(n_kept),
+                                               _stream(stream)))
+
     @staticmethod
     def _adam_groups(groups):
         arr = (F.AdamGroup * len(groups))()

@@ -167,7 +167,9 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.loss_slots, kLossSlots);
   ALLOC(w.field_part, (size_t)kFieldMaxBlocks * field_part_stride(64, 64));
   w.cap_g = l.max_gaussians > 0 ? l.max_gaussians : 1;
-  ALLOC(w.field_denc, (size_t)64 * w.cap_g);
+  ALLOC(w.g64, (size_t)64 * w.cap_g);
+  ALLOC(w.keep, w.cap_g);
+  ALLOC(w.keep_scan, w.cap_g + 1);
   ALLOC(w.field_pn, (size_t)3 * w.cap_g);
   ALLOC(w.field_tpart, (size_t)kFieldPartialFloats);
   ALLOC(w.err, 1);
@@ -615,10 +617,82 @@ dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, cons
   if (m > ctx->ws.cap_g)
     return fail(ctx, DASS_E_CAPACITY, "m %d > max_gaussians %lld (the backward's per-query workspace)", m,
                 (long long)ctx->ws.cap_g);
-  const FieldScratch fs{ctx->ws.field_denc, ctx->ws.field_pn, ctx->ws.field_part, ctx->ws.field_tpart};
+  const FieldScratch fs{ctx->ws.g64, ctx->ws.field_pn, ctx->ws.field_part, ctx->ws.field_tpart};
   launch_field_bwd(fk, field->features, field->hidden, qk, d_dpos, d_drot, gk, fs, st);
   stage_end(ctx, DASS_STAGE_FIELD, st);
   return check_launch(ctx, "dass_hash_field_bwd");
+}
+
+dass_status dass_inherit_apply(dass_ctx ctx, const dass_gaussians* g, const float* m, float* logit_eff,
+                               float* log_scale_eff, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if (g->n > 0 && (!logit_eff || !log_scale_eff)) return fail(ctx, DASS_E_INVALID, "an output plane is NULL");
+  if (g->n > g->n_base && !m) return fail(ctx, DASS_E_INVALID, "m is NULL");
+  if (logit_eff == g->opacity_logit || log_scale_eff == g->log_scale)
+    return fail(ctx, DASS_E_INVALID, "outputs may not alias the scene's planes");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  stage_begin(ctx, DASS_STAGE_INHERIT, st);
+  launch_inherit_apply(scene_of(g), g->n_base, m, logit_eff, log_scale_eff, st);
+  stage_end(ctx, DASS_STAGE_INHERIT, st);
+  return check_launch(ctx, "dass_inherit_apply");
+}
+
+dass_status dass_inherit_adjoint(dass_ctx ctx, const dass_gaussians* g, const float* m, const float* d_logit_eff,
+                                 const float* d_log_scale_eff, float lambda_inher, float* dm, float* loss,
+                                 dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if (!std::isfinite(lambda_inher) || lambda_inher < 0.f)
+    return fail(ctx, DASS_E_INVALID, "lambda_inher must be finite and >= 0");
+  if (g->n > g->n_base && (!m || !d_logit_eff || !d_log_scale_eff || !dm))
+    return fail(ctx, DASS_E_INVALID, "m, the effective-plane gradients or dm is NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  stage_begin(ctx, DASS_STAGE_INHERIT, st);
+  launch_inherit_adjoint(scene_of(g), g->n_base, m, d_logit_eff, d_log_scale_eff, lambda_inher, dm, loss, st);
+  stage_end(ctx, DASS_STAGE_INHERIT, st);
+  return check_launch(ctx, "dass_inherit_adjoint");
+}
+
+dass_status dass_compact_var(dass_ctx ctx, dass_gaussians* g, const float* m, float min_opacity, int32_t* n_kept,
+                             dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  if (!n_kept) return fail(ctx, DASS_E_INVALID, "n_kept is NULL");
+  if (!(min_opacity < 1.f) || std::isnan(min_opacity)) return fail(ctx, DASS_E_INVALID, "min_opacity must be < 1");
+  const int nb = g->n_base, nv = g->n - g->n_base;
+  if (nv > ctx->ws.cap_g) return fail(ctx, DASS_E_CAPACITY, "G^var rows %d > max_gaussians", nv);
+  // keep when logit >= log(min_opacity / (1 - min_opacity)), decided exactly for float logits:
+  // the smallest float not below the float64 threshold
+  float min_logit = -INFINITY;
+  if (min_opacity > 0.f) {
+    const double thr = std::log((double)min_opacity / (1.0 - (double)min_opacity));
+    min_logit = (float)thr;
+    if ((double)min_logit < thr) min_logit = std::nextafter(min_logit, INFINITY);
+  }
+  CompactPlanes P{};
+  const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
+  auto add = [&](float* base, int planes) {
+    for (int p = 0; p < planes; p++) P.plane[P.count++] = base + (int64_t)p * g->capacity;
+  };
+  add(g->mean, 3);
+  add(g->quat, 4);
+  add(g->log_scale, 3);
+  add(g->opacity_logit, 1);
+  add(g->sh, 3 * K);
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  stage_begin(ctx, DASS_STAGE_INHERIT, st);
+  launch_compact_var(P, g->opacity_logit, nb, nv, m, min_logit, ws.keep, ws.keep_scan, ws.scan_tmp, ws.g64,
+                     ws.cap_g, n_kept, st);
+  stage_end(ctx, DASS_STAGE_INHERIT, st);
+  return check_launch(ctx, "dass_compact_var");
 }
 
 static dass_status adam_impl(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,

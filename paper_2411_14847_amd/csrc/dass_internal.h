@@ -126,6 +126,19 @@ void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float
 void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
                       const float* d_drot, const FieldGradsK& g, const FieldScratch& ws, hipStream_t st);
 
+// ---- selective inheritance and G^var compaction (inherit.hip) --------------------------
+constexpr int kMaxPlanes = 64;
+struct CompactPlanes {
+  float* plane[kMaxPlanes];  // every parameter plane of the scene (row r at plane[p][r])
+  int count;
+};
+void launch_inherit_apply(const SceneK& s, int nb, const float* m, float* lg_out, float* ls_out, hipStream_t st);
+void launch_inherit_adjoint(const SceneK& s, int nb, const float* m, const float* g_logit, const float* g_ls,
+                            float lam, float* dm, float* loss, hipStream_t st);
+void launch_compact_var(const CompactPlanes& P, const float* logit, int nb, int nv, const float* m, float min_logit,
+                        uint32_t* keep, uint64_t* dest, uint64_t* scan_tmp, float* stage, int64_t sstride,
+                        int32_t* n_kept, hipStream_t st);
+
 struct Workspace {
   int64_t cap_vn = 0;     // max views * max gaussians
   int64_t cap_keys = 0;
@@ -156,7 +169,10 @@ struct Workspace {
   unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
   float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
   float* field_part = nullptr;          // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
-  float* field_denc = nullptr;          // [64][cap_g] per-query dL/d(encoding) of the field backward
+  float* g64 = nullptr;                 // [64][cap_g] per-Gaussian scratch: the field backward's dL/d(encoding),
+                                        // the compaction's staging copy
+  uint32_t* keep = nullptr;             // [cap_g] compaction keep flags
+  uint64_t* keep_scan = nullptr;        // [cap_g + 1] their exclusive prefix
   double* field_pn = nullptr;           // [3][cap_g] normalised query positions
   float* field_tpart = nullptr;         // [kFieldPartialFloats] table-gradient slices of query parts
   int64_t cap_g = 0;                    // queries per field call (max_gaussians)

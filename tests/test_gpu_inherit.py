@@ -1,0 +1,101 @@
+"""GPU parity of selective inheritance (Sec. 3.2, straight-through estimator of App. B) and of the
+compaction / low-opacity pruning of G^var (Sec. 3.4): dass_inherit_apply, dass_inherit_adjoint
+and dass_compact_var against the oracle, composed with render_fwd / render_bwd."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import assert_grad_close, excluded_pixels, log, make_ctx, to_gpu
+from oracle import inherit as INH
+
+pytestmark = pytest.mark.gpu
+BG = (0.1, 0.05, 0.0)
+
+
+def dev(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda", dtype=dtype)
+
+
+def var_scene(seed, n=1500, n_base=1000, views=3, W=96, H=80):
+    scene, cams, _ = synth.multiview_scene(seed, n=n, n_views=views, width=W, height=H, with_grads=False)
+    scene.n_base = n_base
+    return scene, cams
+
+
+@pytest.mark.parametrize("frac_masked", [0.0, 0.3, 1.0])
+def test_inheritance_stage_step_matches_oracle(frac_masked):
+    """inherit_apply -> render_fwd -> render_bwd -> inherit_adjoint against the oracle."""
+    scene, cams = var_scene(12)
+    nb, nv = scene.n_base, scene.n - scene.n_base
+    log(f"inheritance step n={scene.n} n_base={nb} masked~{frac_masked}")
+    m = synth.inheritance_logits(13, nv, frac_masked=frac_masked)
+    lam = 0.01
+    # oracle
+    lg, ls = INH.inherit_planes(scene.logit, scene.log_scale, nb, m)
+    eff = synth.Scene(scene.mean, scene.quat, ls.astype(np.float32), lg.astype(np.float32), scene.sh,
+                      scene.sh_degree, nb)
+    renders = [oracle.render_view(eff, c, bg=BG) for c in cams]
+    rng = np.random.default_rng(5)
+    dls = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    for d, vr, c in zip(dls, renders, cams):
+        d[:, excluded_pixels(vr, c, grad=True)] = 0.0
+    og, _, _, _ = oracle.render_backward(eff, cams, dls, bg=BG, renders=renders)
+    odm, oloss = INH.inherit_grad(scene.logit, nb, m, og.logit, og.log_scale, lam)
+    # GPU
+    g = to_gpu(scene, n_base=nb)
+    lg_eff = torch.zeros_like(g.logit)
+    ls_eff = torch.zeros_like(g.log_scale)
+    ctx = make_ctx(scene.n, cams)
+    dm_t = dev(m)
+    ctx.inherit_apply(g, dm_t, lg_eff, ls_eff)
+    ctx.sync()
+    np.testing.assert_array_equal(lg_eff[:scene.n].cpu().numpy(), lg.astype(np.float32))
+    np.testing.assert_array_equal(ls_eff[:, :scene.n].cpu().numpy(), ls.astype(np.float32))
+    ge = g.clone()
+    ge.logit, ge.log_scale = lg_eff, ls_eff
+    outs = ctx.render_fwd(ge, cams, BG)
+    for o, vr, c in zip(outs, renders, cams):
+        keep = ~excluded_pixels(vr, c)
+        np.testing.assert_allclose(o.rgb.cpu().numpy()[:, keep], vr.rgb[:, keep], rtol=0, atol=1e-4)
+    grads = g.zeros_like()
+    ctx.render_bwd(ge, cams, BG, outs, [dev(d) for d in dls], grads)
+    dm = torch.zeros(nv, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ctx.inherit_adjoint(g, dm_t, grads.logit, grads.log_scale, lam, dm, loss)
+    ctx.sync()
+    assert np.isfinite(grads.logit.cpu().numpy()).all() and np.isfinite(grads.log_scale.cpu().numpy()).all()
+    assert_grad_close("dm", dm.cpu().numpy(), odm)
+    assert float(loss.item()) == pytest.approx(oloss, rel=1e-5)
+
+
+@pytest.mark.parametrize("mode", ["mask", "opacity", "both", "none_kept", "empty_var"])
+def test_compact_var_matches_oracle(mode):
+    rng = np.random.default_rng(21)
+    n_base = 700
+    nv = 0 if mode == "empty_var" else 2301
+    scene, _, _ = synth.tiny_scene(22, n_base + nv, 32, 32, sh_degree=3)
+    scene.logit[:] = rng.normal(-3.0, 2.5, size=scene.n).astype(np.float32)
+    m = synth.inheritance_logits(23, nv, frac_masked=1.0 if mode == "none_kept" else 0.4)
+    use_m = mode in ("mask", "both", "none_kept", "empty_var")
+    floor = 0.05 if mode in ("opacity", "both") else 0.0
+    if mode == "opacity":
+        scene.logit[n_base + 5] = np.float32(np.log(0.05 / 0.95))  # on the floor's float rounding
+    log(f"compact {mode} n_base={n_base} n_var={nv}")
+    keep = INH.keep_rows(scene.logit, n_base, m if use_m else None, floor)
+    planes = {"mean": scene.mean, "quat": scene.quat, "log_scale": scene.log_scale, "logit": scene.logit,
+              "sh": scene.sh}
+    want = INH.compact(planes, n_base, keep)
+    cap = scene.n + 17
+    g = to_gpu(scene, capacity=cap, n_base=n_base)
+    ctx = make_ctx(cap, synth.streaming_rig(32, 32)[:1])
+    kept = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    ctx.compact_var(g, dev(m) if use_m else None, floor, kept)
+    ctx.sync()
+    k = int(kept.item())
+    assert k == int(keep.sum())
+    n_new = n_base + k
+    got = {"mean": g.mean, "quat": g.quat, "log_scale": g.log_scale, "logit": g.logit, "sh": g.sh}
+    for name, t in got.items():
+        np.testing.assert_array_equal(t[..., :n_new].cpu().numpy(), want[name].astype(np.float32))
