@@ -374,7 +374,8 @@ def bench_streaming(args):
         g = _scene_buffers(scene, cap)
         ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 8 + (1 << 20),
                       max_tiles=tiles)
-        cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, **kw)
+        cfg = StreamConfig(iters=args.iters, k_append=args.densify_k, seed=args.seed, shift=args.shift,
+                           inherit_iters=args.inherit_iters, **kw)
         tr = Trainer(ctx, g, cams, max_dynamic=int(dyns[0].numel()), cfg=cfg)
         tuned = None
         if args.tile:
@@ -405,6 +406,7 @@ def bench_streaming(args):
                      "psnr_final_t": round(rows[-1]["psnr"], 2),
                      "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows])),
                      "ms_series": [round(r["ms"], 1) for r in rows], "n_series": [r["n"] for r in rows],
+                     "inherited_series": [r["inherited"] for r in rows], "pruned_series": [r["pruned"] for r in rows],
                      "tile": tile_name(ctx.tile)}
         if stages is not None:
             res[name]["stage_ms_per_timestep_last3"] = {k: round(v[0] / 3.0, 3) for k, v in stages.items()}
@@ -417,7 +419,10 @@ def bench_streaming(args):
         "value": main_["ms_per_timestep"], "unit": "ms/timestep", "n_gpus": 1, "steps": args.timesteps,
         "warmup": 1, "ms_per_step": round(main_["ms_per_timestep"] / max(1, args.iters), 4),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"streaming_2k_sh0_{len(cams)}x128x128", "iters_per_timestep": args.iters,
+        "config": {"workload": f"streaming_2k_sh0_{len(cams)}x128x128"
+                               + ("_hashfields" if args.shift == "hash" else "")
+                               + (f"_inherit{args.inherit_iters}" if args.inherit_iters else ""),
+                   "iters_per_timestep": args.iters, "inherit_iters": args.inherit_iters, "shift": args.shift,
                    "densify_k": args.densify_k, "erase_every": 20, "dynamic_fraction": 0.1},
         "variants": res,
     }
@@ -632,6 +637,8 @@ def main():
                     help="shift offsets: per-Gaussian for the dynamic group (direct), or produced by the "
                          "H_dyn / H_st hash-encoded deformation fields over every base Gaussian (Sec. 3.3)")
     ap.add_argument("--lr-field", type=float, default=2e-3)
+    ap.add_argument("--inherit-iters", type=int, default=0,
+                    help="streaming: selective-inheritance iterations per timestep (s1 = 20 in the paper)")
     ap.add_argument("--max-keys", type=int, default=0)
     ap.add_argument("--lr-pos", type=float, default=1e-3)
     ap.add_argument("--lr-rot", type=float, default=1e-3)

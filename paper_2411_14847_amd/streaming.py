@@ -10,8 +10,11 @@ where the offsets (dpos, drot) are either learnt directly for the dynamic Gaussi
 "hash") produced by two hash-encoded deformation fields, H_dyn for the dynamic and H_st for the
 static base Gaussians (Sec. 3.3), whose parameters Adam then updates instead;
 
-bakes the shift into G, and appends Gaussians where the error is large (densify_append).  The
-densified set G^var is kept between timesteps and erased every `erase_every` timesteps (App. B).
+bakes the shift into G, prunes G^var rows of very low opacity and appends Gaussians where the error
+is large (densify_append).  The densified set G^var is kept between timesteps and erased every
+`erase_every` timesteps (App. B); in the other timesteps an inheritance stage of `inherit_iters`
+iterations first learns which of its Gaussians to keep (Sec. 3.2: a binary mask on opacity and
+scale, straight-through gradient, mask loss) and removes the others.
 The iteration can be captured once per timestep in a HIP graph and replayed (device-side Adam
 step count; every buffer is preallocated, nothing in the loop allocates or synchronises).
 """
@@ -56,6 +59,14 @@ class StreamConfig:
     field_dyn: tuple = (16, 4, 16, 64, 16, 2048)
     field_st: tuple = (16, 2, 14, 64, 16, 2048)
     lr_field: float = 2e-3
+    # selective inheritance (Sec. 3.2, App. B): s1 iterations (20 in the paper; 0 keeps every
+    # G^var Gaussian), the mask-loss weight and the initial value of m (both not given by the
+    # paper), Adam's learning rate for m
+    inherit_iters: int = 0
+    lambda_inher: float = 1e-6
+    m_init: float = 0.5
+    lr_mask: float = 0.05
+    prune_min_opacity: float = 0.005  # G^var rows below this opacity are removed after each timestep
 
 
 class Trainer:
@@ -92,6 +103,15 @@ class Trainer:
         self.m_var = g.zeros_like()
         self.v_var = g.zeros_like()
         self.nd = 0
+        # selective inheritance: one value per row (G^var rows used), its gradient and moments,
+        # and the opacity-logit / log-scale planes rendered under the mask
+        self.m_inh = torch.zeros(cap, device=dev)
+        self.dm_inh = torch.zeros(cap, device=dev)
+        self.mv_inh = (torch.zeros(cap, device=dev), torch.zeros(cap, device=dev))
+        self.lg_eff = torch.zeros(cap, device=dev)
+        self.ls_eff = torch.zeros(3, cap, device=dev)
+        self.n_kept = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.inherited = None
         self.fields = None
         if cfg.shift == "hash":
             self._init_fields()
@@ -213,10 +233,44 @@ class Trainer:
         return res
 
     # ---- one timestep -----------------------------------------------------------------------
+    def inheritance_stage(self):
+        """Selective inheritance of G^var: cfg.inherit_iters iterations of mask -> render -> fidelity
+        loss -> render_bwd -> straight-through adjoint -> Adam on m, then the masked rows are
+        removed.  Returns (G^var rows before, rows kept)."""
+        ctx, g, cfg = self.ctx, self.g, self.cfg
+        nb, nv = g.n_base, g.n - g.n_base
+        m = self.m_inh[:nv]
+        dm = self.dm_inh[:nv]
+        mm, vm = self.mv_inh[0][:nv], self.mv_inh[1][:nv]
+        m.fill_(cfg.m_init)
+        mm.zero_()
+        vm.zero_()
+        ge = GaussianBuffers(g.mean, g.quat, self.ls_eff, self.lg_eff, g.sh, g.n, g.n_base, g.sh_degree)
+        for it in range(cfg.inherit_iters):
+            for t_ in (*self.grads.planes(), self.loss, dm):
+                t_.zero_()
+            ctx.inherit_apply(g, m, self.lg_eff, self.ls_eff)
+            if cfg.ssim_lambda > 0.0:
+                ctx.render_fwd(ge, self.cams, cfg.bg, out=self.outs)
+                ctx.fidelity_loss_grad(self.cams, [o.rgb for o in self.outs], self.targets, cfg.ssim_lambda, self.dls,
+                                       self.errs, self.loss, scratch=self.ssim_scratch)
+            else:
+                ctx.render_fwd_l1(ge, self.cams, cfg.bg, self.targets, self.dls, self.errs, self.loss, out=self.outs)
+            ctx.render_bwd(ge, self.cams, cfg.bg, self.outs, self.dls, self.grads)
+            ctx.inherit_adjoint(g, m, self.grads.logit, self.grads.log_scale, cfg.lambda_inher, dm, self.loss)
+            ctx.adam_step([(m, dm, mm, vm, cfg.lr_mask)], cfg.beta1, cfg.beta2, cfg.eps, step=it + 1)
+        ctx.compact_var(g, m, 0.0, self.n_kept)
+        kept = int(self.n_kept.item())
+        g.n = nb + kept
+        return nv, kept
+
     def begin_timestep(self, t: int, dyn_idx: torch.Tensor):
         cfg, g = self.cfg, self.g
+        self.inherited = None
         if t % cfg.erase_every == 0:
             g.n = g.n_base  # erase G^var
+        elif cfg.inherit_iters > 0 and g.n > g.n_base:
+            self.inherited = self.inheritance_stage()
         nd = int(dyn_idx.numel())
         self.nd = nd
         for t_ in (*self.m_var.planes(), *self.v_var.planes()):
@@ -306,6 +360,12 @@ class Trainer:
         n = g.n
         g.mean[:, :n].copy_(gs.mean[:, :n])
         g.quat[:, :n].copy_(gs.quat[:, :n])
+        self.pruned = 0
+        if cfg.prune_min_opacity > 0.0 and g.n > g.n_base:
+            self.ctx.compact_var(g, None, cfg.prune_min_opacity, self.n_kept)
+            kept = int(self.n_kept.item())
+            self.pruned = g.n - g.n_base - kept
+            g.n = g.n_base + kept
         self.ctx.densify_append(g, self.errs, self.cams, self.gn, self.cnt, cfg.gamma_err, cfg.tau_pos, cfg.tau_err,
                                 cfg.k_append, cfg.seed * 1_000_003 + t, self.n_app)
         k = int(self.n_app.item())
@@ -316,8 +376,8 @@ class Trainer:
 
     def timestep(self, t: int, dyn_idx: torch.Tensor, targets: List[torch.Tensor]) -> dict:
         t0 = time.perf_counter()
-        self.begin_timestep(t, dyn_idx)
         self.set_targets(targets)
+        self.begin_timestep(t, dyn_idx)
         first = None
         scale = 1.0 / len(self.cams) if self.cfg.per_view else 1.0  # per-view calls each add a view's mean
         if self.cfg.iters > 0:
@@ -328,4 +388,4 @@ class Trainer:
         appended = self.end_timestep(t)
         torch.cuda.current_stream().synchronize()
         return {"t": t, "ms": (time.perf_counter() - t0) * 1e3, "loss_first": first, "loss_last": last,
-                "appended": appended, "n": self.g.n}
+                "appended": appended, "n": self.g.n, "inherited": self.inherited, "pruned": self.pruned}

@@ -99,3 +99,68 @@ def test_compact_var_matches_oracle(mode):
     got = {"mean": g.mean, "quat": g.quat, "log_scale": g.log_scale, "logit": g.logit, "sh": g.sh}
     for name, t in got.items():
         np.testing.assert_array_equal(t[..., :n_new].cpu().numpy(), want[name].astype(np.float32))
+
+
+def _stream_setup(cfg_kw, n=600):
+    from paper_2411_14847_amd import Context, GaussianBuffers
+    from paper_2411_14847_amd.streaming import StreamConfig, Trainer
+    scene, _, _ = synth.single_view_scene(0, n=n)
+    cams = synth.streaming_rig(64, 64)[:4]
+    cfg = StreamConfig(iters=15, k_append=80, **cfg_kw)
+    cap = scene.n + 3 * cfg.k_append
+    g = GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh, 0, capacity=cap)
+    gt = g.clone()
+    ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 32, max_tiles=4 * 16)
+    tr = Trainer(ctx, g, cams, max_dynamic=scene.n // 10, cfg=cfg)
+    gt_ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 32, max_tiles=4 * 16)
+    return scene, cams, tr, gt, gt_ctx
+
+
+def _run(scene, cams, tr, gt, gt_ctx, T):
+    out = []
+    for t in range(1, T + 1):
+        m = synth.timestep_motion(0, t, scene.n)
+        gt_out = gt.zeros_like()
+        gt_ctx.shift_fwd(gt, gt_out, dev(m.dynamic), dev(m.dpos), dev(m.dquat))
+        gt.mean.copy_(gt_out.mean); gt.quat.copy_(gt_out.quat)
+        targets = [o.rgb.clone() for o in gt_ctx.render_fwd(gt, cams, tr.cfg.bg)]
+        st = tr.timestep(t, dev(m.dynamic), targets)
+        log(f"  t={t} loss {st['loss_first']:.5f} -> {st['loss_last']:.5f}, inherited {st['inherited']}, "
+            f"pruned {st['pruned']}, appended {st['appended']}, n {st['n']}")
+        out.append(st)
+    return out
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_streaming_with_selective_inheritance(use_graph):
+    """Timesteps with an inheritance stage: the G^var rows of the previous timestep are kept or
+    removed by the learnt mask, the counts add up, and the loss falls within each timestep."""
+    scene, cams, tr, gt, gt_ctx = _stream_setup(dict(inherit_iters=6, erase_every=3, use_graph=use_graph,
+                                                     lambda_inher=1e-4))
+    rows = _run(scene, cams, tr, gt, gt_ctx, 4)
+    n_var_prev = 0
+    for t, st in enumerate(rows, start=1):
+        assert st["loss_last"] < st["loss_first"]
+        if t % 3 == 0 or n_var_prev == 0:
+            assert st["inherited"] is None
+            n_var = 0
+        else:
+            before, kept = st["inherited"]
+            assert before == n_var_prev and 0 <= kept <= before
+            n_var = kept
+        assert st["n"] == scene.n + n_var - st["pruned"] + st["appended"]
+        n_var_prev = st["n"] - scene.n
+    tr.ctx.sync()
+
+
+def test_inheritance_extremes_keep_all_or_none():
+    """m far above 0 with no mask loss keeps every G^var row; m below 0 keeps none (a masked
+    Gaussian is not drawn, so only the mask loss moves it, further down)."""
+    for m_init, lam, want in ((3.0, 0.0, "all"), (-1.0, 1e-3, "none")):
+        scene, cams, tr, gt, gt_ctx = _stream_setup(dict(inherit_iters=4, m_init=m_init, lambda_inher=lam,
+                                                         prune_min_opacity=0.0))
+        rows = _run(scene, cams, tr, gt, gt_ctx, 2)
+        before, kept = rows[1]["inherited"]
+        assert before == rows[0]["appended"] > 0
+        assert kept == (before if want == "all" else 0)
+        tr.ctx.sync()
