@@ -423,3 +423,54 @@ from .hashfield import Field as HashField, field_bwd as hash_field_bwd, field_fw
 
 # selective inheritance and pruning of G^var (Sec. 3.2, App. B, Sec. 3.4)
 from . import inherit  # noqa: E402,F401
+
+
+# ------------------------------------------------------------------------------------------
+# Identity-feature rendering and the 3D half of the dynamics mask (Sec. 3.3; the Gaussian
+# Grouping identity encodings of App. A)
+# ------------------------------------------------------------------------------------------
+def render_features(vr: "ViewRender", cam, feat, tile=(16, 16)):
+    """C-channel image F_c(p) = sum_i e_{i,c} alpha_i T_i of one view: the blend of the colour
+    render (same lists, same alpha and transmittance) with the Gaussians' identity features
+    feat (C, n) in place of their colours and no background.  The blend is linear in the
+    per-Gaussian values, so the colour blend is run on three channels at a time."""
+    feat = np.asarray(feat, np.float64)
+    Cn, n = feat.shape
+    W, H = cam.width, cam.height
+    out = np.zeros((Cn, H, W))
+    zero_bg = np.zeros(3)
+    p = vr.proj
+    for c0 in range(0, Cn, 3):
+        k = min(3, Cn - c0)
+        vals3 = np.zeros((n, 3))
+        vals3[:, :k] = feat[c0:c0 + k].T
+        img = np.zeros((3, H, W)); T = np.ones((H, W)); nc = np.zeros((H, W), np.int32)
+        fl = np.zeros((H, W), np.int32)
+        lib().orc_blend_fwd(C.c_int32(W), C.c_int32(H), C.c_int32(tile[0]), C.c_int32(tile[1]), _p(vr.ranges),
+                            _p(vr.vals), _p(p.uv), _p(p.conic), _p(p.opacity), _p(np.ascontiguousarray(vals3)),
+                            _p(zero_bg), C.c_int32(0), None, _p(img), _p(T), _p(nc), _p(fl), None)
+        out[c0:c0 + k] = img[:k]
+    return out
+
+
+def object_ids(cls_w, cls_b, x):
+    """Gaussian Grouping's classification of identity features x (C, m): argmax_k of
+    cls_w x + cls_b (first index on ties)."""
+    logits = np.asarray(cls_w, np.float64) @ np.asarray(x, np.float64) + np.asarray(cls_b, np.float64)[:, None]
+    return np.argmax(logits, axis=0)
+
+
+def dynamic_gaussians(feat_imgs, flows, gamma_op, cls_w, cls_b, feat):
+    """Sec. 3.3: pixels whose optical flow exceeds gamma_op are dynamic areas; the objects the
+    rendered segmentation shows there are the dynamic objects; the dynamic Gaussians are those
+    whose own identity is a dynamic object.  Returns (dynamic object flags (K,), sorted
+    Gaussian indices)."""
+    K = np.asarray(cls_w).shape[0]
+    dyn_obj = np.zeros(K, bool)
+    for F, fl in zip(feat_imgs, flows):
+        Cn = F.shape[0]
+        sel = np.asarray(fl, np.float64).reshape(-1) > gamma_op
+        ids = object_ids(cls_w, cls_b, np.asarray(F, np.float64).reshape(Cn, -1)[:, sel])
+        dyn_obj[ids] = True
+    gid = object_ids(cls_w, cls_b, feat)
+    return dyn_obj, np.nonzero(dyn_obj[gid])[0].astype(np.int32)

@@ -339,3 +339,33 @@ def inheritance_logits(seed: int, n_var: int, frac_masked: float = 0.3):
     m[neg] = -m[neg]
     m[rng.random(n_var) < 0.02] = 0.0
     return m.astype(np.float32)
+
+
+def identity_setup(seed: int, n: int, n_objects: int = 8, channels: int = 16, noise: float = 0.15):
+    """Identity features of Gaussian Grouping for n Gaussians: each belongs to one of n_objects
+    objects (uniform), its feature is the object's unit code plus noise; a linear classifier
+    (cls_w (K, C), cls_b (K,)) that maps the codes to their objects.  Returns
+    (feat (C, n) float32, object of each Gaussian (n,), cls_w, cls_b)."""
+    rng = np.random.default_rng(seed)
+    codes = rng.normal(size=(n_objects, channels))
+    codes /= np.linalg.norm(codes, axis=1, keepdims=True)
+    obj = rng.integers(0, n_objects, size=n)
+    feat = (codes[obj].T + noise * rng.normal(size=(channels, n))).astype(np.float32)
+    cls_w = (4.0 * codes).astype(np.float32)
+    cls_b = rng.normal(0.0, 0.05, size=n_objects).astype(np.float32)
+    return feat, obj.astype(np.int32), cls_w, cls_b
+
+
+def flow_maps(seed: int, cams, frac: float = 0.05):
+    """Per-view optical-flow magnitudes (H, W): mostly small, large in a few random discs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in cams:
+        f = np.abs(rng.normal(0.0, 0.2, size=(c.height, c.width)))
+        yy, xx = np.mgrid[0:c.height, 0:c.width]
+        for _ in range(3):
+            cx, cy = rng.uniform(0, c.width), rng.uniform(0, c.height)
+            r = np.sqrt(frac * c.width * c.height / np.pi)
+            f[(xx - cx) ** 2 + (yy - cy) ** 2 < r * r] += 3.0
+        out.append(f.astype(np.float32))
+    return out

@@ -915,3 +915,60 @@ def test_compaction_and_pruning_brute_force():
         rows = list(range(n_base)) + [n_base + j for j in range(nv) if want[j]]
         for k in planes:
             np.testing.assert_array_equal(out[k], planes[k][..., rows])
+
+
+# ------------------------------------------------------------------------------------------
+# Identity-feature rendering and the dynamics mask (Sec. 3.3)
+# ------------------------------------------------------------------------------------------
+class _FeatProj:
+    def __init__(self, p, vals):
+        self.uv, self.conic, self.opacity, self.depth, self.rgb = p.uv, p.conic, p.opacity, p.depth, vals
+
+
+def test_feature_render_equals_brute_force():
+    sc, cams, _ = synth.tiny_scene(3, 40, 40, 36, log_scale_mu=-2.2)
+    cam = cams[0]
+    vr = oracle.render_view(sc, cam)
+    p = vr.proj
+    feat = np.random.default_rng(4).normal(size=(5, sc.n))
+    F = oracle.render_features(vr, cam, feat)
+    for py in range(0, 36, 3):
+        for px in range(0, 40, 3):
+            tx, ty = px // 16, py // 16
+            gids = [g for g in range(sc.n) if p.visible[g] and p.rect[g, 0] <= tx < p.rect[g, 2]
+                    and p.rect[g, 1] <= ty < p.rect[g, 3]]
+            for c0 in (0, 3):
+                vals = np.zeros((sc.n, 3))
+                k = min(3, 5 - c0)
+                vals[:, :k] = feat[c0:c0 + k].T
+                want, _, _ = brute_force_pixel(_FeatProj(p, vals), gids, float(px), float(py), (0.0, 0.0, 0.0))
+                np.testing.assert_allclose(F[c0:c0 + k, py, px], want[:k], atol=1e-14)
+
+
+def test_feature_render_of_ones_is_coverage():
+    """With every feature 1 the image is sum_i alpha_i T_i = 1 - T_final."""
+    sc, cams, _ = synth.tiny_scene(5, 60, 48, 40, log_scale_mu=-2.0)
+    vr = oracle.render_view(sc, cams[0])
+    F = oracle.render_features(vr, cams[0], np.ones((4, sc.n)))
+    for c in range(4):
+        np.testing.assert_allclose(F[c], 1.0 - vr.t_final, atol=1e-13)
+
+
+def test_dynamic_gaussians_brute_force():
+    rng = np.random.default_rng(6)
+    K, Cn, n = 6, 5, 300
+    cls_w, cls_b = rng.normal(size=(K, Cn)), rng.normal(size=K)
+    feat = rng.normal(size=(Cn, n))
+    imgs = [rng.normal(size=(Cn, 7, 9)) for _ in range(2)]
+    flows = [rng.uniform(0, 1, size=(7, 9)) for _ in range(2)]
+    dyn_obj, idx = oracle.dynamic_gaussians(imgs, flows, 0.8, cls_w, cls_b, feat)
+    want_obj = np.zeros(K, bool)
+    for F, fl in zip(imgs, flows):
+        for y in range(7):
+            for x in range(9):
+                if fl[y, x] > 0.8:
+                    s = [float(cls_w[k] @ F[:, y, x] + cls_b[k]) for k in range(K)]
+                    want_obj[max(range(K), key=lambda k: (s[k], -k))] = True
+    np.testing.assert_array_equal(dyn_obj, want_obj)
+    want_idx = [g for g in range(n) if want_obj[max(range(K), key=lambda k: (float(cls_w[k] @ feat[:, g] + cls_b[k]), -k))]]
+    np.testing.assert_array_equal(idx, want_idx)
