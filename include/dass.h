@@ -358,6 +358,40 @@ dass_status dass_inherit_adjoint(dass_ctx ctx, const dass_gaussians* g, const fl
 dass_status dass_compact_var(dass_ctx ctx, dass_gaussians* g, const float* m, float min_opacity,
                              int32_t* n_kept, dass_stream stream);
 
+/* ---- identity features and the dynamics mask (Sec. 3.3) ------------------------------------ */
+
+#define DASS_MAX_FEATURES 16 /* identity-feature channels (Gaussian Grouping uses 16) */
+#define DASS_MAX_OBJECTS 256
+
+/* Renders per-Gaussian identity features with the lists of the last render_fwd on this context
+ * (same g, cams, opts; no render in between): out[v] [channels][H][W] receives
+ * F_c(p) = sum_i e_{i,c} alpha_i T_i, with the colour blend's alpha and transmittance (same
+ * culling, skip and stop) and no background.  features [channels][g->capacity] (row g = the
+ * Gaussian's vector e_g), channels in [1, 16].  This is the render M of Gaussian Grouping's
+ * identity encodings that DASS queries for object IDs (Sec. 3.3).
+ * Errors: DASS_E_INVALID (as render_bwd, bad channels, NULL arrays). */
+dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams,
+                                 int32_t n_views, const float* features, int32_t channels,
+                                 float* const* out, const dass_opts* opts, dass_stream stream);
+
+/* Per-Gaussian dynamics mask (Sec. 3.3): a pixel of view v is dynamic when flow[v] (its
+ * optical-flow magnitude, [H][W]) exceeds gamma_op; the objects of the dynamic pixels,
+ * argmax_k (cls_w[k] . F(p) + cls_b[k]) of the rendered features feat_imgs[v] [channels][H][W]
+ * (first index on ties), are the dynamic objects; Gaussian g in [0, n) is dynamic when the same
+ * classification of its feature features[:, g] ([channels][stride]) is a dynamic object.
+ * Writes the dynamic Gaussians in increasing order to dyn_idx [n] (device) and their count to
+ * the device int *n_dyn (the caller reads it); dyn_objects [n_objects] (device, may be NULL)
+ * receives 1 for each dynamic object, else 0.  cls_w [n_objects][channels], cls_b [n_objects]
+ * (device).  Views' sizes come from cams (their other fields are unused).
+ * Errors: DASS_E_INVALID (channels outside [1, 16], n_objects outside [1, 256], NULL arrays,
+ * n > stride, NaN gamma_op), DASS_E_CAPACITY (n > max_gaussians). */
+dass_status dass_dynamic_mask(dass_ctx ctx, const dass_camera* cams, int32_t n_views,
+                              const float* const* feat_imgs, const float* const* flow,
+                              float gamma_op, const float* cls_w, const float* cls_b,
+                              int32_t n_objects, int32_t channels, const float* features,
+                              int64_t stride, int32_t n, int32_t* dyn_idx, int32_t* n_dyn,
+                              uint32_t* dyn_objects, dass_stream stream);
+
 /* ---- stage timers --------------------------------------------------------------------- */
 
 /* Stages timed with HIP events on the stream of each call while profiling is on. */

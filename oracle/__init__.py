@@ -429,7 +429,7 @@ from . import inherit  # noqa: E402,F401
 # Identity-feature rendering and the 3D half of the dynamics mask (Sec. 3.3; the Gaussian
 # Grouping identity encodings of App. A)
 # ------------------------------------------------------------------------------------------
-def render_features(vr: "ViewRender", cam, feat, tile=(16, 16)):
+def render_features(vr: "ViewRender", cam, feat, tile=(16, 16), tiles=None):
     """C-channel image F_c(p) = sum_i e_{i,c} alpha_i T_i of one view: the blend of the colour
     render (same lists, same alpha and transmittance) with the Gaussians' identity features
     feat (C, n) in place of their colours and no background.  The blend is linear in the
@@ -440,6 +440,7 @@ def render_features(vr: "ViewRender", cam, feat, tile=(16, 16)):
     out = np.zeros((Cn, H, W))
     zero_bg = np.zeros(3)
     p = vr.proj
+    nl, tl = _tile_arr(tiles)
     for c0 in range(0, Cn, 3):
         k = min(3, Cn - c0)
         vals3 = np.zeros((n, 3))
@@ -448,7 +449,8 @@ def render_features(vr: "ViewRender", cam, feat, tile=(16, 16)):
         fl = np.zeros((H, W), np.int32)
         lib().orc_blend_fwd(C.c_int32(W), C.c_int32(H), C.c_int32(tile[0]), C.c_int32(tile[1]), _p(vr.ranges),
                             _p(vr.vals), _p(p.uv), _p(p.conic), _p(p.opacity), _p(np.ascontiguousarray(vals3)),
-                            _p(zero_bg), C.c_int32(0), None, _p(img), _p(T), _p(nc), _p(fl), None)
+                            _p(zero_bg), C.c_int32(nl), _p(tl) if tl is not None else None, _p(img), _p(T), _p(nc),
+                            _p(fl), None)
         out[c0:c0 + k] = img[:k]
     return out
 

@@ -18,7 +18,8 @@ EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "da
            "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_fidelity_loss_grad", "dass_debug_keys",
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count", "dass_hash_field_fwd", "dass_hash_field_bwd",
-           "dass_inherit_apply", "dass_inherit_adjoint", "dass_compact_var")
+           "dass_inherit_apply", "dass_inherit_adjoint", "dass_compact_var", "dass_render_features",
+           "dass_dynamic_mask")
 FLAG_COUNT_PAIRS = 1
 FLAG_SUBTILE8 = 2
 STAGES = ("project", "depth_sort", "binning", "key_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd",
@@ -123,6 +124,9 @@ def lib():
             "dass_inherit_apply": (i32, [vp, P(Gaussians), vp, vp, vp, vp]),
             "dass_inherit_adjoint": (i32, [vp, P(Gaussians), vp, vp, vp, f32, vp, vp, vp]),
             "dass_compact_var": (i32, [vp, P(Gaussians), vp, f32, vp, vp]),
+            "dass_render_features": (i32, [vp, P(Gaussians), P(Camera), i32, vp, i32, P(vp), P(Opts), vp]),
+            "dass_dynamic_mask": (i32, [vp, P(Camera), i32, P(vp), P(vp), f32, vp, vp, i32, i32, vp, i64, i32, vp, vp,
+                                        vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

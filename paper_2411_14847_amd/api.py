@@ -369,6 +369,33 @@ class Context:
         self._check(self._lib.dass_compact_var(self._h, C.byref(gs), _ptr(m), float(min_opacity), _ptr(n_kept),
                                                _stream(stream)))
 
+    # ---- identity features and the dynamics mask -----------------------------------------
+    def render_features(self, g: GaussianBuffers, cams, features: torch.Tensor, out=None, stream=None):
+        """Identity-feature images (C, H, W) per view of the last render_fwd (same g and cams):
+        features is (C, capacity)."""
+        C_ = int(features.shape[0])
+        if out is None:
+            out = [torch.empty(C_, c.height, c.width, device=features.device) for c in cams]
+        gs = g.struct()
+        O = (C.c_void_p * len(cams))(*[_ptr(o) for o in out])
+        opts = self._opts()
+        self._check(self._lib.dass_render_features(self._h, C.byref(gs), cameras_array(cams), len(cams),
+                                                   _ptr(features), C_, O, C.byref(opts), _stream(stream)))
+        return out
+
+    def dynamic_mask(self, cams, feat_imgs, flows, gamma_op: float, cls_w: torch.Tensor, cls_b: torch.Tensor,
+                     features: torch.Tensor, n: int, dyn_idx: torch.Tensor, n_dyn: torch.Tensor,
+                     dyn_objects: Optional[torch.Tensor] = None, stream=None):
+        """Dynamic Gaussians (Sec. 3.3) into dyn_idx (int32, >= n entries); their count lands in
+        n_dyn (device int32).  features (C, stride); cls_w (K, C), cls_b (K,)."""
+        V = len(cams)
+        Fi = (C.c_void_p * V)(*[_ptr(f) for f in feat_imgs])
+        Fl = (C.c_void_p * V)(*[_ptr(f) for f in flows])
+        self._check(self._lib.dass_dynamic_mask(self._h, cameras_array(cams), V, Fi, Fl, float(gamma_op), _ptr(cls_w),
+                                                _ptr(cls_b), int(cls_w.shape[0]), int(cls_w.shape[1]), _ptr(features),
+                                                int(features.shape[1]), int(n), _ptr(dyn_idx), _ptr(n_dyn),
+                                                _ptr(dyn_objects), _stream(stream)))
+
     @staticmethod
     def _adam_groups(groups):
         arr = (F.AdamGroup * len(groups))()

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdass.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "raster.hip", "update.hip", "loss.hip", "field.hip", "inherit.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "raster.hip", "update.hip", "loss.hip", "field.hip", "inherit.hip", "dynmask.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",

@@ -170,6 +170,7 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.g64, (size_t)64 * w.cap_g);
   ALLOC(w.keep, w.cap_g);
   ALLOC(w.keep_scan, w.cap_g + 1);
+  ALLOC(w.dyn_obj, kMaxObjects);
   ALLOC(w.field_pn, (size_t)3 * w.cap_g);
   ALLOC(w.field_tpart, (size_t)kFieldPartialFloats);
   ALLOC(w.err, 1);
@@ -693,6 +694,87 @@ dass_status dass_compact_var(dass_ctx ctx, dass_gaussians* g, const float* m, fl
                      ws.cap_g, n_kept, st);
   stage_end(ctx, DASS_STAGE_INHERIT, st);
   return check_launch(ctx, "dass_compact_var");
+}
+
+dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
+                                 const float* features, int32_t channels, float* const* out, const dass_opts* opts,
+                                 dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  dass_status s;
+  if ((s = check_scene(ctx, g)) != DASS_OK) return s;
+  int tw, th, sub;
+  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  if (channels < 1 || channels > kFeatMaxC) return fail(ctx, DASS_E_INVALID, "channels %d outside [1, 16]", channels);
+  if (!out || (g->n > 0 && !features)) return fail(ctx, DASS_E_INVALID, "NULL features or out");
+  CamsK ck;
+  int64_t total_tiles = 0;
+  if ((s = make_cams(ctx, cams, n_views, tw, th, ck, total_tiles)) != DASS_OK) return s;
+  if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
+      ctx->fwd_stride != g->capacity || ctx->fwd_tw != tw || ctx->fwd_th != th)
+    return fail(ctx, DASS_E_INVALID, "dass_render_features does not match the last render_fwd on this context");
+  ViewsIO io;
+  std::memset(&io, 0, sizeof(io));
+  set_tiling(io, tw, th, sub);
+  FeatIO fo{};
+  for (int v = 0; v < n_views; v++) {
+    if (!out[v]) return fail(ctx, DASS_E_INVALID, "view %d: NULL output", v);
+    fo.out[v] = out[v];
+    io.v[v].W = ck.c[v].W;
+    io.v[v].H = ck.c[v].H;
+    io.v[v].TX = ck.c[v].TX;
+    io.v[v].tile_base = ck.c[v].tile_base;
+  }
+  fo.feat = features;
+  fo.stride = g->capacity;
+  fo.C = channels;
+  fo.n = g->n;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  stage_begin(ctx, DASS_STAGE_BLEND_FWD, st);
+  launch_blend_feat(io, n_views, total_tiles, fo, ctx->ws, ctx->ws.vals[ctx->fwd_key_buf], st);
+  stage_end(ctx, DASS_STAGE_BLEND_FWD, st);
+  return check_launch(ctx, "dass_render_features");
+}
+
+dass_status dass_dynamic_mask(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* feat_imgs,
+                              const float* const* flow, float gamma_op, const float* cls_w, const float* cls_b,
+                              int32_t n_objects, int32_t channels, const float* features, int64_t stride, int32_t n,
+                              int32_t* dyn_idx, int32_t* n_dyn, uint32_t* dyn_objects, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!cams || n_views < 0 || n_views > DASS_MAX_VIEWS)
+    return fail(ctx, DASS_E_INVALID, "cams NULL or n_views outside [0, %d]", DASS_MAX_VIEWS);
+  if (channels < 1 || channels > kFeatMaxC) return fail(ctx, DASS_E_INVALID, "channels %d outside [1, 16]", channels);
+  if (n_objects < 1 || n_objects > kMaxObjects)
+    return fail(ctx, DASS_E_INVALID, "n_objects %d outside [1, %d]", n_objects, kMaxObjects);
+  if (!cls_w || !cls_b || !n_dyn || (n > 0 && (!features || !dyn_idx)))
+    return fail(ctx, DASS_E_INVALID, "NULL classifier, features, dyn_idx or n_dyn");
+  if (n < 0 || stride < n) return fail(ctx, DASS_E_INVALID, "need 0 <= n <= stride");
+  if (n > ctx->ws.cap_g) return fail(ctx, DASS_E_CAPACITY, "n %d > max_gaussians", n);
+  if (std::isnan(gamma_op)) return fail(ctx, DASS_E_INVALID, "gamma_op is NaN");
+  DynMaskArgs a{};
+  for (int v = 0; v < n_views; v++) {
+    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    if (!feat_imgs || !flow || !feat_imgs[v] || !flow[v])
+      return fail(ctx, DASS_E_INVALID, "view %d: NULL feature image or flow", v);
+    a.feat_img[v] = feat_imgs[v];
+    a.flow[v] = flow[v];
+    a.hw[v] = (int64_t)cams[v].width * cams[v].height;
+  }
+  a.nv = n_views;
+  a.gamma_op = gamma_op;
+  a.w = cls_w;
+  a.b = cls_b;
+  a.K = n_objects;
+  a.C = channels;
+  a.feat = features;
+  a.stride = stride;
+  a.n = n;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Workspace& ws = ctx->ws;
+  launch_dynamic_mask(a, dyn_objects ? dyn_objects : ws.dyn_obj, ws.keep, ws.keep_scan, ws.scan_tmp, dyn_idx, n_dyn,
+                      st);
+  return check_launch(ctx, "dass_dynamic_mask");
 }
 
 static dass_status adam_impl(dass_ctx ctx, const dass_adam_group* groups, int32_t n_groups, float beta1, float beta2,

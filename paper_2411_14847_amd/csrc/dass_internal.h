@@ -68,7 +68,15 @@ struct ViewsIO {
   int sub;     // sub-tile edge (16: four pixels per lane, one per 8x8 quadrant; 8: one pixel)
   int sx, sn;  // sub-tiles per tile row, per tile
 };
-constexpr int kLossSlots = 4096;  // partial sums of the fused L1 loss (spread to avoid contention)
+constexpr int kLossSlots = 4096;
+constexpr int kFeatMaxC = 16;  // identity-feature channels per render
+struct FeatIO {
+  float* out[DASS_MAX_VIEWS];  // [C][H][W] per view
+  const float* feat;           // [C][stride]
+  int64_t stride;
+  int C;
+  int n;                       // Gaussians of the render (record index = view * n + Gaussian)
+};  // partial sums of the fused L1 loss (spread to avoid contention)
 
 // The projected record of one (view, Gaussian), as the blend consumes it (48 bytes).
 //   r0 = (u_hi, v_hi, u_lo, v_lo)   pixel-space mean as float hi + lo (fp64-accurate)
@@ -139,6 +147,24 @@ void launch_compact_var(const CompactPlanes& P, const float* logit, int nb, int 
                         uint32_t* keep, uint64_t* dest, uint64_t* scan_tmp, float* stage, int64_t sstride,
                         int32_t* n_kept, hipStream_t st);
 
+// ---- dynamics mask from identity features (dynmask.hip) ---------------------------------
+constexpr int kMaxObjects = 256;
+struct DynMaskArgs {
+  const float* feat_img[DASS_MAX_VIEWS];  // [C][H][W]
+  const float* flow[DASS_MAX_VIEWS];      // [H][W]
+  int64_t hw[DASS_MAX_VIEWS];
+  int nv;
+  float gamma_op;
+  const float* w;  // [K][C]
+  const float* b;  // [K]
+  int K, C;
+  const float* feat;  // [C][stride]
+  int64_t stride;
+  int n;
+};
+void launch_dynamic_mask(const DynMaskArgs& a, uint32_t* dyn_obj, uint32_t* keep, uint64_t* dest, uint64_t* scan_tmp,
+                         int32_t* dyn_idx, int32_t* n_dyn, hipStream_t st);
+
 struct Workspace {
   int64_t cap_vn = 0;     // max views * max gaussians
   int64_t cap_keys = 0;
@@ -173,6 +199,7 @@ struct Workspace {
                                         // the compaction's staging copy
   uint32_t* keep = nullptr;             // [cap_g] compaction keep flags
   uint64_t* keep_scan = nullptr;        // [cap_g + 1] their exclusive prefix
+  uint32_t* dyn_obj = nullptr;          // [kMaxObjects] dynamic-object flags
   double* field_pn = nullptr;           // [3][cap_g] normalised query positions
   float* field_tpart = nullptr;         // [kFieldPartialFloats] table-gradient slices of query parts
   int64_t cap_g = 0;                    // queries per field call (max_gaussians)
@@ -212,6 +239,9 @@ void launch_loss_finish(float* slots, float* loss, float add, hipStream_t st);
 void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, int n, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// identity features of the last render's lists (same weights as its colour blend)
+void launch_blend_feat(const ViewsIO& io, int nv, int64_t total_tiles, const FeatIO& fo, const Workspace& ws,
+                       const uint32_t* vals, hipStream_t st);
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted,
                        const uint32_t* vals_sorted, uint32_t lo, uint32_t cnt, const CamK& cam,
                        uint64_t* kout, uint32_t* vout, int64_t* rout, hipStream_t st);

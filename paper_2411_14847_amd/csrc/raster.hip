@@ -526,6 +526,125 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   }
 }
 
+// Identity-feature render: the forward's walk (same lists, culling, alpha, transmittance and
+// stop, so the weights alpha_i T_i are the colour render's) accumulating up to kFeatMaxC
+// per-Gaussian features instead of colours, with no background.
+template <int SUB>
+__global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int total_blocks, int per, FeatIO fo,
+                                                       const uint2* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec) {
+  constexpr int PW = SUB / 8, NP = PW * PW;
+  __shared__ float2 s_xy[kBatchB];
+  __shared__ float4 s_co[kBatchB];
+  __shared__ uint32_t s_qm[kBatchB];
+  __shared__ float4 s_f[kBatchB][kFeatMaxC / 4];
+  const int lb = xcd_logical(blockIdx.x, per);
+  if (lb >= total_blocks) return;
+  const int b = lb / io.sn, sub = lb - b * io.sn;
+  const int v = view_of(io, nv, b);
+  const ViewIO& V = io.v[v];
+  const int t = b - V.tile_base;
+  const int tx = t % V.TX, ty = t / V.TX;
+  const int ox = tx * io.tw + (sub % io.sx) * SUB, oy = ty * io.th + (sub / io.sx) * SUB;
+  if (ox >= V.W || oy >= V.H) return;
+  const int lane = threadIdx.x;
+  const int qx = lane & 7, qy = lane >> 3;
+  const float fx0 = (float)ox, fy0 = (float)oy;
+  const uint64_t lt = lane_lt_mask(lane);
+  const uint2 r = ranges[b];
+  const uint32_t gbase = (uint32_t)v * (uint32_t)fo.n;  // record index = view * n + Gaussian
+  float T[NP], acc[NP][kFeatMaxC];
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
+    T[k] = (px < V.W && py < V.H) ? 1.f : -1.f;
+#pragma unroll
+    for (int c = 0; c < kFeatMaxC; c++) acc[k][c] = 0.f;
+  }
+  for (uint32_t start = r.x; start < r.y; start += kBatchB) {
+    const int n_in = (int)min((uint32_t)kBatchB, r.y - start);
+    int n_kept = 0;
+#pragma unroll
+    for (int k = 0; k < kBatchB / kLanes; k++) {
+      const int e = k * kLanes + lane;
+      uint32_t qm = 0, rid = 0;
+      float2 xy;
+      float4 co;
+      if (e < n_in) {
+        rid = vals[start + e];
+        const Rec R = rec[rid];
+        xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
+        qm = quad_mask<PW>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
+        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
+      }
+      const bool keep = qm != 0;
+      const uint64_t m = __ballot(keep);
+      if (keep) {
+        const int pos = n_kept + __popcll(m & lt);
+        s_xy[pos] = xy;
+        s_co[pos] = co;
+        s_qm[pos] = qm;
+        const float* __restrict__ f = fo.feat + (rid - gbase);
+        float fv[kFeatMaxC];
+#pragma unroll
+        for (int c = 0; c < kFeatMaxC; c++) fv[c] = c < fo.C ? f[(int64_t)c * fo.stride] : 0.f;
+#pragma unroll
+        for (int c = 0; c < kFeatMaxC / 4; c++) s_f[pos][c] = make_float4(fv[4 * c], fv[4 * c + 1], fv[4 * c + 2], fv[4 * c + 3]);
+      }
+      n_kept += __popcll(m);
+    }
+    uint32_t qalive = 0;
+#pragma unroll
+    for (int k = 0; k < NP; k++) qalive |= __ballot(T[k] > 0.f) != 0 ? 1u << k : 0u;
+    __syncthreads();
+    for (int j = 0; j < n_kept; j++) {
+      const float2 xy = s_xy[j];
+      const float4 co = s_co[j];
+      const uint32_t qm = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_qm[j]) & qalive;
+      const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
+      float4 fe[kFeatMaxC / 4];
+#pragma unroll
+      for (int c = 0; c < kFeatMaxC / 4; c++) fe[c] = s_f[j][c];
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        if (NP > 1 && !((qm >> k) & 1u)) continue;
+        const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
+        const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
+        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
+        const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
+        const float Tn = T[k] - T[k] * a;
+        const bool blend = ok && (Tn >= kTStop);
+        const float wgt = blend ? a * T[k] : 0.f;
+#pragma unroll
+        for (int c = 0; c < kFeatMaxC / 4; c++) {
+          acc[k][4 * c] += fe[c].x * wgt;
+          acc[k][4 * c + 1] += fe[c].y * wgt;
+          acc[k][4 * c + 2] += fe[c].z * wgt;
+          acc[k][4 * c + 3] += fe[c].w * wgt;
+        }
+        T[k] = blend ? Tn : (ok ? -fabsf(T[k]) : T[k]);
+      }
+    }
+    bool alive = false;
+#pragma unroll
+    for (int k = 0; k < NP; k++) alive = alive || T[k] > 0.f;
+    if (__ballot(alive) == 0) break;
+    __syncthreads();
+  }
+  float* __restrict__ out = fo.out[v];
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
+    if (px < V.W && py < V.H) {
+      const int64_t hw = (int64_t)V.W * V.H;
+      const int64_t pix = (int64_t)py * V.W + px;
+#pragma unroll
+      for (int c = 0; c < kFeatMaxC; c++)
+        if (c < fo.C) out[c * hw + pix] = acc[k][c];
+    }
+  }
+}
+
 __global__ void k_debug_keys(int view_tile_base, uint32_t row0, const uint32_t* __restrict__ keys,
                              const uint32_t* __restrict__ vals, const Rec* __restrict__ rec, uint32_t lo,
                              uint32_t cnt, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
@@ -610,6 +729,18 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
     else
       blend_fwd_variant<false, false>(io, nv, (int)total, per, bg, ws, vals, st);
   }
+}
+
+void launch_blend_feat(const ViewsIO& io, int nv, int64_t total_tiles, const FeatIO& fo, const Workspace& ws,
+                       const uint32_t* vals, hipStream_t st) {
+  const int64_t total = total_tiles * io.sn;
+  if (total == 0) return;
+  const int per = per_xcd(total);
+  const dim3 grid(per * kNumXcd), block(kLanes);
+  if (io.sub == 8)
+    k_blend_feat<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, fo, ws.ranges, vals, ws.rec_u);
+  else
+    k_blend_feat<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, fo, ws.ranges, vals, ws.rec_u);
 }
 
 __global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, float* __restrict__ loss, float add) {

@@ -155,3 +155,28 @@ def test_large_footprint_fullsize_sampled_tiles():
         for t in picks:  # the sampled tiles' sorted key lists, bit-exact
             np.testing.assert_array_equal(gk[gr[t, 0]:gr[t, 1]], k[r[t, 0]:r[t, 1]])
             np.testing.assert_array_equal(gv[gr[t, 0]:gr[t, 1]], v[r[t, 0]:r[t, 1]])
+
+
+def test_fullsize_sampled_feature_tiles(full):
+    """16-channel identity features of the full workload (same render call), sampled tiles of
+    two views against the oracle's blend of the same lists."""
+    scene, cams, tile, ctx, g = full["scene"], full["cams"], full["tile"], full["ctx"], full["g"]
+    feat, _, _, _ = synth.identity_setup(40, scene.n)
+    ctx.render_fwd(g, cams, BG)
+    fdev = torch.zeros(16, g.capacity, device="cuda")
+    fdev[:, :scene.n] = torch.as_tensor(feat, device="cuda")
+    F = ctx.render_features(g, cams, fdev)
+    ctx.sync()
+    for view in (0, 13):
+        cam = cams[view]
+        TX, TY = oracle.tiles_of(cam, tile)
+        rng = np.random.default_rng(200 + view)
+        n_pick = max(3, 8 * 256 // (tile[0] * tile[1]))
+        tiles = np.concatenate([rng.choice(TX * TY, n_pick, replace=False), [TX * TY - 1]])
+        vr = oracle.render_view(scene, cam, bg=BG, tile=tile, tiles=tiles, proj=full["projs"][view],
+                                key_data=full["keys"][view])
+        want = oracle.render_features(vr, cam, feat, tile=tile, tiles=tiles)
+        m = vr.computed & ~excluded_pixels(vr, cam, tile=tile)
+        err = np.abs(F[view].cpu().numpy() - want)[:, m].max()
+        log(f"  features view {view}: {m.sum()} pixels, max err {err:.2e}")
+        assert err <= IMG_TOL
