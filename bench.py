@@ -295,6 +295,41 @@ def fwdbwd_latency(s, args, reps):
     return eager, replay
 
 
+def feature_render_times(s, args):
+    """16-channel identity features of every view from the render's lists (Gaussian Grouping's
+    render M, Sec. 3.3) and the dynamics mask built on them, timed with events after one render."""
+    torch = s["torch"]
+    import synth
+    ctx, g, cams = s["ctx"], s["gs"], s["cams"]
+    feat, _, cls_w, cls_b = synth.identity_setup(args.seed + 3, s["N"], n_objects=64)
+    fdev = torch.zeros(16, g.capacity, device="cuda")
+    fdev[:, :s["N"]] = torch.as_tensor(feat, device="cuda")
+    flows = [torch.as_tensor(f, device="cuda") for f in synth.flow_maps(args.seed + 4, cams, frac=0.002)]
+    W, B = torch.as_tensor(cls_w, device="cuda"), torch.as_tensor(cls_b, device="cuda")
+    idx = torch.zeros(g.capacity, dtype=torch.int32, device="cuda")
+    nd = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.render_fwd(g, cams, args.bg, out=s["outs"])
+    out = [torch.empty(16, c.height, c.width, device="cuda") for c in cams]
+    ctx.render_features(g, cams, fdev, out=out)
+    ctx.dynamic_mask(cams, out, flows, 1.0, W, B, fdev, s["N"], idx, nd)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(args.feature_reps):
+        ctx.render_features(g, cams, fdev, out=out)
+    e[1].record()
+    for _ in range(args.feature_reps):
+        ctx.dynamic_mask(cams, out, flows, 1.0, W, B, fdev, s["N"], idx, nd)
+    e[2].record()
+    torch.cuda.synchronize()
+    ms_f = e[0].elapsed_time(e[1]) / args.feature_reps
+    ms_m = e[1].elapsed_time(e[2]) / args.feature_reps
+    log(f"[bench] identity features (16 ch, {len(cams)} views) {ms_f:.3f} ms; dynamics mask {ms_m:.3f} ms "
+        f"({int(nd.item())} dynamic Gaussians)")
+    return {"channels": 16, "render_ms_all_views": round(ms_f, 4), "dynamic_mask_ms": round(ms_m, 4),
+            "n_objects": 64, "n_dynamic": int(nd.item())}
+
+
 def cpu_baseline(s, args):
     """The oracle (single-threaded float64 C) on a bounded sample: view 0 of the same scene,
     forward + backward with a seeded upstream gradient; scaled to iterations of all views."""
@@ -643,6 +678,8 @@ def main():
     ap.add_argument("--lr-pos", type=float, default=1e-3)
     ap.add_argument("--lr-rot", type=float, default=1e-3)
     ap.add_argument("--render-reps", type=int, default=100)
+    ap.add_argument("--feature-reps", type=int, default=5,
+                    help="multiview: timed 16-channel identity-feature renders and dynamics masks (0 skips)")
     ap.add_argument("--per-view-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=100, help="iterations per timestep (streaming, serving)")
@@ -743,6 +780,7 @@ def main():
             "flops_per_launch": float(cand[dom]), "avg_launch_ms": round(dom_ms, 4)}
     p50, p99 = render_latency(s, args, args.render_reps)
     log(f"[bench] render p50 {p50:.3f} ms p99 {p99:.3f} ms")
+    feats = feature_render_times(s, args) if args.workload == "multiview" and args.feature_reps > 0 else None
     lat = None
     if args.workload == "single":
         e_ms, g_ms = fwdbwd_latency(s, args, 200)
@@ -775,6 +813,7 @@ def main():
                    "parallelism": "single GPU"},
         "tile_autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
+        "identity_features": feats,
         "fwd_bwd_latency": lat,
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
