@@ -304,7 +304,10 @@ def feature_render_times(s, args):
     feat, _, cls_w, cls_b = synth.identity_setup(args.seed + 3, s["N"], n_objects=64)
     fdev = torch.zeros(16, g.capacity, device="cuda")
     fdev[:, :s["N"]] = torch.as_tensor(feat, device="cuda")
-    flows = [torch.as_tensor(f, device="cuda") for f in synth.flow_maps(args.seed + 4, cams, frac=0.002)]
+    # flow above the threshold in a few small discs of the first view only (the other views still
+    # run the pixel pass)
+    flows = [torch.as_tensor(f, device="cuda") for f in synth.flow_maps(args.seed + 4, cams[:1], frac=0.002)]
+    flows += [torch.zeros(c.height, c.width, device="cuda") for c in cams[1:]]
     W, B = torch.as_tensor(cls_w, device="cuda"), torch.as_tensor(cls_b, device="cuda")
     idx = torch.zeros(g.capacity, dtype=torch.int32, device="cuda")
     nd = torch.zeros(1, dtype=torch.int32, device="cuda")

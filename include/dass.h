@@ -315,7 +315,8 @@ dass_status dass_hash_field_fwd(dass_ctx ctx, const dass_hash_field* field, cons
  * d_drot [4][ld] (dL/d of the outputs), accumulates dL/d(table, w1, b1, w2, b2) into `grads`.
  * Queries outside [0, n) add nothing.  The weight gradients are summed per workgroup and then
  * over workgroups in a fixed order; table gradients use float atomics (order-nondeterministic).
- * Errors as dass_hash_field_fwd, plus DASS_E_INVALID for a NULL grads. */
+ * Errors as dass_hash_field_fwd, plus DASS_E_INVALID for a NULL grads and DASS_E_CAPACITY for
+ * m > max_gaussians (the per-query workspace reserved by the context). */
 dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, const float* mean,
                                 int64_t stride, int32_t n, const int32_t* idx, int32_t m,
                                 const float* d_dpos, const float* d_drot, int64_t ld,

@@ -167,7 +167,8 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.loss_slots, kLossSlots);
   ALLOC(w.field_part, (size_t)kFieldMaxBlocks * field_part_stride(64, 64));
   w.cap_g = l.max_gaussians > 0 ? l.max_gaussians : 1;
-  ALLOC(w.g64, (size_t)64 * w.cap_g);
+  ALLOC(w.field_rows, (size_t)kFieldRowFloats * w.cap_g);
+  w.g64 = w.field_rows;
   ALLOC(w.keep, w.cap_g);
   ALLOC(w.keep_scan, w.cap_g + 1);
   ALLOC(w.dyn_obj, kMaxObjects);
@@ -610,15 +611,25 @@ dass_status dass_hash_field_bwd(dass_ctx ctx, const dass_hash_field* field, cons
   dass_status s;
   if ((s = field_args(ctx, field, mean, stride, n, idx, m, ld, fk, qk)) != DASS_OK) return s;
   if (!grads) return fail(ctx, DASS_E_INVALID, "grads is NULL");
+  if (m > ctx->ws.cap_g)
+    return fail(ctx, DASS_E_CAPACITY, "m %d > max_gaussians %lld (the backward's per-query workspace)", m,
+                (long long)ctx->ws.cap_g);
   if (m > 0 && (!d_dpos || !d_drot)) return fail(ctx, DASS_E_INVALID, "d_dpos or d_drot is NULL");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const FieldGradsK gk{grads->table, grads->w1, grads->b1, grads->w2, grads->b2};
   stage_begin(ctx, DASS_STAGE_FIELD, st);
-  if (m > ctx->ws.cap_g)
-    return fail(ctx, DASS_E_CAPACITY, "m %d > max_gaussians %lld (the backward's per-query workspace)", m,
-                (long long)ctx->ws.cap_g);
-  const FieldScratch fs{ctx->ws.g64, ctx->ws.field_pn, ctx->ws.field_part, ctx->ws.field_tpart};
+  const int64_t mm = m;
+  FieldScratch fs{};
+  float* r = ctx->ws.field_rows;
+  fs.rows.dpre = r;
+  fs.rows.act = r + 64 * mm;
+  fs.rows.enc = r + 128 * mm;
+  fs.rows.denc = r + 192 * mm;
+  fs.rows.dout = r + 256 * mm;
+  fs.rows.pn = ctx->ws.field_pn;
+  fs.part = ctx->ws.field_part;
+  fs.tpart = ctx->ws.field_tpart;
   launch_field_bwd(fk, field->features, field->hidden, qk, d_dpos, d_drot, gk, fs, st);
   stage_end(ctx, DASS_STAGE_FIELD, st);
   return check_launch(ctx, "dass_hash_field_bwd");

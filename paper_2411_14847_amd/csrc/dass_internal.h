@@ -122,9 +122,18 @@ struct SliceMap {
   int64_t level_floats[kFieldMaxLevels];   // floats of the level's table that can be touched
   int n_slices, n_qparts, features;
 };
+// Per-query rows of the field backward, feature-major over the m queries of the call ([R][m]).
+struct FieldRows {
+  float* dpre;  // [hidden] dL/d(pre-activation)
+  float* act;   // [hidden] activation
+  float* enc;   // [L F] encoding
+  float* denc;  // [L F] dL/d(encoding)
+  float* dout;  // [7] upstream gradient (zeros for rows outside [0, n))
+  double* pn;   // [3] normalised position
+};
+constexpr int kFieldRowFloats = 64 + 64 + 64 + 64 + 8;  // floats per query reserved for the rows above
 struct FieldScratch {
-  float* denc;   // [64][max_gaussians] dL/d(encoding) per query, feature-major
-  double* pn;    // [3][max_gaussians] normalised query positions
+  FieldRows rows;
   float* part;   // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
   float* tpart;  // [kFieldPartialFloats] table-gradient slices of the query parts
 };
@@ -195,8 +204,8 @@ struct Workspace {
   unsigned long long* pairs = nullptr;  // [0] evaluated, [1] blended (pair counting only)
   float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
   float* field_part = nullptr;          // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
-  float* g64 = nullptr;                 // [64][cap_g] per-Gaussian scratch: the field backward's dL/d(encoding),
-                                        // the compaction's staging copy
+  float* field_rows = nullptr;          // [kFieldRowFloats][cap_g] the field backward's per-query rows
+  float* g64 = nullptr;                 // [64][cap_g] the compaction's staging copy (inside field_rows)
   uint32_t* keep = nullptr;             // [cap_g] compaction keep flags
   uint64_t* keep_scan = nullptr;        // [cap_g + 1] their exclusive prefix
   uint32_t* dyn_obj = nullptr;          // [kMaxObjects] dynamic-object flags

@@ -10,46 +10,70 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// argmax_k (cls_w[k] . x + cls_b[k]), first index on ties; weights read with uniform addresses
-__device__ __forceinline__ int classify(const float* __restrict__ w, const float* __restrict__ bias, int K, int C,
-                                        const float* x) {
+// The classifier in LDS, padded to kFeatMaxC weights per object (zeros beyond C).
+struct ClsLds {
+  float4 w[kMaxObjects][kFeatMaxC / 4];
+  float b[kMaxObjects];
+};
+
+__device__ __forceinline__ void load_classifier(ClsLds& s, const float* __restrict__ w, const float* __restrict__ bias,
+                                                int K, int C) {
+  for (int e = threadIdx.x; e < K * kFeatMaxC; e += kThreads) {
+    const int k = e / kFeatMaxC, c = e % kFeatMaxC;
+    reinterpret_cast<float*>(&s.w[k][0])[c] = c < C ? w[k * C + c] : 0.f;
+  }
+  for (int k = threadIdx.x; k < K; k += kThreads) s.b[k] = bias[k];
+  __syncthreads();
+}
+
+// argmax_k (cls_w[k] . x + cls_b[k]), first index on ties
+__device__ __forceinline__ int classify(const ClsLds& s, int K, const float* x) {
   float best = -INFINITY;
   int id = 0;
   for (int k = 0; k < K; ++k) {
-    float s = bias[k];
+    float v = s.b[k];
 #pragma unroll
-    for (int c = 0; c < kFeatMaxC; ++c)
-      if (c < C) s = fmaf(w[k * C + c], x[c], s);
-    if (s > best) {
-      best = s;
+    for (int c = 0; c < kFeatMaxC / 4; ++c) {
+      const float4 w = s.w[k][c];
+      v = fmaf(w.x, x[4 * c], v);
+      v = fmaf(w.y, x[4 * c + 1], v);
+      v = fmaf(w.z, x[4 * c + 2], v);
+      v = fmaf(w.w, x[4 * c + 3], v);
+    }
+    if (v > best) {
+      best = v;
       id = k;
     }
   }
   return id;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dynamic_objects(const float* __restrict__ feat_img, int64_t hw,
-                                                              const float* __restrict__ flow, float gamma_op,
-                                                              const float* __restrict__ w, const float* __restrict__ bias,
-                                                              int K, int C, uint32_t* __restrict__ dyn_obj) {
+// blockIdx.y = view
+__global__ __launch_bounds__(kThreads) void k_dynamic_objects(const DynMaskArgs a, uint32_t* __restrict__ dyn_obj) {
+  __shared__ ClsLds s;
+  const int v = blockIdx.y;
+  const int64_t hw = a.hw[v];
   const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (p >= hw || !(flow[p] > gamma_op)) return;
+  const bool dyn = p < hw && a.flow[v][p] > a.gamma_op;
+  if (__syncthreads_or(dyn) == 0) return;  // uniform: no dynamic pixel in this block
+  load_classifier(s, a.w, a.b, a.K, a.C);
+  if (!dyn) return;
   float x[kFeatMaxC];
 #pragma unroll
-  for (int c = 0; c < kFeatMaxC; ++c) x[c] = c < C ? feat_img[c * hw + p] : 0.f;
-  dyn_obj[classify(w, bias, K, C, x)] = 1u;
+  for (int c = 0; c < kFeatMaxC; ++c) x[c] = c < a.C ? a.feat_img[v][c * hw + p] : 0.f;
+  dyn_obj[classify(s, a.K, x)] = 1u;
 }
 
-__global__ __launch_bounds__(kThreads) void k_dynamic_flags(const float* __restrict__ feat, int64_t stride, int n,
-                                                            const float* __restrict__ w, const float* __restrict__ bias,
-                                                            int K, int C, const uint32_t* __restrict__ dyn_obj,
+__global__ __launch_bounds__(kThreads) void k_dynamic_flags(const DynMaskArgs a, const uint32_t* __restrict__ dyn_obj,
                                                             uint32_t* __restrict__ keep) {
+  __shared__ ClsLds s;
+  load_classifier(s, a.w, a.b, a.K, a.C);
   const int g = blockIdx.x * kThreads + threadIdx.x;
-  if (g >= n) return;
+  if (g >= a.n) return;
   float x[kFeatMaxC];
 #pragma unroll
-  for (int c = 0; c < kFeatMaxC; ++c) x[c] = c < C ? feat[c * stride + g] : 0.f;
-  keep[g] = dyn_obj[classify(w, bias, K, C, x)] ? 1u : 0u;
+  for (int c = 0; c < kFeatMaxC; ++c) x[c] = c < a.C ? a.feat[c * a.stride + g] : 0.f;
+  keep[g] = dyn_obj[classify(s, a.K, x)] ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_dynamic_scatter(int n, const uint32_t* __restrict__ keep,
@@ -65,15 +89,13 @@ __global__ __launch_bounds__(kThreads) void k_dynamic_scatter(int n, const uint3
 void launch_dynamic_mask(const DynMaskArgs& a, uint32_t* dyn_obj, uint32_t* keep, uint64_t* dest, uint64_t* scan_tmp,
                          int32_t* dyn_idx, int32_t* n_dyn, hipStream_t st) {
   launch_fill_u32(dyn_obj, 0u, a.K, st);
-  for (int v = 0; v < a.nv; ++v) {
-    const int64_t hw = a.hw[v];
-    if (hw > 0)
-      k_dynamic_objects<<<(unsigned)((hw + kThreads - 1) / kThreads), kThreads, 0, st>>>(
-          a.feat_img[v], hw, a.flow[v], a.gamma_op, a.w, a.b, a.K, a.C, dyn_obj);
-  }
+  int64_t hw_max = 0;
+  for (int v = 0; v < a.nv; ++v) hw_max = a.hw[v] > hw_max ? a.hw[v] : hw_max;
+  if (hw_max > 0)
+    k_dynamic_objects<<<dim3((unsigned)((hw_max + kThreads - 1) / kThreads), (unsigned)a.nv), kThreads, 0, st>>>(
+        a, dyn_obj);
   const int blocks = a.n > 0 ? (a.n + kThreads - 1) / kThreads : 1;
-  if (a.n > 0)
-    k_dynamic_flags<<<blocks, kThreads, 0, st>>>(a.feat, a.stride, a.n, a.w, a.b, a.K, a.C, dyn_obj, keep);
+  if (a.n > 0) k_dynamic_flags<<<blocks, kThreads, 0, st>>>(a, dyn_obj, keep);
   scan_u32_to_u64(keep, dest, a.n, scan_tmp, st);
   k_dynamic_scatter<<<blocks, kThreads, 0, st>>>(a.n, keep, dest, dyn_idx, n_dyn);
 }

@@ -5,13 +5,12 @@
 //
 // Forward: one query per lane; the encoding (L levels x 8 corners, one F-float row each) sits in
 // registers and the weights are read with wave-uniform addresses.
-// Backward, three kernels:
-//  1. one wave per workgroup, looping over chunks of 64 queries.  Lanes are queries while the
-//     encoding and the MLP adjoint are recomputed; each query's dL/d(encoding) and normalised
-//     position go to a workspace.  Then lanes are hidden units and sum the chunk's weight
-//     gradients from LDS into registers that live across chunks; each workgroup writes its
-//     sums once.
-//  2. the workgroups' weight-gradient partials added in a fixed order.
+// Backward:
+//  1. one query per lane: the encoding and the MLP adjoint are recomputed and the rows the
+//     gradients need (per hidden unit dL/d(pre-activation) and activation, the encoding and its
+//     adjoint, the upstream gradient, the float64 position) go to a workspace, feature-major.
+//  2. weight gradients: each workgroup sums a contiguous part of the queries through LDS and
+//     writes one partial row; the partials are then added in a fixed order.
 //  3. table gradients without global atomics: each workgroup owns one slice (up to 128 KB) of
 //     one level's table, accumulates every query's corner contributions that fall in it with
 //     LDS atomics, then adds the slice to the gradient.  (Float atomics to global memory from
@@ -162,113 +161,139 @@ __global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const
   for (int d = 1; d < 4; ++d) drot[d * q.ld + j] = out[3 + d];
 }
 
+// Backward, per query (one lane each, like the forward): the encoding and the MLP adjoint.  Writes,
+// feature-major over the queries, what the weight and table gradients need: dL/d(pre-activation)
+// and the activation of every hidden unit, the encoding and its adjoint, the upstream gradient
+// (zeros for rows outside [0, n)) and the float64 normalised position.
 template <int F, int HID>
-__global__ __launch_bounds__(64) void k_field_bwd(const FieldK f, const QueryK q, const float* __restrict__ d_dpos,
-                                                  const float* __restrict__ d_drot, float* __restrict__ denc_out,
-                                                  double* __restrict__ p_out, float* __restrict__ part, int chunks) {
+__global__ __launch_bounds__(kFwdThreads) void k_field_bwd_query(const FieldK f, const QueryK q,
+                                                                 const float* __restrict__ d_dpos,
+                                                                 const float* __restrict__ d_drot, FieldRows rows) {
   constexpr int KL = max_levels<F>();
   constexpr int LFM = KL * F;
-  __shared__ float s_enc[64][LFM + 1];
-  __shared__ float s_dp[64][HID + 1];
-  __shared__ float s_h[64][HID + 1];
-  __shared__ float s_do[64][8];
-  const int lane = threadIdx.x;
-  const int LF = f.L * F;
-  float aw1[LFM], aw2[7], ab1 = 0.f, ab2 = 0.f;
+  const int j = blockIdx.x * kFwdThreads + threadIdx.x;
+  if (j >= q.m) return;
+  const int64_t m = q.m;
+  int g = q.idx ? q.idx[j] : j;
+  if (g < 0 || g >= q.n) g = -1;
+  double p[3] = {0.0, 0.0, 0.0};
+  float dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float enc[LFM];
 #pragma unroll
-  for (int i = 0; i < LFM; ++i) aw1[i] = 0.f;
+  for (int i = 0; i < LFM; ++i) enc[i] = 0.f;
+  if (g >= 0) {
+    normalised(f, q, g, p);
 #pragma unroll
-  for (int o = 0; o < 7; ++o) aw2[o] = 0.f;
-
-  for (int c = blockIdx.x; c < chunks; c += gridDim.x) {
-    // ---- lanes = queries: encoding, MLP adjoint, table scatter
-    const int j = c * 64 + lane;
-    int g = -1;
-    if (j < q.m) {
-      g = q.idx ? q.idx[j] : j;
-      if (g < 0 || g >= q.n) g = -1;
-    }
-    double p[3] = {0.0, 0.0, 0.0};
-    float dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float enc[LFM];
+    for (int d = 0; d < 3; ++d) dout[d] = d_dpos[d * q.ld + j];
 #pragma unroll
-    for (int i = 0; i < LFM; ++i) enc[i] = 0.f;
-    if (g >= 0) {
-      normalised(f, q, g, p);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) dout[d] = d_dpos[d * q.ld + j];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) dout[3 + d] = d_drot[d * q.ld + j];
-      encode<F>(f, p, enc);
-    }
-#pragma unroll
-    for (int i = 0; i < LFM; ++i) s_enc[lane][i] = enc[i];
-#pragma unroll
-    for (int o = 0; o < 7; ++o) s_do[lane][o] = dout[o];
-    float denc[LFM];
-#pragma unroll
-    for (int i = 0; i < LFM; ++i) denc[i] = 0.f;
-    for (int h = 0; h < HID; ++h) {
-      const float a = hidden_pre<F>(f, h, LF, enc);
-      float dh = 0.f;
-#pragma unroll
-      for (int o = 0; o < 7; ++o) dh = fmaf(f.w2[o * HID + h], dout[o], dh);
-      const float dp = a > 0.f ? dh : 0.f;
-      s_dp[lane][h] = dp;
-      s_h[lane][h] = fmaxf(a, 0.f);
-      const float* __restrict__ w = f.w1 + h * LF;
-#pragma unroll
-      for (int l = 0; l < KL; ++l)
-        if (l < f.L) {
-#pragma unroll
-          for (int i = 0; i < F; ++i) denc[l * F + i] = fmaf(w[l * F + i], dp, denc[l * F + i]);
-        }
-    }
-    if (j < q.m) {  // feature-major [LF][m]; zeros for rows outside [0, n)
-#pragma unroll
-      for (int l = 0; l < KL; ++l)
-        if (l < f.L) {
-#pragma unroll
-          for (int i = 0; i < F; ++i) denc_out[(size_t)(l * F + i) * q.m + j] = denc[l * F + i];
-        }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) p_out[(size_t)d * q.m + j] = p[d];
-    }
-    __syncthreads();
-    // ---- lanes = hidden units: weight-gradient sums over the chunk's queries
-    if (lane < HID) {
-      for (int s = 0; s < 64; ++s) {
-        const float dp = s_dp[s][lane], hv = s_h[s][lane];
-        ab1 += dp;
-#pragma unroll
-        for (int l = 0; l < KL; ++l)
-          if (l < f.L) {
-#pragma unroll
-            for (int i = 0; i < F; ++i) aw1[l * F + i] = fmaf(dp, s_enc[s][l * F + i], aw1[l * F + i]);
-          }
-#pragma unroll
-        for (int o = 0; o < 7; ++o) aw2[o] = fmaf(s_do[s][o], hv, aw2[o]);
-      }
-    }
-    if (lane < 7)
-      for (int s = 0; s < 64; ++s) ab2 += s_do[s][lane];
-    __syncthreads();
+    for (int d = 0; d < 4; ++d) dout[3 + d] = d_drot[d * q.ld + j];
+    encode<F>(f, p, enc);
   }
-
-  // partial sums of this workgroup: [w1: HID][LF] [b1: HID] [w2: 7][HID] [b2: 7]
-  float* P = part + (size_t)blockIdx.x * field_part_stride(HID, LF);
-  if (lane < HID) {
+  const int LF = f.L * F;
+  float denc[LFM];
+#pragma unroll
+  for (int i = 0; i < LFM; ++i) denc[i] = 0.f;
+  for (int h = 0; h < HID; ++h) {
+    const float a = hidden_pre<F>(f, h, LF, enc);
+    float dh = 0.f;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) dh = fmaf(f.w2[o * HID + h], dout[o], dh);
+    const float dp = a > 0.f ? dh : 0.f;
+    rows.dpre[h * m + j] = dp;
+    rows.act[h * m + j] = fmaxf(a, 0.f);
+    const float* __restrict__ w = f.w1 + h * LF;
 #pragma unroll
     for (int l = 0; l < KL; ++l)
       if (l < f.L) {
 #pragma unroll
-        for (int i = 0; i < F; ++i) P[lane * LF + l * F + i] = aw1[l * F + i];
+        for (int i = 0; i < F; ++i) denc[l * F + i] = fmaf(w[l * F + i], dp, denc[l * F + i]);
       }
-    P[HID * LF + lane] = ab1;
-#pragma unroll
-    for (int o = 0; o < 7; ++o) P[HID * LF + HID + o * HID + lane] = aw2[o];
   }
-  if (lane < 7) P[HID * LF + HID + 7 * HID + lane] = ab2;
+#pragma unroll
+  for (int l = 0; l < KL; ++l)
+    if (l < f.L) {
+#pragma unroll
+      for (int i = 0; i < F; ++i) {
+        rows.enc[(l * F + i) * m + j] = enc[l * F + i];
+        rows.denc[(l * F + i) * m + j] = denc[l * F + i];
+      }
+    }
+#pragma unroll
+  for (int o = 0; o < 7; ++o) rows.dout[o * m + j] = dout[o];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) rows.pn[d * m + j] = p[d];
+}
+
+// Weight gradients: a workgroup sums a contiguous part of the queries, staging 64 queries' rows
+// at a time in LDS; thread (hidden unit j, group gr) owns dW1[j][features of group gr], group 0
+// also db1[j], group 1 dW2[:, j], group 2 db2.  One partial row per workgroup.
+constexpr int kWgThreads = 256;
+template <int F, int HID>
+__global__ __launch_bounds__(kWgThreads) void k_field_wgrad(const FieldK f, int m, FieldRows rows,
+                                                            float* __restrict__ part) {
+  constexpr int KL = max_levels<F>();
+  constexpr int LFM = KL * F;
+  constexpr int PG = LFM / 4;  // features per group
+  __shared__ float s_dp[64][HID + 1];
+  __shared__ float s_h[64][HID + 1];
+  __shared__ float s_e[64][LFM + 1];
+  __shared__ float s_o[64][8];
+  const int t = threadIdx.x;
+  const int j = t & 63, gr = t >> 6;
+  const int LF = f.L * F;
+  const int q0 = (int)((int64_t)m * blockIdx.x / gridDim.x), q1 = (int)((int64_t)m * (blockIdx.x + 1) / gridDim.x);
+  float aw1[PG], aw2[7], ab = 0.f;
+#pragma unroll
+  for (int i = 0; i < PG; ++i) aw1[i] = 0.f;
+#pragma unroll
+  for (int o = 0; o < 7; ++o) aw2[o] = 0.f;
+  for (int base = q0; base < q1; base += 64) {
+    const int nq = min(64, q1 - base);
+    // stage: row r of a [R][m] array, query base + c (c < 64) -> s[c][r]
+    for (int e = t; e < HID * 64; e += kWgThreads) {
+      const int r = e >> 6, c = e & 63;
+      const bool in = c < nq;
+      s_dp[c][r] = in ? rows.dpre[(int64_t)r * m + base + c] : 0.f;
+      s_h[c][r] = in ? rows.act[(int64_t)r * m + base + c] : 0.f;
+    }
+    for (int e = t; e < LFM * 64; e += kWgThreads) {
+      const int r = e >> 6, c = e & 63;
+      s_e[c][r] = (c < nq && r < LF) ? rows.enc[(int64_t)r * m + base + c] : 0.f;
+    }
+    for (int e = t; e < 7 * 64; e += kWgThreads) {
+      const int r = e >> 6, c = e & 63;
+      s_o[c][r] = c < nq ? rows.dout[(int64_t)r * m + base + c] : 0.f;
+    }
+    __syncthreads();
+    if (j < HID) {
+      for (int c = 0; c < nq; ++c) {
+        const float dp = s_dp[c][j];
+#pragma unroll
+        for (int i = 0; i < PG; ++i) aw1[i] = fmaf(dp, s_e[c][gr * PG + i], aw1[i]);
+        if (gr == 0) ab += dp;
+        if (gr == 1) {
+          const float hv = s_h[c][j];
+#pragma unroll
+          for (int o = 0; o < 7; ++o) aw2[o] = fmaf(s_o[c][o], hv, aw2[o]);
+        }
+        if (gr == 2 && j < 7) ab += s_o[c][j];
+      }
+    }
+    __syncthreads();
+  }
+  // partial row: [w1: HID][LF] [b1: HID] [w2: 7][HID] [b2: 7]
+  float* P = part + (size_t)blockIdx.x * field_part_stride(HID, LF);
+  if (j < HID) {
+#pragma unroll
+    for (int i = 0; i < PG; ++i)
+      if (gr * PG + i < LF) P[j * LF + gr * PG + i] = aw1[i];
+    if (gr == 0) P[HID * LF + j] = ab;
+    if (gr == 1) {
+#pragma unroll
+      for (int o = 0; o < 7; ++o) P[HID * LF + HID + o * HID + j] = aw2[o];
+    }
+    if (gr == 2 && j < 7) P[HID * LF + 8 * HID + j] = ab;
+  }
 }
 
 // Level, first float and end of slice b of the table (slice_begin: prefix over levels).
@@ -385,13 +410,26 @@ void fwd_f(int F, const FieldK& f, const QueryK& q, float* dpos, float* drot, hi
 }
 
 template <int HID>
-void bwd_f(int F, int blocks, int chunks, const FieldK& f, const QueryK& q, const float* d_dpos,
-           const float* d_drot, float* denc, double* pn, float* part, hipStream_t st) {
+void bwd_f(int F, int blocks, const FieldK& f, const QueryK& q, const float* d_dpos, const float* d_drot,
+           const FieldRows& rows, float* part, hipStream_t st) {
+  const int qb = (q.m + kFwdThreads - 1) / kFwdThreads;
   switch (F) {
-    case 1: k_field_bwd<1, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
-    case 2: k_field_bwd<2, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
-    case 4: k_field_bwd<4, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
-    default: k_field_bwd<8, HID><<<blocks, 64, 0, st>>>(f, q, d_dpos, d_drot, denc, pn, part, chunks); break;
+    case 1:
+      k_field_bwd_query<1, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_wgrad<1, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
+      break;
+    case 2:
+      k_field_bwd_query<2, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_wgrad<2, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
+      break;
+    case 4:
+      k_field_bwd_query<4, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_wgrad<4, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
+      break;
+    default:
+      k_field_bwd_query<8, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_wgrad<8, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
+      break;
   }
 }
 
@@ -409,12 +447,14 @@ void launch_field_fwd(const FieldK& f, int F, int hidden, const QueryK& q, float
 void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const float* d_dpos,
                       const float* d_drot, const FieldGradsK& g, const FieldScratch& ws, hipStream_t st) {
   if (q.m <= 0) return;
-  const int chunks = (q.m + 63) / 64;
-  const int blocks = chunks < kFieldMaxBlocks ? chunks : kFieldMaxBlocks;
+  // at least 64 queries per weight-gradient workgroup (small calls still spread over the CUs), at
+  // most kFieldMaxBlocks partial rows
+  int blocks = (q.m + 63) / 64;
+  if (blocks > kFieldMaxBlocks) blocks = kFieldMaxBlocks;
   if (hidden == 32)
-    bwd_f<32>(F, blocks, chunks, f, q, d_dpos, d_drot, ws.denc, ws.pn, ws.part, st);
+    bwd_f<32>(F, blocks, f, q, d_dpos, d_drot, ws.rows, ws.part, st);
   else
-    bwd_f<64>(F, blocks, chunks, f, q, d_dpos, d_drot, ws.denc, ws.pn, ws.part, st);
+    bwd_f<64>(F, blocks, f, q, d_dpos, d_drot, ws.rows, ws.part, st);
   const int LF = f.L * F;
   const int stride = field_part_stride(hidden, LF);
   k_field_reduce<<<(stride + kRedCols - 1) / kRedCols, 256, 0, st>>>(ws.part, blocks, stride, hidden * LF, hidden,
@@ -440,10 +480,10 @@ void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const
     sm.features = F;
     const unsigned grid = (unsigned)(total * parts);
     switch (F) {
-      case 1: k_field_table_grad<1><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
-      case 2: k_field_table_grad<2><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
-      case 4: k_field_table_grad<4><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
-      default: k_field_table_grad<8><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.pn, ws.denc, sm, g.table, ws.tpart); break;
+      case 1: k_field_table_grad<1><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.rows.pn, ws.rows.denc, sm, g.table, ws.tpart); break;
+      case 2: k_field_table_grad<2><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.rows.pn, ws.rows.denc, sm, g.table, ws.tpart); break;
+      case 4: k_field_table_grad<4><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.rows.pn, ws.rows.denc, sm, g.table, ws.tpart); break;
+      default: k_field_table_grad<8><<<grid, kSliceThreads, 0, st>>>(f, q.m, ws.rows.pn, ws.rows.denc, sm, g.table, ws.tpart); break;
     }
     if (parts > 1)
       k_field_table_sum<<<(unsigned)total * (kSliceFloats / 256), 256, 0, st>>>(f, sm, ws.tpart, g.table);
