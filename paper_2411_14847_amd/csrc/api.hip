@@ -736,6 +736,7 @@ dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const da
     io.v[v].tile_base = ck.c[v].tile_base;
   }
   fo.feat = features;
+  fo.feat16 = ctx->ws.g64;  // [64][cap_g] floats hold [cap_g][16]
   fo.stride = g->capacity;
   fo.C = channels;
   fo.n = g->n;

@@ -73,6 +73,7 @@ constexpr int kFeatMaxC = 16;  // identity-feature channels per render
 struct FeatIO {
   float* out[DASS_MAX_VIEWS];  // [C][H][W] per view
   const float* feat;           // [C][stride]
+  float* feat16;               // [n][kFeatMaxC] Gaussian-major copy (workspace)
   int64_t stride;
   int C;
   int n;                       // Gaussians of the render (record index = view * n + Gaussian)
@@ -205,7 +206,8 @@ struct Workspace {
   float* loss_slots = nullptr;          // [kLossSlots] partial sums of the fused L1 loss
   float* field_part = nullptr;          // [kFieldMaxBlocks][field_part_stride] weight-gradient partials
   float* field_rows = nullptr;          // [kFieldRowFloats][cap_g] the field backward's per-query rows
-  float* g64 = nullptr;                 // [64][cap_g] the compaction's staging copy (inside field_rows)
+  float* g64 = nullptr;                 // [64][cap_g] the compaction's staging copy and the feature render's
+                                        // Gaussian-major rows (inside field_rows)
   uint32_t* keep = nullptr;             // [cap_g] compaction keep flags
   uint64_t* keep_scan = nullptr;        // [cap_g + 1] their exclusive prefix
   uint32_t* dyn_obj = nullptr;          // [kMaxObjects] dynamic-object flags

@@ -584,12 +584,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
         s_xy[pos] = xy;
         s_co[pos] = co;
         s_qm[pos] = qm;
-        const float* __restrict__ f = fo.feat + (rid - gbase);
-        float fv[kFeatMaxC];
+        // Gaussian-major copy: one 64-byte row per entry
+        const float4* __restrict__ f = reinterpret_cast<const float4*>(fo.feat16) + (size_t)(rid - gbase) * (kFeatMaxC / 4);
 #pragma unroll
-        for (int c = 0; c < kFeatMaxC; c++) fv[c] = c < fo.C ? f[(int64_t)c * fo.stride] : 0.f;
-#pragma unroll
-        for (int c = 0; c < kFeatMaxC / 4; c++) s_f[pos][c] = make_float4(fv[4 * c], fv[4 * c + 1], fv[4 * c + 2], fv[4 * c + 3]);
+        for (int c = 0; c < kFeatMaxC / 4; c++) s_f[pos][c] = f[c];
       }
       n_kept += __popcll(m);
     }
@@ -731,8 +729,23 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   }
 }
 
+// features [C][stride] -> Gaussian-major rows of kFeatMaxC floats (zeros beyond C)
+__global__ __launch_bounds__(256) void k_feat_rows(const float* __restrict__ feat, int64_t stride, int C, int n,
+                                                   float4* __restrict__ rows) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= n) return;
+  float v[kFeatMaxC];
+#pragma unroll
+  for (int c = 0; c < kFeatMaxC; c++) v[c] = c < C ? feat[c * stride + g] : 0.f;
+#pragma unroll
+  for (int c = 0; c < kFeatMaxC / 4; c++)
+    rows[(size_t)g * (kFeatMaxC / 4) + c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+}
+
 void launch_blend_feat(const ViewsIO& io, int nv, int64_t total_tiles, const FeatIO& fo, const Workspace& ws,
                        const uint32_t* vals, hipStream_t st) {
+  if (fo.n > 0)
+    k_feat_rows<<<(fo.n + 255) / 256, 256, 0, st>>>(fo.feat, fo.stride, fo.C, fo.n, reinterpret_cast<float4*>(fo.feat16));
   const int64_t total = total_tiles * io.sn;
   if (total == 0) return;
   const int per = per_xcd(total);
