@@ -150,6 +150,10 @@ def build_workload(args):
                   "st": HashField.init(geometric_res(16, 2048, 16), 2, 14, 64, lo, hi, dev, seed=2)}
         for f in fields.values():  # a field part-way through its optimisation: a non-zero output layer
             f.w2.normal_(0.0, 1e-3)
+        # H_dyn runs on a second stream with its own context (a context's calls may not overlap):
+        # its 20k queries cannot fill the GPU alone, so they share it with H_st's 180k
+        ctx_dyn = Context(max_gaussians=N, max_views=1, max_keys=1 << 10, max_tiles=16)
+        st.update(ctx_dyn=ctx_dyn, side=torch.cuda.Stream())
         st.update(rows=rows, dyn_rows=rows[:nd], st_rows=rows[nd:], ns=N - nd, fields=fields,
                   field_grads={k: f.zeros_like() for k, f in fields.items()},
                   field_mv={k: (f.zeros_like(), f.zeros_like()) for k, f in fields.items()},
@@ -163,12 +167,17 @@ def train_step(s, it, args, per_view=False):
     fields = s.get("fields")
     if fields:
         nd, ns = s["nd"], s["ns"]
-        ctx.hash_field_fwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["dpos"], s["drot"], col=0)
-        ctx.hash_field_fwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["dpos"], s["drot"], col=nd)
-        ctx.shift_fwd(g, gs, s["rows"], s["dpos"], s["drot"])
+        torch = s["torch"]
+        main, side = torch.cuda.current_stream(), s["side"]
         for f in s["field_grads"].values():
             for t in f.arrays():
                 t.zero_()
+        side.wait_stream(main)
+        s["ctx_dyn"].hash_field_fwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["dpos"], s["drot"], col=0,
+                                    stream=side)
+        ctx.hash_field_fwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["dpos"], s["drot"], col=nd)
+        main.wait_stream(side)
+        ctx.shift_fwd(g, gs, s["rows"], s["dpos"], s["drot"])
     else:
         ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
     for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
@@ -202,10 +211,12 @@ def train_step(s, it, args, per_view=False):
                            s["cnt"])
     if fields:
         ctx.shift_adjoint(g, s["rows"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
-        ctx.hash_field_bwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["d_dpos"], s["d_drot"],
-                           s["field_grads"]["dyn"], col=0)
+        side.wait_stream(main)
+        s["ctx_dyn"].hash_field_bwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["d_dpos"], s["d_drot"],
+                                    s["field_grads"]["dyn"], col=0, stream=side)
         ctx.hash_field_bwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["d_dpos"], s["d_drot"],
                            s["field_grads"]["st"], col=nd)
+        main.wait_stream(side)
         groups = []
         for k, f in fields.items():
             m, v = s["field_mv"][k]

@@ -139,6 +139,10 @@ class Trainer:
             self.field_grads[k] = f.zeros_like()
             self.field_mv[k] = (f.zeros_like(), f.zeros_like())
         cap = g.capacity
+        # H_dyn runs on a second stream with a context of its own (calls on one context may not
+        # overlap): its few queries cannot fill the GPU alone, so they share it with H_st's
+        self.ctx_dyn = Context(max_gaussians=cap, max_views=1, max_keys=1 << 10, max_tiles=16)
+        self.side = torch.cuda.Stream()
         self.shift_buf = torch.zeros(cap, dtype=torch.int32, device=dev)
         self.dpos_buf = torch.zeros(3, cap, device=dev)
         self.drot_buf = torch.zeros(4, cap, device=dev)
@@ -175,17 +179,20 @@ class Trainer:
     def iteration(self, stream=None):
         ctx, g, gs, cfg = self.ctx, self.g, self.gs, self.cfg
         gs.n, gs.n_base = g.n, g.n_base
+        cur = stream if stream is not None else torch.cuda.current_stream()
         if self.fields is not None:
             nd, ns, F = self.nd, self.ns, self.fields
-            ctx.hash_field_fwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._dpos, self._drot, col=0, stream=stream)
-            ctx.hash_field_fwd(F["st"], g.mean, g.n_base, self._st, ns, self._dpos, self._drot, col=nd, stream=stream)
-        ctx.shift_fwd(g, gs, self._shift_idx, self._dpos, self._drot, stream=stream)
-        for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
-            t.zero_()
-        if self.fields is not None:
             for k in ("dyn", "st"):
                 for t in self.field_grads[k].arrays():
                     t.zero_()
+            self.side.wait_stream(cur)
+            self.ctx_dyn.hash_field_fwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._dpos, self._drot, col=0,
+                                        stream=self.side)
+            ctx.hash_field_fwd(F["st"], g.mean, g.n_base, self._st, ns, self._dpos, self._drot, col=nd, stream=stream)
+            cur.wait_stream(self.side)
+        ctx.shift_fwd(g, gs, self._shift_idx, self._dpos, self._drot, stream=stream)
+        for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
+            t.zero_()
         if not cfg.per_view:
             if cfg.ssim_lambda > 0.0:
                 ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
@@ -215,10 +222,12 @@ class Trainer:
             ctx.shift_adjoint(g, self._shift_idx, self._drot, self.grads, self._d_dpos, self._d_drot, stream=stream)
         if self.fields is not None:
             nd, ns, F = self.nd, self.ns, self.fields
-            ctx.hash_field_bwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._d_dpos, self._d_drot,
-                               self.field_grads["dyn"], col=0, stream=stream)
+            self.side.wait_stream(cur)
+            self.ctx_dyn.hash_field_bwd(F["dyn"], g.mean, g.n_base, self._dyn, nd, self._d_dpos, self._d_drot,
+                                        self.field_grads["dyn"], col=0, stream=self.side)
             ctx.hash_field_bwd(F["st"], g.mean, g.n_base, self._st, ns, self._d_dpos, self._d_drot,
                                self.field_grads["st"], col=nd, stream=stream)
+            cur.wait_stream(self.side)
         groups = self._adam_groups()
         if groups:
             ctx.adam_step(groups, cfg.beta1, cfg.beta2, cfg.eps, stream=stream, d_step=self.d_step)
