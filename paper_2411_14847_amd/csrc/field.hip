@@ -29,6 +29,7 @@ constexpr int kFwdThreads = 64;     // one wave: small query counts still spread
 constexpr int kSliceFloats = 32768;  // table-gradient slice held in LDS (128 KB)
 constexpr int kSliceThreads = 1024;
 constexpr int kSliceTargetBlocks = 512;
+constexpr int kSliceBatch = 4;
 
 template <int F>
 constexpr int max_levels() { return (64 / F) < kFieldMaxLevels ? 64 / F : kFieldMaxLevels; }
@@ -322,20 +323,30 @@ __global__ __launch_bounds__(kSliceThreads) void k_field_table_grad(const FieldK
   const int q0 = (int)((int64_t)m * qp / sm.n_qparts), q1 = (int)((int64_t)m * (qp + 1) / sm.n_qparts);
   for (int i = threadIdx.x; i < kSliceFloats; i += kSliceThreads) s_g[i] = 0.f;
   __syncthreads();
-  for (int q = q0 + threadIdx.x; q < q1; q += kSliceThreads) {
-    double p[3];
+  // kSliceBatch queries per thread at a time: their loads are issued together
+  for (int q = q0 + threadIdx.x; q < q1; q += kSliceThreads * kSliceBatch) {
+    double p[kSliceBatch][3];
+    float dv[kSliceBatch][F];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) p[d] = pn[(size_t)d * m + q];
-    float dv[F];
+    for (int u = 0; u < kSliceBatch; ++u) {
+      const int qu = q + u * kSliceThreads;
+      const bool in = qu < q1;
 #pragma unroll
-    for (int i = 0; i < F; ++i) dv[i] = denc[(size_t)(l * F + i) * m + q];
-    level_corners(f, l, p, [&](int, uint32_t row, float w) {
-      const int64_t off = (int64_t)row * F;
-      if (off >= lo && off < hi) {
+      for (int d = 0; d < 3; ++d) p[u][d] = in ? pn[(size_t)d * m + qu] : 0.0;
 #pragma unroll
-        for (int i = 0; i < F; ++i) atomicAdd(&s_g[off - lo + i], w * dv[i]);
-      }
-    });
+      for (int i = 0; i < F; ++i) dv[u][i] = in ? denc[(size_t)(l * F + i) * m + qu] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kSliceBatch; ++u) {
+      if (q + u * kSliceThreads >= q1) break;
+      level_corners(f, l, p[u], [&](int, uint32_t row, float w) {
+        const int64_t off = (int64_t)row * F;
+        if (off >= lo && off < hi) {
+#pragma unroll
+          for (int i = 0; i < F; ++i) atomicAdd(&s_g[off - lo + i], w * dv[u][i]);
+        }
+      });
+    }
   }
   __syncthreads();
   if (sm.n_qparts == 1) {
