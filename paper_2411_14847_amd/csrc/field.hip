@@ -3,12 +3,14 @@
 // one ReLU hidden layer and seven outputs, the position offset (3) and the rotation offset (4,
 // added to the identity quaternion).
 //
-// Forward: one query per lane; the encoding (L levels x 8 corners, one F-float row each) sits in
-// registers and the weights are read with wave-uniform addresses.
+// Forward: a quad of lanes per query (lane s encodes the levels l = s mod 4 and takes the hidden
+// units h = s mod 4; DPP quad permutations complete the encoding and add the partial outputs), the
+// MLP weights staged in LDS.
 // Backward:
-//  1. one query per lane: the encoding and the MLP adjoint are recomputed and the rows the
-//     gradients need (per hidden unit dL/d(pre-activation) and activation, the encoding and its
-//     adjoint, the upstream gradient, the float64 position) go to a workspace, feature-major.
+//  1. a quad of lanes per query, as the forward: the encoding and the MLP adjoint are recomputed
+//     and the rows the gradients need (per hidden unit dL/d(pre-activation) and activation, the
+//     encoding and its adjoint, the upstream gradient, the float64 position) go to a workspace,
+//     feature-major.
 //  2. weight gradients: each workgroup sums a contiguous part of the queries through LDS and
 //     writes one partial row; the partials are then added in a fixed order.
 //  3. table gradients without global atomics: each workgroup owns one slice (up to 128 KB) of
@@ -25,7 +27,6 @@ namespace {
 
 constexpr uint32_t kPrimeY = 2654435761u;  // the encoding's spatial-hash primes (x: 1)
 constexpr uint32_t kPrimeZ = 805459861u;
-constexpr int kFwdThreads = 64;     // one wave: small query counts still spread over every CU
 constexpr int kSliceFloats = 32768;  // table-gradient slice held in LDS (128 KB)
 constexpr int kSliceThreads = 1024;
 constexpr int kSliceTargetBlocks = 512;
@@ -91,70 +92,133 @@ __device__ __forceinline__ void level_corners(const FieldK& f, int l, const doub
   }
 }
 
-// Calls fn(level, float offset of the corner's row in the table, trilinear weight) for the 8
-// corners of each level's cell around p.
-template <int F, class Fn>
-__device__ __forceinline__ void for_corners(const FieldK& f, const double p[3], Fn&& fn) {
-  constexpr int KL = max_levels<F>();
+// ---- four lanes per query -------------------------------------------------------------------
+// A quad of lanes shares a query: lane s encodes the levels l = s (mod 4) and takes the hidden
+// units h = s (mod 4); the encoding is completed and the partial sums combined with DPP quad
+// permutations.  Four times the waves of one lane per query, a quarter of the chain each, for the
+// latency-bound small calls (the dynamic group's field queries a tenth of the Gaussians).
+constexpr int kQuadThreads = 256;  // 64 queries per workgroup
+
+template <int CTRL>
+__device__ __forceinline__ float qdpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float quad_sum(float x) {
+  x += qdpp<0xB1>(x);  // quad_perm [1, 0, 3, 2]
+  x += qdpp<0x4E>(x);  // quad_perm [2, 3, 0, 1]
+  return x;
+}
+template <int K>
+__device__ __forceinline__ float quad_bcast(float x) {
+  return qdpp<K * 0x55>(x);  // quad_perm [K, K, K, K]
+}
+
+// MLP weights in LDS: w1 rows padded to LFM + 4 floats (zeros beyond L F), so the quad's four
+// rows h = 4u + s fall in different banks
+template <int F, int HID>
+struct QuadW {
+  static constexpr int LFM = max_levels<F>() * F, LS = LFM + 4;
+  float4 w1[HID * LS / 4];
+  float w2[7][HID];
+  float b1[HID];
+};
+
+template <int F, int HID>
+__device__ __forceinline__ void stage_weights(const FieldK& f, QuadW<F, HID>& s) {
+  constexpr int LFM = QuadW<F, HID>::LFM, LS = QuadW<F, HID>::LS;
+  const int LF = f.L * F;
+  float* w1 = reinterpret_cast<float*>(s.w1);
+  for (int e = threadIdx.x; e < HID * LS; e += kQuadThreads) {
+    const int h = e / LS, k = e % LS;
+    w1[e] = k < LF ? f.w1[h * LF + k] : 0.f;
+  }
+  for (int e = threadIdx.x; e < 7 * HID; e += kQuadThreads) s.w2[e / HID][e % HID] = f.w2[e];
+  for (int e = threadIdx.x; e < HID; e += kQuadThreads) s.b1[e] = f.b1[e];
+  (void)LFM;
+  __syncthreads();
+}
+
+// This lane's levels (l = sub + 4 r) of the encoding, then the whole encoding in every lane of the quad.
+template <int F>
+__device__ __forceinline__ void quad_encode(const FieldK& f, const double p[3], int sub, float* mine, float* enc) {
+  constexpr int KL = max_levels<F>(), KLQ = (KL + 3) / 4;
+#pragma unroll
+  for (int r = 0; r < KLQ; ++r) {
+    const int l = sub + 4 * r;
+#pragma unroll
+    for (int i = 0; i < F; ++i) mine[r * F + i] = 0.f;
+    if (l < f.L && l < KL) {
+      const size_t base = (size_t)l << f.log2T;
+      level_corners(f, l, p, [&](int, uint32_t row, float w) {
+        float v[F];
+        load_row<F>(f.table + (base + row) * F, v);
+#pragma unroll
+        for (int i = 0; i < F; ++i) mine[r * F + i] = fmaf(w, v[i], mine[r * F + i]);
+      });
+    }
+  }
 #pragma unroll
   for (int l = 0; l < KL; ++l) {
-    if (l < f.L) {
-      const size_t base = (size_t)l << f.log2T;
-      level_corners(f, l, p, [&](int, uint32_t row, float w) { fn(l, (base + row) * F, w); });
+#pragma unroll
+    for (int i = 0; i < F; ++i) {
+      const float x = mine[(l >> 2) * F + i];
+      float y;
+      switch (l & 3) {
+        case 0: y = quad_bcast<0>(x); break;
+        case 1: y = quad_bcast<1>(x); break;
+        case 2: y = quad_bcast<2>(x); break;
+        default: y = quad_bcast<3>(x); break;
+      }
+      enc[l * F + i] = y;
     }
   }
 }
 
-template <int F>
-__device__ __forceinline__ void encode(const FieldK& f, const double p[3], float* enc) {
-  constexpr int KL = max_levels<F>();
+template <int F, int HID>
+__device__ __forceinline__ float quad_pre(const QuadW<F, HID>& s, int h, const float* enc) {
+  constexpr int LFM = QuadW<F, HID>::LFM, LS = QuadW<F, HID>::LS;
+  float a = s.b1[h];
 #pragma unroll
-  for (int i = 0; i < KL * F; ++i) enc[i] = 0.f;
-  for_corners<F>(f, p, [&](int l, size_t off, float w) {
-    float v[F];
-    load_row<F>(f.table + off, v);
-#pragma unroll
-    for (int i = 0; i < F; ++i) enc[l * F + i] = fmaf(w, v[i], enc[l * F + i]);
-  });
-}
-
-// pre-activation of hidden unit h: b1[h] + W1[h] . enc (levels beyond L hold zeros)
-template <int F>
-__device__ __forceinline__ float hidden_pre(const FieldK& f, int h, int LF, const float* enc) {
-  constexpr int KL = max_levels<F>();
-  const float* __restrict__ w = f.w1 + h * LF;
-  float a = f.b1[h];
-#pragma unroll
-  for (int l = 0; l < KL; ++l)
-    if (l < f.L) {
-#pragma unroll
-      for (int i = 0; i < F; ++i) a = fmaf(w[l * F + i], enc[l * F + i], a);
-    }
+  for (int c = 0; c < LFM / 4; ++c) {
+    const float4 w = s.w1[(h * LS) / 4 + c];
+    a = fmaf(w.x, enc[4 * c], a);
+    a = fmaf(w.y, enc[4 * c + 1], a);
+    a = fmaf(w.z, enc[4 * c + 2], a);
+    a = fmaf(w.w, enc[4 * c + 3], a);
+  }
   return a;
 }
 
 template <int F, int HID>
-__global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const QueryK q,
-                                                           float* __restrict__ dpos, float* __restrict__ drot) {
-  constexpr int KL = max_levels<F>();
-  const int j = blockIdx.x * kFwdThreads + threadIdx.x;
-  if (j >= q.m) return;
-  const int g = q.idx ? q.idx[j] : j;
+__global__ __launch_bounds__(kQuadThreads) void k_field_fwd4(const FieldK f, const QueryK q, float* __restrict__ dpos,
+                                                            float* __restrict__ drot) {
+  constexpr int KL = max_levels<F>(), LFM = KL * F, KLQ = (KL + 3) / 4;
+  __shared__ QuadW<F, HID> s;
+  stage_weights<F, HID>(f, s);
+  const int sub = threadIdx.x & 3;
+  const int j = blockIdx.x * (kQuadThreads / 4) + (threadIdx.x >> 2);
+  if (j >= q.m) return;  // the whole quad
+  int g = q.idx ? q.idx[j] : j;
+  const bool valid = g >= 0 && g < q.n;
   float out[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (g >= 0 && g < q.n) {
+  if (valid) {
     double p[3];
     normalised(f, q, g, p);
-    float enc[KL * F];
-    encode<F>(f, p, enc);
-    const int LF = f.L * F;
+    float mine[KLQ * F], enc[LFM];
+    quad_encode<F>(f, p, sub, mine, enc);
 #pragma unroll
-    for (int o = 0; o < 7; ++o) out[o] = f.b2[o];
-    for (int h = 0; h < HID; ++h) {
-      const float a = fmaxf(hidden_pre<F>(f, h, LF, enc), 0.f);
+    for (int u = 0; u < HID / 4; ++u) {
+      const int h = 4 * u + sub;
+      const float a = fmaxf(quad_pre<F, HID>(s, h, enc), 0.f);
 #pragma unroll
-      for (int o = 0; o < 7; ++o) out[o] = fmaf(f.w2[o * HID + h], a, out[o]);
+      for (int o = 0; o < 7; ++o) out[o] = fmaf(s.w2[o][h], a, out[o]);
     }
+#pragma unroll
+    for (int o = 0; o < 7; ++o) out[o] = quad_sum(out[o]);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) out[o] += f.b2[o];
   }
+  if (sub != 0) return;
 #pragma unroll
   for (int d = 0; d < 3; ++d) dpos[d * q.ld + j] = out[d];
   drot[j] = 1.f + out[3];
@@ -162,24 +226,29 @@ __global__ __launch_bounds__(kFwdThreads) void k_field_fwd(const FieldK f, const
   for (int d = 1; d < 4; ++d) drot[d * q.ld + j] = out[3 + d];
 }
 
-// Backward, per query (one lane each, like the forward): the encoding and the MLP adjoint.  Writes,
-// feature-major over the queries, what the weight and table gradients need: dL/d(pre-activation)
-// and the activation of every hidden unit, the encoding and its adjoint, the upstream gradient
-// (zeros for rows outside [0, n)) and the float64 normalised position.
+// Backward per query with a quad per query: writes, feature-major over the queries, what the weight
+// and table gradients need -- dL/d(pre-activation) and the activation of every hidden unit (by the
+// lane that owns the unit), the encoding and its adjoint (by the lane that owns the level), the
+// upstream gradient (zeros for rows outside [0, n)) and the float64 normalised position.
 template <int F, int HID>
-__global__ __launch_bounds__(kFwdThreads) void k_field_bwd_query(const FieldK f, const QueryK q,
-                                                                 const float* __restrict__ d_dpos,
-                                                                 const float* __restrict__ d_drot, FieldRows rows) {
-  constexpr int KL = max_levels<F>();
-  constexpr int LFM = KL * F;
-  const int j = blockIdx.x * kFwdThreads + threadIdx.x;
+__global__ __launch_bounds__(kQuadThreads) void k_field_bwd_query4(const FieldK f, const QueryK q,
+                                                                  const float* __restrict__ d_dpos,
+                                                                  const float* __restrict__ d_drot, FieldRows rows) {
+  constexpr int KL = max_levels<F>(), LFM = KL * F, KLQ = (KL + 3) / 4;
+  constexpr int LS = QuadW<F, HID>::LS;
+  __shared__ QuadW<F, HID> s;
+  stage_weights<F, HID>(f, s);
+  const int sub = threadIdx.x & 3;
+  const int j = blockIdx.x * (kQuadThreads / 4) + (threadIdx.x >> 2);
   if (j >= q.m) return;
   const int64_t m = q.m;
   int g = q.idx ? q.idx[j] : j;
   if (g < 0 || g >= q.n) g = -1;
   double p[3] = {0.0, 0.0, 0.0};
   float dout[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float enc[LFM];
+  float mine[KLQ * F], enc[LFM];
+#pragma unroll
+  for (int i = 0; i < KLQ * F; ++i) mine[i] = 0.f;
 #pragma unroll
   for (int i = 0; i < LFM; ++i) enc[i] = 0.f;
   if (g >= 0) {
@@ -188,41 +257,47 @@ __global__ __launch_bounds__(kFwdThreads) void k_field_bwd_query(const FieldK f,
     for (int d = 0; d < 3; ++d) dout[d] = d_dpos[d * q.ld + j];
 #pragma unroll
     for (int d = 0; d < 4; ++d) dout[3 + d] = d_drot[d * q.ld + j];
-    encode<F>(f, p, enc);
+    quad_encode<F>(f, p, sub, mine, enc);
   }
-  const int LF = f.L * F;
   float denc[LFM];
 #pragma unroll
   for (int i = 0; i < LFM; ++i) denc[i] = 0.f;
-  for (int h = 0; h < HID; ++h) {
-    const float a = hidden_pre<F>(f, h, LF, enc);
+#pragma unroll
+  for (int u = 0; u < HID / 4; ++u) {
+    const int h = 4 * u + sub;
+    const float a = quad_pre<F, HID>(s, h, enc);
     float dh = 0.f;
 #pragma unroll
-    for (int o = 0; o < 7; ++o) dh = fmaf(f.w2[o * HID + h], dout[o], dh);
+    for (int o = 0; o < 7; ++o) dh = fmaf(s.w2[o][h], dout[o], dh);
     const float dp = a > 0.f ? dh : 0.f;
     rows.dpre[h * m + j] = dp;
     rows.act[h * m + j] = fmaxf(a, 0.f);
-    const float* __restrict__ w = f.w1 + h * LF;
 #pragma unroll
-    for (int l = 0; l < KL; ++l)
-      if (l < f.L) {
-#pragma unroll
-        for (int i = 0; i < F; ++i) denc[l * F + i] = fmaf(w[l * F + i], dp, denc[l * F + i]);
-      }
+    for (int c = 0; c < LFM / 4; ++c) {
+      const float4 w = s.w1[(h * LS) / 4 + c];
+      denc[4 * c] = fmaf(w.x, dp, denc[4 * c]);
+      denc[4 * c + 1] = fmaf(w.y, dp, denc[4 * c + 1]);
+      denc[4 * c + 2] = fmaf(w.z, dp, denc[4 * c + 2]);
+      denc[4 * c + 3] = fmaf(w.w, dp, denc[4 * c + 3]);
+    }
   }
 #pragma unroll
+  for (int i = 0; i < LFM; ++i) denc[i] = quad_sum(denc[i]);
+#pragma unroll
   for (int l = 0; l < KL; ++l)
-    if (l < f.L) {
+    if ((l & 3) == sub && l < f.L) {
 #pragma unroll
       for (int i = 0; i < F; ++i) {
-        rows.enc[(l * F + i) * m + j] = enc[l * F + i];
+        rows.enc[(l * F + i) * m + j] = mine[(l >> 2) * F + i];
         rows.denc[(l * F + i) * m + j] = denc[l * F + i];
       }
     }
+  if (sub == 0) {
 #pragma unroll
-  for (int o = 0; o < 7; ++o) rows.dout[o * m + j] = dout[o];
+    for (int o = 0; o < 7; ++o) rows.dout[o * m + j] = dout[o];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) rows.pn[d * m + j] = p[d];
+    for (int d = 0; d < 3; ++d) rows.pn[d * m + j] = p[d];
+  }
 }
 
 // Weight gradients: a workgroup sums a contiguous part of the queries, staging 64 queries' rows
@@ -411,34 +486,34 @@ __global__ __launch_bounds__(256) void k_field_reduce(const float* __restrict__ 
 
 template <int HID>
 void fwd_f(int F, const FieldK& f, const QueryK& q, float* dpos, float* drot, hipStream_t st) {
-  const int blocks = (q.m + kFwdThreads - 1) / kFwdThreads;
+  const int blocks = (q.m + kQuadThreads / 4 - 1) / (kQuadThreads / 4);
   switch (F) {
-    case 1: k_field_fwd<1, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
-    case 2: k_field_fwd<2, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
-    case 4: k_field_fwd<4, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
-    default: k_field_fwd<8, HID><<<blocks, kFwdThreads, 0, st>>>(f, q, dpos, drot); break;
+    case 1: k_field_fwd4<1, HID><<<blocks, kQuadThreads, 0, st>>>(f, q, dpos, drot); break;
+    case 2: k_field_fwd4<2, HID><<<blocks, kQuadThreads, 0, st>>>(f, q, dpos, drot); break;
+    case 4: k_field_fwd4<4, HID><<<blocks, kQuadThreads, 0, st>>>(f, q, dpos, drot); break;
+    default: k_field_fwd4<8, HID><<<blocks, kQuadThreads, 0, st>>>(f, q, dpos, drot); break;
   }
 }
 
 template <int HID>
 void bwd_f(int F, int blocks, const FieldK& f, const QueryK& q, const float* d_dpos, const float* d_drot,
            const FieldRows& rows, float* part, hipStream_t st) {
-  const int qb = (q.m + kFwdThreads - 1) / kFwdThreads;
+  const int qb4 = (q.m + kQuadThreads / 4 - 1) / (kQuadThreads / 4);
   switch (F) {
     case 1:
-      k_field_bwd_query<1, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_bwd_query4<1, HID><<<qb4, kQuadThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
       k_field_wgrad<1, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
       break;
     case 2:
-      k_field_bwd_query<2, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_bwd_query4<2, HID><<<qb4, kQuadThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
       k_field_wgrad<2, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
       break;
     case 4:
-      k_field_bwd_query<4, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_bwd_query4<4, HID><<<qb4, kQuadThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
       k_field_wgrad<4, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
       break;
     default:
-      k_field_bwd_query<8, HID><<<qb, kFwdThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
+      k_field_bwd_query4<8, HID><<<qb4, kQuadThreads, 0, st>>>(f, q, d_dpos, d_drot, rows);
       k_field_wgrad<8, HID><<<blocks, kWgThreads, 0, st>>>(f, q.m, rows, part);
       break;
   }
