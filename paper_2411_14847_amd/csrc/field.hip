@@ -449,23 +449,24 @@ __global__ __launch_bounds__(256) void k_field_table_sum(const FieldK f, SliceMa
 }
 
 // grad += sum over the workgroups' partials (fixed order): a workgroup takes kRedCols columns,
-// its 8 row groups each sum every 8th partial row, then the groups are added in order.
-constexpr int kRedCols = 32;
-__global__ __launch_bounds__(256) void k_field_reduce(const float* __restrict__ part, int rows, int stride,
-                                                      int n_w1, int hid, float* __restrict__ gw1,
-                                                      float* __restrict__ gb1, float* __restrict__ gw2,
-                                                      float* __restrict__ gb2) {
-  __shared__ float s_sum[8][kRedCols];
+// its kRedGroups row groups each sum every kRedGroups-th partial row, then the groups are added
+// in order.
+constexpr int kRedCols = 32, kRedGroups = 32;
+__global__ __launch_bounds__(kRedCols * kRedGroups) void k_field_reduce(const float* __restrict__ part, int rows,
+                                                                        int stride, int n_w1, int hid,
+                                                                        float* __restrict__ gw1, float* __restrict__ gb1,
+                                                                        float* __restrict__ gw2, float* __restrict__ gb2) {
+  __shared__ float s_sum[kRedGroups][kRedCols];
   const int col = threadIdx.x % kRedCols, rg = threadIdx.x / kRedCols;
   const int c = blockIdx.x * kRedCols + col;
   float s = 0.f;
   if (c < stride)
-    for (int r = rg; r < rows; r += 8) s += part[(size_t)r * stride + c];
+    for (int r = rg; r < rows; r += kRedGroups) s += part[(size_t)r * stride + c];
   s_sum[rg][col] = s;
   __syncthreads();
   if (rg != 0 || c >= stride) return;
   s = s_sum[0][col];
-  for (int k = 1; k < 8; ++k) s += s_sum[k][col];
+  for (int k = 1; k < kRedGroups; ++k) s += s_sum[k][col];
   float* dst;
   int i;
   if (c < n_w1) {
@@ -543,8 +544,8 @@ void launch_field_bwd(const FieldK& f, int F, int hidden, const QueryK& q, const
     bwd_f<64>(F, blocks, f, q, d_dpos, d_drot, ws.rows, ws.part, st);
   const int LF = f.L * F;
   const int stride = field_part_stride(hidden, LF);
-  k_field_reduce<<<(stride + kRedCols - 1) / kRedCols, 256, 0, st>>>(ws.part, blocks, stride, hidden * LF, hidden,
-                                                                    g.w1, g.b1, g.w2, g.b2);
+  k_field_reduce<<<(stride + kRedCols - 1) / kRedCols, kRedCols * kRedGroups, 0, st>>>(
+      ws.part, blocks, stride, hidden * LF, hidden, g.w1, g.b1, g.w2, g.b2);
   if (g.table) {
     SliceMap sm{};
     int total = 0;
