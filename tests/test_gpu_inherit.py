@@ -164,3 +164,29 @@ def test_inheritance_extremes_keep_all_or_none():
         assert before == rows[0]["appended"] > 0
         assert kept == (before if want == "all" else 0)
         tr.ctx.sync()
+
+
+def test_compact_var_fullsize():
+    """Compaction at the benchmark's scale: 200k Gaussians (SH3), 50k of them G^var, masked by m
+    and floored at opacity 0.005, bit-exact against the oracle."""
+    rng = np.random.default_rng(41)
+    scene, _, _ = synth.multiview_scene(41, n=200_000, n_views=1, width=64, height=48, with_grads=False)
+    n_base = 150_000
+    nv = scene.n - n_base
+    scene.logit[n_base:] = rng.normal(-2.0, 2.5, size=nv).astype(np.float32)
+    m = synth.inheritance_logits(42, nv, frac_masked=0.5)
+    keep = INH.keep_rows(scene.logit, n_base, m, 0.005)
+    planes = {"mean": scene.mean, "quat": scene.quat, "log_scale": scene.log_scale, "logit": scene.logit,
+              "sh": scene.sh}
+    want = INH.compact(planes, n_base, keep)
+    g = to_gpu(scene, n_base=n_base)
+    ctx = make_ctx(scene.n, synth.streaming_rig(32, 32)[:1])
+    kept = torch.zeros(1, dtype=torch.int32, device="cuda")
+    log(f"compact fullsize n={scene.n} n_var={nv} keep={int(keep.sum())}")
+    ctx.compact_var(g, dev(m), 0.005, kept)
+    ctx.sync()
+    k = int(kept.item())
+    assert k == int(keep.sum())
+    got = {"mean": g.mean, "quat": g.quat, "log_scale": g.log_scale, "logit": g.logit, "sh": g.sh}
+    for name, t in got.items():
+        np.testing.assert_array_equal(t[..., :n_base + k].cpu().numpy(), want[name].astype(np.float32))
