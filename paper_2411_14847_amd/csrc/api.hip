@@ -935,14 +935,14 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
     return fail(ctx, DASS_E_INVALID, "bad arguments");
   if (g->n_base > 0 && (!gradnorm_sum || !grad_count))
     return fail(ctx, DASS_E_INVALID, "gradnorm_sum / grad_count is NULL");
-  if (g->n_base > ctx->ws.cap_vn) return fail(ctx, DASS_E_CAPACITY, "n_base exceeds the reserved workspace");
+  if (g->n_base > ctx->ws.cap_vn || g->n_base > ctx->ws.cap_g)
+    return fail(ctx, DASS_E_CAPACITY, "n_base exceeds the reserved workspace");
   DensifyArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nv = n_views;
   a.gamma_err = gamma_err;
   a.tau_pos = tau_pos;
   a.tau_err = tau_err;
-  a.gbits = std::max(1, bit_width((uint64_t)(g->n_base > 0 ? g->n_base - 1 : 0)));
   for (int v = 0; v < n_views; v++) {
     if (!err_maps[v]) return fail(ctx, DASS_E_INVALID, "err_maps[%d] is NULL", v);
     const dass_camera& c = cams[v];
@@ -964,10 +964,13 @@ dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* 
   const SceneK sc = scene_of(g);
   stage_begin(ctx, DASS_STAGE_DENSIFY, st);
   launch_fill_u32(ws.counters + 1, 0u, 1, st);
-  launch_densify_select(sc, a, gradnorm_sum, grad_count, g->n_base, ws.dkey[0], ws.dval[0], ws.counters + 1, st);
-  // rank by score (descending) then index: sort only the 32 + gbits bits the key occupies
-  const int cur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 1, g->n_base, 0, 32 + a.gbits, ws.hist,
-                                 sort_blocks_for(g->n_base), st);
+  // members packed in index order into u32 keys (the depth-sort buffers, free here), the score key
+  // staged in the second buffer; a stable 32-bit sort ranks by score, ties by index
+  uint32_t* k32[2] = {reinterpret_cast<uint32_t*>(ws.dkey[0]), reinterpret_cast<uint32_t*>(ws.dkey[1])};
+  launch_densify_select(sc, a, gradnorm_sum, grad_count, g->n_base, ws.keep, ws.keep_scan, ws.scan_tmp, k32[1], k32[0],
+                        ws.dval[0], ws.counters + 1, st);
+  const int cur = radix_sort_u32(k32, ws.dval, ws.counters + 1, g->n_base, 0, 32, ws.hist, sort_blocks_for(g->n_base),
+                                 st);
   const int K = (g->sh_degree + 1) * (g->sh_degree + 1);
   launch_densify_spawn(g->mean, g->quat, g->log_scale, g->opacity_logit, g->sh, 3 * K, g->capacity, g->n,
                        g->capacity, ws.dval[cur], ws.counters + 1, k_max, seed, n_appended, st);

@@ -325,11 +325,10 @@ struct DensifyArgs {
   CamK cams[DASS_MAX_VIEWS];
   int nv;
   float gamma_err, tau_pos, tau_err;
-  int gbits;  // bits of a base index: ranking key = (~float bits of the score) << gbits | index
 };
-void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* gsum, const int32_t* gcnt,
-                           int n_base, uint64_t* sel_keys, uint32_t* sel_vals, uint32_t* d_count,
-                           hipStream_t st);
+void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* gsum, const int32_t* gcnt, int n_base,
+                           uint32_t* keep, uint64_t* pos, uint64_t* scan_tmp, uint32_t* score_key, uint32_t* sel_keys,
+                           uint32_t* sel_vals, uint32_t* d_count, hipStream_t st);
 void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
                           int stride, int n, int capacity, const uint32_t* sel_idx, const uint32_t* d_count,
                           int k_max, uint64_t seed, int32_t* n_appended, hipStream_t st);

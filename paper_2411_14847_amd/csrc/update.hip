@@ -175,15 +175,16 @@ __device__ bool alg1_pixel(const double* T, int Wi, int Hi, double X, double Y, 
 
 // Selection (Alg. 1): a workgroup takes 64 base Gaussians, its wave w the views w, w + 4, ...
 // (the view index stays uniform over a wave); the score is the largest error at the Gaussian's
-// pixel over the views that see it.  Wave 0 combines the four waves and appends the selected
-// Gaussians with one atomic.
+// pixel over the views that see it.  Wave 0 combines the four waves and writes, per Gaussian, the
+// membership flag and the rank key (complemented score bits: ascending key = descending score);
+// a scan then packs the members in index order, so a stable sort on the 32-bit key alone ranks
+// them with ties by index.
 constexpr int kSelWaves = 4;
 __global__ __launch_bounds__(64 * kSelWaves) void k_densify_select(SceneK s, DensifyArgs a,
                                                                    const float* __restrict__ gsum,
                                                                    const int32_t* __restrict__ gcnt, int n_base,
-                                                                   uint64_t* __restrict__ sel_keys,
-                                                                   uint32_t* __restrict__ sel_vals,
-                                                                   uint32_t* __restrict__ d_count) {
+                                                                   uint32_t* __restrict__ keep,
+                                                                   uint32_t* __restrict__ score_key) {
   __shared__ double s_T[DASS_MAX_VIEWS][12];
   __shared__ float s_score[kSelWaves][64];
   __shared__ int s_ie[kSelWaves][64];
@@ -214,21 +215,25 @@ __global__ __launch_bounds__(64 * kSelWaves) void k_densify_select(SceneK s, Den
     score = fmaxf(score, s_score[w][lane]);
     ie |= s_ie[w][lane];
   }
-  bool in_s = false;
-  if (g < n_base) {
-    const int32_t c = gcnt[g];
-    const float gbar = c > 0 ? gsum[g] / (float)c : 0.f;
-    in_s = (gbar > a.tau_pos) || (ie != 0 && gbar > a.tau_err);
-  }
-  const uint64_t m = __ballot(in_s);
-  if (m == 0) return;
-  uint32_t base = 0;
-  if (lane == 0) base = atomicAdd(d_count, (uint32_t)__popcll(m));
-  base = __shfl(base, 0, 64);
-  if (!in_s) return;
-  const uint32_t pos = base + (uint32_t)__popcll(m & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
-  sel_keys[pos] = ((uint64_t)(~__float_as_uint(score)) << a.gbits) | (uint64_t)(uint32_t)g;
-  sel_vals[pos] = (uint32_t)g;
+  if (g >= n_base) return;
+  const int32_t c = gcnt[g];
+  const float gbar = c > 0 ? gsum[g] / (float)c : 0.f;
+  const bool in_s = (gbar > a.tau_pos) || (ie != 0 && gbar > a.tau_err);
+  keep[g] = in_s ? 1u : 0u;
+  score_key[g] = ~__float_as_uint(score);
+}
+
+// members packed in index order: key and Gaussian index at the member's rank in the scan
+__global__ __launch_bounds__(256) void k_densify_pack(int n_base, const uint32_t* __restrict__ keep,
+                                                      const uint64_t* __restrict__ pos,
+                                                      const uint32_t* __restrict__ score_key,
+                                                      uint32_t* __restrict__ sel_keys, uint32_t* __restrict__ sel_vals,
+                                                      uint32_t* __restrict__ d_count) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g == 0) *d_count = (uint32_t)pos[n_base];
+  if (g >= n_base || !keep[g]) return;
+  sel_keys[pos[g]] = score_key[g];
+  sel_vals[pos[g]] = (uint32_t)g;
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
@@ -324,10 +329,12 @@ void launch_l1(const L1Args& a, int64_t total_blocks, float* loss, hipStream_t s
 }
 
 void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* gsum, const int32_t* gcnt, int n_base,
-                           uint64_t* sel_keys, uint32_t* sel_vals, uint32_t* d_count, hipStream_t st) {
-  if (n_base > 0)
-    k_densify_select<<<(n_base + 63) / 64, 64 * kSelWaves, 0, st>>>(s, a, gsum, gcnt, n_base, sel_keys, sel_vals,
-                                                                    d_count);
+                           uint32_t* keep, uint64_t* pos, uint64_t* scan_tmp, uint32_t* score_key, uint32_t* sel_keys,
+                           uint32_t* sel_vals, uint32_t* d_count, hipStream_t st) {
+  if (n_base <= 0) return;  // *d_count stays at the zero the caller wrote
+  k_densify_select<<<(n_base + 63) / 64, 64 * kSelWaves, 0, st>>>(s, a, gsum, gcnt, n_base, keep, score_key);
+  scan_u32_to_u64(keep, pos, n_base, scan_tmp, st);
+  k_densify_pack<<<(n_base + 255) / 256, 256, 0, st>>>(n_base, keep, pos, score_key, sel_keys, sel_vals, d_count);
 }
 
 void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
