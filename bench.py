@@ -91,6 +91,7 @@ def build_workload(args):
 
     import synth
     from paper_2411_14847_amd import Context, GaussianBuffers, RenderOut
+    from paper_2411_14847_amd.api import zeroed_grads
 
     if args.workload == "multiview":
         scene, cams, _ = synth.multiview_scene(args.seed, n=args.n, n_views=args.views, width=args.width,
@@ -122,6 +123,10 @@ def build_workload(args):
     ctx.shift_fwd(g, gs, dyn, torch.as_tensor(motion.dpos, device=dev), torch.as_tensor(motion.dquat, device=dev))
     targets = [o.rgb.clone() for o in ctx.render_fwd(gs, cams, args.bg)]
     ctx.sync()
+    # the step's accumulators (gradients, loss, historical gradient sums, offset gradients) share
+    # one buffer, cleared by one fill per step
+    zbuf, zgrads, zextra = zeroed_grads(g, [((1,), torch.float32), ((cap,), torch.float32), ((cap,), torch.int32),
+                                            ((3, nd), torch.float32), ((4, nd), torch.float32)])
     st = dict(
         torch=torch, ctx=ctx, g=g, gs=gs, cams=cams, dyn=dyn, targets=targets, name=name, scene=scene,
         outs=[RenderOut.allocate(c) for c in cams],
@@ -129,10 +134,8 @@ def build_workload(args):
         errs=[torch.zeros(c.height, c.width, device=dev) for c in cams],
         ssim_scratch=([torch.empty(9 * c.height * c.width, device=dev) for c in cams]
                       if getattr(args, "ssim_lambda", 0.0) > 0.0 else None),
-        grads=g.zeros_like(), loss=torch.zeros(1, device=dev),
-        gn=torch.zeros(cap, device=dev), cnt=torch.zeros(cap, dtype=torch.int32, device=dev),
+        zbuf=zbuf, grads=zgrads, loss=zextra[0], gn=zextra[1], cnt=zextra[2], d_dpos=zextra[3], d_drot=zextra[4],
         dpos=torch.zeros(3, nd, device=dev), drot=torch.cat([torch.ones(1, nd), torch.zeros(3, nd)]).to(dev),
-        d_dpos=torch.zeros(3, nd, device=dev), d_drot=torch.zeros(4, nd, device=dev),
         m=[torch.zeros(3, nd, device=dev), torch.zeros(4, nd, device=dev)],
         v=[torch.zeros(3, nd, device=dev), torch.zeros(4, nd, device=dev)],
         n_app=torch.zeros(1, dtype=torch.int32, device=dev), nd=nd, N=N, cap=cap,
@@ -180,8 +183,10 @@ def train_step(s, it, args, per_view=False):
         ctx.shift_fwd(g, gs, s["rows"], s["dpos"], s["drot"])
     else:
         ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
-    for t in (*s["grads"].planes(), s["gn"], s["cnt"], s["loss"], s["d_dpos"], s["d_drot"]):
-        t.zero_()
+    s["zbuf"].zero_()
+    if fields:  # the fields' offset gradients cover every base row (their own buffers)
+        s["d_dpos"].zero_()
+        s["d_drot"].zero_()
     lam = getattr(args, "ssim_lambda", 0.0)
     if not per_view and lam > 0.0:
         # Eq. (3) with its D-SSIM term: the render, then the fidelity loss over the images

@@ -93,6 +93,35 @@ class GaussianBuffers:
                                self.sh.clone(), self.n, self.n_base, self.sh_degree)
 
 
+def carve_zeroed(specs, device="cuda"):
+    """One zeroed device buffer holding contiguous tensors of the given (shape, dtype) specs
+    (float32 or int32, each starting on a 256-byte boundary), so that per-step accumulators are
+    cleared by a single fill of the buffer.  Returns (buffer, [tensors])."""
+    sizes = [int(np.prod(shape)) for shape, _ in specs]
+    offs, o = [], 0
+    for n in sizes:
+        offs.append(o)
+        o += (n + 63) // 64 * 64
+    buf = torch.zeros(max(o, 1), dtype=torch.float32, device=device)
+    out = []
+    for (shape, dt), off, n in zip(specs, offs, sizes):
+        t = buf[off:off + n]
+        if dt == torch.int32:
+            t = t.view(torch.int32)
+        out.append(t.view(*shape))
+    return buf, out
+
+
+def zeroed_grads(g: "GaussianBuffers", extra=()):
+    """Gradient planes shaped like g plus the extra (shape, dtype) tensors, carved from one buffer:
+    (buffer, GaussianBuffers of gradients, [extra tensors])."""
+    cap, P = g.capacity, g.sh.shape[0]
+    specs = [((3, cap), torch.float32), ((4, cap), torch.float32), ((3, cap), torch.float32),
+             ((cap,), torch.float32), ((P, cap), torch.float32), *extra]
+    buf, t = carve_zeroed(specs, g.mean.device)
+    return buf, GaussianBuffers(*t[:5], g.n, g.n_base, g.sh_degree), t[5:]
+
+
 def grads_struct(g: Optional[GaussianBuffers]) -> F.Grads:
     if g is None:
         return F.Grads()

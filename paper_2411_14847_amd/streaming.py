@@ -26,7 +26,7 @@ from typing import Dict, List
 
 import torch
 
-from .api import Context, GaussianBuffers, RenderOut
+from .api import Context, GaussianBuffers, RenderOut, zeroed_grads
 
 
 @dataclass
@@ -86,8 +86,9 @@ class Trainer:
         self.ssim_scratch = ([torch.empty(9 * c.height * c.width, device=dev) for c in self.cams]
                              if cfg.ssim_lambda > 0.0 else None)
         self.targets = [torch.zeros(3, c.height, c.width, device=dev) for c in self.cams]
-        self.grads = g.zeros_like()
-        self.loss = torch.zeros(1, device=dev)
+        # gradients and loss share one buffer, cleared by one fill per iteration; the historical
+        # positional-gradient sums (Sec. 3.4) accumulate over the timestep's iterations
+        self.zbuf, self.grads, (self.loss,) = zeroed_grads(g, [((1,), torch.float32)])
         self.gn = torch.zeros(cap, device=dev)
         self.cnt = torch.zeros(cap, dtype=torch.int32, device=dev)
         self.n_app = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -191,8 +192,9 @@ class Trainer:
             ctx.hash_field_fwd(F["st"], g.mean, g.n_base, self._st, ns, self._dpos, self._drot, col=nd, stream=stream)
             cur.wait_stream(self.side)
         ctx.shift_fwd(g, gs, self._shift_idx, self._dpos, self._drot, stream=stream)
-        for t in (*self.grads.planes(), self.gn, self.cnt, self.loss, self._d_dpos, self._d_drot):
-            t.zero_()
+        self.zbuf.zero_()
+        self._d_dpos.zero_()
+        self._d_drot.zero_()
         if not cfg.per_view:
             if cfg.ssim_lambda > 0.0:
                 ctx.render_fwd(gs, self.cams, cfg.bg, out=self.outs, stream=stream)
@@ -256,8 +258,8 @@ class Trainer:
         vm.zero_()
         ge = GaussianBuffers(g.mean, g.quat, self.ls_eff, self.lg_eff, g.sh, g.n, g.n_base, g.sh_degree)
         for it in range(cfg.inherit_iters):
-            for t_ in (*self.grads.planes(), self.loss, dm):
-                t_.zero_()
+            self.zbuf.zero_()
+            dm.zero_()
             ctx.inherit_apply(g, m, self.lg_eff, self.ls_eff)
             if cfg.ssim_lambda > 0.0:
                 ctx.render_fwd(ge, self.cams, cfg.bg, out=self.outs)
@@ -282,6 +284,8 @@ class Trainer:
             self.inherited = self.inheritance_stage()
         nd = int(dyn_idx.numel())
         self.nd = nd
+        self.gn.zero_()
+        self.cnt.zero_()
         for t_ in (*self.m_var.planes(), *self.v_var.planes()):
             t_.zero_()
         self.d_step.zero_()
