@@ -270,7 +270,8 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
 /* A deformation field H_dyn or H_st: the multi-resolution hash encoding of a position followed
  * by an MLP with one ReLU hidden layer, giving the shift offsets of Sec. 3.3.  For a query at
  * mu: p = clamp((mu - aabb_min) / (aabb_max - aabb_min), 0, 1) per axis; at level l, with
- * x = p N_l, the cell c0 = min(floor(x), N_l - 1) and frac = x - c0, the encoding's F features
+ * x = p N_l, the cell c0 = min(floor(x), N_l - 1) and frac = x - c0 (p, x and c0 in float64), the
+ * encoding's F features
  * are the trilinear blend of the rows of the 8 corners c0 + d (d in {0,1}^3, weight
  * prod(d ? frac : 1 - frac)); a corner's row is c_x + (N_l+1)(c_y + (N_l+1) c_z) when
  * (N_l+1)^3 <= T, else (c_x xor c_y 2654435761 xor c_z 805459861) mod T (32-bit unsigned).
