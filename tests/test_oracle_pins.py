@@ -972,3 +972,23 @@ def test_dynamic_gaussians_brute_force():
     np.testing.assert_array_equal(dyn_obj, want_obj)
     want_idx = [g for g in range(n) if want_obj[max(range(K), key=lambda k: (float(cls_w[k] @ feat[:, g] + cls_b[k]), -k))]]
     np.testing.assert_array_equal(idx, want_idx)
+
+
+def test_hash_field_weight_orientation():
+    """w1[h][k] maps feature k to hidden unit h and w2[o][h] hidden unit h to output o: with a
+    single 1 at w1[5][2] and w2[1][5], the y offset is the ReLU of encoding feature 2 and every
+    other output is zero (a misread index would take another feature or write another output)."""
+    f = _field([6], 4, 10, 8)
+    f.table[:] = np.abs(f.table) + 0.1
+    f.w1[:] = 0.0
+    f.w1[5, 2] = 1.0
+    f.b1[:] = 0.0
+    f.w2[:] = 0.0
+    f.w2[1, 5] = 1.0
+    f.b2[:] = 0.0
+    mean = np.random.default_rng(12).uniform(-1.4, 1.4, size=(3, 30))
+    enc = HF.encode(f, HF.normalised(f, mean))
+    dp, dr = HF.field_fwd(f, mean)
+    np.testing.assert_allclose(dp[1], enc[:, 2], rtol=0, atol=1e-15)
+    assert np.all(dp[0] == 0) and np.all(dp[2] == 0) and np.all(dr[1:] == 0) and np.all(dr[0] == 1)
+    assert np.abs(enc[:, 2] - enc[:, 1]).max() > 1e-3  # features differ, so a wrong index shows
