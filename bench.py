@@ -739,8 +739,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         if rank == 0:
-            print("bench.py measures one GPU only: this build has no multi-GPU path (views would shard "
-                  "across GPUs with one gradient all-reduce; see the design notes).", file=sys.stderr)
+            print("bench.py measures one GPU only: the library has no multi-GPU path (views would shard "
+                  "across GPUs with one gradient all-reduce per iteration).", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

@@ -42,7 +42,7 @@ typedef enum {
   DASS_E_OOM = 2,         /* device allocation failed (create / reserve only)      */
   DASS_E_CAPACITY = 3,    /* request exceeds the reserved limits                   */
   DASS_E_HIP = 4,         /* a HIP call failed                                     */
-  DASS_E_UNSUPPORTED = 5  /* valid request this build does not handle              */
+  DASS_E_UNSUPPORTED = 5  /* valid request the library does not handle             */
 } dass_status;
 
 #define DASS_MAX_VIEWS 32  /* views per render call */
