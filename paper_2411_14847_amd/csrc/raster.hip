@@ -117,14 +117,35 @@ __global__ void k_clamp_count(const uint64_t* __restrict__ total, int64_t cap, u
   *count = (uint32_t)(t < (uint64_t)cap ? t : (uint64_t)cap);
 }
 
+// Per-tile ranges of the sorted keys: four consecutive keys per thread (one 16-byte load) and
+// their two neighbours; a key that differs from its predecessor starts a range, one that differs
+// from its successor ends it.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_count,
                                                 uint2* __restrict__ ranges) {
-  const uint32_t count = *d_count;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-    const uint32_t t = keys[i];
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == count - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  const int64_t count = *d_count;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < count; i0 += stride) {
+    uint32_t k[6];  // keys i0 - 1 .. i0 + 4 (entries outside [0, count) unused)
+    if (i0 + 4 <= count) {
+      const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+      k[1] = v.x;
+      k[2] = v.y;
+      k[3] = v.z;
+      k[4] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; j++) k[1 + j] = i0 + j < count ? keys[i0 + j] : 0u;
+    }
+    k[0] = i0 > 0 ? keys[i0 - 1] : 0u;
+    k[5] = i0 + 4 < count ? keys[i0 + 4] : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int64_t i = i0 + j;
+      if (i >= count) break;
+      const uint32_t t = k[1 + j];
+      if (i == 0 || k[j] != t) ranges[t].x = (uint32_t)i;
+      if (i == count - 1 || k[2 + j] != t) ranges[t].y = (uint32_t)(i + 1);
+    }
   }
 }
 
@@ -689,7 +710,7 @@ void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipSt
 
 void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st) {
   launch_fill_u32(reinterpret_cast<uint32_t*>(ws.ranges), 0u, 2 * total_tiles, st);
-  int64_t blocks = (ws.cap_keys + 255) / 256;
+  int64_t blocks = (ws.cap_keys + 1023) / 1024;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   k_ranges<<<(unsigned)blocks, 256, 0, st>>>(keys, ws.counters, ws.ranges);
