@@ -108,3 +108,26 @@ def test_dynamic_mask_matches_oracle(n_objects):
     assert 0 < k <= scene.n
     if n_objects > 8:
         assert 0 < dyn_obj.sum() < n_objects and k < scene.n  # a proper subset
+
+
+def test_dynamic_mask_degenerate_cases():
+    """No flow above the threshold: no dynamic object and no dynamic Gaussian; no Gaussians at
+    all: an empty list with the count written."""
+    scene, cams, _ = synth.multiview_scene(37, n=800, n_views=2, width=64, height=48, with_grads=False)
+    feat, _, cls_w, cls_b = synth.identity_setup(38, scene.n, n_objects=5)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    ctx.render_fwd(g, cams, BG)
+    fdev = torch.zeros(16, g.capacity, device="cuda")
+    fdev[:, :scene.n] = dev(feat)
+    F = ctx.render_features(g, cams, fdev)
+    flows = [torch.zeros(c.height, c.width, device="cuda") for c in cams]
+    idx = torch.full((scene.n,), -1, dtype=torch.int32, device="cuda")
+    nd = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    objs = torch.full((5,), 9, dtype=torch.int32, device="cuda")
+    ctx.dynamic_mask(cams, F, flows, 1.0, dev(cls_w), dev(cls_b), fdev, scene.n, idx, nd, dyn_objects=objs)
+    ctx.sync()
+    assert int(nd.item()) == 0 and int(objs.abs().sum()) == 0
+    ctx.dynamic_mask(cams, F, flows, 1.0, dev(cls_w), dev(cls_b), fdev, 0, idx, nd)
+    ctx.sync()
+    assert int(nd.item()) == 0
