@@ -28,6 +28,12 @@ constexpr int kThreads = 256;
 constexpr float kC1 = 0.01f * 0.01f;
 constexpr float kC2 = 0.03f * 0.03f;
 
+// Workgroups are dealt to the XCDs round-robin; remapping gives each XCD a contiguous range of
+// tiles, so the halos a tile shares with its neighbours are read through the same L2.
+__device__ __forceinline__ int64_t tile_of_block(int64_t bid, int64_t per) {
+  return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
 __device__ __forceinline__ int view_of_block(const SsimArgs& a, int64_t blk) {
   int v = 0;
   while (v + 1 < a.nv && blk >= a.v[v + 1].block_begin) v++;
@@ -72,12 +78,14 @@ __device__ __forceinline__ void stage(float (*dst)[kE][kEP], const float* const 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_ssim_fwd(SsimArgs a, float* __restrict__ loss_slots) {
+__global__ __launch_bounds__(kThreads) void k_ssim_fwd(SsimArgs a, int64_t total, int64_t per,
+                                                           float* __restrict__ loss_slots) {
   __shared__ float s_xy[2][kE][kEP];  // render, target
   __shared__ float s_h[5][kE][kHP];    // horizontal sums of x, y, x^2, y^2, xy
   __shared__ float s_w[4];
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = tile_of_block(blockIdx.x, per);
+  if (blk >= total) return;  // uniform over the workgroup
   const int vi = view_of_block(a, blk);
   const SsimView& V = a.v[vi];
   const int t = (int)(blk - V.block_begin);
@@ -162,12 +170,14 @@ __global__ __launch_bounds__(kThreads) void k_ssim_fwd(SsimArgs a, float* __rest
   add_to_slot(ssum, gS, s_w, loss_slots);
 }
 
-__global__ __launch_bounds__(kThreads) void k_ssim_bwd(SsimArgs a, float* __restrict__ loss_slots) {
+__global__ __launch_bounds__(kThreads) void k_ssim_bwd(SsimArgs a, int64_t total, int64_t per,
+                                                           float* __restrict__ loss_slots) {
   __shared__ float s_p[3][kE][kEP];
   __shared__ float s_h[3][kE][kHP];
   __shared__ float s_w[4];
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  const int64_t blk = tile_of_block(blockIdx.x, per);
+  if (blk >= total) return;  // uniform over the workgroup
   const int vi = view_of_block(a, blk);
   const SsimView& V = a.v[vi];
   const int t = (int)(blk - V.block_begin);
@@ -246,8 +256,9 @@ int ssim_tile_edge() { return kT; }
 
 void launch_ssim(const SsimArgs& a, int64_t total_blocks, float* loss_slots, hipStream_t st) {
   if (total_blocks <= 0) return;
-  k_ssim_fwd<<<(unsigned)total_blocks, kThreads, 0, st>>>(a, loss_slots);
-  k_ssim_bwd<<<(unsigned)total_blocks, kThreads, 0, st>>>(a, loss_slots);
+  const int64_t per = (total_blocks + kNumXcd - 1) / kNumXcd;
+  k_ssim_fwd<<<(unsigned)(per * kNumXcd), kThreads, 0, st>>>(a, total_blocks, per, loss_slots);
+  k_ssim_bwd<<<(unsigned)(per * kNumXcd), kThreads, 0, st>>>(a, total_blocks, per, loss_slots);
 }
 
 }  // namespace dass
