@@ -232,6 +232,12 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, int tw, int
   if (total_tiles > ctx->ws.cap_tiles)
     return fail(ctx, DASS_E_CAPACITY, "%lld tiles exceed max_tiles %lld", (long long)total_tiles,
                 (long long)ctx->ws.cap_tiles);
+  int64_t max_view_tiles = 1;
+  for (int v = 0; v < nv; v++) max_view_tiles = std::max(max_view_tiles, (int64_t)out.c[v].TX * out.c[v].TY);
+  out.local_bits = bit_width((uint64_t)(max_view_tiles - 1));
+  if (out.local_bits > 31 || out.local_bits + bit_width((uint64_t)(nv - 1)) > 32)
+    return fail(ctx, DASS_E_CAPACITY, "%lld tiles per view do not fit a 32-bit tile key", (long long)max_view_tiles);
+  for (int v = 0; v < nv; v++) out.c[v].key_base = (uint32_t)v << out.local_bits;
   return DASS_OK;
 }
 
@@ -424,12 +430,12 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   launch_emit_keys(g->n, vn, ck, ws, st);
   stage_end(ctx, DASS_STAGE_BINNING, st);
   stage_begin(ctx, DASS_STAGE_KEY_SORT, st);
-  const int kcur = radix_sort_u32(ws.keys, ws.vals, ws.counters, ws.cap_keys, 0,
-                                  bit_width((uint64_t)(total_tiles > 0 ? total_tiles - 1 : 0)), ws.hist,
+  // keys arrive in view order, so the tile within the view is the only part left to sort
+  const int kcur = radix_sort_u32(ws.keys, ws.vals, ws.counters, ws.cap_keys, 0, ck.local_bits, ws.hist,
                                   sort_blocks_for(ws.cap_keys), st);
   stage_end(ctx, DASS_STAGE_KEY_SORT, st);
   stage_begin(ctx, DASS_STAGE_RANGES, st);
-  launch_ranges(ws.keys[kcur], total_tiles, ws, st);
+  launch_ranges(ws.keys[kcur], total_tiles, ck, n_views, ws, st);
   stage_end(ctx, DASS_STAGE_RANGES, st);
   // 4. blend
   if (count_pairs) launch_fill_u32(reinterpret_cast<uint32_t*>(ws.pairs), 0u, 4, st);
@@ -989,19 +995,24 @@ dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t
   const int nt = c.TX * c.TY;
   std::vector<uint2> r(nt);
   HIP_TRY(ctx, hipMemcpy(r.data(), ctx->ws.ranges + c.tile_base, nt * sizeof(uint2), hipMemcpyDeviceToHost));
-  uint32_t lo = 0xFFFFFFFFu, hi = 0;
-  for (const uint2& x : r)
-    if (x.y > x.x) {
-      lo = std::min(lo, x.x);
-      hi = std::max(hi, x.y);
+  // the view's tiles are runs of the sorted keys (runs of all views interleave); concatenated in
+  // tile order they are the view's key list
+  std::vector<int64_t> rel(2 * (size_t)nt, 0);
+  int64_t cnt = 0;
+  for (int t = 0; t < nt; t++)
+    if (r[t].y > r[t].x) {
+      rel[2 * t] = cnt;
+      cnt += r[t].y - r[t].x;
+      rel[2 * t + 1] = cnt;
     }
-  if (hi == 0) lo = 0;
-  const uint32_t cnt = hi - lo;
   *count = cnt;
-  if ((int64_t)cnt > max) return fail(ctx, DASS_E_CAPACITY, "view has %u keys", cnt);
+  if (cnt > max) return fail(ctx, DASS_E_CAPACITY, "view has %lld keys", (long long)cnt);
   if (cnt > 0 && (!keys || !vals)) return DASS_E_INVALID;
-  launch_debug_keys(view, ctx->fwd_n, ctx->ws, ctx->ws.keys[ctx->fwd_key_buf], ctx->ws.vals[ctx->fwd_key_buf], lo, cnt,
-                    c, keys, vals, ranges, nullptr);
+  HIP_TRY(ctx, hipMemcpy(ranges, rel.data(), rel.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  for (int t = 0; t < nt; t++)
+    if (r[t].y > r[t].x)
+      launch_debug_keys(view, ctx->fwd_n, ctx->ws, ctx->ws.keys[ctx->fwd_key_buf], ctx->ws.vals[ctx->fwd_key_buf],
+                        r[t].x, r[t].y - r[t].x, c, keys + rel[2 * t], vals + rel[2 * t], nullptr);
   HIP_TRY(ctx, hipDeviceSynchronize());
   return check_launch(ctx, "dass_debug_keys");
 }

@@ -35,10 +35,15 @@ struct CamK {
   float campos[3];
   int W, H, TX, TY;
   int tw, th;     // tile size in pixels
-  int tile_base;  // first global tile index of this view
+  int tile_base;      // first global tile index of this view
+  uint32_t key_base;  // view << CamsK::local_bits: the view's part of a tile key
 };
+// Tile keys are (view << local_bits) | tile within the view, local_bits wide enough for every
+// view's tiles: keys are emitted in view order, so a stable sort of the low local_bits alone
+// groups each (view, tile) into one run.
 struct CamsK {
   CamK c[DASS_MAX_VIEWS];
+  int local_bits;
 };
 
 struct SceneK {
@@ -241,7 +246,7 @@ int sort_blocks_for(int64_t max_count);
 void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspace& ws, hipStream_t st);
 // emits keys into ws.keys[0]/ws.vals[0] and writes the clamped key count to ws.counters[0]
 void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipStream_t st);
-void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st);
+void launch_ranges(const uint32_t* keys, int64_t total_tiles, const CamsK& cams, int nv, Workspace& ws, hipStream_t st);
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3],
                       const Workspace& ws, const uint32_t* vals, bool count_pairs, bool l1, hipStream_t st);
 // Adds the loss partial sums and `add` to *loss (fixed order) and clears the sums.
@@ -253,9 +258,8 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 // identity features of the last render's lists (same weights as its colour blend)
 void launch_blend_feat(const ViewsIO& io, int nv, int64_t total_tiles, const FeatIO& fo, const Workspace& ws,
                        const uint32_t* vals, hipStream_t st);
-void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted,
-                       const uint32_t* vals_sorted, uint32_t lo, uint32_t cnt, const CamK& cam,
-                       uint64_t* kout, uint32_t* vout, int64_t* rout, hipStream_t st);
+void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,
+                       uint32_t lo, uint32_t cnt, const CamK& cam, uint64_t* kout, uint32_t* vout, hipStream_t st);
 
 // update.hip
 void launch_shift_fwd(const SceneK& in, float* out_mean, float* out_quat, const int32_t* dyn_idx,

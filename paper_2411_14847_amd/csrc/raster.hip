@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_emit_keys(int n, int64_t vn, CamsK cams
     const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF;
     const int w = max(x1 - x0, 1);
     const int TX = cams.c[v].TX;
-    s_g[wave][lane] = make_uint4((uint32_t)(cams.c[v].tile_base + y0 * TX + x0), (uint32_t)TX, (uint32_t)w,
+    s_g[wave][lane] = make_uint4(cams.c[v].key_base + (uint32_t)(y0 * TX + x0), (uint32_t)TX, (uint32_t)w,
                                  __float_as_uint(1.0f / (float)w));
     s_rec[wave][lane] = (uint32_t)((int64_t)v * n + sorted_gid[pm]);
   }
@@ -117,11 +117,18 @@ __global__ void k_clamp_count(const uint64_t* __restrict__ total, int64_t cap, u
   *count = (uint32_t)(t < (uint64_t)cap ? t : (uint64_t)cap);
 }
 
+// Global tile index of a key: the view's first tile plus the tile within the view.
+struct KeyTiles {
+  int tile_base[DASS_MAX_VIEWS];
+  int local_bits, nv;
+  uint32_t total_tiles;
+};
+
 // Per-tile ranges of the sorted keys: four consecutive keys per thread (one 16-byte load) and
 // their two neighbours; a key that differs from its predecessor starts a range, one that differs
-// from its successor ends it.
+// from its successor ends it.  Ranges are stored by global tile index.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ d_count,
-                                                uint2* __restrict__ ranges) {
+                                                const KeyTiles kt, uint2* __restrict__ ranges) {
   const int64_t count = *d_count;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
   for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < count; i0 += stride) {
@@ -142,9 +149,15 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     for (int j = 0; j < 4; j++) {
       const int64_t i = i0 + j;
       if (i >= count) break;
-      const uint32_t t = k[1 + j];
-      if (i == 0 || k[j] != t) ranges[t].x = (uint32_t)i;
-      if (i == count - 1 || k[2 + j] != t) ranges[t].y = (uint32_t)(i + 1);
+      const uint32_t key = k[1 + j];
+      const bool starts = i == 0 || k[j] != key, ends = i == count - 1 || k[2 + j] != key;
+      if (!starts && !ends) continue;
+      const uint32_t v = key >> kt.local_bits;
+      if (v >= (uint32_t)kt.nv) continue;  // not reached: every key below the count was emitted
+      const uint32_t t = (uint32_t)kt.tile_base[v] + (key & ((1u << kt.local_bits) - 1u));
+      if (t >= kt.total_tiles) continue;
+      if (starts) ranges[t].x = (uint32_t)i;
+      if (ends) ranges[t].y = (uint32_t)(i + 1);
     }
   }
 }
@@ -664,25 +677,15 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
   }
 }
 
-__global__ void k_debug_keys(int view_tile_base, uint32_t row0, const uint32_t* __restrict__ keys,
+__global__ void k_debug_keys(uint32_t key_base, uint32_t row0, const uint32_t* __restrict__ keys,
                              const uint32_t* __restrict__ vals, const Rec* __restrict__ rec, uint32_t lo,
                              uint32_t cnt, uint64_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   const uint32_t k = keys[lo + i];
   const uint32_t p = vals[lo + i];  // record index of the view's Gaussian
-  kout[i] = ((uint64_t)(k - (uint32_t)view_tile_base) << 32) | (uint64_t)__float_as_uint(rec[p].r2.w);
+  kout[i] = ((uint64_t)(k - key_base) << 32) | (uint64_t)__float_as_uint(rec[p].r2.w);
   vout[i] = p - row0;
-}
-
-__global__ void k_debug_ranges(const uint2* __restrict__ ranges, int tile_base, int n_tiles, uint32_t lo,
-                               int64_t* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const uint2 r = ranges[tile_base + t];
-  const bool empty = r.y <= r.x;
-  out[2 * t] = empty ? 0 : (int64_t)(r.x - lo);
-  out[2 * t + 1] = empty ? 0 : (int64_t)(r.y - lo);
 }
 
 }  // namespace
@@ -708,12 +711,18 @@ void launch_emit_keys(int n, int64_t vn, const CamsK& cams, Workspace& ws, hipSt
   k_clamp_count<<<1, 1, 0, st>>>(ws.off_s + vn, ws.cap_keys, ws.counters);
 }
 
-void launch_ranges(const uint32_t* keys, int64_t total_tiles, Workspace& ws, hipStream_t st) {
+void launch_ranges(const uint32_t* keys, int64_t total_tiles, const CamsK& cams, int nv, Workspace& ws,
+                   hipStream_t st) {
   launch_fill_u32(reinterpret_cast<uint32_t*>(ws.ranges), 0u, 2 * total_tiles, st);
+  KeyTiles kt{};
+  for (int v = 0; v < nv; v++) kt.tile_base[v] = cams.c[v].tile_base;
+  kt.local_bits = cams.local_bits;
+  kt.nv = nv;
+  kt.total_tiles = (uint32_t)total_tiles;
   int64_t blocks = (ws.cap_keys + 1023) / 1024;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
-  k_ranges<<<(unsigned)blocks, 256, 0, st>>>(keys, ws.counters, ws.ranges);
+  k_ranges<<<(unsigned)blocks, 256, 0, st>>>(keys, ws.counters, kt, ws.ranges);
 }
 
 static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNumXcd - 1) / kNumXcd); }
@@ -810,13 +819,10 @@ void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
 }
 
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,
-                       uint32_t lo, uint32_t cnt, const CamK& cam, uint64_t* kout, uint32_t* vout, int64_t* rout,
-                       hipStream_t st) {
+                       uint32_t lo, uint32_t cnt, const CamK& cam, uint64_t* kout, uint32_t* vout, hipStream_t st) {
   if (cnt > 0)
-    k_debug_keys<<<(cnt + 255) / 256, 256, 0, st>>>(cam.tile_base, (uint32_t)((int64_t)view * n), keys_sorted,
+    k_debug_keys<<<(cnt + 255) / 256, 256, 0, st>>>(cam.key_base, (uint32_t)((int64_t)view * n), keys_sorted,
                                                      vals_sorted, ws.rec_u, lo, cnt, kout, vout);
-  const int nt = cam.TX * cam.TY;
-  k_debug_ranges<<<(nt + 255) / 256, 256, 0, st>>>(ws.ranges, cam.tile_base, nt, lo, rout);
 }
 
 }  // namespace dass
