@@ -430,9 +430,11 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   launch_emit_keys(g->n, vn, ck, ws, st);
   stage_end(ctx, DASS_STAGE_BINNING, st);
   stage_begin(ctx, DASS_STAGE_KEY_SORT, st);
-  // keys arrive in view order, so the tile within the view is the only part left to sort
+  // keys arrive in view order, so the tile within the view is the only part left to sort.  An
+  // 11-bit digit costs the scatter twice a 10-bit one's per-batch digit work: over the keys of a
+  // multi-view call two narrower passes are faster, over one view's keys the single pass is
   const int kcur = radix_sort_u32(ws.keys, ws.vals, ws.counters, ws.cap_keys, 0, ck.local_bits, ws.hist,
-                                  sort_blocks_for(ws.cap_keys), st);
+                                  sort_blocks_for(ws.cap_keys), st, n_views > 1 ? 10 : 11);
   stage_end(ctx, DASS_STAGE_KEY_SORT, st);
   stage_begin(ctx, DASS_STAGE_RANGES, st);
   launch_ranges(ws.keys[kcur], total_tiles, ck, n_views, ws, st);

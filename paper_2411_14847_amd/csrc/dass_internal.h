@@ -239,7 +239,8 @@ size_t scan_tmp_elems(int64_t n);
 int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count,
                    int begin_bit, int end_bit, uint32_t* hist, int blocks, hipStream_t st);
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count,
-                   int begin_bit, int end_bit, uint32_t* hist, int blocks, hipStream_t st);
+                   int begin_bit, int end_bit, uint32_t* hist, int blocks, hipStream_t st,
+                   int digit_cap = 11);
 int sort_blocks_for(int64_t max_count);
 
 // raster.hip

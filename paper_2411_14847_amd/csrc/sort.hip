@@ -11,6 +11,8 @@
 //       digit; each wave ranks its own 512 consecutive pairs), orders the batch by digit in
 //       LDS and writes each digit's run contiguously.
 // A pass never depends on forward progress between workgroups.
+#include <algorithm>
+
 #include "dass_internal.h"
 
 namespace dass {
@@ -350,12 +352,12 @@ void radix_pass(K* keys[2], uint32_t* vals[2], int cur, const uint32_t* d_count,
 
 template <typename K>
 int radix_sort_impl(K* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
-                    int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
+                    int end_bit, uint32_t* hist, int blocks, hipStream_t st, int digit_cap) {
   int cur = 0;
   if (max_count == 0 || end_bit <= begin_bit) return cur;
   // fewest passes of at most max_bits, with the narrowest digit (>= 8 bits) that keeps that pass
   // count: wider digits cost LDS and ballots per item
-  constexpr int max_bits = sizeof(K) == 4 ? kMaxRadixBits : kMaxRadixBits - 1;
+  const int max_bits = std::max(8, std::min(digit_cap, sizeof(K) == 4 ? kMaxRadixBits : kMaxRadixBits - 1));
   const int bits = end_bit - begin_bit;
   const int passes = (bits + max_bits - 1) / max_bits;
   const int rb = max(8, (bits + passes - 1) / passes);
@@ -385,12 +387,13 @@ int sort_blocks_for(int64_t max_count) {
 
 int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
                    int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
-  return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st);
+  return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st,
+                                   kMaxRadixBits);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
-                   int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
-  return radix_sort_impl<uint32_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st);
+                   int end_bit, uint32_t* hist, int blocks, hipStream_t st, int digit_cap) {
+  return radix_sort_impl<uint32_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st, digit_cap);
 }
 
 size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
