@@ -160,3 +160,27 @@ def test_autotuner_marks_candidates_over_budget():
     log(f"  autotune under a tight key budget: {res}")
     assert res[(16, 16)] is None and res[(32, 32)] is not None and ctx.tile == (32, 32)
     ctx.sync()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (64, 32)])
+def test_keys_of_views_of_different_sizes(tile):
+    """Tile keys are relative to their view: views of 1352x1014 (5,440 16x16 tiles, whose ids
+    take two sort passes; 352 at 64x32, one pass) batched with a 40x30 view. Keys, values and
+    ranges of every view bit-exact against the oracle."""
+    scene, _, _ = synth.multiview_scene(51, n=3000, n_views=1, width=1352, height=1014, with_grads=False)
+    cams = synth.multiview_rig(1352, 1014)[:2] + synth.multiview_rig(40, 30)[2:3]
+    log(f"[keys by view] tile {tile}, sizes {[(c.width, c.height) for c in cams]}")
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    ctx.tile = tile
+    ctx.render_fwd(g, cams, BG)
+    ctx.sync()
+    for v, cam in enumerate(cams):
+        p = oracle.project(scene, cam, tile)
+        k, val, r = oracle.keys(p, cam, tile)
+        TX, TY = oracle.tiles_of(cam, tile)
+        gk, gv, gr = ctx.debug_keys(v, k.size + 16, TX * TY)
+        assert k.size > 0
+        np.testing.assert_array_equal(gk, k)
+        np.testing.assert_array_equal(gv, val)
+        np.testing.assert_array_equal(gr, r)
