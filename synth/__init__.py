@@ -277,6 +277,52 @@ def tiny_scene(seed: int, n: int, width: int, height: int, sh_degree: int = 0, l
     return Scene(mean, quat, log_scale, logit, sh, sh_degree), [cam], [dl]
 
 
+def yawed_camera(campos, yaw_deg: float, pitch_deg: float, width: int, height: int) -> Camera:
+    """Camera at campos looking along +z turned by yaw (about the camera's y axis) then pitch
+    (about its x axis)."""
+    a, b = math.radians(yaw_deg), math.radians(pitch_deg)
+    ry = np.array([[math.cos(a), 0.0, -math.sin(a)], [0.0, 1.0, 0.0], [math.sin(a), 0.0, math.cos(a)]])
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, math.cos(b), math.sin(b)], [0.0, -math.sin(b), math.cos(b)]])
+    return make_camera(rx @ ry, campos, width, height)
+
+
+def off_frustum_scene(seed: int, n: int, width: int, height: int, n_views: int = 1, sh_degree: int = 3,
+                      frac_outside: float = 0.7):
+    """Gaussians placed beside the field of view with footprints large enough to reach the image,
+    seen by n_views cameras on a short horizontal line, turned by yaw and pitch U[-8, 8] degrees
+    (view 0 looks straight along +z).
+
+    In view 0's image plane a Gaussian's centre sits at (a_x W/2, a_y H/2) pixels from the image
+    centre, at depth U[2, 6].  A fraction frac_outside lies off the image, half to the left or
+    right (|a_x| in U[1.3, 1.75], a_y in U[-1, 1]) and half above or below (|a_y| in U[1.3, 1.75],
+    a_x in U[-1, 1]); the rest lies on the image (|a_x|, |a_y| < 1).  Scales give a footprint
+    standard deviation of U[0.15, 0.35] x W/2 pixels at the Gaussian's depth (log-scales perturbed
+    by N(0, 0.3) per axis), so about three standard deviations reach back into the image.
+    Draw order: views' yaw and pitch, class, offsets, depth, scale factor, log-scale noise, then
+    quaternions, opacity logits, colour coefficients, upstream gradients N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    turns = rng.uniform(-8.0, 8.0, size=(n_views, 2))
+    turns[0] = 0.0
+    cams = [yawed_camera((0.15 * v, 0.0, 0.0), turns[v, 0], turns[v, 1], width, height) for v in range(n_views)]
+    cls = rng.uniform(0.0, 1.0, size=n)
+    off = rng.uniform(1.3, 1.75, size=n) * rng.choice([-1.0, 1.0], size=n)
+    inner = rng.uniform(-1.0, 1.0, size=(2, n))
+    ax = np.where(cls < frac_outside / 2, off, inner[0])
+    ay = np.where((cls >= frac_outside / 2) & (cls < frac_outside), off, inner[1])
+    z = rng.uniform(2.0, 6.0, size=n)
+    f = focal_from_fov(width)
+    xc = np.stack([ax * (width / 2.0) / f * z, ay * (height / 2.0) / f * z, z])
+    c0 = cams[0]
+    mean = (c0.R.astype(np.float64).T @ (xc - c0.t.astype(np.float64)[:, None])).astype(np.float32)
+    sd_px = rng.uniform(0.15, 0.35, size=n) * (width / 2.0)
+    log_scale = (np.log(sd_px * z / f)[None, :] + rng.normal(0.0, 0.3, size=(3, n))).astype(np.float32)
+    quat = _quats(rng, n)
+    logit = rng.normal(0.0, 1.0, size=n).astype(np.float32)
+    sh = _colour_coeffs(rng, n, sh_degree, 0.2)
+    dls = [rng.normal(0.0, 1.0, size=(3, height, width)).astype(np.float32) for _ in cams]
+    return Scene(mean, quat, log_scale, logit, sh, sh_degree), cams, dls
+
+
 @dataclass
 class HashFieldParams:
     """Parameters of one hash-encoded deformation field (float32): per-level grid resolutions,

@@ -98,6 +98,79 @@ def test_projection_matches_numeric_jacobian_and_scipy_rotation(seed):
     assert p.radius[0] == math.ceil(3 * math.sqrt(lam))
 
 
+def clip_ratio_limits(cam):
+    """1.3 x the half field-of-view tangents (the float32 constant 1.3 widened)."""
+    c = float(np.float32(1.3))
+    return c * cam.width / (2.0 * cam.fx), c * cam.height / (2.0 * cam.fy)
+
+
+def clamped_visible(p, cam):
+    """Visible Gaussians whose centre lies beyond the Jacobian clamp in x or y (from the pixel
+    mean: (u - c_x) / f_x = t_x / t_z)."""
+    limx, limy = clip_ratio_limits(cam)
+    rx = (p.uv[:, 0] - cam.cx) / cam.fx
+    ry = (p.uv[:, 1] - cam.cy) / cam.fy
+    return p.visible & ((np.abs(rx) > limx) | (np.abs(ry) > limy))
+
+
+@pytest.mark.parametrize("ax,ay", [(1.55, 0.2), (-1.7, -0.4), (0.3, 1.6), (-0.5, -1.45), (1.5, -1.5)])
+def test_jacobian_clamp_closed_form(ax, ay):
+    """A Gaussian whose centre lies beyond 1.3x the half field of view (App. A.1's J evaluated with
+    t_x/t_z and t_y/t_z clipped) but whose footprint reaches the image: Sigma_2D equals the
+    numerically differentiated pinhole map taken at the clipped point (lim t_z in place of t_x),
+    while the pixel mean stays the unclipped projection.  The unclipped Jacobian gives a
+    different footprint, so the clip is what is pinned."""
+    W, H = 64, 48
+    rng = np.random.default_rng(int(1000 * (ax + 3 * ay)) % 2**31)
+    R_cam = Rotation.from_rotvec(rng.normal(scale=0.1, size=3)).as_matrix()
+    cam = synth.make_camera(R_cam, rng.normal(scale=0.2, size=3), W, H)
+    z = 3.0
+    xc = np.array([ax * (W / 2) / cam.fx * z, ay * (H / 2) / cam.fy * z, z])
+    Rw = cam.R.astype(np.float64)
+    mean = Rw.T @ (xc - cam.t.astype(np.float64))
+    q = rng.normal(size=4).astype(np.float32)
+    ls = np.log(np.array([0.35, 0.3, 0.25]) * z * (W / 2) / cam.fx).astype(np.float32)
+    sc = one_gaussian_scene(mean, q, ls, 1.0)
+    p = oracle.project(sc, cam)
+    assert p.visible[0], "the footprint must reach the image"
+    assert clamped_visible(p, cam)[0]
+    qd = q.astype(np.float64)
+    Rq = Rotation.from_quat([qd[1], qd[2], qd[3], qd[0]]).as_matrix()
+    S = np.diag(np.exp(ls.astype(np.float64)))
+    Sigma = Rq @ S @ S.T @ Rq.T
+    tcam = Rw @ sc.mean[:, 0].astype(np.float64) + cam.t.astype(np.float64)
+    limx, limy = clip_ratio_limits(cam)
+    tclip = np.array([np.clip(tcam[0] / tcam[2], -limx, limx) * tcam[2],
+                      np.clip(tcam[1] / tcam[2], -limy, limy) * tcam[2], tcam[2]])
+
+    def pin(x):
+        return np.array([cam.fx * x[0] / x[2] + cam.cx, cam.fy * x[1] / x[2] + cam.cy])
+
+    def conic_at(point):
+        J = numeric_jacobian(pin, point)
+        S2 = J @ Rw @ Sigma @ Rw.T @ J.T + float(np.float32(0.3)) * np.eye(2)
+        c = np.linalg.inv(S2)
+        return np.array([c[0, 0], c[0, 1], c[1, 1]]), np.linalg.eigvalsh(S2).max()
+
+    want, lam = conic_at(tclip)
+    np.testing.assert_allclose(p.conic[0], want, rtol=1e-6, atol=1e-12)
+    assert p.radius[0] == math.ceil(3 * math.sqrt(lam))
+    unclipped, _ = conic_at(tcam)
+    assert np.abs(unclipped - want).max() > 1e-3 * np.abs(want).max()
+    assert p.uv[0] == pytest.approx(pin(tcam), rel=1e-12)
+
+
+def test_off_frustum_parity_fixture_reaches_the_clamp():
+    """The GPU parity cases beside the field of view do exercise the clipped Jacobian: in every view
+    at least 20 visible Gaussians lie beyond the clamp and receive gradient."""
+    from test_gpu_parity import off_frustum
+    sc, cams, dls = off_frustum()
+    _, g2ds, _, _ = oracle.render_backward(sc, cams, dls, bg=(0.05, 0.1, 0.15))
+    for cam, g2d in zip(cams, g2ds):
+        hit = clamped_visible(oracle.project(sc, cam), cam) & (np.abs(g2d).sum(axis=1) > 0)
+        assert hit.sum() >= 20
+
+
 def test_rotation_invariants_via_isotropy():
     """Isotropic s makes Sigma = s^2 I for every q (R R^T = I), so the footprint ignores q."""
     cam = axis_camera(64, 64)
@@ -340,34 +413,100 @@ def _loss_and_sig(sc, cam, dl, bg):
     return float(np.sum(vr.rgb * dl)), (vr.keys.tobytes(), vr.signature.tobytes())
 
 
-@pytest.mark.parametrize("seed,deg", [(0, 1), (1, 3), (2, 0)])
-def test_gradients_match_finite_differences(seed, deg):
-    sc, cams, dls = synth.tiny_scene(seed, 6, 32, 32, sh_degree=deg, log_scale_mu=-2.0, spread=0.4)
-    cam, dl = cams[0], dls[0].astype(np.float64)
-    bg = (0.2, 0.1, 0.05)
-    g, _, _, _ = oracle.render_backward(sc, [cam], [dl], bg=bg)
-    # scene with float64 planes so the perturbation is exact
-    sc64 = synth.Scene(sc.mean.astype(np.float64), sc.quat.astype(np.float64), sc.log_scale.astype(np.float64),
-                       sc.logit.astype(np.float64), sc.sh.astype(np.float64), deg)
+# Fourth-order central differences, f'(x) = (8 (f(x+h) - f(x-h)) - (f(x+2h) - f(x-2h))) / 12h with
+# h = 1e-4 max(1, |x|): truncation O(h^4) and rounding ~1e-16 |L| / h both stay near 1e-10, so the
+# oracle is held to 1e-6 relative (errors seen: below 2e-8).  When one of the four points crosses a
+# discrete decision the step drops to 1e-5 (errors seen there: below 3e-7).  The second-order
+# stencil at h = 1e-6 has rounding noise of ~1e-9 absolute, 1e-6 of the smallest gradients kept.
+FD_STEPS, FD_REL, FD_FLOOR = (1e-4, 1e-5), 1e-6, 1e-3
+
+
+def fd4(loss_sig, arr, idx):
+    """Fourth-order central difference of loss_sig()[0] in arr[idx]; None when at every step some
+    perturbation changes a discrete decision (the signatures differ)."""
+    x = arr[idx]
+    for step in FD_STEPS:
+        h = step * max(1.0, abs(x))
+        vals, sigs = [], []
+        for k in (2, 1, -1, -2):
+            arr[idx] = x + k * h
+            val, sig = loss_sig()
+            vals.append(val)
+            sigs.append(sig)
+        arr[idx] = x
+        if all(sg == sigs[0] for sg in sigs[1:]):
+            return (8.0 * (vals[1] - vals[2]) - (vals[0] - vals[3])) / (12.0 * h)
+    return None
+
+
+def assert_fd(name, idx, ana, fd):
+    assert abs(ana - fd) <= FD_REL * max(abs(fd), FD_FLOOR), f"{name}{idx}: analytic {ana} fd {fd}"
+
+
+def float64_scene(sc):
+    """The scene with float64 planes, so perturbations are exact."""
+    return synth.Scene(sc.mean.astype(np.float64), sc.quat.astype(np.float64), sc.log_scale.astype(np.float64),
+                       sc.logit.astype(np.float64), sc.sh.astype(np.float64), sc.sh_degree)
+
+
+def decision_trace(vr, cam):
+    """The discrete decisions of one render: each key's tile and the order of the values (the depth
+    bits themselves move with every perturbation of a depth and decide nothing else), which side of
+    the Jacobian clamp each centre lies on, which colour channels the clamp at 0 holds, and each
+    pixel's blended entries."""
+    limx, limy = clip_ratio_limits(cam)
+    p = vr.proj
+    clip = np.stack([np.abs((p.uv[:, 0] - cam.cx) / cam.fx) > limx, np.abs((p.uv[:, 1] - cam.cy) / cam.fy) > limy])
+    dark = np.asarray(p.rgb) <= 0.0
+    return ((vr.keys >> np.uint64(32)).tobytes() + vr.vals.tobytes() + clip.tobytes() + dark.tobytes() +
+            vr.signature.tobytes())
+
+
+def check_all_fd(sc, cams, dls, bg):
+    """Every parameter element of sc against fd4 of L = sum_v <dl_v, render_v>; returns (checked,
+    skipped)."""
+    g, _, _, _ = oracle.render_backward(sc, cams, dls, bg=bg)
+    sc64 = float64_scene(sc)
+
+    def loss_sig():
+        tot, sig = 0.0, []
+        for cam, dl in zip(cams, dls):
+            vr = oracle.render_view(sc64, cam, bg=bg)
+            tot += float(np.sum(vr.rgb * dl))
+            sig.append(decision_trace(vr, cam))
+        return tot, sig
+
     checked = skipped = 0
     for name in ("mean", "quat", "log_scale", "logit", "sh"):
         arr = getattr(sc64, name)
         ana = getattr(g, name)
         for idx in np.ndindex(arr.shape):
-            x = arr[idx]
-            h = 1e-6 * max(1.0, abs(x))
-            arr[idx] = x + h
-            lp, sp = _loss_and_sig(sc64, cam, dl, bg)
-            arr[idx] = x - h
-            lm, sm = _loss_and_sig(sc64, cam, dl, bg)
-            arr[idx] = x
-            if sp != sm:
+            fd = fd4(loss_sig, arr, idx)
+            if fd is None:
                 skipped += 1
                 continue
-            fd = (lp - lm) / (2 * h)
-            scale = max(abs(fd), 1e-3)
-            assert abs(ana[idx] - fd) <= 2e-5 * scale + 1e-7, f"{name}{idx}: analytic {ana[idx]} fd {fd}"
+            assert_fd(name, idx, ana[idx], fd)
             checked += 1
+    return checked, skipped
+
+
+@pytest.mark.parametrize("seed,deg", [(0, 1), (1, 3), (2, 0)])
+def test_gradients_match_finite_differences(seed, deg):
+    sc, cams, dls = synth.tiny_scene(seed, 6, 32, 32, sh_degree=deg, log_scale_mu=-2.0, spread=0.4)
+    checked, skipped = check_all_fd(sc, cams, [dls[0].astype(np.float64)], (0.2, 0.1, 0.05))
+    assert checked > 0.9 * (checked + skipped)
+
+
+@pytest.mark.parametrize("seed,deg", [(1, 1), (4, 3)])
+def test_gradients_beyond_the_jacobian_clamp_match_finite_differences(seed, deg):
+    """Gaussians centred beside the field of view (beyond 1.3x the half field of view in x or y)
+    whose footprints reach the image: the adjoint of the clipped Jacobian (the clipped
+    coordinate is lim t_z, so t_z carries it and t_x / t_y do not) against central differences,
+    over two views turned by yaw and pitch."""
+    sc, cams, dls = synth.off_frustum_scene(seed, 8, 40, 32, n_views=2, sh_degree=deg)
+    for cam in cams:
+        assert clamped_visible(oracle.project(sc, cam), cam).sum() >= 2
+    checked, skipped = check_all_fd(sc, cams, [d.astype(np.float64) for d in dls], (0.1, 0.2, 0.3))
     assert checked > 0.9 * (checked + skipped)
 
 
@@ -377,18 +516,18 @@ def test_large_footprint_subscene_gradients_match_finite_differences():
     differences, on a seeded sample of 240 parameter elements."""
     sc, cams = synth.large_footprint_scene(0, n=64, width=32, height=32)
     rng = np.random.default_rng(17)
-    dls = [rng.normal(size=(3, 32, 32)) for _ in cams]
+    # upstream gradients are float32 at the boundary (the oracle takes them as float32 too)
+    dls = [rng.normal(size=(3, 32, 32)).astype(np.float32).astype(np.float64) for _ in cams]
     bg = (0.1, 0.2, 0.3)
     g, _, _, _ = oracle.render_backward(sc, cams, dls, bg=bg)
-    sc64 = synth.Scene(sc.mean.astype(np.float64), sc.quat.astype(np.float64), sc.log_scale.astype(np.float64),
-                       sc.logit.astype(np.float64), sc.sh.astype(np.float64), 3)
+    sc64 = float64_scene(sc)
 
     def loss_sig():
         tot, sig = 0.0, []
         for cam, dl in zip(cams, dls):
             vr = oracle.render_view(sc64, cam, bg=bg)
             tot += float(np.sum(vr.rgb * dl))
-            sig.append(vr.keys.tobytes() + vr.signature.tobytes())
+            sig.append(decision_trace(vr, cam))
         return tot, sig
 
     names = ("mean", "quat", "log_scale", "logit", "sh")
@@ -400,19 +539,11 @@ def test_large_footprint_subscene_gradients_match_finite_differences():
         name = names[k]
         arr = getattr(sc64, name)
         idx = np.unravel_index(int(flat - (np.cumsum(sizes)[k - 1] if k else 0)), arr.shape)
-        x = arr[idx]
-        h = 1e-6 * max(1.0, abs(x))
-        arr[idx] = x + h
-        lp, sp = loss_sig()
-        arr[idx] = x - h
-        lm, sm = loss_sig()
-        arr[idx] = x
-        if sp != sm:
+        fd = fd4(loss_sig, arr, idx)
+        if fd is None:
             skipped += 1
             continue
-        fd = (lp - lm) / (2 * h)
-        ana = getattr(g, name)[idx]
-        assert abs(ana - fd) <= 2e-5 * max(abs(fd), 1e-3) + 1e-7, f"{name}{idx}: analytic {ana} fd {fd}"
+        assert_fd(name, idx, getattr(g, name)[idx], fd)
         checked += 1
     assert checked > 0.9 * (checked + skipped)
 
