@@ -42,12 +42,20 @@ def large_footprint_sub(seed=0):
     return scene, cams, [rng.normal(size=(3, 32, 32)).astype(np.float32) for _ in cams]
 
 
+def off_frustum(seed=11, n=200, W=96, H=72, views=2):
+    """Gaussians beside the field of view whose footprints reach the image, seen by a yawed and
+    pitched two-view rig (SH3): in every view tens of visible Gaussians lie beyond the Jacobian
+    clamp (1.3x the half field of view), so the clipped J and its zero derivative are exercised."""
+    return synth.off_frustum_scene(seed, n, W, H, n_views=views)
+
+
 CASES = {
     "single_view_2000": lambda: synth.single_view_scene(0),
     "multiview_sh3_ragged": lambda: small_multiview(),
     "multiview_sh1": lambda: small_multiview(seed=5, n=1500, views=2, W=97, H=61, deg=1),
     "tiny_dense": lambda: synth.tiny_scene(2, 300, 40, 36, sh_degree=2, log_scale_mu=-2.0),
     "large_footprint_64_4x32x32": large_footprint_sub,
+    "off_frustum_clamp_2x96x72": off_frustum,
 }
 
 
@@ -219,3 +227,25 @@ def test_invalid_arguments_are_rejected():
         small.render_fwd(g, cams, BG)
     with pytest.raises(DassError, match="DASS_E_INVALID"):
         ctx.render_bwd(g, cams, BG, [], [], g.zeros_like())  # no matching forward yet on a fresh context
+
+
+def test_backward_must_match_the_forward_cameras_and_background():
+    """render_bwd walks the lists of the last render_fwd: a call with other poses of the same image
+    size, or another background, is refused instead of chaining stale records."""
+    from paper_2411_14847_amd import DassError
+    scene, cams, dls = small_multiview(seed=4, n=400, views=2, W=64, H=48)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    out = ctx.render_fwd(g, cams, BG)
+    dl = [torch.as_tensor(d, device="cuda") for d in dls]
+    moved = [synth.make_camera(c.R.astype(np.float64), c.campos.astype(np.float64) + np.array([0.01, 0, 0]),
+                               c.width, c.height) for c in cams]
+    log("[bwd check] moved cameras, other background")
+    with pytest.raises(DassError, match="DASS_E_INVALID"):
+        ctx.render_bwd(g, moved, BG, out, dl, g.zeros_like())
+    with pytest.raises(DassError, match="DASS_E_INVALID"):
+        ctx.render_bwd(g, cams, (0.5, 0.5, 0.5), out, dl, g.zeros_like())
+    grads = g.zeros_like()
+    ctx.render_bwd(g, cams, BG, out, dl, grads)  # the matching call still runs
+    ctx.sync()
+    assert torch.isfinite(grads.mean).all() and grads.mean.abs().sum() > 0
