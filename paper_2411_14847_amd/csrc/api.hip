@@ -38,6 +38,7 @@ struct dass_ctx_s {
   int fwd_tw = kTile, fwd_th = kTile;
   int fwd_key_buf = 0;
   CamsK fwd_cams{};
+  float fwd_bg[3] = {0.f, 0.f, 0.f};
 };
 
 namespace {
@@ -459,6 +460,7 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   ctx->fwd_th = th;
   ctx->fwd_key_buf = kcur;
   ctx->fwd_cams = ck;
+  for (int c = 0; c < 3; c++) ctx->fwd_bg[c] = bg[c];
   return DASS_OK;
 }
 
@@ -475,6 +477,19 @@ dass_status dass_render_fwd_l1(dass_ctx ctx, const dass_gaussians* g, const dass
   return render_fwd_impl(ctx, g, cams, n_views, bg, out, &l1, opts, stream);
 }
 
+// True if a call over (g, cameras, tiling) reads the lists and records of the last render_fwd on
+// this context: same scene size and stride, the same cameras (every field of the kernels' camera
+// records, so poses, intrinsics and image sizes) and the same tile size.  The sub-tile size is
+// free: the walk's results do not depend on it.
+static bool matches_fwd(const dass_ctx ctx, const dass_gaussians* g, int n_views, int64_t total_tiles, int tw, int th,
+                        const CamsK& ck) {
+  if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
+      ctx->fwd_stride != g->capacity || ctx->fwd_tw != tw || ctx->fwd_th != th)
+    return false;
+  static_assert(sizeof(CamK) == 27 * 4, "CamK holds 4-byte fields only (no padding), compared bytewise");
+  return std::memcmp(ctx->fwd_cams.c, ck.c, sizeof(CamK) * (size_t)n_views) == 0;
+}
+
 dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera* cams, int32_t n_views,
                        const float bg[3], const dass_image* fwd_out, const float* const* dl_drgb, dass_grads* grads,
                        float* gradnorm_sum, int32_t* grad_count, const dass_opts* opts, dass_stream stream) {
@@ -487,9 +502,12 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   CamsK ck;
   int64_t total_tiles = 0;
   if ((s = make_cams(ctx, cams, n_views, tw, th, ck, total_tiles)) != DASS_OK) return s;
-  if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
-      ctx->fwd_stride != g->capacity || ctx->fwd_tw != tw || ctx->fwd_th != th)
-    return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context");
+  if (!matches_fwd(ctx, g, n_views, total_tiles, tw, th, ck))
+    return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context "
+                                     "(scene size, cameras or tile size)");
+  for (int c = 0; c < 3; c++)
+    if (bg[c] != ctx->fwd_bg[c])
+      return fail(ctx, DASS_E_INVALID, "render_bwd: background differs from the last render_fwd's");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
   set_tiling(io, tw, th, sub);
@@ -728,9 +746,9 @@ dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const da
   CamsK ck;
   int64_t total_tiles = 0;
   if ((s = make_cams(ctx, cams, n_views, tw, th, ck, total_tiles)) != DASS_OK) return s;
-  if (!ctx->have_fwd || ctx->fwd_n != g->n || ctx->fwd_nv != n_views || ctx->fwd_tiles != total_tiles ||
-      ctx->fwd_stride != g->capacity || ctx->fwd_tw != tw || ctx->fwd_th != th)
-    return fail(ctx, DASS_E_INVALID, "dass_render_features does not match the last render_fwd on this context");
+  if (!matches_fwd(ctx, g, n_views, total_tiles, tw, th, ck))
+    return fail(ctx, DASS_E_INVALID, "dass_render_features does not match the last render_fwd on this context "
+                                     "(scene size, cameras or tile size)");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
   set_tiling(io, tw, th, sub);
@@ -886,16 +904,16 @@ dass_status dass_l1_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_v
   return check_launch(ctx, "dass_l1_loss_grad");
 }
 
-dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* render,
-                                   const float* const* target, float lambda, float* const* dl_drgb,
-                                   float* const* err, float* loss, float* const* scratch, dass_stream stream) {
-  if (!ctx) return DASS_E_INVALID;
-  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(ctx, DASS_E_INVALID, "lambda %g outside [0, 1]", lambda);
-  if (lambda == 0.f)  // the L1 term alone
-    return dass_l1_loss_grad(ctx, cams, n_views, render, target, dl_drgb, err, loss, stream);
-  if (!cams || !render || !target || !dl_drgb || !scratch || n_views < 1 || n_views > DASS_MAX_VIEWS)
-    return fail(ctx, DASS_E_INVALID, "bad arguments");
-  SsimArgs a;
+}  // extern "C"
+
+namespace {
+
+// Arguments of the two D-SSIM passes for n_views views (the window, per-view scales and tiles);
+// the views' derivative maps (9 H W floats each) are scratch[v].  Returns an error message or
+// NULL.
+const char* ssim_args(const dass_camera* cams, int32_t n_views, const float* const* render,
+                      const float* const* target, float lambda, float* const* dl_drgb, float* const* err,
+                      float* const* scratch, SsimArgs& a, int64_t& blocks) {
   std::memset(&a, 0, sizeof(a));
   a.nv = n_views;
   {
@@ -903,11 +921,10 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
     for (int k = 0; k < 11; k++) sum += (g[k] = std::exp(-((k - 5.0) * (k - 5.0)) / (2.0 * 1.5 * 1.5)));
     for (int k = 0; k < 11; k++) a.w[k] = (float)(g[k] / sum);
   }
-  int64_t blocks = 0;
+  blocks = 0;
   for (int v = 0; v < n_views; v++) {
-    if (!render[v] || !target[v] || !dl_drgb[v] || !scratch[v])
-      return fail(ctx, DASS_E_INVALID, "view %d: NULL buffer", v);
-    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    if (!render[v] || !target[v] || !dl_drgb[v] || !scratch[v]) return "NULL buffer";
+    if (cams[v].width <= 0 || cams[v].height <= 0) return "bad size";
     SsimView& V = a.v[v];
     V.render = render[v];
     V.target = target[v];
@@ -923,6 +940,26 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
     a.gS[v] = (float)(-(double)lambda / n);
     a.l1_scale[v] = (float)((1.0 - (double)lambda) / n);
   }
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32_t n_views, const float* const* render,
+                                   const float* const* target, float lambda, float* const* dl_drgb,
+                                   float* const* err, float* loss, float* const* scratch, dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(ctx, DASS_E_INVALID, "lambda %g outside [0, 1]", lambda);
+  if (lambda == 0.f)  // the L1 term alone
+    return dass_l1_loss_grad(ctx, cams, n_views, render, target, dl_drgb, err, loss, stream);
+  if (!cams || !render || !target || !dl_drgb || !scratch || n_views < 1 || n_views > DASS_MAX_VIEWS)
+    return fail(ctx, DASS_E_INVALID, "bad arguments");
+  SsimArgs a;
+  int64_t blocks = 0;
+  if (const char* why = ssim_args(cams, n_views, render, target, lambda, dl_drgb, err, scratch, a, blocks))
+    return fail(ctx, DASS_E_INVALID, "%s", why);
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   stage_begin(ctx, DASS_STAGE_L1, st);
