@@ -367,10 +367,23 @@ class Trainer:
             self.graph.replay()
             self._throttle()
 
+    def shift_final(self):
+        """Shifted means and quaternions of the final parameters: the last iteration shifted G before
+        its Adam step, so the shift is taken again from the updated offsets (or fields, whose
+        offsets are recomputed) and the updated G^var rows."""
+        g, gs = self.g, self.gs
+        gs.n, gs.n_base = g.n, g.n_base
+        if self.fields is not None:
+            F = self.fields
+            self.ctx_dyn.hash_field_fwd(F["dyn"], g.mean, g.n_base, self._dyn, self.nd, self._dpos, self._drot, col=0)
+            self.ctx.hash_field_fwd(F["st"], g.mean, g.n_base, self._st, self.ns, self._dpos, self._drot, col=self.nd)
+        self.ctx.shift_fwd(g, gs, self._shift_idx, self._dpos, self._drot)
+
     def end_timestep(self, t: int) -> int:
         """Bakes the shift into G and appends Gaussians; returns the number appended."""
         cfg, g, gs = self.cfg, self.g, self.gs
         n = g.n
+        self.shift_final()
         g.mean[:, :n].copy_(gs.mean[:, :n])
         g.quat[:, :n].copy_(gs.quat[:, :n])
         self.pruned = 0
@@ -382,6 +395,11 @@ class Trainer:
         self.ctx.densify_append(g, self.errs, self.cams, self.gn, self.cnt, cfg.gamma_err, cfg.tau_pos, cfg.tau_err,
                                 cfg.k_append, cfg.seed * 1_000_003 + t, self.n_app)
         k = int(self.n_app.item())
+        # device-side errors of the timestep (a tile-key overflow truncates the lists of every
+        # iteration after it): raised here, where the host has waited for the work anyway
+        self.ctx.sync()
+        if self.fields is not None:
+            self.ctx_dyn.sync()
         g.n += k
         self.graph = None
         self._inflight.clear()  # the item() above waited for everything queued so far

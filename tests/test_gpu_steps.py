@@ -479,3 +479,63 @@ def test_serving_loop_with_concurrent_training():
     log(f"  serving {st}; training {[round(d['ms'], 1) for d in done]} ms/timestep")
     assert st["frames"] == 80 and st["p99_ms"] is not None and st["p50_ms"] <= st["p99_ms"]
     assert len(done) == 2 and snaps.version == 3
+
+
+@pytest.mark.parametrize("shift", ["direct", "hash"])
+def test_bake_applies_the_final_offsets(shift):
+    """After k iterations of a timestep, the baked scene equals the shift (Sec. 3.3) of the final
+    parameters by the final offsets -- for the hash fields, the offsets the final fields give --
+    on every row, G^var included (their means and quaternions keep the last Adam step)."""
+    import types
+    from oracle import hashfield as HF
+    from paper_2411_14847_amd import Context, GaussianBuffers
+    from paper_2411_14847_amd.streaming import StreamConfig, Trainer
+    scene, _, _ = synth.single_view_scene(0, n=600)
+    cams = synth.streaming_rig(64, 64)[:4]
+    cfg = StreamConfig(iters=6, k_append=80, erase_every=100, prune_min_opacity=0.0, shift=shift,
+                       field_dyn=(8, 4, 12, 64, 4, 64), field_st=(8, 2, 10, 32, 4, 32))
+    cap = scene.n + 2 * cfg.k_append
+    g = GaussianBuffers.from_arrays(scene.mean, scene.quat, scene.log_scale, scene.logit, scene.sh, 0, capacity=cap)
+    gt = g.clone()
+    ctx = Context(max_gaussians=cap, max_views=len(cams), max_keys=cap * len(cams) * 32, max_tiles=4 * 16)
+    tr = Trainer(ctx, g, cams, max_dynamic=scene.n // 10, cfg=cfg)
+    for t in (1, 2):
+        m = synth.timestep_motion(0, t, scene.n)
+        gt_out = gt.zeros_like()
+        ctx.shift_fwd(gt, gt_out, dev(m.dynamic), dev(m.dpos), dev(m.dquat))
+        gt.mean.copy_(gt_out.mean); gt.quat.copy_(gt_out.quat)
+        targets = [o.rgb.clone() for o in ctx.render_fwd(gt, cams, cfg.bg)]
+        if t == 1:
+            tr.timestep(t, dev(m.dynamic), targets)  # leaves 80 G^var rows
+            continue
+        log(f"[bake] {shift}: timestep 2, n {g.n} (n_base {g.n_base})")
+        tr.set_targets(targets)
+        tr.begin_timestep(t, dev(m.dynamic))
+        tr.iteration()
+        tr.run_iterations(cfg.iters - 1)
+        torch.cuda.synchronize()
+        n = g.n
+        assert n > g.n_base
+        fin = synth.Scene(g.mean[:, :n].cpu().numpy(), g.quat[:, :n].cpu().numpy(), g.log_scale[:, :n].cpu().numpy(),
+                          g.logit[:n].cpu().numpy(), g.sh[:, :n].cpu().numpy(), 0)
+        rows = tr._shift_idx.cpu().numpy()
+        if shift == "direct":
+            dpos, drot = tr._dpos.cpu().numpy(), tr._drot.cpu().numpy()
+        else:
+            parts = []
+            for k, idx in (("dyn", tr._dyn), ("st", tr._st)):
+                f = tr.fields[k]
+                p = types.SimpleNamespace(res=f.res, features=f.features, log2_table=f.log2_table,
+                                          aabb_min=np.array(f.aabb_min), aabb_max=np.array(f.aabb_max),
+                                          **{a: t_.cpu().numpy() for a, t_ in zip(("table", "w1", "b1", "w2", "b2"),
+                                                                                  f.arrays())})
+                parts.append(HF.field_fwd(HF.from_params(p), fin.mean[:, idx.cpu().numpy()].astype(np.float64)))
+            dpos = np.concatenate([parts[0][0], parts[1][0]], 1)
+            drot = np.concatenate([parts[0][1], parts[1][1]], 1)
+        om, oq = oracle.shift_fwd(fin, rows, dpos, drot)
+        tr.end_timestep(t)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(g.mean[:, :n].cpu().numpy(), om, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(g.quat[:, :n].cpu().numpy(), oq, rtol=1e-5, atol=1e-6)
+        # G^var rows were not shifted: they hold exactly their final parameters
+        np.testing.assert_array_equal(g.mean[:, g.n_base:n].cpu().numpy(), fin.mean[:, g.n_base:])
