@@ -265,6 +265,23 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
                                     float lambda, float* const* dl_drgb, float* const* err,
                                     float* loss, float* const* scratch, dass_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dass_fidelity_loss_grad with the D-SSIM maps kept
+ * in the library's own static scratch instead of caller scratch.  Same arguments, results
+ * and errors otherwise (bit-identical outputs for the same inputs).  The scratch holds
+ * 9 * DASS_NOALLOC_MAX_PIXELS floats (72 MiB) per GPU, reserved when the library's code is
+ * loaded on that GPU and held until the process ends; its address is looked up once per GPU
+ * when a context is created there.  The views' pixels (sum of width * height) must not exceed
+ * DASS_NOALLOC_MAX_PIXELS: DASS_E_INVALID otherwise, before anything is enqueued.  Calls no
+ * allocator.  Every call on one GPU shares that GPU's scratch, which keeps the last call's
+ * maps: calls that overlap on one GPU (different streams, or threads without ordering) race;
+ * calls ordered on one stream do not. */
+#define DASS_NOALLOC_MAX_PIXELS (1 << 21)
+dass_status dass_fidelity_loss_grad_noalloc(dass_ctx ctx, const dass_camera* cams, int32_t n_views,
+                                            const float* const* render, const float* const* target,
+                                            float lambda, float* const* dl_drgb, float* const* err,
+                                            float* loss, dass_stream stream);
+
 /* ---- hash-encoded deformation fields (Sec. 3.3; sizes in App. B) ------------------------ */
 
 /* A deformation field H_dyn or H_st: the multi-resolution hash encoding of a position followed

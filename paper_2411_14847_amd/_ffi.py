@@ -12,10 +12,11 @@ STATUS_NAMES = {0: "DASS_OK", 1: "DASS_E_INVALID", 2: "DASS_E_OOM", 3: "DASS_E_C
                 5: "DASS_E_UNSUPPORTED"}
 DASS_FWD, DASS_ADJOINT = 0, 1
 MAX_VIEWS = 32
+NOALLOC_MAX_PIXELS = 1 << 21  # DASS_NOALLOC_MAX_PIXELS
 
 # Every exported symbol of include/dass.h (checked by the ABI test).
 EXPORTS = ("dass_create", "dass_reserve", "dass_destroy", "dass_last_error", "dass_sync", "render_fwd",
-           "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_fidelity_loss_grad", "dass_debug_keys",
+           "dass_render_fwd_l1", "render_bwd", "shift_apply", "adam_step", "densify_append", "dass_l1_loss_grad", "dass_fidelity_loss_grad", "dass_fidelity_loss_grad_noalloc", "dass_debug_keys",
            "dass_debug_projection", "dass_autotune_tile", "dass_profile_begin", "dass_profile_end", "dass_debug_pair_counts",
            "adam_step_device_count", "dass_hash_field_fwd", "dass_hash_field_bwd",
            "dass_inherit_apply", "dass_inherit_adjoint", "dass_compact_var", "dass_render_features",
@@ -111,6 +112,7 @@ def lib():
                                      vp]),
             "dass_l1_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), P(vp), P(vp), vp, vp]),
             "dass_fidelity_loss_grad": (i32, [vp, P(Camera), i32, P(vp), P(vp), f32, P(vp), P(vp), vp, P(vp), vp]),
+            "dass_fidelity_loss_grad_noalloc": (i32, [vp, P(Camera), i32, P(vp), P(vp), f32, P(vp), P(vp), vp, vp]),
             "dass_debug_keys": (i32, [vp, i32, vp, vp, i64, vp, P(i64)]),
             "dass_debug_projection": (i32, [vp, P(Gaussians), P(Camera), P(Opts), vp]),
             "dass_autotune_tile": (i32, [vp, P(Gaussians), P(Camera), i32, P(f32), P(Image), P(vp), P(Grads), P(Opts),

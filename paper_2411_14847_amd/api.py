@@ -492,6 +492,18 @@ class Context:
         self._check(self._lib.dass_fidelity_loss_grad(self._h, cameras_array(cams), V, R, T, float(lam), D, E,
                                                       _ptr(loss), S, _stream(stream)))
 
+    def fidelity_loss_grad_noalloc(self, cams, renders, targets, lam: float, dl_out, err_out=None,
+                                   loss: Optional[torch.Tensor] = None, stream=None):
+        """fidelity_loss_grad with the D-SSIM maps in the library's static per-GPU scratch (no
+        allocation anywhere in the call); the views' pixels must fit NOALLOC_MAX_PIXELS."""
+        V = len(cams)
+        R = (C.c_void_p * V)(*[_ptr(r) for r in renders])
+        T = (C.c_void_p * V)(*[_ptr(t) for t in targets])
+        D = (C.c_void_p * V)(*[_ptr(d) for d in dl_out])
+        E = (C.c_void_p * V)(*[_ptr(e) for e in err_out]) if err_out is not None else None
+        self._check(self._lib.dass_fidelity_loss_grad_noalloc(self._h, cameras_array(cams), V, R, T, float(lam), D,
+                                                              E, _ptr(loss), _stream(stream)))
+
     def densify_append(self, g: GaussianBuffers, err_maps, cams, gradnorm, count, gamma_err, tau_pos, tau_err,
                        k_max, seed, n_appended: torch.Tensor, stream=None):
         """Appends children in rows [g.n, g.n + K); K lands in n_appended (device int32); the caller

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct Profiler {
 
 struct dass_ctx_s {
   int device = 0;
+  float* static_scratch = nullptr;  // this device's copy of the allocation-free call's scratch
   Profiler prof;
   dass_limits lim{};
   Workspace ws;
@@ -280,6 +282,37 @@ SceneK scene_of(const dass_gaussians* g) {
   return s;
 }
 
+// Scratch of the allocation-free loss call (dass_fidelity_loss_grad_noalloc): the D-SSIM
+// derivative maps, 9 floats per pixel of the call's views.  Every device the library runs on
+// holds its own copy until the process ends.  In host code the array's name is not a device
+// address: kernels and copies get the address looked up per device by static_scratch_of.
+constexpr int64_t kStaticScratchFloats = 9ll * DASS_NOALLOC_MAX_PIXELS;
+__device__ __align__(256) float scratch[kStaticScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device (the device must be the
+// current one).
+dass_status static_scratch_of(dass_ctx ctx, int device, float** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices)
+    return fail(ctx, DASS_E_UNSUPPORTED, "device %d: the static scratch table holds %d devices", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(ctx, DASS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    }
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return DASS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -306,6 +339,7 @@ dass_status dass_create(dass_ctx* out, int32_t device, const dass_limits* limits
     return DASS_E_HIP;
   }
   s = allocate(ctx, *limits);
+  if (s == DASS_OK) s = static_scratch_of(ctx, device, &ctx->static_scratch);
   if (s != DASS_OK) {
     free_all(ctx);
     delete ctx;
@@ -967,6 +1001,31 @@ dass_status dass_fidelity_loss_grad(dass_ctx ctx, const dass_camera* cams, int32
   launch_loss_finish(ctx->ws.loss_slots, loss, lambda, st);  // + lambda: the 1 of 1 - SSIM, over views
   stage_end(ctx, DASS_STAGE_L1, st);
   return check_launch(ctx, "dass_fidelity_loss_grad");
+}
+
+dass_status dass_fidelity_loss_grad_noalloc(dass_ctx ctx, const dass_camera* cams, int32_t n_views,
+                                           const float* const* render, const float* const* target, float lambda,
+                                           float* const* dl_drgb, float* const* err, float* loss,
+                                           dass_stream stream) {
+  if (!ctx) return DASS_E_INVALID;
+  if (!cams || n_views < 1 || n_views > DASS_MAX_VIEWS) return fail(ctx, DASS_E_INVALID, "bad arguments");
+  int64_t pixels = 0;
+  for (int v = 0; v < n_views; v++) {
+    if (cams[v].width <= 0 || cams[v].height <= 0) return fail(ctx, DASS_E_INVALID, "view %d: bad size", v);
+    pixels += (int64_t)cams[v].width * cams[v].height;
+  }
+  if (pixels > DASS_NOALLOC_MAX_PIXELS)
+    return fail(ctx, DASS_E_INVALID, "%lld pixels over the views; the allocation-free call takes at most %d",
+                (long long)pixels, DASS_NOALLOC_MAX_PIXELS);
+  if (!ctx->static_scratch) return fail(ctx, DASS_E_HIP, "no static scratch on device %d", ctx->device);
+  // each view's 9 H W maps carved in view order from this device's static scratch
+  float* views[DASS_MAX_VIEWS];
+  int64_t off = 0;
+  for (int v = 0; v < n_views; v++) {
+    views[v] = ctx->static_scratch + off;
+    off += 9ll * cams[v].width * cams[v].height;
+  }
+  return dass_fidelity_loss_grad(ctx, cams, n_views, render, target, lambda, dl_drgb, err, loss, views, stream);
 }
 
 dass_status densify_append(dass_ctx ctx, dass_gaussians* g, const float* const* err_maps, const dass_camera* cams,
