@@ -107,6 +107,8 @@ typedef struct {
                                     relative to the smaller sub-tile's origin */
 typedef struct {
   int32_t tile_w, tile_h;
+  int32_t batch;  /* list entries the blend stages in LDS at a time: 64, 128 or 256 (0 means
+                     128); only the speed depends on it */
   uint32_t flags; /* DASS_FLAG_* bits */
 } dass_opts;
 
@@ -454,7 +456,7 @@ dass_status dass_debug_pair_counts(dass_ctx ctx, uint64_t* evaluated, uint64_t* 
 dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t* vals,
                             int64_t max, int64_t* ranges, int64_t* count);
 
-/* Tile-size autotuner.  For each of the n_candidates options (tile_w, tile_h and flags, e.g.
+/* Tile-size autotuner.  For each of the n_candidates options (tile_w, tile_h, batch and flags, e.g.
  * DASS_FLAG_SUBTILE8) runs render_fwd + render_bwd of this workload once to warm up, then
  * `reps` times between two HIP events on `stream`, and writes the mean milliseconds per
  * fwd+bwd into ms[c] (host array; -1 for a candidate whose tiles or keys exceed the

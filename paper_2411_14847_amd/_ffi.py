@@ -49,7 +49,7 @@ class Grads(C.Structure):
 
 
 class Opts(C.Structure):
-    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("flags", C.c_uint32)]
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("batch", C.c_int32), ("flags", C.c_uint32)]
 
 
 class Limits(C.Structure):

@@ -245,6 +245,8 @@ class Context:
         # tile size of render_fwd / render_bwd: (tw, th) with edges 16, 32 or 64, optionally with
         # a third entry, the sub-tile edge of the blend (16, or 8 for one pixel per lane)
         self.tile = (16, 16)
+        # list entries the blend stages in LDS at a time (64, 128 or 256); only speed depends on it
+        self.batch = 128
 
     def close(self):
         if self._h:
@@ -258,13 +260,13 @@ class Context:
             pass
 
     @staticmethod
-    def _opts_for(tile, flags: int = 0) -> F.Opts:
+    def _opts_for(tile, flags: int = 0, batch: int = 128) -> F.Opts:
         if len(tile) > 2 and int(tile[2]) == 8:
             flags |= F.FLAG_SUBTILE8
-        return F.Opts(int(tile[0]), int(tile[1]), flags)
+        return F.Opts(int(tile[0]), int(tile[1]), int(batch), flags)
 
     def _opts(self, flags: int = 0) -> F.Opts:
-        return self._opts_for(self.tile, flags)
+        return self._opts_for(self.tile, flags, self.batch)
 
     def _check(self, st: int):
         if st != F.DASS_OK:
@@ -309,26 +311,32 @@ class Context:
                        (16, 16, 8), (32, 16, 8), (32, 32, 8), (64, 64, 8))
 
     def autotune_tile(self, g: GaussianBuffers, cams: Sequence, bg, out, dl_drgb, grads: GaussianBuffers,
-                      candidates=TILE_CANDIDATES, reps: int = 3, stream=None, apply: bool = True) -> dict:
-        """Times render_fwd + render_bwd of this workload at each candidate tile size (native
-        autotuner; synchronises) and, if `apply`, makes its choice this context's tile size: the
-        first candidate, in the given order, within 2% of the fastest.  Returns {(tw, th): ms,
-        or None if it does not fit the budgets}.  `grads` is scratch."""
+                      candidates=TILE_CANDIDATES, reps: int = 3, stream=None, apply: bool = True,
+                      batches=(128,)) -> dict:
+        """Times render_fwd + render_bwd of this workload at each candidate tile size and blend
+        batch (native autotuner; synchronises) and, if `apply`, makes its choice this context's
+        tile size and batch: the first candidate, in the given order (tiles, then batches), within
+        2% of the fastest.  Returns {(tw, th[, 8]): ms} for a single batch, else
+        {((tw, th[, 8]), batch): ms}; None where a candidate does not fit the budgets.  `grads`
+        is scratch."""
         imgs = (F.Image * len(cams))(*[o.struct() for o in out])
         dls = (C.c_void_p * len(cams))(*[_ptr(d) for d in dl_drgb])
         bgf = (C.c_float * 3)(*[float(x) for x in bg])
         gs = g.struct()
         gr = grads_struct(grads)
-        cand = (F.Opts * len(candidates))(*[self._opts_for(c) for c in candidates])
+        pairs = [(tuple(c), int(b)) for c in candidates for b in batches]
+        cand = (F.Opts * len(pairs))(*[self._opts_for(c, 0, b) for c, b in pairs])
         best = C.c_int32(-1)
-        ms = (C.c_float * len(candidates))()
+        ms = (C.c_float * len(pairs))()
         self.generation += 1
         self._check(self._lib.dass_autotune_tile(self._h, C.byref(gs), cameras_array(cams), len(cams), bgf, imgs, dls,
-                                                 C.byref(gr), cand, len(candidates), int(reps), C.byref(best), ms,
+                                                 C.byref(gr), cand, len(pairs), int(reps), C.byref(best), ms,
                                                  _stream(stream)))
         if apply:
-            self.tile = tuple(int(x) for x in candidates[best.value])
-        return {tuple(c): (float(ms[i]) if ms[i] >= 0 else None) for i, c in enumerate(candidates)}
+            self.tile = tuple(int(x) for x in pairs[best.value][0])
+            self.batch = pairs[best.value][1]
+        res = {p: (float(ms[i]) if ms[i] >= 0 else None) for i, p in enumerate(pairs)}
+        return {p[0]: v for p, v in res.items()} if len(batches) == 1 else res
 
     def shift_fwd(self, g: GaussianBuffers, out: GaussianBuffers, dyn_idx: torch.Tensor, dpos: torch.Tensor,
                   drot: torch.Tensor, stream=None):

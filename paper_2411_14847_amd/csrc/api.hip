@@ -247,24 +247,29 @@ dass_status make_cams(dass_ctx ctx, const dass_camera* cams, int nv, int tw, int
 bool tile_edge_ok(int e) { return e == 16 || e == 32 || e == 64; }
 
 // Validates the options and returns the tile size (16x16 when o is NULL) and sub-tile edge.
-dass_status check_opts(dass_ctx ctx, const dass_opts* o, int& tw, int& th, int& sub) {
+dass_status check_opts(dass_ctx ctx, const dass_opts* o, int& tw, int& th, int& sub, int& batch) {
   tw = th = kTile;
   sub = kTile;
+  batch = kBlendBatch;
   if (!o) return DASS_OK;
   if (!tile_edge_ok(o->tile_w) || !tile_edge_ok(o->tile_h))
     return fail(ctx, DASS_E_INVALID, "tile %dx%d unsupported (edges 16, 32 or 64)", o->tile_w, o->tile_h);
   if (o->flags & ~(DASS_FLAG_COUNT_PAIRS | DASS_FLAG_SUBTILE8))
     return fail(ctx, DASS_E_INVALID, "unknown option flags");
+  if (o->batch != 0 && o->batch != 64 && o->batch != 128 && o->batch != 256)
+    return fail(ctx, DASS_E_INVALID, "blend batch %d unsupported (0, 64, 128 or 256)", o->batch);
   tw = o->tile_w;
   th = o->tile_h;
   sub = (o->flags & DASS_FLAG_SUBTILE8) ? 8 : kTile;
+  batch = o->batch ? o->batch : kBlendBatch;
   return DASS_OK;
 }
 
-void set_tiling(ViewsIO& io, int tw, int th, int sub) {
+void set_tiling(ViewsIO& io, int tw, int th, int sub, int batch) {
   io.tw = tw;
   io.th = th;
   io.sub = sub;
+  io.batch = batch;
   io.sx = tw / sub;
   io.sn = (tw / sub) * (th / sub);
 }
@@ -410,8 +415,8 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  int tw, th, sub;
-  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  int tw, th, sub, batch;
+  if ((s = check_opts(ctx, opts, tw, th, sub, batch)) != DASS_OK) return s;
   if (!bg || !out) return fail(ctx, DASS_E_INVALID, "bg or out is NULL");
   CamsK ck;
   int64_t total_tiles = 0;
@@ -420,7 +425,7 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
     return fail(ctx, DASS_E_CAPACITY, "n=%d exceeds max_gaussians %d", g->n, ctx->lim.max_gaussians);
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
-  set_tiling(io, tw, th, sub);
+  set_tiling(io, tw, th, sub, batch);
   if (l1 && (!l1->target || !l1->dl_drgb)) return fail(ctx, DASS_E_INVALID, "targets or dl_drgb is NULL");
   for (int v = 0; v < n_views; v++) {
     if ((!out[v].rgb && !l1) || !out[v].t_final || !out[v].n_contrib)
@@ -530,8 +535,8 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  int tw, th, sub;
-  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  int tw, th, sub, batch;
+  if ((s = check_opts(ctx, opts, tw, th, sub, batch)) != DASS_OK) return s;
   if (!bg || !fwd_out || !dl_drgb || !grads) return fail(ctx, DASS_E_INVALID, "NULL argument");
   CamsK ck;
   int64_t total_tiles = 0;
@@ -544,7 +549,7 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
       return fail(ctx, DASS_E_INVALID, "render_bwd: background differs from the last render_fwd's");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
-  set_tiling(io, tw, th, sub);
+  set_tiling(io, tw, th, sub, batch);
   for (int v = 0; v < n_views; v++) {
     if (!fwd_out[v].t_final || !fwd_out[v].n_contrib || !dl_drgb[v])
       return fail(ctx, DASS_E_INVALID, "view %d: NULL t_final, n_contrib or dl_drgb", v);
@@ -773,8 +778,8 @@ dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const da
   if (!ctx) return DASS_E_INVALID;
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
-  int tw, th, sub;
-  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  int tw, th, sub, batch;
+  if ((s = check_opts(ctx, opts, tw, th, sub, batch)) != DASS_OK) return s;
   if (channels < 1 || channels > kFeatMaxC) return fail(ctx, DASS_E_INVALID, "channels %d outside [1, 16]", channels);
   if (!out || (g->n > 0 && !features)) return fail(ctx, DASS_E_INVALID, "NULL features or out");
   CamsK ck;
@@ -785,7 +790,7 @@ dass_status dass_render_features(dass_ctx ctx, const dass_gaussians* g, const da
                                      "(scene size, cameras or tile size)");
   ViewsIO io;
   std::memset(&io, 0, sizeof(io));
-  set_tiling(io, tw, th, sub);
+  set_tiling(io, tw, th, sub, batch);
   FeatIO fo{};
   for (int v = 0; v < n_views; v++) {
     if (!out[v]) return fail(ctx, DASS_E_INVALID, "view %d: NULL output", v);
@@ -1121,8 +1126,8 @@ dass_status dass_debug_projection(dass_ctx ctx, const dass_gaussians* g, const d
   dass_status s;
   if ((s = check_scene(ctx, g)) != DASS_OK) return s;
   if (!out) return fail(ctx, DASS_E_INVALID, "out is NULL");
-  int tw, th, sub;
-  if ((s = check_opts(ctx, opts, tw, th, sub)) != DASS_OK) return s;
+  int tw, th, sub, batch;
+  if ((s = check_opts(ctx, opts, tw, th, sub, batch)) != DASS_OK) return s;
   (void)sub;
   CamsK ck;
   int64_t total = 0;

@@ -12,6 +12,7 @@ namespace dass {
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTStop = 1e-4f;
+constexpr int kBlendBatch = 128;  // default list entries the blend stages in LDS at a time
 // Projection constants (fp32 values widened; the projection runs in fp64).
 constexpr double kDilation = (double)0.3f;
 constexpr double kNearZ = (double)0.2f;
@@ -72,6 +73,7 @@ struct ViewsIO {
   int tw, th;  // tile size in pixels
   int sub;     // sub-tile edge (16: four pixels per lane, one per 8x8 quadrant; 8: one pixel)
   int sx, sn;  // sub-tiles per tile row, per tile
+  int batch;   // list entries the blend stages in LDS at a time (64, 128 or 256)
 };
 constexpr int kLossSlots = 4096;
 constexpr int kFeatMaxC = 16;  // identity-feature channels per render

@@ -20,7 +20,7 @@
 namespace dass {
 namespace {
 
-constexpr int kBatchB = 128;  // list entries staged in LDS per batch
+// B: list entries staged in LDS per batch (64, 128 or 256; a per-call option)
 constexpr float kLog2e = 1.4426950408889634f;
 
 __device__ __forceinline__ int xcd_logical(int bid, int per) {
@@ -181,6 +181,7 @@ __device__ __forceinline__ int view_of(const ViewsIO& io, int nv, int b) {
 constexpr int kLanes = 64;
 constexpr int kPosBits = 28;  // list positions carried with the quadrant mask
 constexpr int kPosMask = (1 << kPosBits) - 1;
+constexpr float kNever = 2.0f;  // alpha threshold of a stopped pixel: above every alpha (<= 0.99)
 
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
@@ -212,7 +213,8 @@ template <int PW>
 __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float A, float B, float C, float o) {
   if (!(o * 255.0f > 0.999f)) return 0u;  // alpha <= o < 1/255 everywhere (with margin)
   // q <= 2 ln(255 o)  <=>  o exp(-q/2) >= 1/255; the margin keeps every kept decision
-  const float thr = 2.0f * __logf(255.0f * o) * 1.001f + 1e-3f;
+  // (hardware log2: 255 o > 1 here, and the margin covers its rounding)
+  const float thr = (2.0f * 0.6931471805599453f) * __builtin_amdgcn_logf(255.0f * o) * 1.001f + 1e-3f;
   const float ia = A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f, ic = C > 0.f ? __builtin_amdgcn_rcpf(C) : 0.f;
   uint32_t m = 0;
 #pragma unroll 1  // rolled: unrolled, the four rectangles cost the forward an occupancy step
@@ -228,57 +230,74 @@ __device__ __forceinline__ float dppf(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
-// One halving step of the transposed reduction: lanes with the step's bit clear keep slots
-// [0, H), lanes with it set keep slots [H, 2H) (slots >= N are zero); each adds its partner's copy.
-template <int N, int H, int CTRL>
-__device__ __forceinline__ void tstep(float* v, bool upper) {
-  float out[H];
-#pragma unroll
-  for (int k = 0; k < H; k++) {
-    const float hiv = (H + k < N) ? v[H + k] : 0.f;
-    const float keep = upper ? hiv : v[k];
-    const float send = upper ? v[k] : hiv;
-    out[k] = keep + dppf<CTRL>(send);
-  }
-#pragma unroll
-  for (int k = 0; k < H; k++) v[k] = out[k];
+// Transposing reduction of 9 per-lane values over the wave: each step pairs values (x, y) and
+// adds every value to its copy on the partner lane across one lane bit, keeping x's pair total
+// on the lanes with that bit clear and y's on the lanes with it set, so the number of values
+// per lane halves at each step without selects.
+// Lane bits 5 and 4 (partners 32 or 16 lanes apart): gfx950's permlane swaps exchange the upper
+// half of x with the lower half of y (the odd 16-lane rows of x with the even rows of y), after
+// which x + y holds x's total on one side and y's on the other.
+__device__ __forceinline__ float swap32_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+// Lane bits 3 and 2 (partners 8 or 4 lanes apart in a 16-lane row): two DPP adds whose bank
+// masks (a bank is 4 consecutive lanes of a row) write complementary halves of the lanes.  The
+// leading s_nop gives the DPP reads of x and y the two wait states they need after a VALU write.
+__device__ __forceinline__ float dpp_pair8(float x, float y) {
+  float o;
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"  // lanes with bit 3 clear
+      "v_add_f32_dpp %0, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xc"       // lanes with bit 3 set
+      : "=&v"(o)
+      : "v"(x), "v"(y));
+  return o;
+}
+__device__ __forceinline__ float dpp_pair4(float x, float y) {
+  float o;
+  asm("s_nop 1\n\t"
+      "v_add_f32_dpp %0, %1, %1 row_shl:4 row_mask:0xf bank_mask:0x5\n\t"  // bit 2 clear: lane + 4
+      "v_add_f32_dpp %0, %2, %2 row_shr:4 row_mask:0xf bank_mask:0xa"       // bit 2 set: lane - 4
+      : "=&v"(o)
+      : "v"(x), "v"(y));
+  return o;
 }
 
-// Sums 9 per-lane values over the wave.  Afterwards lane l (l < 16) holds the total of value
-// kRedSlot[l] (-1: none); lanes l + 16, l + 32, l + 48 hold the same total.  DPP moves within
-// rows, two shuffles across rows (measured faster here than gfx950's permlane16/32 swaps, which
-// need more registers and cost an occupancy step).
-__device__ __forceinline__ float wave_reduce9(float* v, int lane) {
-  tstep<9, 5, 0xB1>(v, lane & 1);         // xor 1 (quad_perm 1,0,3,2)
-  tstep<5, 3, 0x4E>(v, (lane >> 1) & 1);  // xor 2 (quad_perm 2,3,0,1)
-  tstep<3, 2, 0x128>(v, (lane >> 3) & 1); // xor 8 (row_ror 8)
-  {                                       // xor 4 (row_shl 4 / row_shr 4)
-    const bool up = (lane >> 2) & 1;
-    const float keep = up ? v[1] : v[0];
-    const float send = up ? v[0] : v[1];
-    const float a = dppf<0x104>(send), b = dppf<0x114>(send);
-    v[0] = keep + (up ? b : a);
-  }
-  float x = v[0];
-  x += __shfl_xor(x, 16, 64);
-  x += __shfl_xor(x, 32, 64);
-  return x;
+// Sums v[0..8] over the wave.  Afterwards lane 4 m + i (i < 4) holds the total of value
+// kRedSlot[m] (-1: a duplicate of another lane's total, or none).
+__device__ __forceinline__ float wave_reduce9(const float* v) {
+  // bit 5 -> upper half of the lanes holds values 5, 6, 7, 8, 4
+  const float a0 = swap32_sum(v[0], v[5]), a1 = swap32_sum(v[1], v[6]), a2 = swap32_sum(v[2], v[7]);
+  const float a3 = swap32_sum(v[3], v[8]), a4 = swap32_sum(v[4], v[4]);
+  // bit 4 -> (bit 5, bit 4) = 00: 0 1 2, 01: 3 4 2, 10: 5 6 7, 11: 8 4 7
+  const float b0 = swap16_sum(a0, a3), b1 = swap16_sum(a1, a4), b2 = swap16_sum(a2, a2);
+  // bit 3 -> (bits 5..3) = 000: 0 1, 001: 2 1, 010: 3 4, 011: 2 4, 100: 5 6, 101: 7 6, 110: 8 4, 111: 7 4
+  const float c0 = dpp_pair8(b0, b2);
+  const float c1 = b1 + dppf<0x128>(b1);  // row_ror 8
+  // bit 2 -> one value per lane (bits 5..2 = m, kRedSlot[m])
+  float d = dpp_pair4(c0, c1);
+  d += dppf<0xB1>(d);  // bits 1, 0: the four lanes of a bank (quad_perm 1,0,3,2 then 2,3,0,1)
+  d += dppf<0x4E>(d);
+  return d;
 }
-// value index held by lanes 0..15 after wave_reduce9 (bits 0,1,3,2 halve 9 -> 5 -> 3 -> 2 -> 1)
-__constant__ int kRedSlot[16] = {0, 5, 3, 8, 1, 6, 4, -1, 2, 7, -1, -1, -1, -1, -1, -1};
+__constant__ int kRedSlot[16] = {0, 1, 2, -1, 3, 4, -1, -1, 5, 6, 7, -1, 8, -1, -1, -1};
 
 // L1: the epilogue also forms the L1 term against the view's target (dL/drgb, error map and
 // this sub-tile's share of the loss, added into one of kLossSlots partial sums).
-template <bool COUNT, bool L1, int SUB>
+template <bool COUNT, bool L1, int SUB, int B>
 __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       unsigned long long* __restrict__ pairs,
                                                       float* __restrict__ loss_slots) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
-  __shared__ float2 s_xy[kBatchB];
-  __shared__ float4 s_co[kBatchB];   // log2-scaled conic, opacity
-  __shared__ float4 s_rgb[kBatchB];  // colour, list position | quadrant mask << 28 (int bits)
+  __shared__ float2 s_xy[B];
+  __shared__ float4 s_co[B];   // log2-scaled conic, opacity
+  __shared__ float4 s_rgb[B];  // colour, list position | quadrant mask << 28 (int bits)
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
@@ -293,23 +312,25 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
-  // T[k] > 0 while the pixel walks its list; a stopped pixel (or one outside the image) keeps
-  // -T: its updates T - T a stay negative, below the stop level, so it never blends again
-  float T[NP], c0[NP], c1[NP], c2[NP];
-  int last[NP];
+  // thr[k]: the alpha a pixel's entries must reach to blend; 1/255 while it walks its list,
+  // kNever once it has stopped (or for a pixel outside the image), so it never blends again and
+  // keeps its transmittance
+  float T[NP], thr[NP], c0[NP], c1[NP], c2[NP];
+  uint32_t last[NP];  // (list position + 1) of the last blended entry, quadrant mask above it
 #pragma unroll
   for (int k = 0; k < NP; k++) {
     const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
-    T[k] = (px < V.W && py < V.H) ? 1.f : -1.f;
+    T[k] = 1.f;
+    thr[k] = (px < V.W && py < V.H) ? kAlphaMin : kNever;
     c0[k] = c1[k] = c2[k] = 0.f;
     last[k] = 0;
   }
   uint32_t n_eval = 0, n_blend = 0;
-  for (uint32_t start = r.x; start < r.y; start += kBatchB) {
-    const int n_in = (int)min((uint32_t)kBatchB, r.y - start);
+  for (uint32_t start = r.x; start < r.y; start += B) {
+    const int n_in = (int)min((uint32_t)B, r.y - start);
     int n_kept = 0;
 #pragma unroll
-    for (int k = 0; k < kBatchB / kLanes; k++) {
+    for (int k = 0; k < B / kLanes; k++) {
       const int e = k * kLanes + lane;
       uint32_t qm = 0;
       float2 xy;
@@ -318,8 +339,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         const Rec R = rec[vals[start + e]];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         qm = quad_mask<PW>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
-        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
-        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float(((int)(start - r.x) + e) | (int)(qm << kPosBits)));
+        // exponent in base 2 with the opacity folded in: alpha = 2^(q' + log2 o)
+        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, __log2f(R.r1.w));
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z,
+                          __int_as_float(((int)(start - r.x) + e + 1) | (int)(qm << kPosBits)));
       }
       const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
@@ -334,44 +357,48 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     // quadrants with a pixel still walking (a stopped pixel stays stopped)
     uint32_t qalive = 0;
 #pragma unroll
-    for (int k = 0; k < NP; k++) qalive |= __ballot(T[k] > 0.f) != 0 ? 1u << k : 0u;
+    for (int k = 0; k < NP; k++) qalive |= __ballot(thr[k] < 1.f) != 0 ? 1u << k : 0u;
     __syncthreads();
     for (int j = 0; j < n_kept; j++) {
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
       const float4 c = s_rgb[j];
-      const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(c.w));  // same for all lanes
-      const int pos1 = (int)(w & kPosMask) + 1;
+      const uint32_t wv = __float_as_uint(c.w);  // (position + 1) | quadrant mask << 28
+      const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)wv);  // same for all lanes
       const uint32_t qm = (w >> kPosBits) & qalive;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
-      // branch-free within a quadrant: every pixel evaluates the entry; selects keep skipped /
-      // stopped pixels unchanged
 #pragma unroll
       for (int k = 0; k < NP; k++) {
         if (NP > 1 && !((qm >> k) & 1u)) continue;  // uniform: no pixel of quadrant k can take it
         const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
-        const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
-        const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
-        const float Tn = T[k] - T[k] * a;
-        const bool go = Tn >= kTStop;  // false for a stopped pixel (T < 0)
-        const bool blend = ok && go;
-        if (COUNT) {
-          n_eval += T[k] > 0.f ? 1u : 0u;
-          n_blend += blend ? 1u : 0u;
+        // the conic is positive definite, so the exponent (before log2 o) is never above 0
+        const float pw = fmaf(dx, fmaf(co.x, dx, co.y * dy), fmaf(co.z * dy, dy, co.w));
+        const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(pw));
+        const bool ok = a >= thr[k];
+        float wgt = ok ? a * T[k] : 0.f;
+        float Tn = T[k] - wgt;
+        bool take = ok;
+        const bool stop = ok && Tn < kTStop;
+        if (__builtin_expect(__ballot(stop) != 0, 0)) {  // uniform: a pixel of the quadrant stops here
+          wgt = stop ? 0.f : wgt;
+          Tn = stop ? T[k] : Tn;
+          take = ok && !stop;
+          if (COUNT) n_eval += thr[k] < 1.f ? 1u : 0u;
+          thr[k] = stop ? kNever : thr[k];
+        } else if (COUNT) {
+          n_eval += thr[k] < 1.f ? 1u : 0u;
         }
-        const float wgt = blend ? a * T[k] : 0.f;
-        c0[k] += c.x * wgt;
-        c1[k] += c.y * wgt;
-        c2[k] += c.z * wgt;
-        // blended: T - T a; the pixel stops here: -|T| (a stopped pixel stays as it is)
-        T[k] = blend ? Tn : (ok ? -fabsf(T[k]) : T[k]);
-        last[k] = blend ? pos1 : last[k];
+        if (COUNT) n_blend += take ? 1u : 0u;
+        c0[k] = fmaf(c.x, wgt, c0[k]);
+        c1[k] = fmaf(c.y, wgt, c1[k]);
+        c2[k] = fmaf(c.z, wgt, c2[k]);
+        T[k] = Tn;
+        last[k] = take ? wv : last[k];
       }
     }
     bool alive = false;
 #pragma unroll
-    for (int k = 0; k < NP; k++) alive = alive || T[k] > 0.f;
+    for (int k = 0; k < NP; k++) alive = alive || thr[k] < 1.f;
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
@@ -382,14 +409,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     if (px < V.W && py < V.H) {
       const int64_t hw = (int64_t)V.W * V.H;
       const int64_t pix = (int64_t)py * V.W + px;
-      T[k] = fabsf(T[k]);
       const float col[3] = {c0[k] + T[k] * bg0, c1[k] + T[k] * bg1, c2[k] + T[k] * bg2};
       if (!L1 || V.rgb) {
 #pragma unroll
         for (int c = 0; c < 3; c++) V.rgb[c * hw + pix] = col[c];
       }
       V.t_final[pix] = T[k];
-      V.n_contrib[pix] = last[k];
+      V.n_contrib[pix] = (int)(last[k] & kPosMask);
       if (L1) {
         const float sc = V.l1_scale;
         float e = 0.f;
@@ -415,16 +441,17 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   }
 }
 
-template <int SUB>
+template <int SUB, int B>
 __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int total_blocks, int per, float bg0,
                                                       float bg1, float bg2, const uint2* __restrict__ ranges,
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       float* __restrict__ g2d) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
-  __shared__ float2 s_xy[kBatchB];
-  __shared__ float4 s_co[kBatchB];   // log2-scaled conic + opacity (as the forward)
-  __shared__ float4 s_rgb[kBatchB];  // colour, list position | quadrant mask << 28 (int bits)
-  __shared__ uint32_t s_p[kBatchB];
+  __shared__ float2 s_xy[B];
+  __shared__ float4 s_co[B];   // log2-scaled conic, log2 opacity (as the forward)
+  __shared__ float4 s_rgb[B];  // colour, list position | quadrant mask << 28 (int bits)
+  __shared__ uint32_t s_p[B];
+  __shared__ float s_io[B];    // 1 / opacity
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
@@ -469,16 +496,16 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   }
   const int max_last = min(max_all, (int)(r.y - r.x));  // n_contrib never exceeds the list length
   if (max_last <= 0) return;
-  const int slot = kRedSlot[lane & 15];
-  const bool writes = lane < 16 && slot >= 0;
-  const int nbatch = (max_last + kBatchB - 1) / kBatchB;
+  const int slot = kRedSlot[lane >> 2];
+  const bool writes = (lane & 3) == 0 && slot >= 0;
+  const int nbatch = (max_last + B - 1) / B;
   for (int bi = nbatch - 1; bi >= 0; bi--) {
-    const uint32_t start = r.x + (uint32_t)bi * kBatchB;
-    const int n_in = min(kBatchB, max_last - bi * kBatchB);
+    const uint32_t start = r.x + (uint32_t)bi * B;
+    const int n_in = min(B, max_last - bi * B);
     __syncthreads();
     int n_kept = 0;
 #pragma unroll
-    for (int k = 0; k < kBatchB / kLanes; k++) {
+    for (int k = 0; k < B / kLanes; k++) {
       const int e = k * kLanes + lane;
       uint32_t qm = 0;
       float2 xy;
@@ -490,16 +517,17 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
         qm = quad_mask<PW>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
-        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((bi * kBatchB + e) | (int)(qm << kPosBits)));
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((bi * B + e) | (int)(qm << kPosBits)));
       }
       const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
       if (keep) {
         const int pos = n_kept + __popcll(m & lt);
         s_xy[pos] = xy;
-        s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, cn.w);
+        s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, __log2f(cn.w));
         s_rgb[pos] = rgb;
         s_p[pos] = p;  // record index = gradient row (view * n + Gaussian)
+        s_io[pos] = 1.0f / cn.w;
       }
       n_kept += __popcll(m);
     }
@@ -513,7 +541,8 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const uint32_t qm = w >> kPosBits;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
       // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
-      // sum dP dy^2, d opacity, d rgb), dP = dL/d(exponent), (dx, dy) = mean - pixel
+      // sum dP dy^2, d opacity (times the opacity until the reduction), d rgb),
+      // dP = dL/d(exponent), (dx, dy) = mean - pixel
       float m[9];
 #pragma unroll
       for (int q = 0; q < 9; q++) m[q] = 0.f;
@@ -524,36 +553,39 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         // pixel there
         if (NP > 1 && !(((qm >> k) & 1u) && idx < qlast[k])) continue;
         const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
-        const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        const float G = __builtin_amdgcn_exp2f(pw);
-        const float araw = co.w * G;
+        const float pw = fmaf(dx, fmaf(co.x, dx, co.y * dy), fmaf(co.z * dy, dy, co.w));  // + log2 o
+        const float araw = __builtin_amdgcn_exp2f(pw);
         const float a = fminf(kAlphaMax, araw);
-        if (!((idx < last[k]) && (pw <= 0.f) && (a >= kAlphaMin))) continue;
+        const bool take = (idx < last[k]) && (a >= kAlphaMin);  // the forward blended this entry here
+        if (__ballot(take) == 0) continue;  // uniform
         any = true;
-        T[k] = T[k] * __builtin_amdgcn_rcpf(1.f - a);  // transmittance before this entry
-        const float wgt = a * T[k];
-        m[6] += wgt * dC0[k];
-        m[7] += wgt * dC1[k];
-        m[8] += wgt * dC2[k];
+        // branch-free over the lanes: a pixel that did not blend the entry sees alpha 0, which
+        // leaves its transmittance and colour-behind unchanged and adds nothing
+        const float ae = take ? a : 0.f;
+        T[k] = T[k] * __builtin_amdgcn_rcpf(1.f - ae);  // transmittance before this entry
+        const float wgt = ae * T[k];
+        m[6] = fmaf(wgt, dC0[k], m[6]);
+        m[7] = fmaf(wgt, dC1[k], m[7]);
+        m[8] = fmaf(wgt, dC2[k], m[8]);
         // dL/d alpha = T (dL/dC . (colour - colour behind)); the colour behind moves by alpha of that
         const float ed = (c.x * dC0[k] + c.y * dC1[k] + c.z * dC2[k]) - S[k];
-        const float da = T[k] * ed;
-        S[k] += a * ed;
-        if (araw < kAlphaMax) {  // no derivative through an active clamp
-          const float dP = da * a;
-          m[5] += da * G;
-          const float pdx = dP * dx, pdy = dP * dy;
-          m[0] += pdx;
-          m[1] += pdy;
-          m[2] += pdx * dx;
-          m[3] += pdx * dy;
-          m[4] += pdy * dy;
-        }
+        S[k] = fmaf(ae, ed, S[k]);
+        // no derivative through an active clamp
+        const float da = (take && araw < kAlphaMax) ? T[k] * ed : 0.f;
+        const float dP = da * a;
+        m[5] = fmaf(da, araw, m[5]);  // d alpha / d o = alpha / o, the 1 / o applied once per entry
+        const float pdx = dP * dx, pdy = dP * dy;
+        m[0] += pdx;
+        m[1] += pdy;
+        m[2] = fmaf(pdx, dx, m[2]);
+        m[3] = fmaf(pdx, dy, m[3]);
+        m[4] = fmaf(pdy, dy, m[4]);
       }
-      if (__ballot(any) != 0) {
+      if (any) {  // uniform
         // the sums are linear in the entry's conic, so the conic is applied once per
         // (view, Gaussian) by the projection adjoint, not here
-        const float tot = wave_reduce9(m, lane);
+        m[5] *= s_io[j];
+        const float tot = wave_reduce9(m);
         if (writes) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], tot);
       }
     }
@@ -563,15 +595,15 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
 // Identity-feature render: the forward's walk (same lists, culling, alpha, transmittance and
 // stop, so the weights alpha_i T_i are the colour render's) accumulating up to kFeatMaxC
 // per-Gaussian features instead of colours, with no background.
-template <int SUB>
+template <int SUB, int B>
 __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int total_blocks, int per, FeatIO fo,
                                                        const uint2* __restrict__ ranges,
                                                        const uint32_t* __restrict__ vals, const Rec* __restrict__ rec) {
   constexpr int PW = SUB / 8, NP = PW * PW;
-  __shared__ float2 s_xy[kBatchB];
-  __shared__ float4 s_co[kBatchB];
-  __shared__ uint32_t s_qm[kBatchB];
-  __shared__ float4 s_f[kBatchB][kFeatMaxC / 4];
+  __shared__ float2 s_xy[B];
+  __shared__ float4 s_co[B];
+  __shared__ uint32_t s_qm[B];
+  __shared__ float4 s_f[B][kFeatMaxC / 4];
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;
@@ -587,19 +619,20 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
   const uint32_t gbase = (uint32_t)v * (uint32_t)fo.n;  // record index = view * n + Gaussian
-  float T[NP], acc[NP][kFeatMaxC];
+  float T[NP], thr[NP], acc[NP][kFeatMaxC];  // thr: as the colour forward's
 #pragma unroll
   for (int k = 0; k < NP; k++) {
     const int px = ox + qx + 8 * (k % PW), py = oy + qy + 8 * (k / PW);
-    T[k] = (px < V.W && py < V.H) ? 1.f : -1.f;
+    T[k] = 1.f;
+    thr[k] = (px < V.W && py < V.H) ? kAlphaMin : kNever;
 #pragma unroll
     for (int c = 0; c < kFeatMaxC; c++) acc[k][c] = 0.f;
   }
-  for (uint32_t start = r.x; start < r.y; start += kBatchB) {
-    const int n_in = (int)min((uint32_t)kBatchB, r.y - start);
+  for (uint32_t start = r.x; start < r.y; start += B) {
+    const int n_in = (int)min((uint32_t)B, r.y - start);
     int n_kept = 0;
 #pragma unroll
-    for (int k = 0; k < kBatchB / kLanes; k++) {
+    for (int k = 0; k < B / kLanes; k++) {
       const int e = k * kLanes + lane;
       uint32_t qm = 0, rid = 0;
       float2 xy;
@@ -609,7 +642,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
         const Rec R = rec[rid];
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         qm = quad_mask<PW>(xy.x, xy.y, R.r1.x, R.r1.y, R.r1.z, R.r1.w);
-        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, R.r1.w);
+        co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, __log2f(R.r1.w));
       }
       const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
@@ -627,7 +660,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
     }
     uint32_t qalive = 0;
 #pragma unroll
-    for (int k = 0; k < NP; k++) qalive |= __ballot(T[k] > 0.f) != 0 ? 1u << k : 0u;
+    for (int k = 0; k < NP; k++) qalive |= __ballot(thr[k] < 1.f) != 0 ? 1u << k : 0u;
     __syncthreads();
     for (int j = 0; j < n_kept; j++) {
       const float2 xy = s_xy[j];
@@ -641,12 +674,16 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
       for (int k = 0; k < NP; k++) {
         if (NP > 1 && !((qm >> k) & 1u)) continue;
         const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
-        const float pw = co.x * dx * dx + co.z * dy * dy + co.y * dx * dy;
-        const float a = fminf(kAlphaMax, co.w * __builtin_amdgcn_exp2f(pw));
-        const bool ok = (pw <= 0.f) && (a >= kAlphaMin);
-        const float Tn = T[k] - T[k] * a;
-        const bool blend = ok && (Tn >= kTStop);
-        const float wgt = blend ? a * T[k] : 0.f;
+        // the colour forward's alpha, weight and stop, operation for operation
+        const float pw = fmaf(dx, fmaf(co.x, dx, co.y * dy), fmaf(co.z * dy, dy, co.w));
+        const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(pw));
+        const bool ok = a >= thr[k];
+        float wgt = ok ? a * T[k] : 0.f;
+        float Tn = T[k] - wgt;
+        const bool stop = ok && Tn < kTStop;
+        wgt = stop ? 0.f : wgt;
+        Tn = stop ? T[k] : Tn;
+        thr[k] = stop ? kNever : thr[k];
 #pragma unroll
         for (int c = 0; c < kFeatMaxC / 4; c++) {
           acc[k][4 * c] += fe[c].x * wgt;
@@ -654,12 +691,12 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
           acc[k][4 * c + 2] += fe[c].z * wgt;
           acc[k][4 * c + 3] += fe[c].w * wgt;
         }
-        T[k] = blend ? Tn : (ok ? -fabsf(T[k]) : T[k]);
+        T[k] = Tn;
       }
     }
     bool alive = false;
 #pragma unroll
-    for (int k = 0; k < NP; k++) alive = alive || T[k] > 0.f;
+    for (int k = 0; k < NP; k++) alive = alive || thr[k] < 1.f;
     if (__ballot(alive) == 0) break;
     __syncthreads();
   }
@@ -729,16 +766,27 @@ static inline int per_xcd(int64_t total_tiles) { return (int)((total_tiles + kNu
 
 // One wave per (tile, sub-tile); the sub-tiles of a tile are consecutive logical blocks, so they
 // run on the same XCD and share its L2 for the tile's list and records.
+template <bool COUNT, bool L1, int B>
+void blend_fwd_batch(const ViewsIO& io, int nv, int total, int per, const float bg[3], const Workspace& ws,
+                     const uint32_t* vals, hipStream_t st) {
+  const dim3 grid(per * kNumXcd), block(kLanes);
+  if (io.sub == 8)
+    k_blend_fwd<COUNT, L1, 8, B><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                        ws.rec_u, ws.pairs, ws.loss_slots);
+  else
+    k_blend_fwd<COUNT, L1, 16, B><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
+                                                         ws.rec_u, ws.pairs, ws.loss_slots);
+}
+
 template <bool COUNT, bool L1>
 void blend_fwd_variant(const ViewsIO& io, int nv, int total, int per, const float bg[3], const Workspace& ws,
                        const uint32_t* vals, hipStream_t st) {
-  const dim3 grid(per * kNumXcd), block(kLanes);
-  if (io.sub == 8)
-    k_blend_fwd<COUNT, L1, 8><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                     ws.rec_u, ws.pairs, ws.loss_slots);
+  if (io.batch == 64)
+    blend_fwd_batch<COUNT, L1, 64>(io, nv, total, per, bg, ws, vals, st);
+  else if (io.batch == 256)
+    blend_fwd_batch<COUNT, L1, 256>(io, nv, total, per, bg, ws, vals, st);
   else
-    k_blend_fwd<COUNT, L1, 16><<<grid, block, 0, st>>>(io, nv, total, per, bg[0], bg[1], bg[2], ws.ranges, vals,
-                                                      ws.rec_u, ws.pairs, ws.loss_slots);
+    blend_fwd_batch<COUNT, L1, 128>(io, nv, total, per, bg, ws, vals, st);
 }
 
 void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const float bg[3], const Workspace& ws,
@@ -780,10 +828,17 @@ void launch_blend_feat(const ViewsIO& io, int nv, int64_t total_tiles, const Fea
   if (total == 0) return;
   const int per = per_xcd(total);
   const dim3 grid(per * kNumXcd), block(kLanes);
-  if (io.sub == 8)
-    k_blend_feat<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, fo, ws.ranges, vals, ws.rec_u);
-  else
-    k_blend_feat<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, fo, ws.ranges, vals, ws.rec_u);
+#define DASS_FEAT(SUBT, BT) k_blend_feat<SUBT, BT><<<grid, block, 0, st>>>(io, nv, (int)total, per, fo, ws.ranges, vals, ws.rec_u)
+  if (io.sub == 8) {
+    if (io.batch == 64) DASS_FEAT(8, 64);
+    else if (io.batch == 256) DASS_FEAT(8, 256);
+    else DASS_FEAT(8, 128);
+  } else {
+    if (io.batch == 64) DASS_FEAT(16, 64);
+    else if (io.batch == 256) DASS_FEAT(16, 256);
+    else DASS_FEAT(16, 128);
+  }
+#undef DASS_FEAT
 }
 
 __global__ __launch_bounds__(256) void k_loss_finish(float* __restrict__ slots, float* __restrict__ loss, float add) {
@@ -810,12 +865,19 @@ void launch_blend_bwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   if (total == 0) return;
   const int per = per_xcd(total);
   const dim3 grid(per * kNumXcd), block(kLanes);
-  if (io.sub == 8)
-    k_blend_bwd<8><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_u,
-                                           ws.g2d);
-  else
-    k_blend_bwd<16><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, ws.rec_u,
-                                            ws.g2d);
+#define DASS_BWD(SUBT, BT)                                                                                     \
+  k_blend_bwd<SUBT, BT><<<grid, block, 0, st>>>(io, nv, (int)total, per, bg[0], bg[1], bg[2], ws.ranges, vals, \
+                                                ws.rec_u, ws.g2d)
+  if (io.sub == 8) {
+    if (io.batch == 64) DASS_BWD(8, 64);
+    else if (io.batch == 256) DASS_BWD(8, 256);
+    else DASS_BWD(8, 128);
+  } else {
+    if (io.batch == 64) DASS_BWD(16, 64);
+    else if (io.batch == 256) DASS_BWD(16, 256);
+    else DASS_BWD(16, 128);
+  }
+#undef DASS_BWD
 }
 
 void launch_debug_keys(int view, int n, const Workspace& ws, const uint32_t* keys_sorted, const uint32_t* vals_sorted,
