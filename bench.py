@@ -47,6 +47,17 @@ def tile_name(t) -> str:
     return f"{t[0]}x{t[1]}" + ("s8" if len(t) > 2 and int(t[2]) == 8 else "")
 
 
+# LDS batches of the blend tried by the autotuner, in order of preference
+BATCH_CANDIDATES = (128, 64, 256)
+
+
+def autotune_name(key) -> str:
+    """'WxH' (one batch tried) or 'WxH/bB' for an autotuner result key."""
+    if len(key) == 2 and isinstance(key[1], int) and isinstance(key[0], tuple):
+        return f"{tile_name(key[0])}/b{key[1]}"
+    return tile_name(key)
+
+
 def parse_tile(name: str):
     name = name.lower()
     sub = 8 if name.endswith("s8") else 16
@@ -231,8 +242,11 @@ def train_step(s, it, args, per_view=False):
     else:
         ctx.shift_adjoint(g, s["dyn"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
         ctx.adam_step([(s["dpos"], s["d_dpos"], s["m"][0], s["v"][0], args.lr_pos),
-                       (s["drot"], s["d_drot"], s["m"][1], s["v"][1], args.lr_rot)], step=it)
-    ctx.densify_append(g, s["errs"], cams, s["gn"], s["cnt"], 0.0, 0.0, 0.0, args.densify_k, it, s["n_app"])
+                       (s["drot"], s["d_drot"], s["m"][1], s["v"][1], args.lr_rot)], step=it,
+                      d_step=s.get("d_step") if it is None else None)
+    # (a replayed graph keeps the densify seed of its capture; Adam counts its steps on the device)
+    ctx.densify_append(g, s["errs"], cams, s["gn"], s["cnt"], 0.0, 0.0, 0.0, args.densify_k,
+                       0 if it is None else it, s["n_app"])
 
 
 def time_steps(s, args, k, warm, per_view=False):
@@ -252,6 +266,34 @@ def time_steps(s, args, k, warm, per_view=False):
     wall = time.perf_counter() - t0
     s["ctx"].sync()
     return e0.elapsed_time(e1) / k, wall
+
+
+def time_graph_steps(s, args, k, warm, first_step):
+    """The same training step captured once in a HIP graph and replayed k times (after `warm`
+    untimed replays): Adam's step count lives on the device and advances per replay."""
+    torch = s["torch"]
+    s["d_step"] = torch.full((1,), first_step - 1, dtype=torch.int32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        train_step(s, None, args)  # warm-up on a side stream (also a real step)
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        train_step(s, None, args)
+    for _ in range(warm):
+        graph.replay()
+    torch.cuda.synchronize()
+    s["ctx"].sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    s["ctx"].sync()
+    del graph
+    return e0.elapsed_time(e1) / k
 
 
 def render_latency(s, args, reps):
@@ -349,23 +391,134 @@ def feature_render_times(s, args):
             "n_objects": 64, "n_dynamic": int(nd.item())}
 
 
-def cpu_baseline(s, args):
-    """The oracle (single-threaded float64 C) on a bounded sample: view 0 of the same scene,
-    forward + backward with a seeded upstream gradient; scaled to iterations of all views."""
+def host_cpu():
+    """(CPU model name, threads this process may use, capped at the 16-thread share of a one-GPU
+    host)."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return model, max(1, min(n, 16))
+
+
+def oracle_fwd_bwd(scene, cam, bg, seed):
+    """One fwd+bwd of the oracle on one view with a seeded upstream gradient N(0, 1)."""
     import oracle
-    scene, cam = s["scene"], s["cams"][0]
-    rng = np.random.default_rng(args.seed + 7)
+    rng = np.random.default_rng(seed)
     dl = rng.normal(0, 1, size=(3, cam.height, cam.width)).astype(np.float32)
+    vr = oracle.render_view(scene, cam, bg=bg)
+    oracle.render_backward(scene, [cam], [dl], bg=bg, renders=[vr])
+
+
+def cpu_baseline(s, args):
+    """The oracle (float64 C, untuned) on a bounded sample of the same workload: view 0 fwd+bwd
+    on one thread, then views 0..T-1 at once on T threads (one view per thread; the oracle's C
+    calls release the interpreter lock), T = the host threads this process may use (at most 16).
+    Scaled to iterations of all views: value = T views / wall time / n_views."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    scene, cams = s["scene"], s["cams"]
+    V = len(cams)
+    model, T = host_cpu()
+    T = min(T, V)
     oracle.lib()
     t0 = time.perf_counter()
-    vr = oracle.render_view(scene, cam, bg=args.bg)
-    oracle.render_backward(scene, [cam], [dl], bg=args.bg, renders=[vr])
-    dt = time.perf_counter() - t0
-    per_iter = dt * len(s["cams"])
-    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"view 0 of {len(s['cams'])} ({cam.width}x{cam.height}, {scene.n} Gaussians), fwd+bwd, "
-                      f"{dt:.1f} s; value = 1 / ({len(s['cams'])} x that time)",
-            "cpu": platform.processor() or platform.machine()}
+    oracle_fwd_bwd(scene, cams[0], args.bg, args.seed + 7)
+    dt1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=T) as ex:
+        list(ex.map(lambda v: oracle_fwd_bwd(scene, cams[v], args.bg, args.seed + 7 + v), range(T)))
+    dtT = time.perf_counter() - t0
+    cam = cams[0]
+    return {"value": T / dtT / V, "unit": "iters/s", "cores": T, "kind": "oracle",
+            "sample": f"views 0..{T - 1} of {V} ({cam.width}x{cam.height}, {scene.n} Gaussians), fwd+bwd, one "
+                      f"view per thread on {T} threads: {dtT:.1f} s; value = {T} / ({V} x that time)",
+            "cpu": model,
+            "single_thread": {"value": 1.0 / (dt1 * V), "cores": 1,
+                              "sample": f"view 0 fwd+bwd on one thread: {dt1:.1f} s; value = 1 / ({V} x that time)"}}
+
+
+def bench_oracle_timings(args):
+    """Host-only timings of the oracle (float64 C, untuned) on the other workloads: medians of 5
+    runs after one warm-up, on one thread and with one view per thread over T threads.
+      single view: 2,000 Gaussians SH0 at 128x128, fwd+bwd;
+      streaming: one iteration (shift, 20-view fwd, L1 gradient, 20-view bwd, shift adjoint,
+        Adam) of the 2,000-Gaussian scene on the 20-camera 128x128 rig, times 100 per timestep;
+      stress sub-scene: the large-footprint generator at 64 Gaussians, four 32x32 views, fwd+bwd;
+      serving: one render of the 200k-Gaussian scene at 640x480, 1280x720 and 1920x1080."""
+    import oracle
+    import synth
+    from concurrent.futures import ThreadPoolExecutor
+    model, T = host_cpu()
+    oracle.lib()
+    bg = args.bg
+
+    def median_s(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    res = {}
+    scene, cams1, _ = synth.single_view_scene(args.seed)
+    res["single_view_2k_sh0_128x128_fwd_bwd_ms"] = 1e3 * median_s(lambda: oracle_fwd_bwd(scene, cams1[0], bg, 1))
+    log(f"[oracle] single view {res['single_view_2k_sh0_128x128_fwd_bwd_ms']:.1f} ms")
+    rig = synth.streaming_rig(128, 128)
+    motion = synth.timestep_motion(args.seed, 1, scene.n)
+    rng = np.random.default_rng(args.seed + 11)
+    targets = [rng.uniform(0, 1, size=(3, 128, 128)) for _ in rig]
+    nd = motion.dynamic.size
+    dpos = np.zeros((3, nd)); drot = np.concatenate([np.ones((1, nd)), np.zeros((3, nd))])
+    mom = [np.zeros((3, nd)), np.zeros((4, nd))]
+    vel = [np.zeros((3, nd)), np.zeros((4, nd))]
+
+    def iteration(threads):
+        m, q = oracle.shift_fwd(scene, motion.dynamic, dpos, drot)
+        sc = synth.Scene(m.astype(np.float32), q.astype(np.float32), scene.log_scale, scene.logit, scene.sh,
+                         scene.sh_degree)
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            vrs = list(ex.map(lambda c: oracle.render_view(sc, c, bg=bg), rig))
+        _, dls, _ = oracle.l1_loss_grad(np.stack([v.rgb for v in vrs]), np.stack(targets))
+
+        def bwd(v):
+            return oracle.render_backward(sc, [rig[v]], [dls[v]], bg=bg, renders=[vrs[v]])[0]
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            gs = list(ex.map(bwd, range(len(rig))))
+        gm = sum(g.mean for g in gs)
+        gq = sum(g.quat for g in gs)
+        dm, dq = oracle.shift_adj(sc, motion.dynamic, drot, gm, gq)
+        for i, (p, g) in enumerate(((dpos, dm), (drot, dq))):
+            oracle.adam(p, g, mom[i], vel[i], 1e-3, 0.9, 0.999, 1e-15, 1)
+
+    for th in (1, T):
+        ms = 1e3 * median_s(lambda: iteration(th), reps=3)
+        res[f"streaming_iteration_20x128x128_ms_T{th}"] = ms
+        res[f"streaming_ms_per_timestep_100_iters_T{th}"] = 100.0 * ms
+        log(f"[oracle] streaming iteration {ms:.1f} ms on {th} threads")
+    sub, subcams = synth.large_footprint_scene(args.seed, n=64, width=32, height=32)
+    res["stress_subscene_64_4x32x32_fwd_bwd_ms"] = 1e3 * median_s(
+        lambda: [oracle_fwd_bwd(sub, c, bg, 3) for c in subcams])
+    big, _, _ = synth.multiview_scene(args.seed, n=args.n, n_views=1, width=64, height=64, with_grads=False)
+    pos = synth.rig_positions()
+    for W, H in synth.RESOLUTIONS:
+        cam = synth.make_camera(np.eye(3), pos[7], W, H)
+        res[f"serving_render_{W}x{H}_ms"] = 1e3 * median_s(lambda: oracle.render_view(big, cam, bg=bg), reps=3)
+        log(f"[oracle] render {W}x{H} {res[f'serving_render_{W}x{H}_ms']:.0f} ms")
+    line = {"metric": "oracle (float64 C) timings on the host", "value": None, "unit": "ms", "n_gpus": 0,
+            "cpu": model, "threads": T, "data": "synthetic",
+            "timings_ms": {k: round(v, 3) for k, v in res.items()}}
+    print(json.dumps(line), flush=True)
 
 
 def _scene_buffers(scene, capacity):
@@ -491,11 +644,13 @@ def bench_streaming(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_serving(args):
+def serving_leg(args, n_requests):
     """Continuous-batching render serving of the 200k-Gaussian SH3 scene while a training thread
     runs timesteps of the streaming loop on the 20-view 1352x1014 rig (its own stream) and
     publishes each finished timestep.  Requests arrive Poisson at `rate` from 64 viewers, at
-    640x480, 1280x720 or 1920x1080; latency is arrival to completion event."""
+    640x480, 1280x720 or 1920x1080; latency is arrival to completion event.  Returns the
+    figures of the open-loop run with training, of a closed batch without training, and the
+    training times."""
     import threading
     import torch
     import synth
@@ -521,7 +676,7 @@ def bench_serving(args):
     server = RenderServer(snaps, max_gaussians=cap, n_slots=args.slots, max_batch=args.max_batch,
                           max_tiles=args.max_batch * 8160, keys_per_tile=args.keys_per_tile)
     reqs = [Request(i, r.arrival_s, r.camera)
-            for i, r in enumerate(synth.serving_requests(args.seed, n_requests=args.requests, rate_hz=args.rate))]
+            for i, r in enumerate(synth.serving_requests(args.seed, n_requests=n_requests, rate_hz=args.rate))]
     train_stream = torch.cuda.Stream()
     t_state = {"t": 0}
 
@@ -566,15 +721,11 @@ def bench_serving(args):
     torch.cuda.synchronize()
     log(f"[bench] serving with training: {st}; training ms/timestep {[round(d['ms'], 1) for d in during]}")
     train_alone_ms = float(np.mean([a["ms"] for a in alone[1:]] or [a["ms"] for a in alone]))
-    line = {
-        "metric": "serving frames/s and p50/p99 latency (Poisson 500/s, mixed 640x480..1920x1080, 200k Gaussians) "
-                  "with concurrent training",
-        "value": round(st["frames_per_s"], 2), "unit": "frames/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
-        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"serving_{N // 1000}k_sh3_poisson{int(args.rate)}_64viewers_mixedres",
-                   "requests": len(reqs), "slots": args.slots, "max_batch": args.max_batch,
-                   "training": f"{len(cams)} views {args.width}x{args.height}, {args.iters} iters/timestep"},
+    return {
+        "workload": f"serving_{N // 1000}k_sh3_poisson{int(args.rate)}_64viewers_mixedres",
+        "requests": len(reqs), "slots": args.slots, "max_batch": args.max_batch,
+        "training": f"{len(cams)} views {args.width}x{args.height}, {args.iters} iters/timestep",
+        "frames_per_s": round(st["frames_per_s"], 2),
         "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "retried": st["retried"],
         "train_ms_per_timestep_concurrent": round(float(np.mean([d["ms"] for d in during])), 2) if during else None,
         "timesteps_during_serving": len(during),
@@ -582,6 +733,20 @@ def bench_serving(args):
         "capacity_frames_per_s": round(st_cap["frames_per_s"], 2),
         "capacity_p50_ms": round(st_cap["p50_ms"], 3), "capacity_p99_ms": round(st_cap["p99_ms"], 3),
     }
+
+
+def bench_serving(args):
+    """The serving leg alone, with its own JSON line (frames/s, p50/p99)."""
+    r = serving_leg(args, args.requests)
+    line = {
+        "metric": "serving frames/s and p50/p99 latency (Poisson 500/s, mixed 640x480..1920x1080, 200k Gaussians) "
+                  "with concurrent training",
+        "value": r["frames_per_s"], "unit": "frames/s", "n_gpus": 1, "steps": r["requests"], "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {k: r[k] for k in ("workload", "requests", "slots", "max_batch", "training")},
+    }
+    line.update({k: v for k, v in r.items() if k not in line["config"] and k != "frames_per_s"})
     print(json.dumps(line), flush=True)
 
 
@@ -616,8 +781,8 @@ def bench_stress(args):
 
     tuned = None
     if not args.no_autotune:
-        tuned = ctx.autotune_tile(g, cams, args.bg, outs, dls, grads, reps=2)
-        log(f"[bench] stress autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
+        tuned = ctx.autotune_tile(g, cams, args.bg, outs, dls, grads, reps=2, batches=BATCH_CANDIDATES)
+        log(f"[bench] stress autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}, batch {ctx.batch}")
     step()
     tile = ctx.tile
     ctx.tile = (16, 16)  # pair counts at 16x16 tiles (see the multi-view benchmark)
@@ -670,7 +835,7 @@ def bench_stress(args):
         "warmup": args.warmup, "ms_per_step": round(graph_ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"stress_{N // 1000}k_sh3_4x1920x1080", "tile": tile_name(ctx.tile)},
-        "autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
+        "autotune_ms": {autotune_name(t): v for t, v in tuned.items()} if tuned else None, "blend_batch": ctx.batch,
         "eager_ms_per_step": round(eager_ms, 3),
         "stage_ms_per_step": {k: round(v, 4) for k, v in per_stage.items()},
         "pairs": {"evaluated_fwd": evaluated, "blended": blended, "walked_bwd": walked},
@@ -686,7 +851,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["multiview", "single", "streaming", "serving", "stress"], default="multiview")
+    ap.add_argument("--workload", choices=["multiview", "single", "streaming", "serving", "stress", "oracle"],
+                    default="multiview")
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--views", type=int, default=20)
     ap.add_argument("--width", type=int, default=1352)
@@ -708,6 +874,8 @@ def main():
     ap.add_argument("--feature-reps", type=int, default=5,
                     help="multiview: timed 16-channel identity-feature renders and dynamics masks (0 skips)")
     ap.add_argument("--per-view-steps", type=int, default=3)
+    ap.add_argument("--graph-steps", type=int, default=20,
+                    help="multiview: also time this many steps replayed from one captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=100, help="iterations per timestep (streaming, serving)")
     ap.add_argument("--timesteps", type=int, default=40, help="timesteps (streaming)")
@@ -716,7 +884,9 @@ def main():
     ap.add_argument("--stream-scene", choices=["rig", "multiview"], default="rig",
                     help="streaming: the 2k-Gaussian scene on a 128x128 rig, or the full multi-view scene "
                          "(--n Gaussians, --views cameras at --width x --height)")
-    ap.add_argument("--requests", type=int, default=3000, help="requests (serving)")
+    ap.add_argument("--requests", type=int, default=30000, help="requests (serving workload)")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="multiview: requests of the serving leg run after the training steps (0: none)")
     ap.add_argument("--rate", type=float, default=500.0)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--max-batch", type=int, default=8)
@@ -729,6 +899,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="stress: keep 16x16 tiles")
     ap.add_argument("--no-tile-autotune", action="store_true",
                     help="multiview/single: keep 16x16 tiles instead of the native autotuner's choice")
+    ap.add_argument("--batch", type=int, default=0, choices=[0, 64, 128, 256],
+                    help="blend LDS batch (0: autotuned with the tile size)")
     ap.add_argument("--tile", default="",
                     help="multiview/single: fixed tile size WxH (edges 16, 32 or 64; suffix s8 for 8x8 "
                          "sub-tiles) instead of autotuning")
@@ -742,6 +914,8 @@ def main():
             print("bench.py measures one GPU only: the library has no multi-GPU path (views would shard "
                   "across GPUs with one gradient all-reduce per iteration).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "oracle":  # host only
+        return bench_oracle_timings(args)
     import torch
     torch.cuda.set_device(0)
     if args.copy_probe:
@@ -765,12 +939,16 @@ def main():
     ctx = s["ctx"]
     train_step(s, 1, args)
     tuned = None
+    if args.batch:
+        ctx.batch = args.batch
     if args.tile:
         ctx.tile = parse_tile(args.tile)
     elif not args.no_tile_autotune:
-        # native autotuner over tile sizes on this workload (outside the timed region)
-        tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3)
-        log(f"[bench] autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}")
+        # native autotuner over tile sizes and blend batches on this workload (outside the timed
+        # region)
+        tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3,
+                                  batches=(args.batch,) if args.batch else BATCH_CANDIDATES)
+        log(f"[bench] autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}, batch {ctx.batch}")
     # pair counts of the blend (outside the timed region), always at 16x16 tiles: with larger
     # tiles n_contrib counts positions in a longer list whose extra entries are culled per
     # sub-tile, so only the 16x16 counts measure the work the definition asks for
@@ -808,9 +986,16 @@ def main():
     roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_FLOPS / 1e12,
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": traffic,
             "flops_per_launch": float(cand[dom]), "avg_launch_ms": round(dom_ms, 4)}
+    graph_ms = None
+    if args.workload == "multiview" and args.shift == "direct" and args.graph_steps > 0:
+        graph_ms = time_graph_steps(s, args, args.graph_steps, 2, args.warmup + args.steps + 2)
+        log(f"[bench] graph-replayed step {graph_ms:.3f} ms ({1000.0 / graph_ms:.2f} iters/s)")
     p50, p99 = render_latency(s, args, args.render_reps)
     log(f"[bench] render p50 {p50:.3f} ms p99 {p99:.3f} ms")
     feats = feature_render_times(s, args) if args.workload == "multiview" and args.feature_reps > 0 else None
+    serving = None
+    if args.workload == "multiview" and args.serving_requests > 0:
+        serving = serving_leg(args, args.serving_requests)
     lat = None
     if args.workload == "single":
         e_ms, g_ms = fwdbwd_latency(s, args, 200)
@@ -824,7 +1009,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(s, args)
-        log(f"[bench] cpu baseline {cpu['value']:.3e} iters/s")
+        log(f"[bench] cpu baseline {cpu['value']:.3e} iters/s on {cpu['cores']} threads "
+            f"({cpu['single_thread']['value']:.3e} on one), {cpu['cpu']}")
     cams = s["cams"]
     line = {
         "metric": ("fwd+bwd iters/s @200k Gaussians x 20 views 1352x1014; render p50/p99 ms"
@@ -835,14 +1021,17 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": s["name"], "n_gaussians": s["N"], "sh_degree": int(s["g"].sh_degree),
                    "views": len(cams), "width": cams[0].width, "height": cams[0].height,
-                   "tile": tile_name(ctx.tile),
+                   "tile": tile_name(ctx.tile), "blend_batch": ctx.batch,
                    "n_dynamic": s["nd"], "densify_k": args.densify_k,
                    "loss": "l1" if args.ssim_lambda == 0.0 else f"(1-l) L1 + l D-SSIM, l = {args.ssim_lambda}",
                    "shift": ("direct offsets of the dynamic group" if args.shift == "direct" else
                              "H_dyn (T 2^16, F 4) / H_st (T 2^14, F 2) hash fields, 16 levels, 64 hidden"),
                    "parallelism": "single GPU"},
-        "tile_autotune_ms": {tile_name(t): v for t, v in tuned.items()} if tuned else None,
+        "tile_autotune_ms": ({autotune_name(t): v for t, v in tuned.items()} if tuned else None),
+        "graph_replay": ({"ms_per_step": round(graph_ms, 3), "iters_per_s": round(1000.0 / graph_ms, 3),
+                          "steps": args.graph_steps} if graph_ms else None),
         "render_p50_ms": round(p50, 4), "render_p99_ms": round(p99, 4),
+        "serving": serving,
         "identity_features": feats,
         "fwd_bwd_latency": lat,
         "per_view_loop_iters_per_s": round(1000.0 / pv_ms, 3) if pv_ms else None,
