@@ -25,6 +25,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Hardware queues per process, read when the HIP runtime starts: the serving legs run training
+# and three render slots on streams of their own, and with HIP's default of 4 queues one slot
+# shares the training stream's queue, where its renders wait behind training kernels (p50/p99
+# 15/43 ms against 2.4/5.5 ms with 8 queues on the 500/s workload).  Set before torch loads
+# (serving.MIN_HW_QUEUES states the same number for library users).
+SERVING_HW_QUEUES = 8
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < SERVING_HW_QUEUES:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(SERVING_HW_QUEUES)
+
 PEAK_FP32_FLOPS = 157.3e12   # MI355X fp32 vector, published
 PEAK_HBM_BPS = 8.0e12        # MI355X HBM3E, published
 # Algorithmic flops per (pixel, list entry) pair of the blend (counted from its definition):

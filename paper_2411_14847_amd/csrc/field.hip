@@ -300,76 +300,138 @@ __global__ __launch_bounds__(kQuadThreads) void k_field_bwd_query4(const FieldK 
   }
 }
 
-// Weight gradients: a workgroup sums a contiguous part of the queries, staging 64 queries' rows
-// at a time in LDS; thread (hidden unit j, group gr) owns dW1[j][features of group gr], group 0
-// also db1[j], group 1 dW2[:, j], group 2 db2.  One partial row per workgroup.
+// Weight gradients on the matrix cores: over a contiguous part of the queries, a workgroup forms
+//   dW1 [HID][LF] = dpre [HID][q] . enc [LF][q]^T   and   dW2 [7][HID] = dout [7][q] . act [HID][q]^T
+// with fp32 MFMA (v_mfma_f32_16x16x4f32: 16x16 output tiles, four queries per instruction), and
+// the bias sums db1 = sum_q dpre, db2 = sum_q dout on the vector units beside them.  Queries
+// are staged 64 at a time in LDS, feature-major as the rows are stored (row stride 66 floats:
+// a tile operand's 16 rows x 4 queries land in 32 different banks); each thread prefetches its
+// share of the next 64 queries into registers while the current ones are multiplied.  One
+// partial row per workgroup, summed in a fixed order afterwards.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWgThreads = 256;
+constexpr int kWgQ = 64;        // queries per staged chunk
+constexpr int kWgS = kWgQ + 2;  // LDS row stride (floats)
+
+template <int F, int HID>
+struct WgradShape {
+  static constexpr int KL = max_levels<F>();
+  static constexpr int LFM = KL * F;                     // encoding rows (a multiple of 16)
+  static constexpr int R = 2 * HID + LFM + 8;            // staged rows: dpre, act, enc, dout (+1 zero)
+  static constexpr int PER = (R * kWgQ) / kWgThreads;    // values each thread stages per chunk
+  static constexpr int RT = HID / 16, CT = LFM / 16;     // dW1 tiles
+  static constexpr int TILES = RT * CT + HID / 16;       // + dW2 tiles (7 rows padded to 16)
+  static constexpr int TPW = (TILES + 3) / 4;            // tiles per wave
+};
+
 template <int F, int HID>
 __global__ __launch_bounds__(kWgThreads) void k_field_wgrad(const FieldK f, int m, FieldRows rows,
                                                             float* __restrict__ part) {
-  constexpr int KL = max_levels<F>();
-  constexpr int LFM = KL * F;
-  constexpr int PG = LFM / 4;  // features per group
-  __shared__ float s_dp[64][HID + 1];
-  __shared__ float s_h[64][HID + 1];
-  __shared__ float s_e[64][LFM + 1];
-  __shared__ float s_o[64][8];
-  const int t = threadIdx.x;
-  const int j = t & 63, gr = t >> 6;
+  using S = WgradShape<F, HID>;
+  static_assert(S::R * kWgQ % kWgThreads == 0, "staging split");
+  static_assert(S::LFM % 16 == 0 && HID % 16 == 0, "tile split");
+  __shared__ float s_v[S::R][kWgS];  // rows: dpre [HID], act [HID], enc [LFM], dout [8]
+  __shared__ float s_b1[4][HID];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int LF = f.L * F;
   const int q0 = (int)((int64_t)m * blockIdx.x / gridDim.x), q1 = (int)((int64_t)m * (blockIdx.x + 1) / gridDim.x);
-  float aw1[PG], aw2[7], ab = 0.f;
+  // staging map: value i of this thread is row (t / kWgQ) + i * (kWgThreads / kWgQ), query t % kWgQ
+  const int sc = t % kWgQ, sr = t / kWgQ;
+  constexpr int RS = kWgThreads / kWgQ;  // rows apart of a thread's consecutive values
+  float pre[S::PER];
+  // value i: row sr + RS i of the stacked rows (dpre, act, enc padded to LFM, dout padded to 8)
+  auto fetch = [&](int base) {
+    const int q = base + sc;
+    if (q >= q1) {
 #pragma unroll
-  for (int i = 0; i < PG; ++i) aw1[i] = 0.f;
+      for (int i = 0; i < S::PER; ++i) pre[i] = 0.f;
+      return;
+    }
+    const int64_t step = (int64_t)RS * m;
+    const float* pd = rows.dpre + (int64_t)sr * m + q;
+    const float* pa = rows.act + (int64_t)sr * m + q;
+    const float* pe = rows.enc + (int64_t)sr * m + q;
 #pragma unroll
-  for (int o = 0; o < 7; ++o) aw2[o] = 0.f;
-  for (int base = q0; base < q1; base += 64) {
-    const int nq = min(64, q1 - base);
-    // stage: row r of a [R][m] array, query base + c (c < 64) -> s[c][r]
-    for (int e = t; e < HID * 64; e += kWgThreads) {
-      const int r = e >> 6, c = e & 63;
-      const bool in = c < nq;
-      s_dp[c][r] = in ? rows.dpre[(int64_t)r * m + base + c] : 0.f;
-      s_h[c][r] = in ? rows.act[(int64_t)r * m + base + c] : 0.f;
+    for (int i = 0; i < HID / RS; ++i) pre[i] = pd[i * step];
+#pragma unroll
+    for (int i = 0; i < HID / RS; ++i) pre[HID / RS + i] = pa[i * step];
+#pragma unroll
+    for (int i = 0; i < S::LFM / RS; ++i) pre[2 * HID / RS + i] = (sr + RS * i) < LF ? pe[i * step] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 8 / RS; ++i) {
+      const int o = sr + RS * i;
+      pre[(2 * HID + S::LFM) / RS + i] = o < 7 ? rows.dout[(int64_t)o * m + q] : 0.f;
     }
-    for (int e = t; e < LFM * 64; e += kWgThreads) {
-      const int r = e >> 6, c = e & 63;
-      s_e[c][r] = (c < nq && r < LF) ? rows.enc[(int64_t)r * m + base + c] : 0.f;
-    }
-    for (int e = t; e < 7 * 64; e += kWgThreads) {
-      const int r = e >> 6, c = e & 63;
-      s_o[c][r] = c < nq ? rows.dout[(int64_t)r * m + base + c] : 0.f;
-    }
+  };
+  f32x4 acc[S::TPW];
+#pragma unroll
+  for (int k = 0; k < S::TPW; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float b1 = 0.f, b2 = 0.f;  // thread t: db1 of hidden unit t % HID over its quarter; db2 of o = t / 16
+  const int i16 = lane & 15, k4 = lane >> 4;  // operand lane -> (tile row or column, query of 4)
+  if (q0 < q1) fetch(q0);
+  for (int base = q0; base < q1; base += kWgQ) {
+#pragma unroll
+    for (int i = 0; i < S::PER; ++i) s_v[sr + i * (kWgThreads / kWgQ)][sc] = pre[i];
     __syncthreads();
-    if (j < HID) {
-      for (int c = 0; c < nq; ++c) {
-        const float dp = s_dp[c][j];
+    if (base + kWgQ < q1) fetch(base + kWgQ);  // next chunk's loads in flight during the products
 #pragma unroll
-        for (int i = 0; i < PG; ++i) aw1[i] = fmaf(dp, s_e[c][gr * PG + i], aw1[i]);
-        if (gr == 0) ab += dp;
-        if (gr == 1) {
-          const float hv = s_h[c][j];
+    for (int kq = 0; kq < kWgQ; kq += 4) {
 #pragma unroll
-          for (int o = 0; o < 7; ++o) aw2[o] = fmaf(s_o[c][o], hv, aw2[o]);
+      for (int k = 0; k < S::TPW; ++k) {
+        const int tile = wave + 4 * k;
+        if (tile >= S::TILES) break;
+        float a, b;
+        if (tile < S::RT * S::CT) {  // dW1 tile (row tile, column tile)
+          const int rt = tile / S::CT, ct = tile % S::CT;
+          a = s_v[rt * 16 + i16][kq + k4];                  // dpre[h][q]
+          b = s_v[2 * HID + ct * 16 + i16][kq + k4];        // enc[k][q]
+        } else {  // dW2 column tile: dout [7 -> 16 rows] x act
+          const int ct = tile - S::RT * S::CT;
+          a = s_v[2 * HID + S::LFM + (i16 < 8 ? i16 : 7)][kq + k4];  // row 7 of the dout block is zero
+          a = i16 < 7 ? a : 0.f;
+          b = s_v[HID + ct * 16 + i16][kq + k4];            // act[h][q]
         }
-        if (gr == 2 && j < 7) ab += s_o[c][j];
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[k], 0, 0, 0);
       }
+    }
+    // bias sums on the vector units
+    if (t < 4 * HID) {
+#pragma unroll 4
+      for (int c = 0; c < kWgQ / 4; ++c) b1 += s_v[t % HID][(t / HID) * (kWgQ / 4) + c];
+    }
+    if (t < 7 * 16) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b2 += s_v[2 * HID + S::LFM + t / 16][(t % 16) * 4 + c];
     }
     __syncthreads();
   }
   // partial row: [w1: HID][LF] [b1: HID] [w2: 7][HID] [b2: 7]
   float* P = part + (size_t)blockIdx.x * field_part_stride(HID, LF);
-  if (j < HID) {
 #pragma unroll
-    for (int i = 0; i < PG; ++i)
-      if (gr * PG + i < LF) P[j * LF + gr * PG + i] = aw1[i];
-    if (gr == 0) P[HID * LF + j] = ab;
-    if (gr == 1) {
+  for (int k = 0; k < S::TPW; ++k) {
+    const int tile = wave + 4 * k;
+    if (tile >= S::TILES) break;
 #pragma unroll
-      for (int o = 0; o < 7; ++o) P[HID * LF + HID + o * HID + j] = aw2[o];
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * k4 + r, col = i16;  // D[row][col] of the tile
+      if (tile < S::RT * S::CT) {
+        const int h = (tile / S::CT) * 16 + row, kk = (tile % S::CT) * 16 + col;
+        if (kk < LF) P[h * LF + kk] = acc[k][r];
+      } else {
+        const int h = (tile - S::RT * S::CT) * 16 + col;
+        if (row < 7) P[HID * LF + HID + row * HID + h] = acc[k][r];
+      }
     }
-    if (gr == 2 && j < 7) P[HID * LF + 8 * HID + j] = ab;
   }
+  // db1: four quarters of the queries per hidden unit (HID * 4 <= 256 threads), added in order
+  if (t < 4 * HID) s_b1[t / HID][t % HID] = b1;
+  // db2: 16 consecutive lanes per output, summed across them in order
+  float b2s = b2;
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) b2s += __shfl_xor(b2s, d, 64);
+  __syncthreads();
+  if (t < HID) P[HID * LF + t] = ((s_b1[0][t] + s_b1[1][t]) + s_b1[2][t]) + s_b1[3][t];
+  if (t < 7 * 16 && (t % 16) == 0) P[HID * LF + 8 * HID + t / 16] = b2s;
 }
 
 // Level, first float and end of slice b of the table (slice_begin: prefix over levels).

@@ -9,6 +9,11 @@ The scene is read from a published snapshot (double-buffered), so renders never 
 half-updated timestep.  Every request's image is the same alone and in any batch (the forward
 has no cross-view interaction and no atomics).  Latency = completion time of the batch's HIP
 event (polled) minus the request's arrival time.
+
+Each slot's stream and the training stream need hardware queues of their own: streams that share
+a hardware queue run in submission order, so a slot sharing the training stream's queue waits
+behind its kernels.  HIP maps streams onto GPU_MAX_HW_QUEUES queues (4 by default, read when the
+runtime starts): a serving process should start with at least MIN_HW_QUEUES.
 """
 from __future__ import annotations
 
@@ -23,6 +28,9 @@ import torch
 
 from ._ffi import DASS_E_CAPACITY
 from .api import Context, DassError, GaussianBuffers, RenderOut
+
+# hardware queues a serving process wants (default stream, training, three slots, spare)
+MIN_HW_QUEUES = 8
 
 
 def tiles_of(cam) -> int:
