@@ -607,7 +607,7 @@ def bench_streaming(args):
             tr.set_targets(targets[0])
             tr.iteration()
             tuned = tr.autotune_tile()
-            log(f"[bench] streaming {name}: autotune {tuned}; using {ctx.tile}")
+            log(f"[bench] streaming {name}: autotune {tuned}; using {ctx.tile}, batch {ctx.batch}")
         T = args.timesteps if name != "per_view_eager" else min(args.timesteps, args.per_view_timesteps)
         rows = []
         prof_from = T - 2 if name == "batched_eager" and T >= 3 else None
@@ -628,7 +628,7 @@ def bench_streaming(args):
                      "mean_loss_drop": float(np.mean([r["loss_first"] - r["loss_last"] for r in rows])),
                      "ms_series": [round(r["ms"], 1) for r in rows], "n_series": [r["n"] for r in rows],
                      "inherited_series": [r["inherited"] for r in rows], "pruned_series": [r["pruned"] for r in rows],
-                     "tile": tile_name(ctx.tile)}
+                     "tile": tile_name(ctx.tile), "blend_batch": ctx.batch}
         if stages is not None:
             res[name]["stage_ms_per_timestep_last3"] = {k: round(v[0] / 3.0, 3) for k, v in stages.items()}
         log(f"[bench] streaming {name}: {res[name]}")

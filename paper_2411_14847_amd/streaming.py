@@ -234,12 +234,13 @@ class Trainer:
         if groups:
             ctx.adam_step(groups, cfg.beta1, cfg.beta2, cfg.eps, stream=stream, d_step=self.d_step)
 
-    def autotune_tile(self, reps: int = 3) -> dict:
-        """Picks the context's tile size with the native autotuner on the current timestep's
-        render (call after at least one iteration of the timestep, so the upstream gradients
-        are real).  The graph of the timestep is re-captured at the next replay."""
+    def autotune_tile(self, reps: int = 3, batches=(128, 64)) -> dict:
+        """Picks the context's tile size and blend batch with the native autotuner on the current
+        timestep's render (call after at least one iteration of the timestep, so the upstream
+        gradients are real).  The graph of the timestep is re-captured at the next replay."""
         scratch = self.g.zeros_like()
-        res = self.ctx.autotune_tile(self.gs, self.cams, self.cfg.bg, self.outs, self.dls, scratch, reps=reps)
+        res = self.ctx.autotune_tile(self.gs, self.cams, self.cfg.bg, self.outs, self.dls, scratch, reps=reps,
+                                     batches=batches)
         self.graph = None
         return res
 

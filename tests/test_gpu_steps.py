@@ -331,6 +331,38 @@ def test_autograd_function_matches_render_bwd():
         assert torch.equal(img.detach(), o.rgb)
 
 
+def test_autograd_function_matches_oracle():
+    """The autograd path against the float64 oracle: images within the image tolerance, and the
+    parameter gradients of L = sum_v <dl_v, image_v> (upstream zeroed where a decision sits within
+    rounding of its threshold) within the gradient tolerance."""
+    from paper_2411_14847_amd.autograd import rasterize
+    from gpu_util import IMG_TOL, assert_grad_close, excluded_pixels
+    scene, cams, dls = synth.multiview_scene(6, n=1500, n_views=2, width=96, height=72)
+    log("[autograd vs oracle]")
+    renders = [oracle.render_view(scene, c, bg=BG) for c in cams]
+    dls = [d.copy() for d in dls]
+    for d, vr, cam in zip(dls, renders, cams):
+        d[:, excluded_pixels(vr, cam, grad=True)] = 0.0
+    og, _, _, _ = oracle.render_backward(scene, cams, dls, bg=BG, renders=renders)
+    g = to_gpu(scene)
+    ctx = make_ctx(scene.n, cams)
+    params = [t[..., :scene.n].clone().requires_grad_(True) for t in g.planes()]
+    imgs = rasterize(*params, ctx, cams, BG, scene.sh_degree)
+    loss = sum((img * dev(d)).sum() for img, d in zip(imgs, dls))
+    loss.backward()
+    ctx.sync()
+    for img, vr, cam in zip(imgs, renders, cams):
+        ex = excluded_pixels(vr, cam)
+        err = np.abs(img.detach().cpu().numpy() - vr.rgb)[:, ~ex]
+        assert err.max() <= IMG_TOL, err.max()
+    gflag = np.zeros(scene.n, bool)
+    for cam in cams:
+        gflag |= (oracle.project(scene, cam).flags & oracle.GAUSS_GRAD_FLAGS) != 0
+    for name, p in zip(("mean", "quat", "log_scale", "logit", "sh"), params):
+        rel = assert_grad_close(name, p.grad.cpu().numpy(), getattr(og, name), exclude=gflag)
+        log(f"  {name}: max rel err (significant) {rel:.2e}")
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 @pytest.mark.parametrize("lam", [0.0, 0.2], ids=["l1", "l1_dssim"])
 def test_streaming_driver(use_graph, lam):
