@@ -74,10 +74,10 @@ def parse_tile(name: str):
     return (w, h, sub) if sub == 8 else (w, h)
 
 
-def measured_traffic(kernel: str, workload: str, tile: str):
+def measured_traffic(kernel: str, workload: str, tile: str, batch: int):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None if
-    there is none for this workload and tile size, or the blend source changed since the
-    counters were taken."""
+    there is none for this workload, tile size and blend batch, or the blend source changed
+    since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
     src = os.path.join(ROOT, "paper_2411_14847_amd", "csrc", "raster.hip")
@@ -88,6 +88,8 @@ def measured_traffic(kernel: str, workload: str, tile: str):
         return None
     rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     if rec.get("kernel") != kernel or rec.get("workload") != workload or tile not in rec.get("by_tile", {}):
+        return None
+    if int(rec.get("batch", 128)) != int(batch):
         return None
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("raster_hip_sha256"):
         return None
@@ -991,7 +993,7 @@ def main():
     kname = {"blend_bwd": "k_blend_bwd", "blend_fwd": "k_blend_fwd"}[dom]
     wl_key = f"multiview_{args.n // 1000}k_{args.views}x{args.width}x{args.height}"
     tile_s = tile_name(ctx.tile)
-    traffic = measured_traffic(kname, wl_key, tile_s) if args.workload == "multiview" else None
+    traffic = measured_traffic(kname, wl_key, tile_s, ctx.batch) if args.workload == "multiview" else None
     roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_FLOPS / 1e12,
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_FLOPS, 4), "traffic": traffic,
             "flops_per_launch": float(cand[dom]), "avg_launch_ms": round(dom_ms, 4)}
