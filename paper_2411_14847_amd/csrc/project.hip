@@ -251,7 +251,9 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
   float shc[3 * K];
 #pragma unroll
   for (int k = 0; k < 3 * K; k++) shc[k] = sc.sh[(int64_t)k * sc.stride + g];
-  for (int v = 0; v < nv; v++) {
+  // views blockIdx.y, blockIdx.y + gridDim.y, ...: a Gaussian's views are split over gridDim.y
+  // threads (each forms the Gaussian's 3D covariance itself), so the launch has enough waves
+  for (int v = blockIdx.y; v < nv; v += gridDim.y) {
     const CamK& cam = cams.c[v];
     const int64_t i = (int64_t)v * sc.n + g;
     ViewD V;
@@ -554,7 +556,11 @@ __global__ void k_debug_projection(SceneK sc, CamK cam, double* out) {
 
 void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws, hipStream_t st) {
   if (s.n == 0) return;
-  dim3 grid((s.n + 255) / 256), block(256);
+  // view groups per Gaussian: about 3,000+ workgroups in flight once there are enough views
+  const int blocks_g = (s.n + 255) / 256;
+  int vs = 1;
+  while (vs < 4 && vs * 2 <= nv && (int64_t)blocks_g * vs < 4096) vs *= 2;
+  dim3 grid(blocks_g, vs), block(256);
   switch (s.deg) {
     case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
     case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
