@@ -376,12 +376,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(pw));
         const bool ok = a >= thr[k];
         float wgt = ok ? a * T[k] : 0.f;
-        float Tn = T[k] - wgt;
+        T[k] -= wgt;  // updated in place: a pixel that stops here gets its transmittance back below
         bool take = ok;
-        const bool stop = ok && Tn < kTStop;
+        const bool stop = ok && T[k] < kTStop;
         if (__builtin_expect(__ballot(stop) != 0, 0)) {  // uniform: a pixel of the quadrant stops here
+          // T - w + w: the transmittance before this entry up to one rounding
+          T[k] = stop ? T[k] + wgt : T[k];
           wgt = stop ? 0.f : wgt;
-          Tn = stop ? T[k] : Tn;
           take = ok && !stop;
           if (COUNT) n_eval += thr[k] < 1.f ? 1u : 0u;
           thr[k] = stop ? kNever : thr[k];
@@ -392,7 +393,6 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         c0[k] = fmaf(c.x, wgt, c0[k]);
         c1[k] = fmaf(c.y, wgt, c1[k]);
         c2[k] = fmaf(c.z, wgt, c2[k]);
-        T[k] = Tn;
         last[k] = take ? wv : last[k];
       }
     }
@@ -679,10 +679,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
         const float a = fminf(kAlphaMax, __builtin_amdgcn_exp2f(pw));
         const bool ok = a >= thr[k];
         float wgt = ok ? a * T[k] : 0.f;
-        float Tn = T[k] - wgt;
-        const bool stop = ok && Tn < kTStop;
+        T[k] -= wgt;
+        const bool stop = ok && T[k] < kTStop;
+        T[k] = stop ? T[k] + wgt : T[k];
         wgt = stop ? 0.f : wgt;
-        Tn = stop ? T[k] : Tn;
         thr[k] = stop ? kNever : thr[k];
 #pragma unroll
         for (int c = 0; c < kFeatMaxC / 4; c++) {
@@ -691,7 +691,6 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
           acc[k][4 * c + 2] += fe[c].z * wgt;
           acc[k][4 * c + 3] += fe[c].w * wgt;
         }
-        T[k] = Tn;
       }
     }
     bool alive = false;
