@@ -397,6 +397,8 @@ dass_status dass_sync(dass_ctx ctx, dass_stream stream) {
     launch_fill_u32(ctx->ws.err, 0u, 1, st);
     HIP_TRY(ctx, hipStreamSynchronize(st));
     if (err & kErrKeyOverflow) return fail(ctx, DASS_E_CAPACITY, "tile-key buffer overflow (raise max_keys)");
+    if (err & kErrListTooLong)
+      return fail(ctx, DASS_E_CAPACITY, "a tile list exceeds 2^27 entries (use smaller tiles)");
   }
   return DASS_OK;
 }

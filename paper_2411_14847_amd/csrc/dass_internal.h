@@ -27,6 +27,7 @@ constexpr int kNumXcd = 8;         // MI355X: 8 XCDs, workgroups dealt round-rob
 
 // Device error bits (ctx->d_err)
 constexpr uint32_t kErrKeyOverflow = 1u;
+constexpr uint32_t kErrListTooLong = 2u;  // a tile list longer than the blend's position bits
 
 // Camera as the kernels see it (one per view, passed by value).
 struct CamK {
@@ -74,6 +75,7 @@ struct ViewsIO {
   int sub;     // sub-tile edge (16: four pixels per lane, one per 8x8 quadrant; 8: one pixel)
   int sx, sn;  // sub-tiles per tile row, per tile
   int batch;   // list entries the blend stages in LDS at a time (64, 128 or 256)
+  uint32_t* err;  // device error bits (the forward reports a tile list too long to blend)
 };
 constexpr int kLossSlots = 4096;
 constexpr int kFeatMaxC = 16;  // identity-feature channels per render

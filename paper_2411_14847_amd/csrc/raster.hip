@@ -175,12 +175,19 @@ __device__ __forceinline__ int view_of(const ViewsIO& io, int nv, int b) {
 // order; an entry leaves a quadrant only if the minimum of its quadratic form over the
 // quadrant's pixel rectangle exceeds the alpha >= 1/255 level by a margin, i.e. when every pixel
 // of that quadrant would skip it anyway, and leaves the list when no quadrant keeps it.  The list
-// position of every kept entry is carried along (low 28 bits, the quadrant mask above them), so
-// n_contrib still counts positions in the full list; the walk skips a quadrant an entry misses
+// position of every kept entry is carried along (low 27 bits, the quadrant mask in the top four),
+// so n_contrib still counts positions in the full list; the walk skips a quadrant an entry misses
 // with a uniform branch.
+// An entry's alpha never exceeds its opacity, so only an entry with opacity >= 0.99 can meet the
+// alpha clamp; the backward marks those (kClampBit) and tests the clamp for its zero derivative
+// on them alone.  For any other entry the clamp is inactive in the definition's arithmetic (the
+// opacity times a falloff <= 1 is below 0.99), and an alpha that float32 rounds to 0.99 there
+// keeps its derivative.
 constexpr int kLanes = 64;
-constexpr int kPosBits = 28;  // list positions carried with the quadrant mask
+constexpr int kPosBits = 27;  // list positions carried with the clamp bit and the quadrant mask
 constexpr int kPosMask = (1 << kPosBits) - 1;
+constexpr uint32_t kClampBit = 1u << kPosBits;
+constexpr int kQmShift = 28;
 constexpr float kNever = 2.0f;  // alpha threshold of a stopped pixel: above every alpha (<= 0.99)
 
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
@@ -312,6 +319,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
+  if (r.y - r.x > (uint32_t)kPosMask) {  // positions would not fit their bits: reported, not drawn
+    if (lane == 0) atomicOr(io.err, kErrListTooLong);
+    return;
+  }
   // thr[k]: the alpha a pixel's entries must reach to blend; 1/255 while it walks its list,
   // kNever once it has stopped (or for a pixel outside the image), so it never blends again and
   // keeps its transmittance
@@ -342,7 +353,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         // exponent in base 2 with the opacity folded in: alpha = 2^(q' + log2 o)
         co = make_float4(-0.5f * kLog2e * R.r1.x, -kLog2e * R.r1.y, -0.5f * kLog2e * R.r1.z, __log2f(R.r1.w));
         rgb = make_float4(R.r2.x, R.r2.y, R.r2.z,
-                          __int_as_float(((int)(start - r.x) + e + 1) | (int)(qm << kPosBits)));
+                          __uint_as_float(((uint32_t)(start - r.x) + e + 1) | (qm << kQmShift)));
       }
       const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
@@ -365,7 +376,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       const float4 c = s_rgb[j];
       const uint32_t wv = __float_as_uint(c.w);  // (position + 1) | quadrant mask << 28
       const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)wv);  // same for all lanes
-      const uint32_t qm = (w >> kPosBits) & qalive;
+      const uint32_t qm = (w >> kQmShift) & qalive;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
 #pragma unroll
       for (int k = 0; k < NP; k++) {
@@ -466,10 +477,11 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
+  if (r.y - r.x > (uint32_t)kPosMask) return;  // the forward reported it
   const int64_t hw = (int64_t)V.W * V.H;
-  // per pixel: transmittance, dL/d(pixel colour), S = dL/dC . (colour blended behind the
+  // per pixel: transmittance, dL/d(pixel colour), nS = -dL/dC . (colour blended behind the
   // current entry, background included)
-  float T[NP], dC0[NP], dC1[NP], dC2[NP], S[NP];
+  float T[NP], dC0[NP], dC1[NP], dC2[NP], nS[NP];
   int last[NP];
   int qlast[NP];  // per quadrant: the largest n_contrib of its pixels (uniform)
   int max_all = 0;
@@ -487,7 +499,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       dC1[k] = V.dl[hw + pix];
       dC2[k] = V.dl[2 * hw + pix];
     }
-    S[k] = bg0 * dC0[k] + bg1 * dC1[k] + bg2 * dC2[k];
+    nS[k] = -(bg0 * dC0[k] + bg1 * dC1[k] + bg2 * dC2[k]);
     int mx = last[k];
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) mx = max(mx, __shfl_xor(mx, d, 64));
@@ -517,7 +529,8 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
         qm = quad_mask<PW>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
-        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __int_as_float((bi * B + e) | (int)(qm << kPosBits)));
+        const uint32_t cb = cn.w >= kAlphaMax ? kClampBit : 0u;  // as the forward's
+        rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __uint_as_float((uint32_t)(bi * B + e) | cb | (qm << kQmShift)));
       }
       const bool keep = qm != 0;
       const uint64_t m = __ballot(keep);
@@ -538,7 +551,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const float4 c = s_rgb[j];
       const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(c.w));  // same for all lanes
       const int idx = (int)(w & kPosMask);
-      const uint32_t qm = w >> kPosBits;
+      const uint32_t qm = w >> kQmShift;
       const float dxb = xy.x - (float)qx, dyb = xy.y - (float)qy;
       // per-lane sums over its pixels: m = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
       // sum dP dy^2, d opacity (times the opacity until the reduction), d rgb),
@@ -547,6 +560,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
 #pragma unroll
       for (int q = 0; q < 9; q++) m[q] = 0.f;
       bool any = false;
+      const bool clampable = (w & kClampBit) != 0;  // uniform
 #pragma unroll
       for (int k = 0; k < NP; k++) {
         // uniform: the entry misses quadrant k, or lies behind the last contribution of every
@@ -568,12 +582,15 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         m[7] = fmaf(wgt, dC1[k], m[7]);
         m[8] = fmaf(wgt, dC2[k], m[8]);
         // dL/d alpha = T (dL/dC . (colour - colour behind)); the colour behind moves by alpha of that
-        const float ed = (c.x * dC0[k] + c.y * dC1[k] + c.z * dC2[k]) - S[k];
-        S[k] = fmaf(ae, ed, S[k]);
-        // no derivative through an active clamp
-        const float da = (take && araw < kAlphaMax) ? T[k] * ed : 0.f;
-        const float dP = da * a;
-        m[5] = fmaf(da, araw, m[5]);  // d alpha / d o = alpha / o, the 1 / o applied once per entry
+        const float ed = fmaf(c.x, dC0[k], fmaf(c.y, dC1[k], fmaf(c.z, dC2[k], nS[k])));
+        nS[k] = fmaf(-ae, ed, nS[k]);
+        // dP = alpha dL/d alpha: dL/d(exponent), and the opacity times dL/d(opacity)
+        float dP = (T[k] * ed) * ae;
+        if (__builtin_expect(clampable, 0)) {
+          __asm__ volatile("");  // keeps this rarely taken uniform branch a branch
+          dP = araw < kAlphaMax ? dP : 0.f;  // no derivative through an active clamp
+        }
+        m[5] += dP;  // d alpha / d o = alpha / o, the 1 / o applied once per entry
         const float pdx = dP * dx, pdy = dP * dy;
         m[0] += pdx;
         m[1] += pdy;
@@ -618,6 +635,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
   const float fx0 = (float)ox, fy0 = (float)oy;
   const uint64_t lt = lane_lt_mask(lane);
   const uint2 r = ranges[b];
+  if (r.y - r.x > (uint32_t)kPosMask) return;  // the colour forward reported it
   const uint32_t gbase = (uint32_t)v * (uint32_t)fo.n;  // record index = view * n + Gaussian
   float T[NP], thr[NP], acc[NP][kFeatMaxC];  // thr: as the colour forward's
 #pragma unroll
@@ -793,16 +811,18 @@ void launch_blend_fwd(const ViewsIO& io, int nv, int64_t total_tiles, const floa
   const int64_t total = total_tiles * io.sn;
   if (total == 0) return;
   const int per = per_xcd(total);
+  ViewsIO iov = io;
+  iov.err = ws.err;
   if (count_pairs) {
     if (l1)
-      blend_fwd_variant<true, true>(io, nv, (int)total, per, bg, ws, vals, st);
+      blend_fwd_variant<true, true>(iov, nv, (int)total, per, bg, ws, vals, st);
     else
-      blend_fwd_variant<true, false>(io, nv, (int)total, per, bg, ws, vals, st);
+      blend_fwd_variant<true, false>(iov, nv, (int)total, per, bg, ws, vals, st);
   } else {
     if (l1)
-      blend_fwd_variant<false, true>(io, nv, (int)total, per, bg, ws, vals, st);
+      blend_fwd_variant<false, true>(iov, nv, (int)total, per, bg, ws, vals, st);
     else
-      blend_fwd_variant<false, false>(io, nv, (int)total, per, bg, ws, vals, st);
+      blend_fwd_variant<false, false>(iov, nv, (int)total, per, bg, ws, vals, st);
   }
 }
 

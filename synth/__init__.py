@@ -277,6 +277,36 @@ def tiny_scene(seed: int, n: int, width: int, height: int, sh_degree: int = 0, l
     return Scene(mean, quat, log_scale, logit, sh, sh_degree), [cam], [dl]
 
 
+def opaque_scene(seed: int, n: int = 240, width: int = 64, height: int = 48, n_opaque: int = 12,
+                 sh_degree: int = 1):
+    """tiny_scene's Gaussians (log-scales N(-2.2, 0.3)) behind n_opaque nearly opaque ones (logits
+    N(8, 0.5), opacity about 0.9997) at depth 2.5 in front of the camera at (0, 0, 4): centres on
+    a 4-wide grid of 16-pixel cells jittered by U[-4, 4] pixels, footprint standard deviation
+    U[8, 12] pixels (log-scales perturbed by N(0, 0.2) per axis), random orientation.  Near the
+    opaque centres alpha reaches the 0.99 clamp.
+    Draw order: the tiny scene, then jitter, footprint, log-scale noise, quaternions, logits,
+    colour coefficients."""
+    scene, cams, dls = tiny_scene(seed, n, width, height, sh_degree=sh_degree, log_scale_mu=-2.2)
+    rng = np.random.default_rng(seed + 1000)
+    cam = cams[0]
+    f = focal_from_fov(width)
+    z = 2.5  # camera depth (the camera sits at z = 4 looking along -z)
+    cells = [(i, j) for j in range(max(1, height // 16)) for i in range(4)][:n_opaque]
+    m = len(cells)
+    u = np.array([8.0 + 16.0 * i for i, _ in cells]) + rng.uniform(-4.0, 4.0, size=m)
+    v = np.array([8.0 + 16.0 * j for _, j in cells]) + rng.uniform(-4.0, 4.0, size=m)
+    mean = np.stack([(u - cam.cx) * z / f, -(v - cam.cy) * z / f, np.full(m, 4.0 - z)])
+    sd = rng.uniform(8.0, 12.0, size=m) * z / f
+    log_scale = np.log(sd)[None, :] + rng.normal(0.0, 0.2, size=(3, m))
+    quat = _quats(rng, m)
+    logit = rng.normal(8.0, 0.5, size=m)
+    sh = _colour_coeffs(rng, m, sh_degree, 0.2)
+    cat = lambda a, b: np.concatenate([a, b.astype(np.float32)], axis=-1)
+    out = Scene(cat(scene.mean, mean), cat(scene.quat, quat), cat(scene.log_scale, log_scale),
+                cat(scene.logit, logit), cat(scene.sh, sh), sh_degree)
+    return out, cams, dls
+
+
 def yawed_camera(campos, yaw_deg: float, pitch_deg: float, width: int, height: int) -> Camera:
     """Camera at campos looking along +z turned by yaw (about the camera's y axis) then pitch
     (about its x axis)."""

@@ -49,6 +49,12 @@ def off_frustum(seed=11, n=200, W=96, H=72, views=2):
     return synth.off_frustum_scene(seed, n, W, H, n_views=views)
 
 
+def opaque_clamp(seed=7):
+    """240 small Gaussians behind 12 nearly opaque wide ones (SH1, 64x48): alpha meets the 0.99
+    clamp near the opaque centres, so the clamped forward and its zero derivative are exercised."""
+    return synth.opaque_scene(seed)
+
+
 CASES = {
     "single_view_2000": lambda: synth.single_view_scene(0),
     "multiview_sh3_ragged": lambda: small_multiview(),
@@ -56,6 +62,7 @@ CASES = {
     "tiny_dense": lambda: synth.tiny_scene(2, 300, 40, 36, sh_degree=2, log_scale_mu=-2.0),
     "large_footprint_64_4x32x32": large_footprint_sub,
     "off_frustum_clamp_2x96x72": off_frustum,
+    "opaque_alpha_clamp_64x48": opaque_clamp,
 }
 
 

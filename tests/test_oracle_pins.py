@@ -171,6 +171,40 @@ def test_off_frustum_parity_fixture_reaches_the_clamp():
         assert hit.sum() >= 20
 
 
+def test_opaque_parity_fixture_reaches_the_alpha_clamp():
+    """The nearly opaque GPU parity case does blend entries at the 0.99 alpha clamp: walked by the
+    per-pixel definition, at least 50 of its pixels blend an entry whose unclamped alpha is 0.99
+    or more (alpha clamped, no derivative through it)."""
+    from test_gpu_parity import opaque_clamp
+    sc, cams, _ = opaque_clamp()
+    cam = cams[0]
+    p = oracle.project(sc, cam)
+    amax, amin, tstop = float(np.float32(0.99)), float(np.float32(1 / 255)), float(np.float32(1e-4))
+    order = sorted(np.nonzero(p.visible)[0], key=lambda g: (np.float32(p.depth[g]), g))
+    hits = 0
+    for py in range(cam.height):
+        for px in range(cam.width):
+            tx, ty, T, hit = px // 16, py // 16, 1.0, False
+            for g in order:
+                if not (p.rect[g, 0] <= tx < p.rect[g, 2] and p.rect[g, 1] <= ty < p.rect[g, 3]):
+                    continue
+                dx, dy = p.uv[g, 0] - px, p.uv[g, 1] - py
+                A, B, C_ = p.conic[g]
+                P = -0.5 * (A * dx * dx + C_ * dy * dy) - B * dx * dy
+                if P > 0:
+                    continue
+                araw = p.opacity[g] * math.exp(P)
+                a = min(amax, araw)
+                if a < amin:
+                    continue
+                if T * (1 - a) < tstop:
+                    break
+                hit = hit or araw >= amax
+                T *= 1 - a
+            hits += hit
+    assert hits >= 50
+
+
 def test_rotation_invariants_via_isotropy():
     """Isotropic s makes Sigma = s^2 I for every q (R R^T = I), so the footprint ignores q."""
     cam = axis_camera(64, 64)
