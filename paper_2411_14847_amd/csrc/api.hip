@@ -158,6 +158,7 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
   ALLOC(w.tt_s, vn);
   ALLOC(w.off_s, vn + 1);
   ALLOC(w.g2d, vn * 9);
+  ALLOC(w.vis, vn);
   ALLOC(w.keys[0], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.keys[1], w.cap_keys > 0 ? w.cap_keys : 1);
   ALLOC(w.vals[0], w.cap_keys > 0 ? w.cap_keys : 1);

@@ -203,6 +203,8 @@ struct Workspace {
   // tile keys carry the record index v * n + g as their value
   float* g2d = nullptr;            // [cap_vn][9], row v * n + g: blend-backward sums (moments of
                                    // dL/d(exponent) over the offsets, d opacity, d rgb)
+  uint8_t* vis = nullptr;          // [cap_vn], row v * n + g: bit 3 visible, bit c colour channel c
+                                   // above its clamp at 0 (the colour adjoint's only record reads)
   // keys
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};

@@ -242,7 +242,8 @@ __device__ __forceinline__ void colour(const GT& G, const CamK& cam, const float
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int nv, Rec* __restrict__ rec,
                                                     uint32_t* __restrict__ tt, uint2* __restrict__ rect,
-                                                    uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval) {
+                                                    uint8_t* __restrict__ vis, uint64_t* __restrict__ dkey,
+                                                    uint32_t* __restrict__ dval) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sc.n) return;
@@ -267,10 +268,12 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
       r.r1 = make_float4((float)V.A, (float)V.B, (float)V.C, (float)G.o);
       r.r2 = make_float4((float)fmax(rgb_pre[0], 0.0), (float)fmax(rgb_pre[1], 0.0),
                          (float)fmax(rgb_pre[2], 0.0), (float)V.t[2]);
+      vis[i] = (uint8_t)(8u | (r.r2.x > 0.f ? 1u : 0u) | (r.r2.y > 0.f ? 2u : 0u) | (r.r2.z > 0.f ? 4u : 0u));
       tt[i] = (uint32_t)((V.x1 - V.x0) * (V.y1 - V.y0));
       rect[i] = make_uint2((uint32_t)V.x0 | ((uint32_t)V.y0 << 16), (uint32_t)V.x1 | ((uint32_t)V.y1 << 16));
     } else {
       r.r0 = r.r1 = r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+      vis[i] = 0;
       tt[i] = 0;
       rect[i] = make_uint2(0, 0);
     }
@@ -456,13 +459,12 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK s
 // Colour part: rgb_c = max(0, sum_k sh[k,c] Y_k(dhat) + 0.5), dhat = normalise(mu - campos).
 // Four lanes per Gaussian: lane c < 3 owns channel c (its K coefficients and their gradients,
 // over all views); the direction gradients of the three channels are summed at the end.
-// Visibility in a view is read from the forward's per-(view, Gaussian) tile counts (a visible
-// Gaussian touches >= 1 tile) and the clamp from the forward's stored colour (0 where the
-// clamp was active), so neither is recomputed; the gradient arithmetic itself is float32.
+// Visibility in a view and the clamp of each channel are read from the forward's per-(view,
+// Gaussian) flags (taken from its stored colour, 0 where the clamp was active), so neither is
+// recomputed; the gradient arithmetic itself is float32.
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK cams, int nv,
-                                                               const uint32_t* __restrict__ tt_u,
-                                                               const Rec* __restrict__ rec_u,
+                                                               const uint8_t* __restrict__ vis,
                                                                const float* __restrict__ g2d, dass_grads gr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -481,23 +483,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_colour(SceneK sc, CamsK 
   float dmu[3] = {0.f, 0.f, 0.f};
   constexpr int kAhead = 4;  // views whose inputs are loaded together
   for (int v0 = 0; v0 < nv && live; v0 += kAhead) {
-    uint32_t tt4[kAhead];
-    float rgb4[kAhead], d4[kAhead];
+    uint32_t f4[kAhead];
+    float d4[kAhead];
 #pragma unroll
     for (int u = 0; u < kAhead; u++) {
-      tt4[u] = 0;
+      f4[u] = 0;
       if (v0 + u < nv) {
         const int64_t row = (int64_t)(v0 + u) * sc.n + g;
-        tt4[u] = tt_u[row];
-        rgb4[u] = reinterpret_cast<const float*>(&rec_u[row].r2)[c];
+        f4[u] = vis[row];
         d4[u] = g2d[row * 9 + 6 + c];
       }
     }
 #pragma unroll
     for (int u = 0; u < kAhead; u++) {
       const int v = v0 + u;
-      if (tt4[u] == 0) continue;  // not visible in this view (or past the last view)
-      if (!(rgb4[u] > 0.f)) continue;  // clamped channel: no derivative
+      // not visible in this view (or past the last view), or a clamped channel (no derivative)
+      if ((f4[u] & (8u | (1u << c))) != (8u | (1u << c))) continue;
       const CamK& cam = cams.c[v];
       float dir[3];
       for (int i = 0; i < 3; i++) dir[i] = mu[i] - cam.campos[i];
@@ -562,10 +563,18 @@ void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws
   while (vs < 4 && vs * 2 <= nv && (int64_t)blocks_g * vs < 4096) vs *= 2;
   dim3 grid(blocks_g, vs), block(256);
   switch (s.deg) {
-    case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
-    case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
-    case 2: k_preprocess<2><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
-    default: k_preprocess<3><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.dkey[0], ws.dval[0]); break;
+    case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+                                                     ws.dval[0]);
+      break;
+    case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+                                                     ws.dval[0]);
+      break;
+    case 2: k_preprocess<2><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+                                                     ws.dval[0]);
+      break;
+    default: k_preprocess<3><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+                                                     ws.dval[0]);
+      break;
   }
 }
 
@@ -577,10 +586,10 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   k_preprocess_bwd_geom<<<(s.n + 63) / 64, 64 * kAdjWaves, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
   if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
-    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
-    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
-    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
-    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.tt_u, ws.rec_u, ws.g2d, grads); break;
+    case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads); break;
+    case 1: k_preprocess_bwd_colour<1><<<grid, block, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads); break;
+    case 2: k_preprocess_bwd_colour<2><<<grid, block, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads); break;
+    default: k_preprocess_bwd_colour<3><<<grid, block, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads); break;
   }
 }
 
