@@ -293,6 +293,21 @@ __device__ __forceinline__ float wave_reduce9(const float* v) {
 }
 __constant__ int kRedSlot[16] = {0, 1, 2, -1, 3, 4, -1, -1, 5, 6, 7, -1, 8, -1, -1, -1};
 
+// A staged list entry in LDS: one 48-byte row, so a wave reads an entry's fields from one address.
+struct FwdStage {
+  float4 co;   // log2-scaled conic, log2 opacity
+  float4 rgb;  // colour, (list position + 1) | quadrant mask << 28 (int bits)
+  float2 xy;   // mean relative to the sub-tile origin
+  float2 pad;
+};
+struct BwdStage {
+  float4 co;   // as the forward's
+  float4 rgb;  // colour, list position | clamp bit | quadrant mask << 28 (int bits)
+  float2 xy;
+  uint32_t p;  // record index = gradient row (view * n + Gaussian)
+  float io;    // 1 / opacity
+};
+
 // L1: the epilogue also forms the L1 term against the view's target (dL/drgb, error map and
 // this sub-tile's share of the loss, added into one of kLossSlots partial sums).
 template <bool COUNT, bool L1, int SUB, int B>
@@ -302,9 +317,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
                                                       unsigned long long* __restrict__ pairs,
                                                       float* __restrict__ loss_slots) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
-  __shared__ float2 s_xy[B];
-  __shared__ float4 s_co[B];   // log2-scaled conic, opacity
-  __shared__ float4 s_rgb[B];  // colour, list position | quadrant mask << 28 (int bits)
+  __shared__ FwdStage s_st[B];
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
@@ -359,9 +372,9 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       const uint64_t m = __ballot(keep);
       if (keep) {
         const int pos = n_kept + __popcll(m & lt);
-        s_xy[pos] = xy;
-        s_co[pos] = co;
-        s_rgb[pos] = rgb;
+        s_st[pos].co = co;
+        s_st[pos].rgb = rgb;
+        s_st[pos].xy = xy;
       }
       n_kept += __popcll(m);
     }
@@ -371,9 +384,9 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
     for (int k = 0; k < NP; k++) qalive |= __ballot(thr[k] < 1.f) != 0 ? 1u << k : 0u;
     __syncthreads();
     for (int j = 0; j < n_kept; j++) {
-      const float2 xy = s_xy[j];
-      const float4 co = s_co[j];
-      const float4 c = s_rgb[j];
+      const float2 xy = s_st[j].xy;
+      const float4 co = s_st[j].co;
+      const float4 c = s_st[j].rgb;
       const uint32_t wv = __float_as_uint(c.w);  // (position + 1) | quadrant mask << 28
       const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)wv);  // same for all lanes
       const uint32_t qm = (w >> kQmShift) & qalive;
@@ -458,11 +471,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
                                                       const uint32_t* __restrict__ vals, const Rec* __restrict__ rec,
                                                       float* __restrict__ g2d) {
   constexpr int PW = SUB / 8, NP = PW * PW;  // quadrants per edge, pixels per lane
-  __shared__ float2 s_xy[B];
-  __shared__ float4 s_co[B];   // log2-scaled conic, log2 opacity (as the forward)
-  __shared__ float4 s_rgb[B];  // colour, list position | quadrant mask << 28 (int bits)
-  __shared__ uint32_t s_p[B];
-  __shared__ float s_io[B];    // 1 / opacity
+  __shared__ BwdStage s_st[B];
   const int lb = xcd_logical(blockIdx.x, per);
   if (lb >= total_blocks) return;
   const int b = lb / io.sn, sub = lb - b * io.sn;  // tile, SUB x SUB sub-tile of it
@@ -536,19 +545,19 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       const uint64_t m = __ballot(keep);
       if (keep) {
         const int pos = n_kept + __popcll(m & lt);
-        s_xy[pos] = xy;
-        s_co[pos] = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, __log2f(cn.w));
-        s_rgb[pos] = rgb;
-        s_p[pos] = p;  // record index = gradient row (view * n + Gaussian)
-        s_io[pos] = 1.0f / cn.w;
+        s_st[pos].co = make_float4(-0.5f * kLog2e * cn.x, -kLog2e * cn.y, -0.5f * kLog2e * cn.z, __log2f(cn.w));
+        s_st[pos].rgb = rgb;
+        s_st[pos].xy = xy;
+        s_st[pos].p = p;
+        s_st[pos].io = 1.0f / cn.w;
       }
       n_kept += __popcll(m);
     }
     __syncthreads();
     for (int j = n_kept - 1; j >= 0; j--) {
-      const float2 xy = s_xy[j];
-      const float4 co = s_co[j];
-      const float4 c = s_rgb[j];
+      const float2 xy = s_st[j].xy;
+      const float4 co = s_st[j].co;
+      const float4 c = s_st[j].rgb;
       const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane(__float_as_int(c.w));  // same for all lanes
       const int idx = (int)(w & kPosMask);
       const uint32_t qm = w >> kQmShift;
@@ -601,9 +610,9 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
       if (any) {  // uniform
         // the sums are linear in the entry's conic, so the conic is applied once per
         // (view, Gaussian) by the projection adjoint, not here
-        m[5] *= s_io[j];
+        m[5] *= s_st[j].io;
         const float tot = wave_reduce9(m);
-        if (writes) atomicAdd(&g2d[(int64_t)s_p[j] * 9 + slot], tot);
+        if (writes) atomicAdd(&g2d[(int64_t)s_st[j].p * 9 + slot], tot);
       }
     }
   }
