@@ -378,12 +378,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
       }
       n_kept += __popcll(m);
     }
-    // quadrants with a pixel still walking (a stopped pixel stays stopped)
+    // quadrants with a pixel still walking (a stopped pixel stays stopped); a quadrant leaves the
+    // mask as soon as its last pixel stops, and the wave leaves the batch when none is left
     uint32_t qalive = 0;
 #pragma unroll
     for (int k = 0; k < NP; k++) qalive |= __ballot(thr[k] < 1.f) != 0 ? 1u << k : 0u;
     __syncthreads();
-    for (int j = 0; j < n_kept; j++) {
+    for (int j = 0; j < n_kept && qalive != 0; j++) {
       const float2 xy = s_st[j].xy;
       const float4 co = s_st[j].co;
       const float4 c = s_st[j].rgb;
@@ -410,6 +411,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
           take = ok && !stop;
           if (COUNT) n_eval += thr[k] < 1.f ? 1u : 0u;
           thr[k] = stop ? kNever : thr[k];
+          if (__ballot(thr[k] < 1.f) == 0) qalive &= ~(1u << k);
         } else if (COUNT) {
           n_eval += thr[k] < 1.f ? 1u : 0u;
         }
