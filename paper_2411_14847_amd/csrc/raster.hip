@@ -193,25 +193,21 @@ constexpr float kNever = 2.0f;  // alpha threshold of a stopped pixel: above eve
 __device__ __forceinline__ uint64_t lane_lt_mask(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
 // Minimum of q(d) = A dx^2 + 2B dx dy + C dy^2, d = pixel - mean, over the pixel-centre
-// rectangle [x0, x1] x [y0, y1] (mean at (mx, my)); ia, ic = 1/A, 1/C (0 if not positive).  Off
-// the rectangle the minimum is on an edge, where the line minimiser is clamped to the segment.
+// rectangle [x0, x1] x [y0, y1] (mean at (mx, my)); ia, ic = 1/A, 1/C (0 if not positive).  For
+// a convex q the minimiser is the mean when it lies inside; otherwise it lies on the edge that
+// faces the mean in x (when mx is outside [x0, x1]) or on the one that faces it in y: the
+// vertical segment at the rectangle's x nearest mx and the horizontal segment at its y nearest my
+// hold it in every case, and on each segment the line minimiser is clamped to the segment.
 __device__ __forceinline__ float rect_min_q(float mx, float my, float A, float B, float C, float ia, float ic,
                                             float x0, float x1, float y0, float y1) {
-  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.f;
-  float qmin = 3.0e38f;
-#pragma unroll
-  for (int e = 0; e < 2; e++) {  // vertical edges
-    const float dx = (e ? x1 : x0) - mx;
-    const float dy = fminf(fmaxf(-B * dx * ic, y0 - my), y1 - my);
-    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
-  }
-#pragma unroll
-  for (int e = 0; e < 2; e++) {  // horizontal edges
-    const float dy = (e ? y1 : y0) - my;
-    const float dx = fminf(fmaxf(-B * dy * ia, x0 - mx), x1 - mx);
-    qmin = fminf(qmin, A * dx * dx + 2.f * B * dx * dy + C * dy * dy);
-  }
-  return qmin;
+  // (med3 of a value and an ordered pair clamps it to the pair's interval)
+  float dx = __builtin_amdgcn_fmed3f(mx, x0, x1) - mx;
+  float dy = __builtin_amdgcn_fmed3f(-B * dx * ic, y0 - my, y1 - my);
+  const float qv = A * dx * dx + 2.f * B * dx * dy + C * dy * dy;
+  dy = __builtin_amdgcn_fmed3f(my, y0, y1) - my;
+  dx = __builtin_amdgcn_fmed3f(-B * dy * ia, x0 - mx, x1 - mx);
+  const float qh = A * dx * dx + 2.f * B * dx * dy + C * dy * dy;
+  return fminf(qv, qh);
 }
 
 // Bit k set if the entry (mean (mx, my) relative to the sub-tile origin, conic A B C, opacity o)
