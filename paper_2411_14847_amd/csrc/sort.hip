@@ -6,9 +6,10 @@
 //   (1) upsweep: every block histograms its contiguous chunk into LDS (per-wave
 //       sub-histograms to spread LDS atomics), written digit-major to global memory;
 //   (2) scan: one workgroup per digit turns the [radix][blocks] counts into global offsets;
-//   (3) scatter: every block re-reads its chunk in batches of 2048 pairs, ranks them stably
+//   (3) scatter: every block re-reads its chunk in batches of 2048 pairs (4096 for 10-bit
+//       digits), ranks them stably
 //       with wave ballots (8-11 ballots give each lane the mask of lanes holding the same
-//       digit; each wave ranks its own 512 consecutive pairs), orders the batch by digit in
+//       digit; each wave ranks its own quarter of the batch), orders the batch by digit in
 //       LDS and writes each digit's run contiguously.
 // A pass never depends on forward progress between workgroups.
 #include <algorithm>
@@ -145,12 +146,16 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Each batch of 2048 pairs is split into four runs of 512 consecutive pairs, one per wave; a
+// Each batch of 256 IT pairs is split into four runs of 64 IT consecutive pairs, one per wave; a
 // wave ranks its run slot by slot (64 pairs at a time) against its own running digit counts,
 // with no workgroup barrier, so the ranks follow the input order.  Waves are then combined by
 // an exclusive prefix of their counts per digit, the batch is ordered by digit in LDS, and each
 // digit's run is written to its global position.
-template <typename K, int RB>
+// IT items per thread per batch: 16 for 10-bit digits, where a 2,048-pair batch would leave
+// runs of about two pairs per digit and the stores would barely coalesce (one 10-bit pass over
+// the 1.5e7 tile keys of a 20-view call at 64x32 tiles: 0.199 -> 0.167 ms), else 8 (wider
+// batches measured slower for 8-bit digits, and for the 11-bit passes over a few 1e5 keys).
+template <typename K, int RB, int IT>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                           K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                           const uint32_t* __restrict__ d_count, int shift, int blocks,
@@ -158,13 +163,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
                                                           const uint32_t* __restrict__ totals) {
   constexpr int R = 1 << RB;
   constexpr int D = R / kSortThreads;        // digits owned per thread
-  constexpr int kWaveRun = kSortItems * 64;  // consecutive pairs ranked by one wave per batch
+  constexpr int kWaveRun = IT * 64;          // consecutive pairs ranked by one wave per batch
+  constexpr int kBatchP = kSortThreads * IT;  // pairs per batch
   __shared__ uint32_t s_base[R];             // global write position of the next item of each digit
   __shared__ uint32_t s_boff[R];             // exclusive digit offsets within the batch
   __shared__ uint32_t s_wc[4][R];            // per-wave digit counts, then their prefix over waves
   __shared__ uint32_t s_tmp[4];
-  __shared__ K s_k[kBatch];
-  __shared__ uint32_t s_v[kBatch];
+  __shared__ K s_k[kBatchP];
+  __shared__ uint32_t s_v[kBatchP];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint32_t count = *d_count;
@@ -184,14 +190,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
   }
   const uint64_t lt = lanemask_lt();
 
-  for (uint32_t batch = lo; batch < hi; batch += kBatch) {
-    const uint32_t nb = min((uint32_t)kBatch, hi - batch);
+  for (uint32_t batch = lo; batch < hi; batch += kBatchP) {
+    const uint32_t nb = min((uint32_t)kBatchP, hi - batch);
     const uint32_t wbase = batch + (uint32_t)(wave * kWaveRun);
     for (int d = lane; d < R; d += 64) s_wc[wave][d] = 0;
-    K key[kSortItems];
-    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+    K key[IT];
+    uint32_t val[IT], rank[IT], dig[IT];
 #pragma unroll
-    for (int s = 0; s < kSortItems; s++) {
+    for (int s = 0; s < IT; s++) {
       const uint32_t idx = wbase + (uint32_t)(s * 64 + lane);
       if (idx < hi) {
         key[s] = kin[idx];
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
     }
     wave_lds_sync();
 #pragma unroll
-    for (int s = 0; s < kSortItems; s++) {
+    for (int s = 0; s < IT; s++) {
       const bool valid = wbase + (uint32_t)(s * 64 + lane) < hi;
       const uint32_t d = valid ? digit_of<RB>(key[s], shift) : 0u;
       dig[s] = d;
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kSortItems; s++) {
+    for (int s = 0; s < IT; s++) {
       if (wbase + (uint32_t)(s * 64 + lane) < hi) {
         const uint32_t pos = s_boff[dig[s]] + s_wc[wave][dig[s]] + rank[s];
         s_k[pos] = key[s];
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const K* __restrict__ 
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < kSortItems; s++) {
+    for (int s = 0; s < IT; s++) {
       const uint32_t j = s * kSortThreads + tid;
       if (j < nb) {
         const K k = s_k[j];
@@ -346,8 +352,9 @@ void radix_pass(K* keys[2], uint32_t* vals[2], int cur, const uint32_t* d_count,
                 uint32_t* hist, uint32_t* totals, hipStream_t st) {
   k_upsweep<K, RB><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
   k_scan_rows<<<1 << RB, kSortThreads, 0, st>>>(hist, blocks, totals);
-  k_scatter<K, RB><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], d_count, shift,
-                                                   blocks, hist, totals);
+  k_scatter<K, RB, RB == 10 ? 16 : 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                                      vals[cur ^ 1], d_count, shift, blocks, hist,
+                                                                      totals);
 }
 
 template <typename K>
