@@ -148,7 +148,6 @@ dass_status allocate(dass_ctx ctx, const dass_limits& l) {
 #define ALLOC(ptr, cnt) \
   if ((s = dev_alloc(ctx, &(ptr), (size_t)(cnt))) != DASS_OK) return s;
   ALLOC(w.rec_u, vn);
-  ALLOC(w.tt_u, vn);
   ALLOC(w.rect_u, vn);
   ALLOC(w.dkey[0], vn);
   ALLOC(w.dkey[1], vn);

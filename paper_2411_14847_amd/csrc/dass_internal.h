@@ -191,7 +191,6 @@ struct Workspace {
   int sort_blocks = 0;
   // per (view, gaussian), view-major, unsorted
   Rec* rec_u = nullptr;
-  uint32_t* tt_u = nullptr;        // tiles touched
   uint2* rect_u = nullptr;         // (x0 | y0 << 16, x1 | y1 << 16)
   uint64_t* dkey[2] = {nullptr, nullptr};
   uint32_t* dval[2] = {nullptr, nullptr};

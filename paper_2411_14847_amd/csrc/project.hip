@@ -241,7 +241,7 @@ __device__ __forceinline__ void colour(const GT& G, const CamK& cam, const float
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int nv, Rec* __restrict__ rec,
-                                                    uint32_t* __restrict__ tt, uint2* __restrict__ rect,
+                                                    uint2* __restrict__ rect,
                                                     uint8_t* __restrict__ vis, uint64_t* __restrict__ dkey,
                                                     uint32_t* __restrict__ dval) {
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -269,12 +269,10 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
       r.r2 = make_float4((float)fmax(rgb_pre[0], 0.0), (float)fmax(rgb_pre[1], 0.0),
                          (float)fmax(rgb_pre[2], 0.0), (float)V.t[2]);
       vis[i] = (uint8_t)(8u | (r.r2.x > 0.f ? 1u : 0u) | (r.r2.y > 0.f ? 2u : 0u) | (r.r2.z > 0.f ? 4u : 0u));
-      tt[i] = (uint32_t)((V.x1 - V.x0) * (V.y1 - V.y0));
       rect[i] = make_uint2((uint32_t)V.x0 | ((uint32_t)V.y0 << 16), (uint32_t)V.x1 | ((uint32_t)V.y1 << 16));
     } else {
       r.r0 = r.r1 = r.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
       vis[i] = 0;
-      tt[i] = 0;
       rect[i] = make_uint2(0, 0);
     }
     rec[i] = r;
@@ -563,16 +561,16 @@ void launch_preprocess(const SceneK& s, const CamsK& cams, int nv, Workspace& ws
   while (vs < 4 && vs * 2 <= nv && (int64_t)blocks_g * vs < 4096) vs *= 2;
   dim3 grid(blocks_g, vs), block(256);
   switch (s.deg) {
-    case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+    case 0: k_preprocess<0><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.rect_u, ws.vis, ws.dkey[0],
                                                      ws.dval[0]);
       break;
-    case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+    case 1: k_preprocess<1><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.rect_u, ws.vis, ws.dkey[0],
                                                      ws.dval[0]);
       break;
-    case 2: k_preprocess<2><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+    case 2: k_preprocess<2><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.rect_u, ws.vis, ws.dkey[0],
                                                      ws.dval[0]);
       break;
-    default: k_preprocess<3><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.tt_u, ws.rect_u, ws.vis, ws.dkey[0],
+    default: k_preprocess<3><<<grid, block, 0, st>>>(s, cams, nv, ws.rec_u, ws.rect_u, ws.vis, ws.dkey[0],
                                                      ws.dval[0]);
       break;
   }

@@ -34,17 +34,18 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   for (int64_t j = i; j < n; j += stride) p[j] = v;
 }
 
-// Tiles touched and tile rectangle of each (view, Gaussian) in (view, depth) order, for the scan
-// and the key emission; the records themselves stay where the projection wrote them.
+// Tile rectangle and tiles touched (the rectangle's area) of each (view, Gaussian) in (view,
+// depth) order, for the scan and the key emission: one gathered 8-byte rectangle per position;
+// the records themselves stay where the projection wrote them.
 __global__ __launch_bounds__(256) void k_gather_sorted(int n, int64_t vn, const uint32_t* __restrict__ sorted_gid,
-                                                       const uint32_t* __restrict__ tt_u, const uint2* __restrict__ rect_u,
-                                                       uint32_t* __restrict__ tt_s, uint2* __restrict__ rect_s) {
+                                                       const uint2* __restrict__ rect_u, uint32_t* __restrict__ tt_s,
+                                                       uint2* __restrict__ rect_s) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= vn) return;
   const int64_t v = p / n;
-  const int64_t i = v * n + sorted_gid[p];
-  tt_s[p] = tt_u[i];
-  rect_s[p] = rect_u[i];
+  const uint2 r = rect_u[v * n + sorted_gid[p]];
+  tt_s[p] = ((r.y & 0xFFFFu) - (r.x & 0xFFFFu)) * ((r.y >> 16) - (r.x >> 16));
+  rect_s[p] = r;
 }
 
 // Each wave takes 64 consecutive sorted positions (Gaussian-views) and writes all their keys
@@ -760,7 +761,7 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
 
 void launch_gather_sorted(int n, int64_t vn, const uint32_t* sorted_gid, Workspace& ws, hipStream_t st) {
   if (vn == 0) return;
-  k_gather_sorted<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, sorted_gid, ws.tt_u, ws.rect_u, ws.tt_s,
+  k_gather_sorted<<<(unsigned)((vn + 255) / 256), 256, 0, st>>>(n, vn, sorted_gid, ws.rect_u, ws.tt_s,
                                                                  ws.rect_s);
 }
 
