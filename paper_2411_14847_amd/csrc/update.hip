@@ -245,6 +245,10 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i) {
 
 __device__ __forceinline__ double u01(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
 
+// A quad of lanes per child, so the float64 chains run side by side: lane i < 3 forms the
+// child's i-th normal draw and scale, lane 3 copies the quaternion and the opacity logit; every
+// lane then forms its mean component from the quad's draws (the same products and sums as
+// written for one thread) and copies a quarter of the SH planes.
 __global__ __launch_bounds__(256) void k_densify_spawn(float* __restrict__ mean, float* __restrict__ quat,
                                                        float* __restrict__ log_scale, float* __restrict__ logit,
                                                        float* __restrict__ sh, int n_sh, int stride, int n, int capacity,
@@ -254,48 +258,60 @@ __global__ __launch_bounds__(256) void k_densify_spawn(float* __restrict__ mean,
   const uint32_t ns = *d_count;
   const int room = capacity - n;
   const int n_app = ns == 0 ? 0 : (k_max < room ? k_max : room);
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0 && n_appended) *n_appended = n_app < 0 ? 0 : n_app;
-  if (j >= n_app) return;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = tid >> 2, l = tid & 3;
+  if (tid == 0 && n_appended) *n_appended = n_app < 0 ? 0 : n_app;
+  if (j >= n_app) return;  // uniform over a quad (n_app whole children)
   const int64_t p = (int64_t)sel_idx[j % ns];  // parents in rank order
   const int64_t c = (int64_t)n + j;
   const int64_t st = stride;
-  double q[4], qn = 0.0;
-  for (int i = 0; i < 4; i++) {
-    q[i] = quat[i * st + p];
-    qn += q[i] * q[i];
+  // lane l < 3: scale l and normal draw l (Box-Muller on draws 4j .. 4j+3: z0, z1 from the
+  // first pair, z2 from the second)
+  double scl = 0.0, zl = 0.0;
+  if (l < 3) {
+    const double TWO_PI = 6.283185307179586476925;
+    const uint64_t d0 = 4ull * (uint64_t)j + (l == 2 ? 2u : 0u);
+    const double ua = 1.0 - u01(splitmix64(seed, d0)), ub = u01(splitmix64(seed, d0 + 1));
+    const double r = sqrt(-2.0 * log(ua));
+    zl = l == 1 ? r * sin(TWO_PI * ub) : r * cos(TWO_PI * ub);
+    scl = exp((double)log_scale[l * st + p]);
   }
-  qn = sqrt(qn);
-  for (int i = 0; i < 4; i++) q[i] /= qn;
-  const double w = q[0], x = q[1], y = q[2], zq = q[3];
-  const double R[9] = {1.0 - 2.0 * (y * y + zq * zq), 2.0 * (x * y - w * zq), 2.0 * (x * zq + w * y),
-                       2.0 * (x * y + w * zq), 1.0 - 2.0 * (x * x + zq * zq), 2.0 * (y * zq - w * x),
-                       2.0 * (x * zq - w * y), 2.0 * (y * zq + w * x), 1.0 - 2.0 * (x * x + y * y)};
-  double sc[3];
-  for (int i = 0; i < 3; i++) sc[i] = exp((double)log_scale[i * st + p]);
-  // three standard normals: Box-Muller on draws 4j .. 4j+3
-  const double TWO_PI = 6.283185307179586476925;
-  const uint64_t d0 = 4ull * (uint64_t)j;
-  const double u0 = 1.0 - u01(splitmix64(seed, d0 + 0)), u1 = u01(splitmix64(seed, d0 + 1));
-  const double u2 = 1.0 - u01(splitmix64(seed, d0 + 2)), u3 = u01(splitmix64(seed, d0 + 3));
-  const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
-  const double z[3] = {r0 * cos(TWO_PI * u1), r0 * sin(TWO_PI * u1), r1 * cos(TWO_PI * u3)};
-  for (int i = 0; i < 3; i++) {
+  const int q0 = (int)(threadIdx.x & 63) & ~3;  // the quad's first lane in the wave
+  double sc[3], z[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    sc[k] = __shfl(scl, q0 + k, 64);
+    z[k] = __shfl(zl, q0 + k, 64);
+  }
+  if (l < 3) {
+    double q[4], qn = 0.0;
+    for (int i = 0; i < 4; i++) {
+      q[i] = quat[i * st + p];
+      qn += q[i] * q[i];
+    }
+    qn = sqrt(qn);
+    for (int i = 0; i < 4; i++) q[i] /= qn;
+    const double w = q[0], x = q[1], y = q[2], zq = q[3];
+    const double R[9] = {1.0 - 2.0 * (y * y + zq * zq), 2.0 * (x * y - w * zq), 2.0 * (x * zq + w * y),
+                         2.0 * (x * y + w * zq), 1.0 - 2.0 * (x * x + zq * zq), 2.0 * (y * zq - w * x),
+                         2.0 * (x * zq - w * y), 2.0 * (y * zq + w * x), 1.0 - 2.0 * (x * x + y * y)};
+    const int i = l;
     const double off = R[i * 3 + 0] * sc[0] * z[0] + R[i * 3 + 1] * sc[1] * z[1] + R[i * 3 + 2] * sc[2] * z[2];
     mean[i * st + c] = (float)((double)mean[i * st + p] + off);
+    const double ln16 = 0.47000362924573558;  // ln 1.6
+    log_scale[i * st + c] = (float)((double)log_scale[i * st + p] - ln16);
+  } else {
+    for (int i = 0; i < 4; i++) quat[i * st + c] = quat[i * st + p];
+    logit[c] = logit[p];
   }
-  for (int i = 0; i < 4; i++) quat[i * st + c] = quat[i * st + p];
-  const double ln16 = 0.47000362924573558;  // ln 1.6
-  for (int i = 0; i < 3; i++) log_scale[i * st + c] = (float)((double)log_scale[i * st + p] - ln16);
-  logit[c] = logit[p];
-  // the child row c >= n never overlaps a parent row p < n: load every coefficient first so the
-  // loads are in flight together, then store
-  float shv[48];
+  // the child row c >= n never overlaps a parent row p < n: a quarter of the planes per lane,
+  // loaded together, then stored
+  float shv[12];
 #pragma unroll
-  for (int k = 0; k < 48; k++) shv[k] = k < n_sh ? sh[k * st + p] : 0.f;
+  for (int k = 0; k < 12; k++) shv[k] = 4 * k + l < n_sh ? sh[(int64_t)(4 * k + l) * st + p] : 0.f;
 #pragma unroll
-  for (int k = 0; k < 48; k++)
-    if (k < n_sh) sh[k * st + c] = shv[k];
+  for (int k = 0; k < 12; k++)
+    if (4 * k + l < n_sh) sh[(int64_t)(4 * k + l) * st + c] = shv[k];
 }
 
 }  // namespace
@@ -340,7 +356,7 @@ void launch_densify_select(const SceneK& s, const DensifyArgs& a, const float* g
 void launch_densify_spawn(float* mean, float* quat, float* log_scale, float* logit, float* sh, int n_planes_sh,
                           int stride, int n, int capacity, const uint32_t* sel_idx, const uint32_t* d_count, int k_max,
                           uint64_t seed, int32_t* n_appended, hipStream_t st) {
-  const int blocks = k_max > 0 ? (k_max + 255) / 256 : 1;
+  const int blocks = k_max > 0 ? (int)(((int64_t)k_max * 4 + 255) / 256) : 1;
   k_densify_spawn<<<blocks, 256, 0, st>>>(mean, quat, log_scale, logit, sh, n_planes_sh, stride, n, capacity, sel_idx,
                                            d_count, k_max, seed, n_appended);
 }
