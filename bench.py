@@ -187,21 +187,27 @@ def build_workload(args):
     return st
 
 
-def train_step(s, it, args, per_view=False):
+def train_step(s, it, args, per_view=False, overlap=True):
+    """One training step; with `overlap` the H_dyn field runs on a second stream beside H_st,
+    without it (graph capture: a captured fork replays on separate hardware queues) on the
+    current stream."""
     ctx, g, gs, cams = s["ctx"], s["g"], s["gs"], s["cams"]
     fields = s.get("fields")
     if fields:
         nd, ns = s["nd"], s["ns"]
         torch = s["torch"]
-        main, side = torch.cuda.current_stream(), s["side"]
+        main = torch.cuda.current_stream()
+        side = s["side"] if overlap else main
         for f in s["field_grads"].values():
             for t in f.arrays():
                 t.zero_()
-        side.wait_stream(main)
+        if overlap:
+            side.wait_stream(main)
         s["ctx_dyn"].hash_field_fwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["dpos"], s["drot"], col=0,
                                     stream=side)
         ctx.hash_field_fwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["dpos"], s["drot"], col=nd)
-        main.wait_stream(side)
+        if overlap:
+            main.wait_stream(side)
         ctx.shift_fwd(g, gs, s["rows"], s["dpos"], s["drot"])
     else:
         ctx.shift_fwd(g, gs, s["dyn"], s["dpos"], s["drot"])
@@ -238,12 +244,14 @@ def train_step(s, it, args, per_view=False):
                            s["cnt"])
     if fields:
         ctx.shift_adjoint(g, s["rows"], s["drot"], s["grads"], s["d_dpos"], s["d_drot"])
-        side.wait_stream(main)
+        if overlap:
+            side.wait_stream(main)
         s["ctx_dyn"].hash_field_bwd(fields["dyn"], g.mean, s["N"], s["dyn_rows"], nd, s["d_dpos"], s["d_drot"],
                                     s["field_grads"]["dyn"], col=0, stream=side)
         ctx.hash_field_bwd(fields["st"], g.mean, s["N"], s["st_rows"], ns, s["d_dpos"], s["d_drot"],
                            s["field_grads"]["st"], col=nd)
-        main.wait_stream(side)
+        if overlap:
+            main.wait_stream(side)
         groups = []
         for k, f in fields.items():
             m, v = s["field_mv"][k]
@@ -287,11 +295,11 @@ def time_graph_steps(s, args, k, warm, first_step):
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        train_step(s, None, args)  # warm-up on a side stream (also a real step)
+        train_step(s, None, args, overlap=False)  # warm-up on a side stream (also a real step)
     torch.cuda.current_stream().wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        train_step(s, None, args)
+        train_step(s, None, args, overlap=False)
     for _ in range(warm):
         graph.replay()
     torch.cuda.synchronize()
