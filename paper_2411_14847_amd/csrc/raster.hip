@@ -221,6 +221,38 @@ __device__ __forceinline__ uint32_t quad_mask(float mx, float my, float A, float
   const float thr = (2.0f * 0.6931471805599453f) * __builtin_amdgcn_logf(255.0f * o) * 1.001f + 1e-3f;
   const float ia = A > 0.f ? __builtin_amdgcn_rcpf(A) : 0.f, ic = C > 0.f ? __builtin_amdgcn_rcpf(C) : 0.f;
   uint32_t m = 0;
+  if constexpr (PW == 2) {
+    // rect_min_q for the 2x2 grid of quadrants, sharing the work of each column and row: the
+    // vertical segment of column cx sits at the same x (and the line minimiser there at the
+    // same y) for both rows, and likewise for the horizontal segment of row cy; relative to the
+    // mean, clamp(mx, x0, x1) - mx = clamp(0, x0 - mx, x1 - mx).
+    const float xl[2] = {-mx, 8.f - mx}, xh[2] = {7.f - mx, 15.f - mx};
+    const float yl[2] = {-my, 8.f - my}, yh[2] = {7.f - my, 15.f - my};
+    const float nbc = -B * ic, nba = -B * ia, b2 = 2.f * B;
+    float qv[4];
+#pragma unroll
+    for (int cx = 0; cx < 2; cx++) {
+      const float dx = __builtin_amdgcn_fmed3f(0.f, xl[cx], xh[cx]);
+      const float ys = dx * nbc, ax = A * dx * dx, bx = b2 * dx;
+#pragma unroll
+      for (int cy = 0; cy < 2; cy++) {
+        const float dy = __builtin_amdgcn_fmed3f(ys, yl[cy], yh[cy]);
+        qv[cx + 2 * cy] = fmaf(dy, fmaf(C, dy, bx), ax);  // A dx^2 + 2B dx dy + C dy^2
+      }
+    }
+#pragma unroll
+    for (int cy = 0; cy < 2; cy++) {
+      const float dy = __builtin_amdgcn_fmed3f(0.f, yl[cy], yh[cy]);
+      const float xs = dy * nba, cy2 = C * dy * dy, by = b2 * dy;
+#pragma unroll
+      for (int cx = 0; cx < 2; cx++) {
+        const float dx = __builtin_amdgcn_fmed3f(xs, xl[cx], xh[cx]);
+        const float qh = fmaf(dx, fmaf(A, dx, by), cy2);
+        if (fminf(qv[cx + 2 * cy], qh) <= thr) m |= 1u << (cx + 2 * cy);
+      }
+    }
+    return m;
+  }
 #pragma unroll 1  // rolled: unrolled, the four rectangles cost the forward an occupancy step
   for (int k = 0; k < PW * PW; k++) {
     const float x0 = (float)(8 * (k % PW)), y0 = (float)(8 * (k / PW));
