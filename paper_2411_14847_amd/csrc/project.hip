@@ -219,6 +219,58 @@ __device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD
   V.depth_bits = V.visible ? __float_as_uint((float)tz) : 0xFFFFFFFFu;
 }
 
+// What the adjoint needs of a (view, Gaussian) that the forward found visible: the camera-space
+// mean and the clip decisions and clamped tangents exactly as the forward computes them (so the
+// adjoint takes the same branch of the clamp), then the Jacobian, T = J W and the conic from
+// reciprocals of tz and det (gradients: a rounding apart from the forward's quotients).
+struct ViewAdj {
+  double t[3], limx, limy, txc, tyc, itz, J0, J2, J4, J5, T[6], A, B, C;
+  bool clipx, clipy;
+};
+
+__device__ __forceinline__ void adjoint_view(const GaussLite& G, const CamK& cam, ViewAdj& V) {
+  double W[9];
+  for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
+  const double fx = (double)cam.fx, fy = (double)cam.fy;
+  {
+#pragma clang fp contract(off)
+    for (int i = 0; i < 3; i++)
+      V.t[i] = ((W[i * 3 + 0] * G.mu[0] + W[i * 3 + 1] * G.mu[1]) + W[i * 3 + 2] * G.mu[2]) + (double)cam.t[i];
+    V.limx = kClip * ((double)cam.W / (2.0 * fx));
+    V.limy = kClip * ((double)cam.H / (2.0 * fy));
+    const double rx = V.t[0] / V.t[2], ry = V.t[1] / V.t[2];
+    V.clipx = (rx < -V.limx) || (rx > V.limx);
+    V.clipy = (ry < -V.limy) || (ry > V.limy);
+    V.txc = fmin(fmax(rx, -V.limx), V.limx) * V.t[2];
+    V.tyc = fmin(fmax(ry, -V.limy), V.limy) * V.t[2];
+  }
+  V.itz = 1.0 / V.t[2];
+  const double itz2 = V.itz * V.itz;
+  V.J0 = fx * V.itz;
+  V.J2 = -fx * V.txc * itz2;
+  V.J4 = fy * V.itz;
+  V.J5 = -fy * V.tyc * itz2;
+  for (int j = 0; j < 3; j++) {
+    V.T[j] = V.J0 * W[j] + V.J2 * W[6 + j];
+    V.T[3 + j] = V.J4 * W[3 + j] + V.J5 * W[6 + j];
+  }
+  const double* S = G.Sig;
+  double TS[6];
+  for (int i = 0; i < 2; i++) {
+    const double* Ti = V.T + 3 * i;
+    TS[3 * i + 0] = Ti[0] * S[0] + Ti[1] * S[1] + Ti[2] * S[2];
+    TS[3 * i + 1] = Ti[0] * S[1] + Ti[1] * S[3] + Ti[2] * S[4];
+    TS[3 * i + 2] = Ti[0] * S[2] + Ti[1] * S[4] + Ti[2] * S[5];
+  }
+  const double a = (TS[0] * V.T[0] + TS[1] * V.T[1] + TS[2] * V.T[2]) + kDilation;
+  const double b = TS[0] * V.T[3] + TS[1] * V.T[4] + TS[2] * V.T[5];
+  const double c = (TS[3] * V.T[3] + TS[4] * V.T[4] + TS[5] * V.T[5]) + kDilation;
+  const double rdet = 1.0 / (a * c - b * b);
+  V.A = c * rdet;
+  V.B = -b * rdet;
+  V.C = a * rdet;
+}
+
 template <int DEG, typename GT>
 __device__ __forceinline__ void colour(const GT& G, const CamK& cam, const float* shc, double* rgb_pre,
                                        double* dhat, double& dn) {
@@ -301,6 +353,7 @@ __device__ __forceinline__ float quad_sumf(float x) {
 // and chains them back to the parameters with every lane busy.
 constexpr int kAdjWaves = 4;
 __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK sc, CamsK cams, int nv,
+                                                                        const uint8_t* __restrict__ vis,
                                                                         const float* __restrict__ g2d, dass_grads gr,
                                                                         float* __restrict__ gradnorm,
                                                                         int32_t* __restrict__ gcount) {
@@ -325,14 +378,16 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK s
   double dop = 0.0, gnorm = 0.0;
   int cnt = 0;
   for (int v = wave; v < nv && live; v += kAdjWaves) {
+    // the forward's visibility flag of this (view, Gaussian): its projection is not redone
+    // where it did not draw
+    if (!(vis[(int64_t)v * sc.n + g] & 8u)) continue;
     const CamK& cam = cams.c[v];
     const float* gd = g2d + ((int64_t)v * sc.n + g) * 9;
     float gv[6];  // issued before the projection so that the loads overlap it
 #pragma unroll
     for (int i = 0; i < 6; i++) gv[i] = gd[i];
-    ViewD V;
-    project_view(L, cam, V);
-    if (!V.visible) continue;
+    ViewAdj V;
+    adjoint_view(L, cam, V);
     // blend sums of this (view, Gaussian): M = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
     // sum dP dy^2, d opacity, d rgb) with dP = dL/d(exponent), exponent = -(A dx^2 + 2B dx dy +
     // C dy^2)/2 and (dx, dy) = mean - pixel, so dL/du = -(A M0 + B M1), dL/dv = -(B M0 + C M1),
@@ -380,18 +435,18 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK s
     const double dJ4 = dT[3] * W[3] + dT[4] * W[4] + dT[5] * W[5];
     const double dJ5 = dT[3] * W[6] + dT[4] * W[7] + dT[5] * W[8];
     const double fx = (double)cam.fx, fy = (double)cam.fy;
-    const double tx = V.t[0], ty = V.t[1], tz = V.t[2];
-    const double tz2 = tz * tz, tz3 = tz2 * tz;
+    const double tx = V.t[0], ty = V.t[1];
+    const double itz = V.itz, itz2 = itz * itz, itz3 = itz2 * itz;
     double dt[3] = {0.0, 0.0, 0.0};
-    dt[2] += -dJ0 * fx / tz2 - dJ4 * fy / tz2;
-    dt[2] += 2.0 * dJ2 * fx * V.txc / tz3 + 2.0 * dJ5 * fy * V.tyc / tz3;
-    const double dtxc = -dJ2 * fx / tz2, dtyc = -dJ5 * fy / tz2;
+    dt[2] += -dJ0 * fx * itz2 - dJ4 * fy * itz2;
+    dt[2] += 2.0 * dJ2 * fx * V.txc * itz3 + 2.0 * dJ5 * fy * V.tyc * itz3;
+    const double dtxc = -dJ2 * fx * itz2, dtyc = -dJ5 * fy * itz2;
     if (!V.clipx) dt[0] += dtxc; else dt[2] += dtxc * (tx > 0.0 ? V.limx : -V.limx);
     if (!V.clipy) dt[1] += dtyc; else dt[2] += dtyc * (ty > 0.0 ? V.limy : -V.limy);
     // pixel-space mean
-    dt[0] += du * fx / tz;
-    dt[1] += dv * fy / tz;
-    dt[2] -= (du * fx * tx + dv * fy * ty) / tz2;
+    dt[0] += du * fx * itz;
+    dt[1] += dv * fy * itz;
+    dt[2] -= (du * fx * tx + dv * fy * ty) * itz2;
     for (int i = 0; i < 3; i++) dmu[i] += W[i] * dt[0] + W[3 + i] * dt[1] + W[6 + i] * dt[2];
   }
   // combine the waves of this Gaussian (fixed order)
@@ -581,7 +636,8 @@ void launch_preprocess_bwd(const SceneK& s, const CamsK& cams, int nv, const Wor
   if (s.n == 0) return;
   const int64_t threads = (int64_t)s.n * kBwdSplit;
   dim3 grid((unsigned)((threads + 255) / 256)), block(256);
-  k_preprocess_bwd_geom<<<(s.n + 63) / 64, 64 * kAdjWaves, 0, st>>>(s, cams, nv, ws.g2d, grads, gradnorm, gcount);
+  k_preprocess_bwd_geom<<<(s.n + 63) / 64, 64 * kAdjWaves, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads, gradnorm,
+                                                                 gcount);
   if (!grads.mean && !grads.sh) return;
   switch (s.deg) {
     case 0: k_preprocess_bwd_colour<0><<<grid, block, 0, st>>>(s, cams, nv, ws.vis, ws.g2d, grads); break;
