@@ -459,10 +459,10 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   stage_begin(ctx, DASS_STAGE_PROJECT, st);
   launch_preprocess(sc, ck, n_views, ws, st);
   stage_end(ctx, DASS_STAGE_PROJECT, st);
-  // 2. per-view depth order: sort (view << 32 | depth bits, index)
+  // 2. per-view depth order: sort (view << 31 | depth bits, index)
   stage_begin(ctx, DASS_STAGE_DEPTH_SORT, st);
   launch_fill_u32(ws.counters + 2, (uint32_t)vn, 1, st);
-  const int dcur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 2, vn, 0, 32 + bit_width((uint64_t)(n_views - 1)),
+  const int dcur = radix_sort_u64(ws.dkey, ws.dval, ws.counters + 2, vn, 0, 31 + bit_width((uint64_t)(n_views - 1)),
                                   ws.hist, sort_blocks_for(vn), st);
   ws.gid_s = ws.dval[dcur];
   stage_end(ctx, DASS_STAGE_DEPTH_SORT, st);

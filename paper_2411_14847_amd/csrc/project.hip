@@ -328,7 +328,8 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
       rect[i] = make_uint2(0, 0);
     }
     rec[i] = r;
-    dkey[i] = ((uint64_t)v << 32) | (uint64_t)V.depth_bits;
+    // the depth is a positive float (or the all-ones sentinel), so 31 bits order it
+    dkey[i] = ((uint64_t)v << 31) | (uint64_t)(V.depth_bits & 0x7FFFFFFFu);
     dval[i] = (uint32_t)g;
   }
 }

@@ -394,10 +394,11 @@ int sort_blocks_for(int64_t max_count) {
 
 int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
                    int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
-  // 8-bit digits: over the 4M (view, depth) keys of a 200k-Gaussian, 20-view call five 8-bit passes
-  // took 0.229 ms against 0.249 for four 10-bit ones (the scatter's runs per digit are four
-  // times longer, so its stores coalesce)
-  return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st, 8);
+  // digits of at most 9 bits: over the 4M 36-bit (view, depth) keys of a 200k-Gaussian, 20-view
+  // call four 9-bit passes take 0.219 ms, five 8-bit ones 0.233 and four 10-bit ones 0.249 (with
+  // 1,024 digits a batch leaves about two pairs per digit run, so the scatter's stores barely
+  // coalesce)
+  return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st, 9);
 }
 
 int radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
