@@ -150,8 +150,25 @@ struct ViewD {
   uint32_t depth_bits;
 };
 
+// Half-FOV clip limits of the tangents t_x / t_z and t_y / t_z (1.3 times the half-FOV tangent).
+__device__ __forceinline__ void clip_limits(const CamK& cam, double& limx, double& limy) {
+#pragma clang fp contract(off)
+  limx = kClip * ((double)cam.W / (2.0 * (double)cam.fx));
+  limy = kClip * ((double)cam.H / (2.0 * (double)cam.fy));
+}
+
+// Views' clip limits computed once per workgroup (threads 0..nv-1; the caller synchronises).
+struct ClipTable {
+  double lim[DASS_MAX_VIEWS][2];
+};
+
+__device__ __forceinline__ void fill_clip_table(const CamsK& cams, int nv, ClipTable& t) {
+  for (int v = threadIdx.x + threadIdx.y * blockDim.x; v < nv; v += blockDim.x * blockDim.y)
+    clip_limits(cams.c[v], t.lim[v][0], t.lim[v][1]);
+}
+
 template <typename GT>
-__device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD& V) {
+__device__ __forceinline__ void project_view(const GT& G, const CamK& cam, double limx, double limy, ViewD& V) {
 #pragma clang fp contract(off)
   double W[9];
   for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
@@ -165,8 +182,8 @@ __device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD
   V.depth_bits = 0xFFFFFFFFu;
   if (!G.ok || !(tz > kNearZ)) return;
   const double fx = (double)cam.fx, fy = (double)cam.fy;
-  V.limx = kClip * ((double)cam.W / (2.0 * fx));
-  V.limy = kClip * ((double)cam.H / (2.0 * fy));
+  V.limx = limx;
+  V.limy = limy;
   const double rx = tx / tz, ry = ty / tz;
   V.clipx = (rx < -V.limx) || (rx > V.limx);
   V.clipy = (ry < -V.limy) || (ry > V.limy);
@@ -206,11 +223,14 @@ __device__ __forceinline__ void project_view(const GT& G, const CamK& cam, ViewD
   V.radius = (int)r;
   V.u = ((fx * tx) / tz) + (double)cam.cx;
   V.v = ((fy * ty) / tz) + (double)cam.cy;
+  // tile edges are powers of two (16, 32 or 64), so scaling by the edge's exponent is the exact
+  // quotient
   const double tw = (double)cam.tw, th = (double)cam.th;
-  const double fx0 = floor((V.u - r) / tw);
-  const double fx1 = floor(((V.u + r) + (tw - 1.0)) / tw);
-  const double fy0 = floor((V.v - r) / th);
-  const double fy1 = floor(((V.v + r) + (th - 1.0)) / th);
+  const int ew = __builtin_ctz((unsigned)cam.tw), eh = __builtin_ctz((unsigned)cam.th);
+  const double fx0 = floor(ldexp(V.u - r, -ew));
+  const double fx1 = floor(ldexp((V.u + r) + (tw - 1.0), -ew));
+  const double fy0 = floor(ldexp(V.v - r, -eh));
+  const double fy1 = floor(ldexp((V.v + r) + (th - 1.0), -eh));
   V.x0 = (int)fmin(fmax(fx0, 0.0), (double)cam.TX);
   V.x1 = (int)fmin(fmax(fx1, 0.0), (double)cam.TX);
   V.y0 = (int)fmin(fmax(fy0, 0.0), (double)cam.TY);
@@ -228,7 +248,8 @@ struct ViewAdj {
   bool clipx, clipy;
 };
 
-__device__ __forceinline__ void adjoint_view(const GaussLite& G, const CamK& cam, ViewAdj& V) {
+__device__ __forceinline__ void adjoint_view(const GaussLite& G, const CamK& cam, double limx, double limy,
+                                             ViewAdj& V) {
   double W[9];
   for (int i = 0; i < 9; i++) W[i] = (double)cam.R[i];
   const double fx = (double)cam.fx, fy = (double)cam.fy;
@@ -236,8 +257,8 @@ __device__ __forceinline__ void adjoint_view(const GaussLite& G, const CamK& cam
 #pragma clang fp contract(off)
     for (int i = 0; i < 3; i++)
       V.t[i] = ((W[i * 3 + 0] * G.mu[0] + W[i * 3 + 1] * G.mu[1]) + W[i * 3 + 2] * G.mu[2]) + (double)cam.t[i];
-    V.limx = kClip * ((double)cam.W / (2.0 * fx));
-    V.limy = kClip * ((double)cam.H / (2.0 * fy));
+    V.limx = limx;
+    V.limy = limy;
     const double rx = V.t[0] / V.t[2], ry = V.t[1] / V.t[2];
     V.clipx = (rx < -V.limx) || (rx > V.limx);
     V.clipy = (ry < -V.limy) || (ry > V.limy);
@@ -297,6 +318,9 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
                                                     uint8_t* __restrict__ vis, uint64_t* __restrict__ dkey,
                                                     uint32_t* __restrict__ dval) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ ClipTable s_clip;
+  fill_clip_table(cams, nv, s_clip);
+  __syncthreads();
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= sc.n) return;
   GaussD G;
@@ -310,7 +334,7 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneK sc, CamsK cams, int n
     const CamK& cam = cams.c[v];
     const int64_t i = (int64_t)v * sc.n + g;
     ViewD V;
-    project_view(G, cam, V);
+    project_view(G, cam, s_clip.lim[v][0], s_clip.lim[v][1], V);
     Rec r;
     if (V.visible) {
       double rgb_pre[3], dhat[3], dn;
@@ -360,6 +384,9 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK s
                                                                         int32_t* __restrict__ gcount) {
   __shared__ double s_part[kAdjWaves - 1][11][64];  // dmu[3], dSig[6], dop, gnorm of waves 1..3
   __shared__ int s_cnt[kAdjWaves - 1][64];
+  __shared__ ClipTable s_clip;
+  fill_clip_table(cams, nv, s_clip);
+  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g_raw = blockIdx.x * 64 + lane;
   const bool live = g_raw < sc.n;
@@ -388,7 +415,7 @@ __global__ __launch_bounds__(64 * kAdjWaves) void k_preprocess_bwd_geom(SceneK s
 #pragma unroll
     for (int i = 0; i < 6; i++) gv[i] = gd[i];
     ViewAdj V;
-    adjoint_view(L, cam, V);
+    adjoint_view(L, cam, s_clip.lim[v][0], s_clip.lim[v][1], V);
     // blend sums of this (view, Gaussian): M = (sum dP dx, sum dP dy, sum dP dx^2, sum dP dx dy,
     // sum dP dy^2, d opacity, d rgb) with dP = dL/d(exponent), exponent = -(A dx^2 + 2B dx dy +
     // C dy^2)/2 and (dx, dy) = mean - pixel, so dL/du = -(A M0 + B M1), dL/dv = -(B M0 + C M1),
@@ -593,8 +620,10 @@ __global__ void k_debug_projection(SceneK sc, CamK cam, double* out) {
   if (g >= sc.n) return;
   GaussD G;
   load_gaussian(sc, g, G);
+  double limx, limy;
+  clip_limits(cam, limx, limy);
   ViewD V;
-  project_view(G, cam, V);
+  project_view(G, cam, limx, limy, V);
   double* o = out + (int64_t)g * 16;
   double rgb_pre[3] = {0, 0, 0}, dhat[3], dn;
   float shc[48];
