@@ -8,8 +8,8 @@
 //
 // Blend.  One wave per sub-tile of a tile (16x16 with four pixels per lane, one in each 8x8
 // quadrant, or 8x8 with one pixel per lane, for small images where the lists are walked by few
-// waves).  The tile's list is consumed in batches of 128 entries, each culled against the
-// quadrants of the wave's sub-tile and compacted into LDS; every lane walks its pixels front
+// waves).  The tile's list is consumed in batches of 64, 128 or 256 entries (a per-call option),
+// each culled against the quadrants of the wave's sub-tile and compacted into LDS; every lane walks its pixels front
 // to back, skipping the quadrants an entry misses, and the wave stops as soon as every pixel
 // has hit the transmittance stop.
 // The backward recomputes each entry's alpha per batch, recovers the transmittance by dividing
@@ -624,8 +624,8 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         // dL/d alpha = T (dL/dC . (colour - colour behind)); the colour behind moves by alpha of that
         const float ed = fmaf(c.x, dC0[k], fmaf(c.y, dC1[k], fmaf(c.z, dC2[k], nS[k])));
         nS[k] = fmaf(-ae, ed, nS[k]);
-        // dP = alpha dL/d alpha: dL/d(exponent), and the opacity times dL/d(opacity)
-        float dP = (T[k] * ed) * ae;
+        // dP = alpha dL/d alpha = alpha T ed: dL/d(exponent), and the opacity times dL/d(opacity)
+        float dP = wgt * ed;
         if (__builtin_expect(clampable, 0)) {
           __asm__ volatile("");  // keeps this rarely taken uniform branch a branch
           dP = araw < kAlphaMax ? dP : 0.f;  // no derivative through an active clamp
