@@ -965,7 +965,7 @@ def main():
     elif not args.no_tile_autotune:
         # native autotuner over tile sizes and blend batches on this workload (outside the timed
         # region)
-        tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=3,
+        tuned = ctx.autotune_tile(s["gs"], s["cams"], args.bg, s["outs"], s["dls"], s["grads"], reps=5,
                                   batches=(args.batch,) if args.batch else BATCH_CANDIDATES)
         log(f"[bench] autotune (ms per fwd+bwd): {tuned}; using {ctx.tile}, batch {ctx.batch}")
     # pair counts of the blend (outside the timed region), always at 16x16 tiles: with larger

@@ -461,7 +461,7 @@ dass_status dass_debug_keys(dass_ctx ctx, int32_t view, uint64_t* keys, uint32_t
  * `reps` times between two HIP events on `stream`, and writes the mean milliseconds per
  * fwd+bwd into ms[c] (host array; -1 for a candidate whose tiles or keys exceed the
  * context's budgets) and into *best (host) the index of the first candidate, in the given
- * order of preference, whose time is within 2% of the fastest.  out, dl_drgb and grads
+ * order of preference, whose time is within 1% of the fastest.  out, dl_drgb and grads
  * are as for render_fwd / render_bwd; grads is accumulated into (scratch for the caller).
  * Synchronises the stream (not for graph capture) and leaves no state for render_bwd.
  * DASS_E_CAPACITY if no candidate fits. */

@@ -316,7 +316,7 @@ class Context:
         """Times render_fwd + render_bwd of this workload at each candidate tile size and blend
         batch (native autotuner; synchronises) and, if `apply`, makes its choice this context's
         tile size and batch: the first candidate, in the given order (tiles, then batches), within
-        2% of the fastest.  Returns {(tw, th[, 8]): ms} for a single batch, else
+        1% of the fastest.  Returns {(tw, th[, 8]): ms} for a single batch, else
         {((tw, th[, 8]), batch): ms}; None where a candidate does not fit the budgets.  `grads`
         is scratch."""
         imgs = (F.Image * len(cams))(*[o.struct() for o in out])

@@ -132,7 +132,9 @@ def test_autotuner_picks_a_timed_candidate_and_keeps_parity():
     log(f"  autotune: {res}; chose {ctx.tile}")
     assert ctx.tile in res and res[ctx.tile] is not None
     fastest = min(v for v in res.values() if v is not None)
-    first_close = next(c for c, v in res.items() if v is not None and v <= 1.02 * fastest)
+    # the library's rule, in its float32 arithmetic: the first candidate within 1% of the fastest
+    lim = np.float32(1.01) * np.float32(fastest)
+    first_close = next(c for c, v in res.items() if v is not None and np.float32(v) <= lim)
     assert ctx.tile == first_close
     out = ctx.render_fwd(g, cams, BG)
     ctx.sync()
