@@ -37,7 +37,7 @@ struct dass_ctx_s {
   bool have_fwd = false;
   int fwd_n = 0, fwd_nv = 0, fwd_stride = 0;
   int64_t fwd_tiles = 0;
-  int fwd_tw = kTile, fwd_th = kTile;
+  int fwd_tw = kTile, fwd_th = kTile, fwd_sub = kTile;
   int fwd_key_buf = 0;
   CamsK fwd_cams{};
   float fwd_bg[3] = {0.f, 0.f, 0.f};
@@ -499,6 +499,7 @@ dass_status render_fwd_impl(dass_ctx ctx, const dass_gaussians* g, const dass_ca
   ctx->fwd_tiles = total_tiles;
   ctx->fwd_tw = tw;
   ctx->fwd_th = th;
+  ctx->fwd_sub = sub;
   ctx->fwd_key_buf = kcur;
   ctx->fwd_cams = ck;
   for (int c = 0; c < 3; c++) ctx->fwd_bg[c] = bg[c];
@@ -546,6 +547,11 @@ dass_status render_bwd(dass_ctx ctx, const dass_gaussians* g, const dass_camera*
   if (!matches_fwd(ctx, g, n_views, total_tiles, tw, th, ck))
     return fail(ctx, DASS_E_INVALID, "render_bwd does not match the last render_fwd on this context "
                                      "(scene size, cameras or tile size)");
+  // alpha is recomputed from pixel offsets relative to the sub-tile's origin, rounded as the
+  // forward's (whose blend decisions n_contrib records) only at the same sub-tile size
+  if (sub != ctx->fwd_sub)
+    return fail(ctx, DASS_E_INVALID, "render_bwd: sub-tile size %d differs from the last render_fwd's %d", sub,
+                ctx->fwd_sub);
   for (int c = 0; c < 3; c++)
     if (bg[c] != ctx->fwd_bg[c])
       return fail(ctx, DASS_E_INVALID, "render_bwd: background differs from the last render_fwd's");
