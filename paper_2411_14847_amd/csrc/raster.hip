@@ -432,7 +432,10 @@ __global__ __launch_bounds__(kLanes) void k_blend_fwd(ViewsIO io, int nv, int to
         float wgt = ok ? a * T[k] : 0.f;
         T[k] -= wgt;  // updated in place: a pixel that stops here gets its transmittance back below
         bool take = ok;
-        const bool stop = ok && T[k] < kTStop;
+        // only a pixel that passed the test can cross the stop: the others keep a transmittance at
+        // or above it (a stopped pixel's is restored below, to within one rounding of the value
+        // before its stop; were that under the stop, this branch would only repeat the restore)
+        const bool stop = T[k] < kTStop;
         if (__builtin_expect(__ballot(stop) != 0, 0)) {  // uniform: a pixel of the quadrant stops here
           // T - w + w: the transmittance before this entry up to one rounding
           T[k] = stop ? T[k] + wgt : T[k];
@@ -569,6 +572,12 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
         xy = make_float2((R.r0.x - fx0) + R.r0.z, (R.r0.y - fy0) + R.r0.w);
         cn = R.r1;
         qm = quad_mask<PW>(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w);
+        // and only the quadrants where some pixel's last contribution is at or after the entry
+        // (a compare per lane and quadrant here instead of a scalar test per entry and quadrant
+        // in the walk; an entry left with none is not staged)
+#pragma unroll
+        for (int k = 0; k < NP; k++)
+          if (bi * B + e >= qlast[k]) qm &= ~(1u << k);
         const uint32_t cb = cn.w >= kAlphaMax ? kClampBit : 0u;  // as the forward's
         rgb = make_float4(R.r2.x, R.r2.y, R.r2.z, __uint_as_float((uint32_t)(bi * B + e) | cb | (qm << kQmShift)));
       }
@@ -604,8 +613,8 @@ __global__ __launch_bounds__(kLanes) void k_blend_bwd(ViewsIO io, int nv, int to
 #pragma unroll
       for (int k = 0; k < NP; k++) {
         // uniform: the entry misses quadrant k, or lies behind the last contribution of every
-        // pixel there
-        if (NP > 1 && !(((qm >> k) & 1u) && idx < qlast[k])) continue;
+        // pixel there (both folded into the staged mask)
+        if (NP > 1 && !((qm >> k) & 1u)) continue;
         const float dx = dxb - (float)(8 * (k % PW)), dy = dyb - (float)(8 * (k / PW));
         const float pw = fmaf(dx, fmaf(co.x, dx, co.y * dy), fmaf(co.z * dy, dy, co.w));  // + log2 o
         const float araw = __builtin_amdgcn_exp2f(pw);
