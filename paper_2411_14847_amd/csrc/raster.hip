@@ -729,7 +729,7 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
 #pragma unroll
     for (int k = 0; k < NP; k++) qalive |= __ballot(thr[k] < 1.f) != 0 ? 1u << k : 0u;
     __syncthreads();
-    for (int j = 0; j < n_kept; j++) {
+    for (int j = 0; j < n_kept && qalive != 0; j++) {
       const float2 xy = s_xy[j];
       const float4 co = s_co[j];
       const uint32_t qm = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_qm[j]) & qalive;
@@ -747,10 +747,13 @@ __global__ __launch_bounds__(kLanes) void k_blend_feat(ViewsIO io, int nv, int t
         const bool ok = a >= thr[k];
         float wgt = ok ? a * T[k] : 0.f;
         T[k] -= wgt;
-        const bool stop = ok && T[k] < kTStop;
-        T[k] = stop ? T[k] + wgt : T[k];
-        wgt = stop ? 0.f : wgt;
-        thr[k] = stop ? kNever : thr[k];
+        const bool stop = T[k] < kTStop;  // as the colour forward's: only a passing pixel can cross it
+        if (__builtin_expect(__ballot(stop) != 0, 0)) {  // uniform: a pixel of the quadrant stops here
+          T[k] = stop ? T[k] + wgt : T[k];
+          wgt = stop ? 0.f : wgt;
+          thr[k] = stop ? kNever : thr[k];
+          if (__ballot(thr[k] < 1.f) == 0) qalive &= ~(1u << k);
+        }
 #pragma unroll
         for (int c = 0; c < kFeatMaxC / 4; c++) {
           acc[k][4 * c] += fe[c].x * wgt;
