@@ -6,8 +6,8 @@
 //   (1) upsweep: every block histograms its contiguous chunk into LDS (per-wave
 //       sub-histograms to spread LDS atomics), written digit-major to global memory;
 //   (2) scan: one workgroup per digit turns the [radix][blocks] counts into global offsets;
-//   (3) scatter: every block re-reads its chunk in batches of 2048 pairs (4096 for 10-bit
-//       digits), ranks them stably
+//   (3) scatter: every block re-reads its chunk in batches of 2048 pairs (4096 for 9- and
+//       10-bit digits), ranks them stably
 //       with wave ballots (8-11 ballots give each lane the mask of lanes holding the same
 //       digit; each wave ranks its own quarter of the batch), orders the batch by digit in
 //       LDS and writes each digit's run contiguously.
@@ -352,7 +352,7 @@ void radix_pass(K* keys[2], uint32_t* vals[2], int cur, const uint32_t* d_count,
                 uint32_t* hist, uint32_t* totals, hipStream_t st) {
   k_upsweep<K, RB><<<blocks, kSortThreads, 0, st>>>(keys[cur], d_count, shift, blocks, hist);
   k_scan_rows<<<1 << RB, kSortThreads, 0, st>>>(hist, blocks, totals);
-  k_scatter<K, RB, RB == 10 ? 16 : 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1],
+  k_scatter<K, RB, RB >= 9 ? 16 : 8><<<blocks, kSortThreads, 0, st>>>(keys[cur], vals[cur], keys[cur ^ 1],
                                                                       vals[cur ^ 1], d_count, shift, blocks, hist,
                                                                       totals);
 }
@@ -395,9 +395,9 @@ int sort_blocks_for(int64_t max_count) {
 int radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], const uint32_t* d_count, int64_t max_count, int begin_bit,
                    int end_bit, uint32_t* hist, int blocks, hipStream_t st) {
   // digits of at most 9 bits: over the 4M 36-bit (view, depth) keys of a 200k-Gaussian, 20-view
-  // call four 9-bit passes take 0.219 ms, five 8-bit ones 0.233 and four 10-bit ones 0.249 (with
-  // 1,024 digits a batch leaves about two pairs per digit run, so the scatter's stores barely
-  // coalesce)
+  // call four 9-bit passes take 0.219 ms in 2,048-pair batches and 0.205 in 4,096-pair ones, five
+  // 8-bit ones 0.233 and four 10-bit ones 0.249 (with 1,024 digits a batch leaves about two pairs
+  // per digit run, so the scatter's stores barely coalesce)
   return radix_sort_impl<uint64_t>(keys, vals, d_count, max_count, begin_bit, end_bit, hist, blocks, st, 9);
 }
 
