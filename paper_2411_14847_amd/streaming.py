@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from typing import Dict, List
+from typing import Dict, List, Optional
 
 import torch
 
@@ -177,11 +177,20 @@ class Trainer:
                                self.v_var.sh[i, lo:hi], lr["sh0"] if i < 3 else lr["sh_rest"]))
         return groups
 
-    def iteration(self, stream=None, overlap: bool = True):
+    # scenes from which H_dyn's queries run beside H_st's on the side stream by default
+    OVERLAP_MIN_GAUSSIANS = 50_000
+
+    def iteration(self, stream=None, overlap: Optional[bool] = None):
         """One shift-stage iteration on `stream`.  With `overlap`, H_dyn runs on a second stream
-        beside H_st; without it (graph capture), on `stream` too: a captured fork is replayed with
-        its branches on separate hardware queues once HIP has more than four, which cost the
-        replayed iteration more than the overlap gains (1.3 ms per 20-view iteration at 8 queues)."""
+        beside H_st; without it, on `stream` too.  Once HIP has more than four hardware queues the
+        fork and join cost about 1 ms per iteration, eager or replayed from a graph (1.3 ms per
+        replayed 20-view iteration at 8 queues): the overlap pays for that only when the fields
+        have many queries, so by default (None) it is used from OVERLAP_MIN_GAUSSIANS base
+        Gaussians on (the 200k-Gaussian scene: 604 ms per timestep eager with it, 615 replayed
+        without; the 7k-Gaussian rig: 180 ms eager with it, 62 replayed without), and graph
+        capture passes False."""
+        if overlap is None:
+            overlap = self.g.n_base >= self.OVERLAP_MIN_GAUSSIANS
         ctx, g, gs, cfg = self.ctx, self.g, self.gs, self.cfg
         gs.n, gs.n_base = g.n, g.n_base
         cur = stream if stream is not None else torch.cuda.current_stream()
